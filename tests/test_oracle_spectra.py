@@ -1,0 +1,105 @@
+"""Pins of the oracle's spectral read-out (running DFTs, flux boxes).
+
+* The running transforms equal sum_n dt e^{+i w t_n} f_n recomputed in numpy
+  from per-step recordings, with E-type samples stamped at (n+1) dt and
+  H/J-type samples at (n+1/2) dt.
+* Vacuum with no particle: the scattering box sees nothing and the net flux
+  of the incident plane wave through the absorption box vanishes once the
+  pulse has left it (lossless Yee propagation has unit transfer magnitude);
+  the inward flux through one face equals the incident intensity times the
+  face area times cos(k dx / 2) (H's half-cell average, k from the Yee
+  dispersion relation).
+* Extinction by the induced current (volume optical theorem) agrees with
+  absorption + scattering from the flux boxes on a run whose fields have
+  decayed.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2005_06997_amd import workloads as W
+from tests.helpers import oracle_mask, oracle_problem
+
+
+def test_running_dft_time_stamps_match_numpy():
+    w = W.early_pulse(W.small_sphere(n=30, radius=1.0e-9, npml=4, seed=5))
+    om = W.spectrum_omegas(7)
+    p = oracle_problem(w, flux=False, omega=om)
+    s = orc.OracleSim(p, oracle_mask(w))
+    off = orc.constants()["aux_off"]
+    dt = s.dt
+    Jsum, Einc = [], []
+    nsteps = 90
+    for _ in range(nsteps):
+        s.run(1)
+        J = s.get("Jx")  # J^{n+1/2} after step n, zero outside the metal
+        Jsum.append(J.sum(axis=(1, 2)))
+        e1, _ = s.aux()
+        Einc.append(e1[np.arange(w.nz) + off])
+    Jsum = np.array(Jsum)
+    Einc = np.array(Einc)
+    n = np.arange(nsteps)
+    phJ = np.exp(1j * np.outer(n + 0.5, om) * dt) * dt
+    phE = np.exp(1j * np.outer(n + 1.0, om) * dt) * dt
+    A_np = Jsum.T @ phJ
+    B_np = Einc.T @ phE
+    A, B = s.dft()
+    assert np.abs(Jsum).max() > 0
+    assert np.abs(A - A_np).max() <= 1e-12 * np.abs(A_np).max()
+    assert np.abs(B - B_np).max() <= 1e-12 * np.abs(B_np).max()
+
+
+def test_vacuum_flux_boxes_plane_wave():
+    """No particle: nothing is scattered, no extinction, zero net flux through
+    the absorption box, and the inward flux through its -z face is exactly
+    |E|^2 area cos(k dx / 2) / eta0 (the half-cell average of H across the
+    face, with k from the Yee dispersion relation)."""
+    n = 30
+    dx = 5e-9  # coarse cells so the pulse crosses the grid in a few hundred steps
+    w = W.sphere_problem("vacuum_flux", n, dx, 4, [(n - 1) / 2.0] * 3, 3 * dx)
+    w.t0 = 4.5 * w.tau  # smooth start (~e^-20): the transform of the whole pulse converges
+    om = W.spectrum_omegas(9, 2.0, 5.0)
+    p = oracle_problem(w, flux=True, omega=om)
+    p.norm_k = w.abs_lo[2]
+    s = orc.OracleSim(p, np.zeros((n, n, n), np.uint8))
+    s.run(1400)
+    sp = s.spectra()
+    eta0 = orc.constants()["eta0"]
+    c0 = orc.constants()["c0"]
+    lo, hi = np.array(w.abs_lo), np.array(w.abs_hi)
+    area = float((hi[0] - lo[0]) * (hi[1] - lo[1])) * dx ** 2
+    assert np.abs(sp["ext"]).max() == 0.0
+    assert np.abs(sp["sca"]).max() <= 1e-25 * area  # rounding-level leakage, squared
+    dt = s.dt
+    kn = 2.0 * np.arcsin(np.sin(om * dt / 2.0) * dx / (c0 * dt)) / dx
+    inward = np.array([-s.face_flux(0, 4, m) for m in range(len(om))])
+    outward = np.array([s.face_flux(0, 5, m) for m in range(len(om))])
+    side = np.array([[s.face_flux(0, f, m) for m in range(len(om))] for f in range(4)])
+    ratio = eta0 * inward / (sp["inc"] * area)
+    # limited at ~6e-6 by the auxiliary line's CPML reflection (first order in
+    # |B|^2 through the forward/backward cross term); a half-step error in the
+    # H time stamp would show up as 1 - cos(w dt / 2) ~ 5e-4 at 5 eV
+    assert np.abs(ratio / np.cos(kn * dx / 2.0) - 1.0).max() <= 1e-4
+    assert np.abs(side).max() * eta0 / sp["inc"].min() <= 1e-14 * area
+    assert np.abs(outward / inward - 1.0).max() <= 1e-10
+    assert np.abs(sp["abs"]).max() <= 1e-10 * area
+
+
+@pytest.mark.slow
+def test_extinction_equals_absorption_plus_scattering():
+    """J-route extinction vs flux-box absorption + scattering on a strongly
+    damped sphere (fields decay within the run)."""
+    n = 40
+    dx = 1.0e-9
+    w = W.sphere_problem("ext_balance", n, dx, 6, [(n - 1) / 2.0] * 3, 8.0e-9)
+    w = W.early_pulse(w)
+    om = W.spectrum_omegas(21, 2.0, 7.0)
+    p = oracle_problem(w, flux=True, omega=om, gamma=1.0e15, beta=0.0, diff=0.0, threads=8)
+    s = orc.OracleSim(p, oracle_mask(w))
+    s.run(4000)
+    sp = s.spectra()
+    tot = sp["abs"] + sp["sca"]
+    rel = np.abs(sp["ext"] - tot) / np.abs(sp["ext"]).max()
+    assert rel.max() < 0.03, rel.max()
+    assert np.all(sp["abs"] > 0)
+    assert np.all(sp["sca"] > 0)
