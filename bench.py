@@ -1,0 +1,172 @@
+"""Throughput of the GNOR-FDTD step on one MI355X.
+
+A step is one full leapfrog step of the hot path: H update with CPML and
+TF/SF, fused E / free-electron-current update (GNOR) with CPML and TF/SF,
+auxiliary incident line, FP64 running transforms of the induced current and
+the incident field, and the flux-box transforms.  The workload is a
+gold-like sphere of radius 10 nm on a 320^3 grid at dx = 0.1 nm (12-cell
+CPML), FP32 fields and currents with FP64 spectral accumulators.
+
+Prints one JSON line:  value = Gcell-updates/s (nx ny nz steps / time) of the
+FP32 path; roofline = achieved algorithmic HBM bytes / s of the dominant
+kernel (E/J update) from HIP events on the library's stream; cpu_baseline =
+the FP64 CPU oracle on the host cores on a 10-step sample of the same grid.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(w, mask, word):
+    """Per-launch algorithmic bytes of the H and E/J kernels.
+
+    H:   read E (3) + H (3), write H (3) per cell; CPML: psi read + write for
+         two H components per (cell, axis) inside an absorbing slab.
+    E/J: read H (3) + E^n (3), write E^{n+1} (3) per cell; per metal cell
+         E^{n-1} (3), J read (3) and write (3), Phi_P and Phi_J read + write
+         (4); CPML as for H.
+    """
+    N = w.nx * w.ny * w.nz
+    nm = int(np.count_nonzero(mask))
+    n = (w.nx, w.ny, w.nz)
+    cd = sum(2 * w.npml * (N // n[a]) for a in range(3))
+    h = word * (9 * N + 4 * cd)
+    ej = word * (9 * N + 13 * nm + 4 * cd)
+    return h, ej, nm, cd
+
+
+def run_gpu(w, precision, steps, warmup):
+    import torch
+    from paper_2005_06997_amd import binding
+
+    sim = binding.Sim(w, precision=precision)
+    sim.run(warmup)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return sim, dt
+
+
+def cpu_baseline(w, steps):
+    from oracle import oracle as orc
+    from tests.helpers import oracle_mask, oracle_problem
+
+    threads = min(16, os.cpu_count() or 1)
+    p = oracle_problem(w, threads=threads)
+    s = orc.OracleSim(p, oracle_mask(w))
+    s.run(1)  # first-touch of the arrays
+    t0 = time.perf_counter()
+    s.run(steps)
+    dt = time.perf_counter() - t0
+    s.close()
+    return w.cells * steps / dt / 1e9, threads, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 2 GiB (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU sharding); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_calibration:
+        a = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 31, "launches": 5}))
+        return
+
+    from paper_2005_06997_amd import workloads as W
+
+    w = W.config2("fp32")
+    sim, dt = run_gpu(w, "fp32", args.steps, args.warmup)
+    value = w.cells * args.steps / dt / 1e9
+    ms_step = dt / args.steps * 1e3
+    spec32 = sim.spectra()  # after warmup + steps, before profiling adds steps
+    prof = sim.profile(args.profile_steps)
+    hb, ejb, nmetal, ncd = algorithmic_bytes(w, sim.mask, 4)
+    ach = ejb / (prof["ej"] * 1e-3) / 1e9
+    out = {
+        "metric": "Gcell-updates/s and % HBM roofline, FP32 vs FP64 GNOR-FDTD at stated error",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sphere_r10nm_320^3_dx0.1nm_gnor_fp32_fields_fp64_spectra",
+                   "grid": [w.nx, w.ny, w.nz], "npml": w.npml, "metal_cells": nmetal,
+                   "nfreq": int(len(w.omega)), "flux_boxes": bool(w.flux)},
+        "roofline": {"bound": "hbm", "kernel": "k_ej (E/J update)",
+                     "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": ejb, "avg_launch_ms": round(prof["ej"], 5)},
+        "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
+        "h_roofline_frac": round(hb / (prof["h"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_fp64:
+        steps64 = max(2, args.steps // 2)
+        sim64, dt64 = run_gpu(w, "fp64", steps64, args.warmup)
+        v64 = w.cells * steps64 / dt64 / 1e9
+        prof64 = sim64.profile(max(2, args.profile_steps // 2))
+        _, ejb64, _, _ = algorithmic_bytes(w, sim64.mask, 8)
+        out["fp64"] = {"value": round(v64, 3), "ms_per_step": round(dt64 / steps64 * 1e3, 5),
+                       "roofline_frac": round(ejb64 / (prof64["ej"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "fp32_speedup": round(value / v64, 3)}
+        # FP32 and FP64 runs of equal length, compared spectrum by spectrum
+        sim64.reset()
+        sim64.run(args.warmup + args.steps)
+        s64 = sim64.spectra()
+        err = {}
+        for k in ("ext", "abs", "sca"):
+            den = np.linalg.norm(s64[k])
+            err[k] = float(np.linalg.norm(spec32[k] - s64[k]) / den) if den > 0 else None
+        out["fp32_vs_fp64_spectra_rel_l2"] = err
+        del sim64
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        v, cores, secs = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = {"value": round(v, 5), "unit": "Gcell-updates/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{args.cpu_steps} FP64 oracle steps of the same 320^3 problem "
+                                         f"({secs:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * gnor_fdtd.h -- C ABI of libgnorfdtd, an MI355X (gfx950) implementation of
+ * the hydrodynamic (nonlocal Drude) and GNOR FDTD time step of Baxter,
+ * Cala Lesina & Ramunno, "Parallel FDTD modelling of nonlocality in
+ * plasmonics" (arXiv:2005.06997).
+ *
+ * The problem statement is the paper's: a uniform Yee grid (Sec. III,
+ * Table I), a free-electron metal described by the Drude parameters wp and
+ * gamma plus the hydrodynamic pressure coefficient beta and the GNOR
+ * diffusion constant D (Sec. II, Eqs. NonlocDrude and GNOR), the Pekar
+ * boundary condition (P_f = 0 outside the metal, end of Sec. III), nonlocal
+ * material confined to the total-field region of a TF/SF plane-wave source
+ * (end of Sec. III), a CPML-terminated domain (Sec. V), and absorption /
+ * extinction spectra read from the run (Sec. V).
+ *
+ * Conventions
+ *  - Units are SI.  Arrays are x-fastest, index ((k * ny) + j) * nx + i.
+ *  - Yee positions (Sec. III, Table I): E_x and P_x at (i+1/2, j, k),
+ *    E_y at (i, j+1/2, k), E_z at (i, j, k+1/2); H_x at (i, j+1/2, k+1/2),
+ *    H_y at (i+1/2, j, k+1/2), H_z at (i+1/2, j+1/2, k).  nx, ny, nz count
+ *    nodes including the CPML; PEC walls sit on the outer node planes.
+ *  - Time: E^n at n dt, H at (n - 1/2) dt; a step advances H to n+1/2 and
+ *    E, P_f to n+1 (update order of Sec. III: f1, f2, f4).
+ *  - Ownership: the caller allocates ONE device buffer of
+ *    gnor_required_bytes() bytes and a HIP stream and binds both with
+ *    gnor_bind_memory(); the library carves all device state out of that
+ *    buffer, never frees it, and enqueues all work on that stream.  Host
+ *    inputs are copied before a call returns; outputs go to caller arrays.
+ *  - Errors: every call returns a gnor_status; nothing is thrown across the
+ *    ABI.  gnor_last_error() gives a message for the last failure on a sim.
+ *  - Threads: one gnor_sim must not be used by two host threads at once.
+ */
+#ifndef GNOR_FDTD_H
+#define GNOR_FDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gnor_sim gnor_sim;
+typedef struct gnor_batch gnor_batch;
+
+typedef enum {
+  GNOR_OK = 0,
+  GNOR_E_INVALID_ARG = 1,     /* a size, pointer or parameter is out of range */
+  GNOR_E_UNSTABLE = 2,        /* Courant number outside (0, 1/sqrt(3)) */
+  GNOR_E_OUT_OF_MEMORY = 3,   /* host allocation failed */
+  GNOR_E_DEVICE = 4,          /* a HIP call failed */
+  GNOR_E_STATE = 5,           /* call out of order (e.g. run before bind) */
+  GNOR_E_BUFFER_TOO_SMALL = 6,/* caller buffer smaller than required */
+  GNOR_E_NONFINITE = 7        /* the non-finite watchdog found NaN/Inf */
+} gnor_status;
+
+typedef enum { GNOR_FP32 = 0, GNOR_FP64 = 1 } gnor_precision;
+
+/* Grid, absorbing layers and TF/SF box.
+ * dx: cell size (m); courant: S = c dt / dx, must lie in (0, 1/sqrt(3)).
+ * npml: CPML thickness in cells on every face (0 = bare PEC box).  The
+ * layers use polynomial grading of order pml_order, sigma_max =
+ * pml_sigma_scale (m+1) / (eta0 dx sqrt(eps_background)), kappa rising to
+ * pml_kappa_max and alpha falling from pml_alpha_max (Roden-Gedney CPML).
+ * tf_lo/tf_hi: node indices of the TF box [tf_lo, tf_hi] (inclusive); the
+ * box must lie outside the CPML with one spare cell.  precision: storage and
+ * arithmetic type of fields, free-electron current and CPML memory; the
+ * spectral accumulators are always FP64. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx, courant;
+  int32_t npml;
+  double pml_order, pml_sigma_scale, pml_kappa_max, pml_alpha_max;
+  double eps_background;
+  int32_t tf_lo[3], tf_hi[3];
+  int32_t precision; /* gnor_precision */
+} gnor_grid_desc;
+
+/* Free-electron metal (Sec. II): wp (rad/s), gamma (rad/s), beta (m/s; the
+ * hydrodynamic pressure coefficient is beta^2), diffusion D (m^2/s; GNOR,
+ * eta = beta^2 + D gamma), eps_inf (background permittivity of the metal).
+ * beta = D = 0 is the local Drude model; D = 0 the nonlocal Drude model. */
+typedef struct {
+  double wp, gamma, beta, diffusion, eps_inf;
+} gnor_material_desc;
+
+/* Plane-wave source: x-polarised, travelling along +z, injected through the
+ * TF/SF box from a 1D auxiliary line (same dx, dt, background; 20-cell CPML
+ * at both ends; node k of the grid is line cell k + 25; soft source at line
+ * cell 22).  kind 1: e0 exp(-((t - t0)/tau)^2) sin(omega_c (t - t0));
+ * kind 2: e0 [(1 - cos(omega_max t))/2]^3 for 0 <= t <= 2 pi / omega_max
+ * (the raised-cosine pulse of Sec. V); kind 0: no source. */
+typedef struct {
+  int32_t kind;
+  double e0, omega_c, tau, t0, omega_max;
+} gnor_source_desc;
+
+/* Spectral monitors: running DFTs (factor dt, e^{+i w t}) at nfreq angular
+ * frequencies omega[] (rad/s), every dft_every-th step.  norm_k: grid plane
+ * whose incident transform normalises the cross sections.  flux_enabled:
+ * also accumulate tangential E and H on the faces of the absorption box
+ * (abs_lo..abs_hi, inside the TF box) and the scattering box (sca_lo..sca_hi,
+ * outside it, outside the CPML). */
+typedef struct {
+  int32_t nfreq;
+  const double *omega;
+  int32_t norm_k;
+  int32_t dft_every;
+  int32_t flux_enabled;
+  int32_t abs_lo[3], abs_hi[3];
+  int32_t sca_lo[3], sca_hi[3];
+} gnor_monitor_desc;
+
+/* Create a simulation for a grid.  Checks sizes and the Courant number
+ * (GNOR_E_UNSTABLE if S >= 1/sqrt(3)).  *out receives an opaque handle. */
+gnor_status gnor_create(const gnor_grid_desc *grid, gnor_sim **out);
+void gnor_destroy(gnor_sim *sim);
+
+/* Metal: mask is a host array of nx*ny*nz bytes, bit c (c = 0, 1, 2) set iff
+ * P_c at that cell's Yee point is inside the metal (Pekar condition, Sec.
+ * III).  Every metal point must lie at least 2 cells inside the TF box
+ * (nonlocal material only in the total-field region, end of Sec. III);
+ * otherwise GNOR_E_INVALID_ARG. */
+gnor_status gnor_set_material(gnor_sim *sim, const uint8_t *mask, const gnor_material_desc *mat);
+gnor_status gnor_set_source(gnor_sim *sim, const gnor_source_desc *src);
+gnor_status gnor_set_monitors(gnor_sim *sim, const gnor_monitor_desc *mon);
+
+/* Device bytes needed for the current material and monitors. */
+size_t gnor_required_bytes(const gnor_sim *sim);
+
+/* Bind the caller's device buffer (>= gnor_required_bytes, 256-byte aligned)
+ * and HIP stream (NULL = default stream), upload the problem and zero the
+ * state (step index 0).  Must follow set_material/set_source/set_monitors. */
+gnor_status gnor_bind_memory(gnor_sim *sim, void *device_ptr, size_t bytes, void *hip_stream);
+
+/* Zero all fields, currents, CPML memory and accumulators (step index 0). */
+gnor_status gnor_reset(gnor_sim *sim);
+
+/* Enqueue nsteps leapfrog steps on the bound stream (asynchronous).  Steps
+ * are replayed from captured HIP graphs in chunks (gnor_set_graph_chunk). */
+gnor_status gnor_run(gnor_sim *sim, int64_t nsteps);
+gnor_status gnor_synchronize(gnor_sim *sim);
+int64_t gnor_step_index(const gnor_sim *sim);
+
+/* Steps per captured graph (even; 0 = launch every kernel directly). */
+gnor_status gnor_set_graph_chunk(gnor_sim *sim, int32_t steps);
+
+/* Cross sections (m^2) per monitor frequency, any pointer may be NULL:
+ * inc = |B(norm_k, w)|^2 (incident spectral energy, (V s/m)^2);
+ * ext = eta0 dx^3 sum_k Re(A(k, w) conj(B(k, w))) / inc with A the transform
+ *       of the plane-summed induced current J_x (volume optical theorem);
+ * abs = -eta0 (outward flux of Re(E x H*) through the absorption box) / inc;
+ * sca = +eta0 (outward flux through the scattering box) / inc.
+ * Synchronises the stream. */
+gnor_status gnor_get_spectra(gnor_sim *sim, double *inc, double *ext, double *abs_, double *sca);
+
+/* Raw transforms (SI): A[k][m], B[k][m] as separate real/imag arrays of
+ * nz * nfreq doubles each. */
+gnor_status gnor_get_dft(gnor_sim *sim, double *a_re, double *a_im, double *b_re, double *b_im);
+
+/* Copy one field to host as nx*ny*nz doubles in SI units:
+ * 0-2 E^n (V/m), 3-5 H^{n-1/2} (A/m), 6-8 J^{n-1/2} = dP_f/dt (A/m^2).
+ * count must be nx*ny*nz.  Synchronises the stream. */
+gnor_status gnor_get_field(gnor_sim *sim, int32_t which, double *host_dst, size_t count);
+
+/* Auxiliary line E_inc^n, H_inc^{n-1/2} (SI), n1 = nz + 50 doubles each. */
+gnor_status gnor_get_aux(gnor_sim *sim, double *e1, double *h1, size_t count);
+
+/* Full state snapshot (fields, currents, node scalars, CPML memory,
+ * auxiliary line, accumulators, step index) to/from host memory. */
+size_t gnor_state_bytes(const gnor_sim *sim);
+gnor_status gnor_save_state(gnor_sim *sim, void *host_dst, size_t bytes);
+gnor_status gnor_load_state(gnor_sim *sim, const void *host_src, size_t bytes);
+
+/* Non-finite watchdog: scans E and H; GNOR_E_NONFINITE if any is NaN/Inf. */
+gnor_status gnor_check_finite(gnor_sim *sim);
+
+/* Average device time per launch (ms) of each kernel over nsteps steps run
+ * with events around every launch (no graphs):
+ * ms[0] H update, ms[1] E/J update, ms[2] spectra, ms[3] auxiliary line
+ * (both halves), ms[4] flux accumulation (per step, amortised). */
+gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int32_t count);
+
+/* Voxelisers.  Spheres: n spheres as (cx, cy, cz, r) in metres from node
+ * (0,0,0); a P_c point is inside iff its squared distance to a centre is
+ * strictly below r^2 after quantising all coordinates to 2^-20 cell (exact
+ * integer test).  Star: desc = [cx, cy, cz, R, r_tip, tan(theta),
+ * sin(theta), ntips, (ax, ay, az, L) x ntips]: sphere of radius R plus
+ * sphere-capped cones of half-angle theta along unit axes a whose rounded
+ * apex (radius r_tip) ends L beyond the sphere surface; FP64 tests in a
+ * fixed operation order.  mask_out receives nx*ny*nz bytes. */
+gnor_status gnor_voxelize_spheres(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t n,
+                                  const double *cxyz_r, uint8_t *mask_out);
+gnor_status gnor_voxelize_star(int32_t nx, int32_t ny, int32_t nz, double dx, const double *desc,
+                               int32_t desc_len, uint8_t *mask_out);
+
+const char *gnor_status_string(gnor_status s);
+const char *gnor_last_error(const gnor_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GNOR_FDTD_H */

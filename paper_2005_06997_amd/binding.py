@@ -1,0 +1,259 @@
+"""Python binding of libgnorfdtd (ctypes; argument marshalling only).
+
+Every step of the time loop runs in the HIP kernels of ``libgnorfdtd.so``.
+PyTorch provides the device buffer the library carves its state from and the
+HIP stream it enqueues on.  If the library has not been built, or no GPU is
+present, constructing a :class:`Sim` raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgnorfdtd.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gnor_fdtd.h")
+
+GNOR_FP32, GNOR_FP64 = 0, 1
+STATUS = {0: "GNOR_OK", 1: "GNOR_E_INVALID_ARG", 2: "GNOR_E_UNSTABLE", 3: "GNOR_E_OUT_OF_MEMORY",
+          4: "GNOR_E_DEVICE", 5: "GNOR_E_STATE", 6: "GNOR_E_BUFFER_TOO_SMALL", 7: "GNOR_E_NONFINITE"}
+FIELDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Hx": 3, "Hy": 4, "Hz": 5, "Jx": 6, "Jy": 7, "Jz": 8}
+
+
+class GnorError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("courant", C.c_double), ("npml", C.c_int32),
+                ("pml_order", C.c_double), ("pml_sigma_scale", C.c_double),
+                ("pml_kappa_max", C.c_double), ("pml_alpha_max", C.c_double),
+                ("eps_background", C.c_double),
+                ("tf_lo", C.c_int32 * 3), ("tf_hi", C.c_int32 * 3), ("precision", C.c_int32)]
+
+
+class MaterialDesc(C.Structure):
+    _fields_ = [("wp", C.c_double), ("gamma", C.c_double), ("beta", C.c_double),
+                ("diffusion", C.c_double), ("eps_inf", C.c_double)]
+
+
+class SourceDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("e0", C.c_double), ("omega_c", C.c_double),
+                ("tau", C.c_double), ("t0", C.c_double), ("omega_max", C.c_double)]
+
+
+class MonitorDesc(C.Structure):
+    _fields_ = [("nfreq", C.c_int32), ("omega", C.POINTER(C.c_double)), ("norm_k", C.c_int32),
+                ("dft_every", C.c_int32), ("flux_enabled", C.c_int32),
+                ("abs_lo", C.c_int32 * 3), ("abs_hi", C.c_int32 * 3),
+                ("sca_lo", C.c_int32 * 3), ("sca_hi", C.c_int32 * 3)]
+
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions declared in include/gnor_fdtd.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gnor_[a-z_0-9]+)\s*\(", txt)))
+
+
+def load() -> C.CDLL:
+    """Load libgnorfdtd.so (built in-tree by ``paper_2005_06997_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2005_06997_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    dp = C.POINTER(C.c_double)
+    sig = {
+        "gnor_create": (i32, [C.POINTER(GridDesc), C.POINTER(vp)]),
+        "gnor_destroy": (None, [vp]),
+        "gnor_set_material": (i32, [vp, vp, C.POINTER(MaterialDesc)]),
+        "gnor_set_source": (i32, [vp, C.POINTER(SourceDesc)]),
+        "gnor_set_monitors": (i32, [vp, C.POINTER(MonitorDesc)]),
+        "gnor_required_bytes": (sz, [vp]),
+        "gnor_bind_memory": (i32, [vp, vp, sz, vp]),
+        "gnor_reset": (i32, [vp]),
+        "gnor_run": (i32, [vp, i64]),
+        "gnor_synchronize": (i32, [vp]),
+        "gnor_step_index": (i64, [vp]),
+        "gnor_set_graph_chunk": (i32, [vp, i32]),
+        "gnor_get_spectra": (i32, [vp, dp, dp, dp, dp]),
+        "gnor_get_dft": (i32, [vp, dp, dp, dp, dp]),
+        "gnor_get_field": (i32, [vp, i32, dp, sz]),
+        "gnor_get_aux": (i32, [vp, dp, dp, sz]),
+        "gnor_state_bytes": (sz, [vp]),
+        "gnor_save_state": (i32, [vp, vp, sz]),
+        "gnor_load_state": (i32, [vp, vp, sz]),
+        "gnor_check_finite": (i32, [vp]),
+        "gnor_profile_kernels": (i32, [vp, i64, dp, i32]),
+        "gnor_voxelize_spheres": (i32, [i32, i32, i32, dbl, i32, vp, vp]),
+        "gnor_voxelize_star": (i32, [i32, i32, i32, dbl, vp, i32, vp]),
+        "gnor_status_string": (C.c_char_p, [i32]),
+        "gnor_last_error": (C.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def voxelize(w) -> np.ndarray:
+    """The library's own voxeliser for a workload's geometry (x-fastest mask)."""
+    L = load()
+    out = np.zeros((w.nz, w.ny, w.nx), np.uint8)
+    if w.geometry == "star":
+        d = np.ascontiguousarray(w.star, dtype=np.float64)
+        st = L.gnor_voxelize_star(w.nx, w.ny, w.nz, w.dx, d.ctypes.data, len(d), out.ctypes.data)
+    else:
+        s = np.ascontiguousarray(w.spheres, dtype=np.float64).reshape(-1, 4)
+        st = L.gnor_voxelize_spheres(w.nx, w.ny, w.nz, w.dx, s.shape[0], s.ctypes.data, out.ctypes.data)
+    if st:
+        raise GnorError(st, "voxeliser rejected the geometry")
+    return out
+
+
+class Sim:
+    """One simulation on one GPU.  `w` is a workload record (see
+    :mod:`paper_2005_06997_amd.workloads`); `mask` overrides the voxelised
+    geometry."""
+
+    def __init__(self, w, precision: Optional[str] = None, device: str = "cuda:0",
+                 mask: Optional[np.ndarray] = None, graph_chunk: int = 64):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgnorfdtd needs a GPU: torch.cuda.is_available() is False")
+        self.L = load()
+        self.w = w
+        prec = (precision or w.precision).lower()
+        self.precision = prec
+        g = GridDesc(nx=w.nx, ny=w.ny, nz=w.nz, dx=w.dx, courant=w.courant, npml=w.npml,
+                     pml_order=w.pml_order, pml_sigma_scale=w.pml_sigma_scale,
+                     pml_kappa_max=w.pml_kappa_max, pml_alpha_max=w.pml_alpha_max,
+                     eps_background=w.eps_b, precision=GNOR_FP32 if prec == "fp32" else GNOR_FP64)
+        g.tf_lo[:] = list(w.tf_lo)
+        g.tf_hi[:] = list(w.tf_hi)
+        h = C.c_void_p()
+        st = self.L.gnor_create(C.byref(g), C.byref(h))
+        if st:
+            raise GnorError(st, "gnor_create rejected the grid")
+        self.h = h
+        self.mask = voxelize(w) if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        mat = MaterialDesc(wp=w.wp, gamma=w.gamma, beta=w.beta, diffusion=w.diff, eps_inf=w.eps_inf)
+        self._check(self.L.gnor_set_material(h, self.mask.ctypes.data, C.byref(mat)))
+        src = SourceDesc(kind=w.src_kind, e0=w.e0, omega_c=w.omega_c, tau=w.tau, t0=w.t0,
+                         omega_max=w.omega_max)
+        self._check(self.L.gnor_set_source(h, C.byref(src)))
+        self._omega = np.ascontiguousarray(w.omega, dtype=np.float64)
+        mon = MonitorDesc(nfreq=len(self._omega), omega=_dp(self._omega), norm_k=w.norm_k,
+                          dft_every=w.dft_every, flux_enabled=int(bool(w.flux)))
+        mon.abs_lo[:] = list(w.abs_lo); mon.abs_hi[:] = list(w.abs_hi)
+        mon.sca_lo[:] = list(w.sca_lo); mon.sca_hi[:] = list(w.sca_hi)
+        self._check(self.L.gnor_set_monitors(h, C.byref(mon)))
+        nbytes = int(self.L.gnor_required_bytes(h))
+        self.device = torch.device(device)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self._check(self.L.gnor_set_graph_chunk(h, int(graph_chunk)))
+        self._check(self.L.gnor_bind_memory(h, self.buffer.data_ptr(), nbytes,
+                                            C.c_void_p(self.stream.cuda_stream)))
+        self.nbytes = nbytes
+
+    # ------------------------------------------------------------------ utils
+    def _check(self, st: int):
+        if st:
+            raise GnorError(st, self.L.gnor_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            try:
+                self.stream.synchronize()
+            except Exception:
+                pass
+            self.L.gnor_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # -------------------------------------------------------------- stepping
+    @property
+    def step(self) -> int:
+        return int(self.L.gnor_step_index(self.h))
+
+    @property
+    def dt(self) -> float:
+        return self.w.courant * self.w.dx / 299792458.0
+
+    def run(self, nsteps: int):
+        self._check(self.L.gnor_run(self.h, int(nsteps)))
+
+    def synchronize(self):
+        self._check(self.L.gnor_synchronize(self.h))
+
+    def reset(self):
+        self._check(self.L.gnor_reset(self.h))
+
+    def check_finite(self) -> bool:
+        st = self.L.gnor_check_finite(self.h)
+        if st == 7:
+            return False
+        self._check(st)
+        return True
+
+    # ---------------------------------------------------------------- output
+    def field(self, name: str) -> np.ndarray:
+        out = np.empty((self.w.nz, self.w.ny, self.w.nx), np.float64)
+        self._check(self.L.gnor_get_field(self.h, FIELDS[name], _dp(out), out.size))
+        return out
+
+    def aux(self):
+        n1 = self.w.nz + 50
+        e1 = np.empty(n1); h1 = np.empty(n1)
+        self._check(self.L.gnor_get_aux(self.h, _dp(e1), _dp(h1), n1))
+        return e1, h1
+
+    def dft(self):
+        nf = len(self._omega)
+        a = [np.empty((self.w.nz, nf)) for _ in range(4)]
+        self._check(self.L.gnor_get_dft(self.h, *[_dp(x) for x in a]))
+        return a[0] + 1j * a[1], a[2] + 1j * a[3]
+
+    def spectra(self) -> Dict[str, np.ndarray]:
+        nf = len(self._omega)
+        out = [np.empty(nf) for _ in range(4)]
+        self._check(self.L.gnor_get_spectra(self.h, *[_dp(x) for x in out]))
+        return dict(inc=out[0], ext=out[1], abs=out[2], sca=out[3])
+
+    def save_state(self) -> bytearray:
+        n = int(self.L.gnor_state_bytes(self.h))
+        buf = bytearray(n)
+        self._check(self.L.gnor_save_state(self.h, (C.c_char * n).from_buffer(buf), n))
+        return buf
+
+    def load_state(self, buf: bytearray):
+        n = len(buf)
+        self._check(self.L.gnor_load_state(self.h, (C.c_char * n).from_buffer(buf), n))
+
+    def profile(self, nsteps: int) -> Dict[str, float]:
+        ms = np.zeros(5)
+        self._check(self.L.gnor_profile_kernels(self.h, int(nsteps), _dp(ms), 5))
+        return dict(h=ms[0], ej=ms[1], dft=ms[2], aux=ms[3], flux_acc=ms[4])

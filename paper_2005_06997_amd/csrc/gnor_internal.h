@@ -1,0 +1,157 @@
+// Internal definitions shared by the host runtime and the HIP kernels of
+// libgnorfdtd.  Not part of the ABI.
+//
+// Units inside the library are scaled so that every update coefficient is
+// O(1) (important for FP32 storage):
+//   E~ = E (V/m),  H~ = eta0 H,  J~ = J dt / eps0,  P~ = P / eps0,
+//   node scalars Phi~_P = dx div P / eps0 and Phi~_J = dx dt div J / eps0,
+// so that, with S = c dt / dx and integer-index differences D_a,
+//   H~  -= S curl_idx E                           (f1, Sec. III)
+//   E   += (S / eps_b) curl_idx H~                (vacuum)
+// and in the metal (f2 + f4 of Sec. III rewritten for the current):
+//   E^{n+1} = E^n + [S curl H~ - 3 d3 E^n - d3 E^{n-1} + D2 J~ - G] / (eps_inf + d3)
+//   J~^{n+1/2} = J~ - a_g J~ + d3 (E^{n-1} + 2 E^n + E^{n+1}) + G
+// with d3 = D3 / eps0, a_g = 1 + D2 = gamma dt / (1 + gamma dt / 2), and
+// G_a = Q(node + e_a) - Q(node), Q = g1 Phi~_P^n + g2 (3 Phi~_J^{n-1/2} - Phi~_J^{n-3/2}),
+// g1 = D_G1 / dx^2, g2 = D_G2 / dx^2, Phi~_P^n = Phi~_P^{n-1} + Phi~_J^{n-1/2}.
+// This is Eq. (GNORUpdate) with D1 = 1 - D2, grad(div P) = Grad(Div P)
+// (Eq. GradDiv is exactly the gradient of the node divergence), and the BDF2
+// combination 3 GD^n - 4 GD^{n-1} + GD^{n-2} = Grad(dt (3 Div J^{n-1/2} -
+// Div J^{n-3/2})).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace gnor {
+
+// Auxiliary incident line: CPML cells at each end, offset of grid plane k = 0,
+// soft-source cell.
+constexpr int kAuxPml = 20;
+constexpr int kAuxOff = 25;
+constexpr int kAuxSrc = 22;
+
+// Threads per block of the field sweeps (x, y).
+constexpr int kBX = 64;
+constexpr int kBY = 4;
+
+template <class T>
+struct CpmlAxis {
+  int n;          // nodes along the axis
+  int np;         // slab thickness (0 = none)
+  const T* be;    // [2 np] at integer positions (E updates)
+  const T* ae;
+  const T* ke;
+  const T* bh;    // [2 np] at half-integer positions (H updates)
+  const T* ah;
+  const T* kh;
+};
+
+// Device pointers and coefficients of one simulation (one precision).
+template <class T>
+struct Params {
+  int nx, ny, nz;
+  T S;            // Courant number: H coefficient
+  T SE;           // S / eps_b: vacuum E coefficient
+  // full-grid fields
+  T* E[3];        // E^n
+  T* O[3];        // E^{n-1} (read at metal points) -> E^{n+1} (written everywhere)
+  T* H[3];
+  // metal sub-grid [mlo, mlo + mn)
+  int mlo[3], mn[3];
+  const uint8_t* mask;  // sub-grid, bit c = P_c is metal
+  const float* rho;     // optional per-cell weight of wp^2, beta^2, D (sub-grid); null = 1
+  const T* Ji[3];
+  T* Jo[3];
+  const T* PPi;
+  T* PPo;
+  const T* PJi;
+  T* PJo;
+  T eps_inf, d3, agam, D2, g1, g2, ebd;  // ebd = eps_inf - eps_b
+  T cS, c3, c1, cJ, cG;                   // E metal coefficients divided by (eps_inf + d3)
+  // CPML memory: psi[axis][t], t = 0 for component (axis+2)%3, 1 for (axis+1)%3
+  T* psiE[3][2];
+  T* psiH[3][2];
+  CpmlAxis<T> cp[3];
+  // TF/SF
+  int tfsf;
+  int tf_lo[3], tf_hi[3];
+  const double* e1;
+  const double* h1;
+  // per-(plane, block) partial sums of the induced current for the spectra
+  double* jpart;      // [nz][nbxy]
+  int nbx, nby;
+  // step counter
+  const int64_t* step_base;
+};
+
+// Auxiliary line state (FP64 always).
+struct AuxParams {
+  int n1;
+  double S, SE;
+  double* e1;
+  double* h1;
+  double* pe;
+  double* ph;
+  const double* be;
+  const double* ae;
+  const double* ke;
+  const double* bh;
+  const double* ah;
+  const double* kh;
+  int src_kind;
+  double e0, omega_c, tau, t0, omega_max, dt;
+  const int64_t* step_base;
+};
+
+struct DftParams {
+  int nz, nf;
+  int kz0, kz1;          // planes [kz0, kz1) carry induced current
+  int nbxy;              // partial sums per plane
+  const double* jpart;
+  const double* omega;
+  double dt, wdt;
+  int every;
+  const double* e1;      // auxiliary line, E_inc^{n+1}
+  double* a_re;          // [nz][nf]
+  double* a_im;
+  double* b_re;
+  double* b_im;
+  const int64_t* step_base;
+};
+
+// Flux monitors: staged samples, accumulated every `slots` steps.
+struct FluxParams {
+  int nsamp;             // samples per step (both boxes)
+  int nf;
+  int slots;             // staging depth
+  const int32_t* desc;   // per sample: kind and index (see runtime)
+  double* stage;         // [slots][nsamp]
+  double* acc_re;        // [nf][nsamp]
+  double* acc_im;
+  const double* omega;
+  double dt, wdt;
+  int every;
+  const int64_t* step_base;
+};
+
+template <class T>
+void launch_h(const Params<T>& p, int sub, hipStream_t s);
+template <class T>
+void launch_ej(const Params<T>& p, int sub, hipStream_t s);
+void launch_aux_h(const AuxParams& p, int sub, hipStream_t s);
+void launch_aux_e(const AuxParams& p, int sub, hipStream_t s);
+void launch_dft(const DftParams& p, int sub, hipStream_t s);
+void launch_advance(int64_t* base, int64_t count, hipStream_t s);
+template <class T>
+void launch_flux_stage(const FluxParams& f, const Params<T>& p, const int64_t* sidx, int sub,
+                       hipStream_t s);
+void launch_flux_accumulate(const FluxParams& f, int* lo_ptr, int sub, hipStream_t s);
+void launch_flux_reduce(const double* acc_re, const double* acc_im, const double* pw, int npairs,
+                        int npairs_box0, int nf, double* out, hipStream_t s);
+template <class T>
+void launch_nonfinite(const T* a, size_t n, int* flag, hipStream_t s);
+
+}  // namespace gnor

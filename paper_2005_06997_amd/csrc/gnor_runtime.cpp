@@ -1,0 +1,982 @@
+// Host runtime of libgnorfdtd: the C ABI declared in include/gnor_fdtd.h.
+//
+// One simulation owns a caller-provided device buffer, carved into a static
+// region (masks, CPML and auxiliary-line profiles, monitor descriptors,
+// frequencies) and a state region (fields, currents, node scalars, CPML
+// memory, auxiliary line, accumulators, step counter) that gnor_reset zeroes.
+// Steps are enqueued on the bound stream, either directly or from captured
+// HIP graphs of a fixed number of steps.
+#include "../../include/gnor_fdtd.h"
+#include "gnor_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kMu0 = 1.25663706212e-6;
+double eps0() { return 1.0 / (kMu0 * kC0 * kC0); }
+double eta0() { return std::sqrt(kMu0 / eps0()); }
+
+struct Err {
+  gnor_status st;
+  std::string msg;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Region planner: assigns 256-byte aligned offsets.
+struct Planner {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  }
+};
+
+struct Layout {
+  // static region
+  size_t mask = 0, rho = 0, cpml[3] = {0, 0, 0}, aux_prof = 0, omega = 0, fdesc = 0, fsidx = 0,
+         fpw = 0, fbox = 0;
+  size_t static_end = 0;
+  // state region
+  size_t state_begin = 0;
+  size_t E[2][3] = {{0}}, H[3] = {0, 0, 0};
+  size_t J[2][3] = {{0}}, PP[2] = {0, 0}, PJ[2] = {0, 0};
+  size_t psiE[3][2] = {{0}}, psiH[3][2] = {{0}};
+  size_t aux = 0, jpart = 0, dft = 0, fstage = 0, facc = 0, step = 0, flux_lo = 0, flag = 0,
+         fsum = 0;
+  size_t state_end = 0;
+};
+
+}  // namespace
+
+struct gnor_sim {
+  gnor_grid_desc g{};
+  gnor_material_desc mat{};
+  gnor_source_desc src{};
+  std::vector<double> omega;
+  gnor_monitor_desc mon{};
+  bool have_material = false, have_source = false, have_monitors = false, bound = false;
+  std::vector<uint8_t> mask;     // full grid
+  int mlo[3] = {0, 0, 0}, mn[3] = {0, 0, 0};  // metal sub-grid (with halo)
+  bool any_metal = false;
+  size_t N = 0, M = 0;
+  int elem = 8;                  // bytes per field value
+  double dt = 0;
+  int n1 = 0;
+  int nbx = 0, nby = 0;
+  // flux plan
+  int nsamp = 0, npairs = 0, npairs_box0 = 0, slots = 32;
+  std::vector<int32_t> fdesc;
+  std::vector<int64_t> fsidx;
+  std::vector<double> fpw;
+  Layout L;
+  char* dev = nullptr;
+  size_t dev_bytes = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int64_t step = 0;
+  int graph_chunk = 64;
+  hipGraphExec_t graph = nullptr;
+  int graph_steps = 0;
+  std::string last_error;
+};
+
+namespace {
+
+gnor_status fail(gnor_sim* s, gnor_status st, const std::string& m) {
+  if (s) s->last_error = m;
+  return st;
+}
+
+#define HIPCHECK(sim, call)                                                              \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(sim, GNOR_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// CPML coefficients at a depth (cells) into a layer of L cells.
+void pml_coeffs(const gnor_grid_desc& g, double dt, double depth, int L, double& b, double& a,
+                double& kinv) {
+  b = 1.0; a = 0.0; kinv = 1.0;
+  if (L <= 0 || depth <= 0.0) return;
+  const double m = g.pml_order;
+  const double smax = g.pml_sigma_scale * (m + 1.0) / (eta0() * g.dx * std::sqrt(g.eps_background));
+  const double u = depth / L;
+  const double sigma = smax * std::pow(u, m);
+  const double kappa = 1.0 + (g.pml_kappa_max - 1.0) * std::pow(u, m);
+  const double alpha = g.pml_alpha_max * (1.0 - u);
+  b = std::exp(-(sigma / kappa + alpha) * dt / eps0());
+  a = sigma > 0.0 ? sigma * (b - 1.0) / (kappa * (sigma + kappa * alpha)) : 0.0;
+  kinv = 1.0 / kappa;
+}
+double layer_depth(double x, int n, int L) {
+  double d = 0.0;
+  if (x < L) d = L - x;
+  if (x > (n - 1 - L)) d = x - (n - 1 - L);
+  return d;
+}
+
+void plan_flux(gnor_sim* s) {
+  s->fdesc.clear(); s->fsidx.clear(); s->fpw.clear();
+  s->nsamp = s->npairs = s->npairs_box0 = 0;
+  if (!s->have_monitors || !s->mon.flux_enabled || s->mon.nfreq <= 0) return;
+  const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
+  const int64_t stride[3] = {1, (int64_t)n[0], (int64_t)n[0] * n[1]};
+  const double h2 = s->g.dx * s->g.dx;
+  for (int box = 0; box < 2; ++box) {
+    const int32_t* lo = box == 0 ? s->mon.abs_lo : s->mon.sca_lo;
+    const int32_t* hi = box == 0 ? s->mon.abs_hi : s->mon.sca_hi;
+    for (int a = 0; a < 3; ++a)
+      for (int side = -1; side <= 1; side += 2) {
+        const int p = side < 0 ? lo[a] : hi[a];
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        auto lin = [&](int ib, int ic) {
+          int ii[3];
+          ii[a] = p; ii[b] = ib; ii[c] = ic;
+          return (int64_t)ii[0] + stride[1] * ii[1] + stride[2] * ii[2];
+        };
+        auto add_pair = [&](int ecomp, int hcomp, int64_t idx, double w) {
+          s->fdesc.insert(s->fdesc.end(), {0, ecomp, 0});
+          s->fsidx.push_back(idx);
+          s->fdesc.insert(s->fdesc.end(), {1, hcomp, (int32_t)stride[a]});
+          s->fsidx.push_back(idx);
+          s->fpw.push_back(w);
+        };
+        // E_b with H_c averaged across the face (trapezoid weights along c)
+        for (int kc = lo[c]; kc <= hi[c]; ++kc)
+          for (int jb = lo[b]; jb < hi[b]; ++jb) {
+            const double wt = (kc == lo[c] || kc == hi[c]) ? 0.5 : 1.0;
+            add_pair(b, c, lin(jb, kc), side * h2 * wt);
+          }
+        // E_c with H_b averaged across the face (trapezoid weights along b)
+        for (int kc = lo[c]; kc < hi[c]; ++kc)
+          for (int jb = lo[b]; jb <= hi[b]; ++jb) {
+            const double wt = (jb == lo[b] || jb == hi[b]) ? 0.5 : 1.0;
+            add_pair(c, b, lin(jb, kc), -side * h2 * wt);
+          }
+      }
+    if (box == 0) s->npairs_box0 = (int)s->fpw.size();
+  }
+  s->npairs = (int)s->fpw.size();
+  s->nsamp = 2 * s->npairs;
+}
+
+void plan_layout(gnor_sim* s) {
+  Layout& L = s->L;
+  L = Layout();
+  Planner P;
+  const size_t N = s->N, M = s->M;
+  const int e = s->elem;
+  const int np = s->g.npml;
+  L.mask = P.take(M);
+  L.rho = P.take(M * sizeof(float));
+  for (int a = 0; a < 3; ++a) L.cpml[a] = P.take((size_t)6 * 2 * np * e + 8);
+  L.aux_prof = P.take((size_t)6 * s->n1 * 8);
+  L.omega = P.take((size_t)std::max(1, s->mon.nfreq) * 8);
+  L.fdesc = P.take((size_t)3 * s->nsamp * 4 + 4);
+  L.fsidx = P.take((size_t)s->nsamp * 8 + 8);
+  L.fpw = P.take((size_t)s->npairs * 8 + 8);
+  L.static_end = P.off;
+  L.state_begin = P.off;
+  for (int pp = 0; pp < 2; ++pp)
+    for (int c = 0; c < 3; ++c) L.E[pp][c] = P.take(N * e);
+  for (int c = 0; c < 3; ++c) L.H[c] = P.take(N * e);
+  for (int pp = 0; pp < 2; ++pp) {
+    for (int c = 0; c < 3; ++c) L.J[pp][c] = P.take(M * e);
+    L.PP[pp] = P.take(M * e);
+    L.PJ[pp] = P.take(M * e);
+  }
+  const size_t nx = s->g.nx, ny = s->g.ny, nz = s->g.nz;
+  const size_t slab[3] = {nz * ny * 2 * np, nz * 2 * np * nx, 2 * np * ny * nx};
+  for (int a = 0; a < 3; ++a)
+    for (int t = 0; t < 2; ++t) {
+      L.psiE[a][t] = P.take(slab[a] * e + 8);
+      L.psiH[a][t] = P.take(slab[a] * e + 8);
+    }
+  L.aux = P.take((size_t)4 * s->n1 * 8);
+  L.jpart = P.take(nz * (size_t)s->nbx * s->nby * 8);
+  L.dft = P.take((size_t)4 * nz * std::max(1, s->mon.nfreq) * 8);
+  L.fstage = P.take((size_t)s->slots * s->nsamp * 8 + 8);
+  L.facc = P.take((size_t)2 * std::max(1, s->mon.nfreq) * s->nsamp * 8 + 8);
+  L.fsum = P.take((size_t)2 * std::max(1, s->mon.nfreq) * 8);
+  L.step = P.take(8);
+  L.flux_lo = P.take(4);
+  L.flag = P.take(4);
+  L.state_end = P.off;
+}
+
+template <class T>
+T* ptr(gnor_sim* s, size_t off) {
+  return reinterpret_cast<T*>(s->dev + off);
+}
+
+template <class T>
+gnor::Params<T> make_params(gnor_sim* s, int parity) {
+  gnor::Params<T> p{};
+  const gnor_grid_desc& g = s->g;
+  p.nx = g.nx; p.ny = g.ny; p.nz = g.nz;
+  const double S = g.courant;
+  p.S = (T)S;
+  p.SE = (T)(S / g.eps_background);
+  const int a = parity & 1, b = a ^ 1;
+  for (int c = 0; c < 3; ++c) {
+    p.E[c] = ptr<T>(s, s->L.E[a][c]);
+    p.O[c] = ptr<T>(s, s->L.E[b][c]);
+    p.H[c] = ptr<T>(s, s->L.H[c]);
+    p.Ji[c] = ptr<T>(s, s->L.J[a][c]);
+    p.Jo[c] = ptr<T>(s, s->L.J[b][c]);
+  }
+  p.PPi = ptr<T>(s, s->L.PP[a]); p.PPo = ptr<T>(s, s->L.PP[b]);
+  p.PJi = ptr<T>(s, s->L.PJ[a]); p.PJo = ptr<T>(s, s->L.PJ[b]);
+  for (int d = 0; d < 3; ++d) { p.mlo[d] = s->mlo[d]; p.mn[d] = s->mn[d]; }
+  p.mask = ptr<uint8_t>(s, s->L.mask);
+  p.rho = nullptr;
+  // metal coefficients (Sec. III), scaled by eps0 and dx^2
+  const double dt = s->dt, dx = g.dx;
+  const double gam = s->mat.gamma, wp = s->mat.wp, beta = s->mat.beta, D = s->mat.diffusion;
+  const double Dd = gam / (2 * dt) + 1.0 / (dt * dt);
+  const double D2 = (gam / (2 * dt) - 1.0 / (dt * dt)) / Dd;
+  const double d3 = wp * wp / (4.0 * Dd);          // D3 / eps0
+  const double agam = gam * dt / (1.0 + gam * dt / 2.0);  // 1 + D2 without cancellation
+  const double eta = beta * beta + D * gam;
+  const double g1 = eta / Dd / (dx * dx);
+  const double g2 = D / (2.0 * dt * Dd) / (dx * dx);
+  const double ei = s->mat.eps_inf;
+  const double inv = 1.0 / (ei + d3);
+  p.eps_inf = (T)ei; p.d3 = (T)d3; p.agam = (T)agam; p.D2 = (T)D2; p.g1 = (T)g1; p.g2 = (T)g2;
+  p.ebd = (T)(ei - g.eps_background);
+  p.cS = (T)(S * inv); p.c3 = (T)(3.0 * d3 * inv); p.c1 = (T)(d3 * inv); p.cJ = (T)(D2 * inv);
+  p.cG = (T)inv;
+  const int np = g.npml;
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  for (int ax = 0; ax < 3; ++ax) {
+    for (int t = 0; t < 2; ++t) {
+      p.psiE[ax][t] = ptr<T>(s, s->L.psiE[ax][t]);
+      p.psiH[ax][t] = ptr<T>(s, s->L.psiH[ax][t]);
+    }
+    gnor::CpmlAxis<T>& c = p.cp[ax];
+    c.n = nn[ax]; c.np = np;
+    T* base = ptr<T>(s, s->L.cpml[ax]);
+    c.be = base; c.ae = base + 2 * np; c.ke = base + 4 * np;
+    c.bh = base + 6 * np; c.ah = base + 8 * np; c.kh = base + 10 * np;
+  }
+  p.tfsf = 1;
+  for (int d = 0; d < 3; ++d) { p.tf_lo[d] = g.tf_lo[d]; p.tf_hi[d] = g.tf_hi[d]; }
+  double* aux = ptr<double>(s, s->L.aux);
+  p.e1 = aux; p.h1 = aux + s->n1;
+  p.jpart = ptr<double>(s, s->L.jpart);
+  p.nbx = s->nbx; p.nby = s->nby;
+  p.step_base = ptr<int64_t>(s, s->L.step);
+  return p;
+}
+
+gnor::AuxParams make_aux(gnor_sim* s) {
+  gnor::AuxParams a{};
+  a.n1 = s->n1;
+  a.S = s->g.courant;
+  a.SE = s->g.courant / s->g.eps_background;
+  double* st = ptr<double>(s, s->L.aux);
+  a.e1 = st; a.h1 = st + s->n1; a.pe = st + 2 * s->n1; a.ph = st + 3 * s->n1;
+  const double* pr = ptr<double>(s, s->L.aux_prof);
+  a.be = pr; a.ae = pr + s->n1; a.ke = pr + 2 * s->n1;
+  a.bh = pr + 3 * s->n1; a.ah = pr + 4 * s->n1; a.kh = pr + 5 * s->n1;
+  a.src_kind = s->have_source ? s->src.kind : 0;
+  a.e0 = s->src.e0; a.omega_c = s->src.omega_c; a.tau = s->src.tau; a.t0 = s->src.t0;
+  a.omega_max = s->src.omega_max; a.dt = s->dt;
+  a.step_base = ptr<int64_t>(s, s->L.step);
+  return a;
+}
+
+gnor::DftParams make_dft(gnor_sim* s) {
+  gnor::DftParams d{};
+  d.nz = s->g.nz; d.nf = s->mon.nfreq;
+  d.kz0 = s->any_metal ? s->mlo[2] : 0;
+  d.kz1 = s->any_metal ? s->mlo[2] + s->mn[2] : 0;
+  d.nbxy = s->nbx * s->nby;
+  d.jpart = ptr<double>(s, s->L.jpart);
+  d.omega = ptr<double>(s, s->L.omega);
+  d.dt = s->dt;
+  d.every = std::max(1, s->mon.dft_every);
+  d.wdt = s->dt * d.every;
+  d.e1 = ptr<double>(s, s->L.aux);
+  const size_t nzf = (size_t)s->g.nz * std::max(1, s->mon.nfreq);
+  double* base = ptr<double>(s, s->L.dft);
+  d.a_re = base; d.a_im = base + nzf; d.b_re = base + 2 * nzf; d.b_im = base + 3 * nzf;
+  d.step_base = ptr<int64_t>(s, s->L.step);
+  return d;
+}
+
+gnor::FluxParams make_flux(gnor_sim* s) {
+  gnor::FluxParams f{};
+  f.nsamp = s->nsamp; f.nf = s->mon.nfreq; f.slots = s->slots;
+  f.desc = ptr<int32_t>(s, s->L.fdesc);
+  f.stage = ptr<double>(s, s->L.fstage);
+  f.acc_re = ptr<double>(s, s->L.facc);
+  f.acc_im = f.acc_re + (size_t)s->mon.nfreq * s->nsamp;
+  f.omega = ptr<double>(s, s->L.omega);
+  f.dt = s->dt; f.wdt = s->dt; f.every = 1;
+  f.step_base = ptr<int64_t>(s, s->L.step);
+  return f;
+}
+
+// Enqueue one step; `sub` is the step's offset from the device step counter.
+template <class T>
+void enqueue_step(gnor_sim* s, int parity, int sub, hipStream_t st) {
+  const gnor::Params<T> p = make_params<T>(s, parity);
+  const gnor::AuxParams a = make_aux(s);
+  gnor::launch_h<T>(p, sub, st);
+  gnor::launch_aux_h(a, sub, st);
+  gnor::launch_ej<T>(p, sub, st);
+  gnor::launch_aux_e(a, sub, st);
+  if (s->mon.nfreq > 0) gnor::launch_dft(make_dft(s), sub, st);
+  if (s->nsamp > 0) {
+    const gnor::FluxParams f = make_flux(s);
+    gnor::launch_flux_stage<T>(f, p, ptr<int64_t>(s, s->L.fsidx), sub, st);
+  }
+}
+
+void enqueue_flux_acc(gnor_sim* s, int sub, hipStream_t st) {
+  gnor::launch_flux_accumulate(make_flux(s), ptr<int>(s, s->L.flux_lo), sub, st);
+}
+
+void enqueue_steps_eager(gnor_sim* s, int64_t n0, int64_t count, hipStream_t st) {
+  // steps n0 .. n0+count-1; the device counter holds n0 on entry
+  for (int64_t q = 0; q < count; ++q) {
+    const int64_t n = n0 + q;
+    const int sub = (int)q;
+    if (s->g.precision == GNOR_FP32) enqueue_step<float>(s, (int)(n & 1), sub, st);
+    else enqueue_step<double>(s, (int)(n & 1), sub, st);
+    if (s->nsamp > 0 && (n % s->slots) == s->slots - 1) enqueue_flux_acc(s, sub, st);
+  }
+  gnor::launch_advance(ptr<int64_t>(s, s->L.step), count, st);
+}
+
+void drop_graph(gnor_sim* s) {
+  if (s->graph) (void)hipGraphExecDestroy(s->graph);
+  s->graph = nullptr;
+  s->graph_steps = 0;
+}
+
+gnor_status build_graph(gnor_sim* s, int steps) {
+  drop_graph(s);
+  hipGraph_t gr = nullptr;
+  HIPCHECK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  // the chunk always starts at an even step aligned to the flux staging depth
+  enqueue_steps_eager(s, 0, steps, s->stream);
+  HIPCHECK(s, hipStreamEndCapture(s->stream, &gr));
+  hipError_t e = hipGraphInstantiate(&s->graph, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) {
+    s->graph = nullptr;
+    return fail(s, GNOR_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  s->graph_steps = steps;
+  return GNOR_OK;
+}
+
+int chunk_alignment(const gnor_sim* s) {
+  return s->nsamp > 0 ? std::max(2, s->slots) : 2;  // slots is even
+}
+
+gnor_status check_ready(gnor_sim* s) {
+  if (!s) return GNOR_E_INVALID_ARG;
+  if (!s->bound) return fail(s, GNOR_E_STATE, "gnor_bind_memory has not been called");
+  return GNOR_OK;
+}
+
+gnor_status upload_static(gnor_sim* s) {
+  const gnor_grid_desc& g = s->g;
+  // metal sub-grid mask
+  std::vector<uint8_t> sub(s->M, 0);
+  for (int z = 0; z < s->mn[2]; ++z)
+    for (int y = 0; y < s->mn[1]; ++y)
+      for (int x = 0; x < s->mn[0]; ++x) {
+        const size_t gi = ((size_t)(z + s->mlo[2]) * g.ny + (y + s->mlo[1])) * g.nx + (x + s->mlo[0]);
+        sub[((size_t)z * s->mn[1] + y) * s->mn[0] + x] = s->any_metal ? s->mask[gi] : 0;
+      }
+  HIPCHECK(s, hipMemcpy(s->dev + s->L.mask, sub.data(), s->M, hipMemcpyHostToDevice));
+  // CPML profiles per axis: be, ae, ke, bh, ah, kh over the 2 npml slab cells
+  const int np = g.npml;
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    std::vector<double> pr((size_t)12 * np, 0.0);
+    for (int sl = 0; sl < 2 * np; ++sl) {
+      const int ge = sl < np ? sl : sl + (nn[a] - 2 * np);
+      const int gh = sl < np ? sl : sl + (nn[a] - 1 - 2 * np);
+      pml_coeffs(g, s->dt, layer_depth((double)ge, nn[a], np), np, pr[sl], pr[2 * np + sl], pr[4 * np + sl]);
+      pml_coeffs(g, s->dt, layer_depth(gh + 0.5, nn[a], np), np, pr[6 * np + sl], pr[8 * np + sl],
+                 pr[10 * np + sl]);
+    }
+    if (np > 0) {
+      if (g.precision == GNOR_FP32) {
+        std::vector<float> f(pr.begin(), pr.end());
+        HIPCHECK(s, hipMemcpy(s->dev + s->L.cpml[a], f.data(), f.size() * 4, hipMemcpyHostToDevice));
+      } else {
+        HIPCHECK(s, hipMemcpy(s->dev + s->L.cpml[a], pr.data(), pr.size() * 8, hipMemcpyHostToDevice));
+      }
+    }
+  }
+  // auxiliary line profiles
+  std::vector<double> ap((size_t)6 * s->n1);
+  for (int q = 0; q < s->n1; ++q) {
+    pml_coeffs(g, s->dt, layer_depth((double)q, s->n1, gnor::kAuxPml), gnor::kAuxPml, ap[q],
+               ap[s->n1 + q], ap[2 * s->n1 + q]);
+    pml_coeffs(g, s->dt, layer_depth(q + 0.5, s->n1, gnor::kAuxPml), gnor::kAuxPml, ap[3 * s->n1 + q],
+               ap[4 * s->n1 + q], ap[5 * s->n1 + q]);
+  }
+  HIPCHECK(s, hipMemcpy(s->dev + s->L.aux_prof, ap.data(), ap.size() * 8, hipMemcpyHostToDevice));
+  if (s->mon.nfreq > 0)
+    HIPCHECK(s, hipMemcpy(s->dev + s->L.omega, s->omega.data(), s->omega.size() * 8, hipMemcpyHostToDevice));
+  if (s->nsamp > 0) {
+    HIPCHECK(s, hipMemcpy(s->dev + s->L.fdesc, s->fdesc.data(), s->fdesc.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(s, hipMemcpy(s->dev + s->L.fsidx, s->fsidx.data(), s->fsidx.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(s, hipMemcpy(s->dev + s->L.fpw, s->fpw.data(), s->fpw.size() * 8, hipMemcpyHostToDevice));
+  }
+  return GNOR_OK;
+}
+
+void prepare(gnor_sim* s) {
+  const gnor_grid_desc& g = s->g;
+  s->elem = g.precision == GNOR_FP32 ? 4 : 8;
+  s->N = (size_t)g.nx * g.ny * g.nz;
+  s->n1 = g.nz + 2 * gnor::kAuxOff;
+  s->nbx = (g.nx + gnor::kBX - 1) / gnor::kBX;
+  s->nby = (g.ny + gnor::kBY - 1) / gnor::kBY;
+  if (!s->any_metal) {
+    for (int d = 0; d < 3; ++d) { s->mlo[d] = 0; s->mn[d] = 1; }
+  }
+  s->M = (size_t)s->mn[0] * s->mn[1] * s->mn[2];
+  plan_flux(s);
+  plan_layout(s);
+}
+
+}  // namespace
+
+// ============================================================ C ABI
+extern "C" {
+
+const char* gnor_status_string(gnor_status st) {
+  switch (st) {
+    case GNOR_OK: return "ok";
+    case GNOR_E_INVALID_ARG: return "invalid argument";
+    case GNOR_E_UNSTABLE: return "unstable time step";
+    case GNOR_E_OUT_OF_MEMORY: return "out of host memory";
+    case GNOR_E_DEVICE: return "HIP device error";
+    case GNOR_E_STATE: return "call out of order";
+    case GNOR_E_BUFFER_TOO_SMALL: return "buffer too small";
+    case GNOR_E_NONFINITE: return "non-finite field values";
+  }
+  return "unknown status";
+}
+
+const char* gnor_last_error(const gnor_sim* s) { return s ? s->last_error.c_str() : "null sim"; }
+
+gnor_status gnor_create(const gnor_grid_desc* g, gnor_sim** out) {
+  if (!g || !out) return GNOR_E_INVALID_ARG;
+  *out = nullptr;
+  if (g->nx < 4 || g->ny < 4 || g->nz < 4 || !(g->dx > 0.0) || !(g->eps_background > 0.0))
+    return GNOR_E_INVALID_ARG;
+  if ((double)g->nx * g->ny * g->nz > 4.0e9) return GNOR_E_INVALID_ARG;
+  if (g->precision != GNOR_FP32 && g->precision != GNOR_FP64) return GNOR_E_INVALID_ARG;
+  if (!(g->courant > 0.0) || g->courant >= 1.0 / std::sqrt(3.0)) return GNOR_E_UNSTABLE;
+  if (g->npml < 0 || 2 * g->npml + 4 > std::min(g->nx, std::min(g->ny, g->nz))) return GNOR_E_INVALID_ARG;
+  const int n[3] = {g->nx, g->ny, g->nz};
+  for (int d = 0; d < 3; ++d)
+    if (g->tf_lo[d] < g->npml + 1 || g->tf_hi[d] > n[d] - 2 - g->npml || g->tf_hi[d] - g->tf_lo[d] < 4)
+      return GNOR_E_INVALID_ARG;
+  gnor_sim* s = new (std::nothrow) gnor_sim();
+  if (!s) return GNOR_E_OUT_OF_MEMORY;
+  s->g = *g;
+  s->dt = g->courant * g->dx / kC0;
+  *out = s;
+  return GNOR_OK;
+}
+
+void gnor_destroy(gnor_sim* s) {
+  if (!s) return;
+  drop_graph(s);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+gnor_status gnor_set_material(gnor_sim* s, const uint8_t* mask, const gnor_material_desc* m) {
+  if (!s || !m) return GNOR_E_INVALID_ARG;
+  if (s->bound) return fail(s, GNOR_E_STATE, "material must be set before gnor_bind_memory");
+  if (!(m->wp >= 0) || !(m->gamma >= 0) || !(m->beta >= 0) || !(m->diffusion >= 0) || !(m->eps_inf > 0))
+    return fail(s, GNOR_E_INVALID_ARG, "material parameters must be non-negative (eps_inf > 0)");
+  const gnor_grid_desc& g = s->g;
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
+  s->mask.assign(N, 0);
+  int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+  bool any = false;
+  if (mask) {
+    for (int k = 0; k < g.nz; ++k)
+      for (int j = 0; j < g.ny; ++j)
+        for (int i = 0; i < g.nx; ++i) {
+          const size_t q = ((size_t)k * g.ny + j) * g.nx + i;
+          const uint8_t b = mask[q] & 7u;
+          if (mask[q] & ~7u) return fail(s, GNOR_E_INVALID_ARG, "mask bytes may only use bits 0-2");
+          if (!b) continue;
+          const int ii[3] = {i, j, k};
+          for (int d = 0; d < 3; ++d) {
+            if (ii[d] < g.tf_lo[d] + 2 || ii[d] > g.tf_hi[d] - 2) {
+              char buf[160];
+              std::snprintf(buf, sizeof buf,
+                            "metal at (%d,%d,%d) is not 2 cells inside the TF box: nonlocal material "
+                            "must stay in the total-field region", i, j, k);
+              return fail(s, GNOR_E_INVALID_ARG, buf);
+            }
+            lo[d] = std::min(lo[d], ii[d]);
+            hi[d] = std::max(hi[d], ii[d]);
+          }
+          s->mask[q] = b;
+          any = true;
+        }
+  }
+  s->any_metal = any;
+  if (any)
+    for (int d = 0; d < 3; ++d) { s->mlo[d] = lo[d] - 1; s->mn[d] = hi[d] - lo[d] + 3; }
+  s->mat = *m;
+  s->have_material = true;
+  return GNOR_OK;
+}
+
+gnor_status gnor_set_source(gnor_sim* s, const gnor_source_desc* src) {
+  if (!s || !src) return GNOR_E_INVALID_ARG;
+  if (s->bound) return fail(s, GNOR_E_STATE, "source must be set before gnor_bind_memory");
+  if (src->kind < 0 || src->kind > 2) return fail(s, GNOR_E_INVALID_ARG, "unknown source kind");
+  if (src->kind == 1 && !(src->tau > 0)) return fail(s, GNOR_E_INVALID_ARG, "tau must be positive");
+  if (src->kind == 2 && !(src->omega_max > 0)) return fail(s, GNOR_E_INVALID_ARG, "omega_max must be positive");
+  s->src = *src;
+  s->have_source = true;
+  return GNOR_OK;
+}
+
+gnor_status gnor_set_monitors(gnor_sim* s, const gnor_monitor_desc* m) {
+  if (!s || !m) return GNOR_E_INVALID_ARG;
+  if (s->bound) return fail(s, GNOR_E_STATE, "monitors must be set before gnor_bind_memory");
+  if (m->nfreq < 0 || (m->nfreq > 0 && !m->omega)) return fail(s, GNOR_E_INVALID_ARG, "bad frequency list");
+  if (m->norm_k < 0 || m->norm_k >= s->g.nz) return fail(s, GNOR_E_INVALID_ARG, "norm_k outside the grid");
+  if (m->dft_every < 0) return fail(s, GNOR_E_INVALID_ARG, "dft_every must be >= 0");
+  if (m->flux_enabled) {
+    if (m->dft_every > 1) return fail(s, GNOR_E_INVALID_ARG, "flux boxes require dft_every = 1");
+    const gnor_grid_desc& g = s->g;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int d = 0; d < 3; ++d) {
+      if (m->abs_lo[d] <= g.tf_lo[d] || m->abs_hi[d] >= g.tf_hi[d] || m->abs_hi[d] - m->abs_lo[d] < 1)
+        return fail(s, GNOR_E_INVALID_ARG, "absorption box must lie strictly inside the TF box");
+      if (m->sca_lo[d] >= g.tf_lo[d] - 1 || m->sca_hi[d] <= g.tf_hi[d] + 1 ||
+          m->sca_lo[d] < g.npml + 1 || m->sca_hi[d] > n[d] - 2 - g.npml)
+        return fail(s, GNOR_E_INVALID_ARG,
+                    "scattering box must enclose the TF box with a spare cell and stay out of the CPML");
+    }
+  }
+  s->mon = *m;
+  s->omega.assign(m->omega, m->omega + m->nfreq);
+  s->mon.omega = nullptr;
+  s->have_monitors = true;
+  return GNOR_OK;
+}
+
+size_t gnor_required_bytes(const gnor_sim* cs) {
+  if (!cs) return 0;
+  gnor_sim* s = const_cast<gnor_sim*>(cs);
+  prepare(s);
+  return s->L.state_end + 256;
+}
+
+gnor_status gnor_reset(gnor_sim* s) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  HIPCHECK(s, hipMemsetAsync(s->dev + s->L.state_begin, 0, s->L.state_end - s->L.state_begin, s->stream));
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  s->step = 0;
+  return GNOR_OK;
+}
+
+gnor_status gnor_bind_memory(gnor_sim* s, void* dptr, size_t bytes, void* stream) {
+  if (!s || !dptr) return GNOR_E_INVALID_ARG;
+  if (!s->have_material) return fail(s, GNOR_E_STATE, "gnor_set_material has not been called");
+  if (!s->have_monitors) {
+    gnor_monitor_desc m{};
+    m.norm_k = s->g.nz / 2;
+    gnor_set_monitors(s, &m);
+  }
+  if (((uintptr_t)dptr) & 255u) return fail(s, GNOR_E_INVALID_ARG, "device buffer must be 256-byte aligned");
+  prepare(s);
+  if (bytes < s->L.state_end) return fail(s, GNOR_E_BUFFER_TOO_SMALL, "device buffer smaller than gnor_required_bytes");
+  drop_graph(s);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  s->own_stream = false;
+  s->stream = reinterpret_cast<hipStream_t>(stream);
+  if (!s->stream) {
+    HIPCHECK(s, hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    s->own_stream = true;
+  }
+  s->dev = reinterpret_cast<char*>(dptr);
+  s->dev_bytes = bytes;
+  s->bound = true;
+  gnor_status st = upload_static(s);
+  if (st != GNOR_OK) return st;
+  return gnor_reset(s);
+}
+
+gnor_status gnor_set_graph_chunk(gnor_sim* s, int32_t steps) {
+  if (!s) return GNOR_E_INVALID_ARG;
+  if (steps < 0 || (steps & 1)) return fail(s, GNOR_E_INVALID_ARG, "graph chunk must be even and >= 0");
+  s->graph_chunk = steps;
+  drop_graph(s);
+  return GNOR_OK;
+}
+
+gnor_status gnor_run(gnor_sim* s, int64_t nsteps) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  if (nsteps < 0) return fail(s, GNOR_E_INVALID_ARG, "nsteps < 0");
+  int64_t left = nsteps;
+  const int align = chunk_alignment(s);
+  int chunk = s->graph_chunk;
+  if (chunk > 0) chunk = std::max(align, chunk / align * align);
+  while (left > 0) {
+    if (chunk > 0 && (s->step % align) == 0 && left >= chunk) {
+      if (!s->graph || s->graph_steps != chunk) {
+        st = build_graph(s, chunk);
+        if (st != GNOR_OK) return st;
+      }
+      HIPCHECK(s, hipGraphLaunch(s->graph, s->stream));
+      s->step += chunk;
+      left -= chunk;
+      continue;
+    }
+    // eager steps until the next aligned chunk start (or the end)
+    int64_t n = left;
+    if (chunk > 0) {
+      const int64_t to_align = (align - (s->step % align)) % align;
+      n = to_align > 0 ? std::min(left, to_align) : std::min(left, (int64_t)chunk);
+      if (to_align == 0 && left < chunk) n = left;
+    }
+    enqueue_steps_eager(s, s->step, n, s->stream);
+    HIPCHECK(s, hipGetLastError());
+    s->step += n;
+    left -= n;
+  }
+  return GNOR_OK;
+}
+
+gnor_status gnor_synchronize(gnor_sim* s) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  return GNOR_OK;
+}
+
+int64_t gnor_step_index(const gnor_sim* s) { return s ? s->step : -1; }
+
+gnor_status gnor_get_dft(gnor_sim* s, double* are, double* aim, double* bre, double* bim) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  const size_t nzf = (size_t)s->g.nz * s->mon.nfreq;
+  if (nzf == 0) return GNOR_OK;
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  std::vector<double> buf(4 * nzf);
+  HIPCHECK(s, hipMemcpy(buf.data(), s->dev + s->L.dft, 4 * nzf * 8, hipMemcpyDeviceToHost));
+  const double aconv = eps0() / s->dt;  // J~ = J dt / eps0
+  for (size_t q = 0; q < nzf; ++q) {
+    if (are) are[q] = buf[q] * aconv;
+    if (aim) aim[q] = buf[nzf + q] * aconv;
+    if (bre) bre[q] = buf[2 * nzf + q];
+    if (bim) bim[q] = buf[3 * nzf + q];
+  }
+  return GNOR_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+gnor_status gnor_get_spectra(gnor_sim* s, double* inc, double* ext, double* absn, double* sca) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  const int nf = s->mon.nfreq;
+  if (nf == 0) return GNOR_OK;
+  std::vector<double> fs(2 * (size_t)nf, 0.0);
+  if (s->nsamp > 0) {
+    // fold the partially filled staging window into the accumulators
+    if (s->step > 0 && (s->step % s->slots) != 0) {
+      enqueue_flux_acc(s, -1, s->stream);  // last staged step = counter - 1
+    }
+    gnor::launch_flux_reduce(ptr<double>(s, s->L.facc), ptr<double>(s, s->L.facc) + (size_t)nf * s->nsamp,
+                       ptr<double>(s, s->L.fpw), s->npairs, s->npairs_box0, nf,
+                       ptr<double>(s, s->L.fsum), s->stream);
+    HIPCHECK(s, hipGetLastError());
+    HIPCHECK(s, hipStreamSynchronize(s->stream));
+    HIPCHECK(s, hipMemcpy(fs.data(), s->dev + s->L.fsum, fs.size() * 8, hipMemcpyDeviceToHost));
+  }
+  const int nz = s->g.nz;
+  std::vector<double> are((size_t)nz * nf), aim((size_t)nz * nf), bre((size_t)nz * nf), bim((size_t)nz * nf);
+  st = gnor_get_dft(s, are.data(), aim.data(), bre.data(), bim.data());
+  if (st != GNOR_OK) return st;
+  const double h3 = s->g.dx * s->g.dx * s->g.dx;
+  for (int m = 0; m < nf; ++m) {
+    const size_t qc = (size_t)s->mon.norm_k * nf + m;
+    const double b2 = bre[qc] * bre[qc] + bim[qc] * bim[qc];
+    if (inc) inc[m] = b2;
+    double acc = 0.0;
+    for (int k = 0; k < nz; ++k) {
+      const size_t q = (size_t)k * nf + m;
+      acc += are[q] * bre[q] + aim[q] * bim[q];
+    }
+    if (ext) ext[m] = eta0() * h3 * acc / b2;
+    // flux sums are of Re(E conj(H~)) with H~ = eta0 H: flux_SI = sum / eta0
+    if (absn) absn[m] = s->nsamp > 0 ? -fs[m] / b2 : 0.0;
+    if (sca) sca[m] = s->nsamp > 0 ? fs[nf + m] / b2 : 0.0;
+  }
+  return GNOR_OK;
+}
+
+gnor_status gnor_get_field(gnor_sim* s, int32_t which, double* dst, size_t count) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  if (!dst) return GNOR_E_INVALID_ARG;
+  if (count != s->N) return fail(s, GNOR_E_BUFFER_TOO_SMALL, "count must be nx*ny*nz");
+  if (which < 0 || which > 8) return fail(s, GNOR_E_INVALID_ARG, "field index out of range");
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  const int parity = (int)(s->step & 1);
+  const int c = which % 3;
+  const bool fp32 = s->g.precision == GNOR_FP32;
+  auto fetch = [&](size_t off, size_t n, std::vector<double>& out) -> gnor_status {
+    out.resize(n);
+    if (fp32) {
+      std::vector<float> f(n);
+      HIPCHECK(s, hipMemcpy(f.data(), s->dev + off, n * 4, hipMemcpyDeviceToHost));
+      for (size_t q = 0; q < n; ++q) out[q] = f[q];
+    } else {
+      HIPCHECK(s, hipMemcpy(out.data(), s->dev + off, n * 8, hipMemcpyDeviceToHost));
+    }
+    return GNOR_OK;
+  };
+  std::vector<double> v;
+  if (which < 3) {
+    st = fetch(s->L.E[parity][c], s->N, v);
+    if (st != GNOR_OK) return st;
+    std::memcpy(dst, v.data(), s->N * 8);
+  } else if (which < 6) {
+    st = fetch(s->L.H[c], s->N, v);
+    if (st != GNOR_OK) return st;
+    const double k = 1.0 / eta0();
+    for (size_t q = 0; q < s->N; ++q) dst[q] = v[q] * k;
+  } else {
+    std::memset(dst, 0, s->N * 8);
+    if (s->any_metal) {
+      st = fetch(s->L.J[parity][c], s->M, v);
+      if (st != GNOR_OK) return st;
+      const double k = eps0() / s->dt;
+      const gnor_grid_desc& g = s->g;
+      for (int z = 0; z < s->mn[2]; ++z)
+        for (int y = 0; y < s->mn[1]; ++y)
+          for (int x = 0; x < s->mn[0]; ++x)
+            dst[((size_t)(z + s->mlo[2]) * g.ny + (y + s->mlo[1])) * g.nx + (x + s->mlo[0])] =
+                v[((size_t)z * s->mn[1] + y) * s->mn[0] + x] * k;
+    }
+  }
+  return GNOR_OK;
+}
+
+gnor_status gnor_get_aux(gnor_sim* s, double* e1, double* h1, size_t count) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  if (count != (size_t)s->n1) return fail(s, GNOR_E_BUFFER_TOO_SMALL, "count must be nz + 50");
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  std::vector<double> buf(2 * (size_t)s->n1);
+  HIPCHECK(s, hipMemcpy(buf.data(), s->dev + s->L.aux, buf.size() * 8, hipMemcpyDeviceToHost));
+  if (e1) std::memcpy(e1, buf.data(), s->n1 * 8);
+  if (h1)
+    for (int q = 0; q < s->n1; ++q) h1[q] = buf[s->n1 + q] / eta0();
+  return GNOR_OK;
+}
+
+size_t gnor_state_bytes(const gnor_sim* s) {
+  if (!s || !s->bound) return 0;
+  return s->L.state_end - s->L.state_begin + 8;
+}
+
+gnor_status gnor_save_state(gnor_sim* s, void* dst, size_t bytes) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  if (!dst) return GNOR_E_INVALID_ARG;
+  const size_t n = s->L.state_end - s->L.state_begin;
+  if (bytes < n + 8) return fail(s, GNOR_E_BUFFER_TOO_SMALL, "state buffer too small");
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  std::memcpy(dst, &s->step, 8);
+  HIPCHECK(s, hipMemcpy(static_cast<char*>(dst) + 8, s->dev + s->L.state_begin, n, hipMemcpyDeviceToHost));
+  return GNOR_OK;
+}
+
+gnor_status gnor_load_state(gnor_sim* s, const void* src, size_t bytes) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  if (!src) return GNOR_E_INVALID_ARG;
+  const size_t n = s->L.state_end - s->L.state_begin;
+  if (bytes < n + 8) return fail(s, GNOR_E_BUFFER_TOO_SMALL, "state buffer too small");
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  std::memcpy(&s->step, src, 8);
+  HIPCHECK(s, hipMemcpy(s->dev + s->L.state_begin, static_cast<const char*>(src) + 8, n, hipMemcpyHostToDevice));
+  return GNOR_OK;
+}
+
+gnor_status gnor_check_finite(gnor_sim* s) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  int* flag = ptr<int>(s, s->L.flag);
+  HIPCHECK(s, hipMemsetAsync(flag, 0, 4, s->stream));
+  const int parity = (int)(s->step & 1);
+  for (int c = 0; c < 3; ++c) {
+    if (s->g.precision == GNOR_FP32) {
+      gnor::launch_nonfinite<float>(ptr<float>(s, s->L.E[parity][c]), s->N, flag, s->stream);
+      gnor::launch_nonfinite<float>(ptr<float>(s, s->L.H[c]), s->N, flag, s->stream);
+    } else {
+      gnor::launch_nonfinite<double>(ptr<double>(s, s->L.E[parity][c]), s->N, flag, s->stream);
+      gnor::launch_nonfinite<double>(ptr<double>(s, s->L.H[c]), s->N, flag, s->stream);
+    }
+  }
+  int h = 0;
+  HIPCHECK(s, hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s->stream));
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  return h ? fail(s, GNOR_E_NONFINITE, "non-finite value in E or H") : GNOR_OK;
+}
+
+gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_t count) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  if (!ms || count < 5 || nsteps <= 0) return GNOR_E_INVALID_ARG;
+  hipEvent_t ev[12];
+  for (auto& e : ev) HIPCHECK(s, hipEventCreate(&e));
+  double acc[5] = {0, 0, 0, 0, 0};
+  int64_t nacc = 0;
+  for (int64_t q = 0; q < nsteps; ++q) {
+    const int64_t n = s->step;
+    const int parity = (int)(n & 1);
+    const hipStream_t str = s->stream;
+    const gnor::AuxParams a = make_aux(s);
+    (void)hipEventRecord(ev[0], str);
+    if (s->g.precision == GNOR_FP32) gnor::launch_h<float>(make_params<float>(s, parity), 0, str);
+    else gnor::launch_h<double>(make_params<double>(s, parity), 0, str);
+    (void)hipEventRecord(ev[1], str);
+    gnor::launch_aux_h(a, 0, str);
+    (void)hipEventRecord(ev[2], str);
+    if (s->g.precision == GNOR_FP32) gnor::launch_ej<float>(make_params<float>(s, parity), 0, str);
+    else gnor::launch_ej<double>(make_params<double>(s, parity), 0, str);
+    (void)hipEventRecord(ev[3], str);
+    gnor::launch_aux_e(a, 0, str);
+    (void)hipEventRecord(ev[4], str);
+    if (s->mon.nfreq > 0) gnor::launch_dft(make_dft(s), 0, str);
+    if (s->nsamp > 0) {
+      if (s->g.precision == GNOR_FP32)
+        gnor::launch_flux_stage<float>(make_flux(s), make_params<float>(s, parity), ptr<int64_t>(s, s->L.fsidx), 0, str);
+      else
+        gnor::launch_flux_stage<double>(make_flux(s), make_params<double>(s, parity), ptr<int64_t>(s, s->L.fsidx), 0, str);
+    }
+    (void)hipEventRecord(ev[5], str);
+    if (s->nsamp > 0 && (n % s->slots) == s->slots - 1) enqueue_flux_acc(s, 0, str);
+    (void)hipEventRecord(ev[6], str);
+    gnor::launch_advance(ptr<int64_t>(s, s->L.step), 1, str);
+    HIPCHECK(s, hipGetLastError());
+    HIPCHECK(s, hipEventSynchronize(ev[6]));
+    float t[6];
+    for (int e = 0; e < 6; ++e) (void)hipEventElapsedTime(&t[e], ev[e], ev[e + 1]);
+    acc[0] += t[0]; acc[3] += t[1]; acc[1] += t[2]; acc[3] += t[3]; acc[2] += t[4]; acc[4] += t[5];
+    ++nacc;
+    s->step += 1;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  for (int i = 0; i < 5; ++i) ms[i] = acc[i] / (double)nacc;
+  return GNOR_OK;
+}
+
+// ----------------------------------------------------------------- voxelisers
+gnor_status gnor_voxelize_spheres(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t n,
+                                  const double* cr, uint8_t* out) {
+  if (nx <= 0 || ny <= 0 || nz <= 0 || !(dx > 0) || n < 0 || (n > 0 && !cr) || !out)
+    return GNOR_E_INVALID_ARG;
+  // quantise centre and radius to 2^-20 cell; exact int64 comparison
+  std::vector<long long> q((size_t)4 * n);
+  for (int s = 0; s < n; ++s)
+    for (int t = 0; t < 4; ++t) q[4 * s + t] = std::llround(cr[4 * s + t] / dx * 1048576.0);
+  const long long one = 1048576, half = 524288;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        uint8_t bits = 0;
+        const long long X = i * one, Y = j * one, Z = k * one;
+        for (int c = 0; c < 3; ++c) {
+          const long long px = X + (c == 0 ? half : 0), py = Y + (c == 1 ? half : 0), pz = Z + (c == 2 ? half : 0);
+          for (int s = 0; s < n; ++s) {
+            const long long ex = px - q[4 * s], ey = py - q[4 * s + 1], ez = pz - q[4 * s + 2];
+            const long long r = q[4 * s + 3];
+            if (ex * ex + ey * ey + ez * ez < r * r) { bits |= (uint8_t)(1u << c); break; }
+          }
+        }
+        out[((size_t)k * ny + j) * nx + i] = bits;
+      }
+  return GNOR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Inside test of the star (sphere + sphere-capped cones), FP64 in a fixed
+// operation order (this file is compiled with -ffp-contract=off).
+bool star_point(const double* d, double x, double y, double z) {
+  const double ox = x - d[0], oy = y - d[1], oz = z - d[2];
+  const double R = d[3], rt = d[4], tn = d[5], sn = d[6];
+  const int nt = (int)d[7];
+  const double r2 = ox * ox + oy * oy + oz * oz;
+  if (r2 < R * R) return true;
+  for (int t = 0; t < nt; ++t) {
+    const double* a = d + 8 + 4 * t;
+    const double s_cap = R + a[3] - rt;
+    const double s_apex = s_cap + rt / sn;
+    const double s_tan = s_cap + rt * sn;
+    const double s = ox * a[0] + oy * a[1] + oz * a[2];
+    const double q2 = r2 - s * s;
+    if (s >= 0.0 && s <= s_tan) {
+      const double rad = (s_apex - s) * tn;
+      if (q2 < rad * rad) return true;
+    }
+    const double ux = ox - s_cap * a[0], uy = oy - s_cap * a[1], uz = oz - s_cap * a[2];
+    if (ux * ux + uy * uy + uz * uz < rt * rt) return true;
+  }
+  return false;
+}
+}  // namespace
+
+extern "C" gnor_status gnor_voxelize_star(int32_t nx, int32_t ny, int32_t nz, double dx, const double* d,
+                                          int32_t len, uint8_t* out) {
+  if (nx <= 0 || ny <= 0 || nz <= 0 || !(dx > 0) || !d || !out || len < 8) return GNOR_E_INVALID_ARG;
+  if (len != 8 + 4 * (int)d[7]) return GNOR_E_INVALID_ARG;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const double xi = (double)i * dx, yj = (double)j * dx, zk = (double)k * dx;
+        const double xh = ((double)i + 0.5) * dx, yh = ((double)j + 0.5) * dx, zh = ((double)k + 0.5) * dx;
+        uint8_t b = 0;
+        if (star_point(d, xh, yj, zk)) b |= 1u;
+        if (star_point(d, xi, yh, zk)) b |= 2u;
+        if (star_point(d, xi, yj, zh)) b |= 4u;
+        out[((size_t)k * ny + j) * nx + i] = b;
+      }
+  return GNOR_OK;
+}

@@ -1,0 +1,108 @@
+"""C-ABI contract checks that need no GPU: the library loads and exports every
+function include/gnor_fdtd.h declares; host-side validation returns the
+documented status codes; the library's voxelisers match the oracle's
+independent voxelisers bit for bit."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2005_06997_amd import binding as B
+from paper_2005_06997_amd import workloads as W
+from tests.helpers import oracle_mask
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = B.header_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code in range(8):
+        assert lib.gnor_status_string(code)
+
+
+def _grid(w, **over):
+    g = B.GridDesc(nx=w.nx, ny=w.ny, nz=w.nz, dx=w.dx, courant=w.courant, npml=w.npml,
+                   pml_order=3.0, pml_sigma_scale=0.8, pml_kappa_max=1.0, pml_alpha_max=0.0,
+                   eps_background=1.0, precision=B.GNOR_FP64)
+    g.tf_lo[:] = list(w.tf_lo)
+    g.tf_hi[:] = list(w.tf_hi)
+    for k, v in over.items():
+        setattr(g, k, v)
+    return g
+
+
+def _create(lib, g):
+    h = C.c_void_p()
+    st = lib.gnor_create(C.byref(g), C.byref(h))
+    return st, h
+
+
+def test_create_rejects_unstable_courant(lib):
+    w = W.config1(0)
+    st, h = _create(lib, _grid(w, courant=0.6))
+    assert st == 2  # GNOR_E_UNSTABLE
+    st, h = _create(lib, _grid(w, courant=0.0))
+    assert st == 2
+    st, h = _create(lib, _grid(w, courant=0.5))
+    assert st == 0
+    lib.gnor_destroy(h)
+
+
+def test_create_rejects_bad_sizes_and_boxes(lib):
+    w = W.config1(0)
+    assert _create(lib, _grid(w, nx=0))[0] == 1
+    assert _create(lib, _grid(w, dx=-1.0))[0] == 1
+    assert _create(lib, _grid(w, precision=7))[0] == 1
+    g = _grid(w)
+    g.tf_lo[0] = w.npml  # TF box touching the CPML
+    assert _create(lib, g)[0] == 1
+
+
+def test_material_outside_tf_rejected_and_run_before_bind(lib):
+    w = W.config1(0)
+    st, h = _create(lib, _grid(w))
+    assert st == 0
+    mask = np.zeros((w.nz, w.ny, w.nx), np.uint8)
+    mask[w.tf_lo[2] + 1, 24, 24] = 1  # one cell inside the TF box: too close to its face
+    mat = B.MaterialDesc(wp=W.WP, gamma=W.GAMMA, beta=W.BETA, diffusion=W.DIFF, eps_inf=1.0)
+    assert lib.gnor_set_material(h, mask.ctypes.data, C.byref(mat)) == 1
+    assert b"TF box" in lib.gnor_last_error(h)
+    mask[:] = 0
+    mask[24, 24, 24] = 8  # bits above 2 are not allowed
+    assert lib.gnor_set_material(h, mask.ctypes.data, C.byref(mat)) == 1
+    mask[:] = 0
+    mask[24, 24, 24] = 7
+    assert lib.gnor_set_material(h, mask.ctypes.data, C.byref(mat)) == 0
+    assert lib.gnor_run(h, 1) == 5  # GNOR_E_STATE: nothing bound
+    assert lib.gnor_required_bytes(h) > 0
+    lib.gnor_destroy(h)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_sphere_masks_bit_exact_vs_oracle(seed):
+    w = W.config1(seed)
+    assert np.array_equal(B.voxelize(w), oracle_mask(w))
+
+
+def test_dimer_and_batch_masks_bit_exact_vs_oracle():
+    for w in W.config4(seed=0, count=6):
+        assert np.array_equal(B.voxelize(w), oracle_mask(w))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_star_mask_bit_exact_vs_oracle(seed):
+    w = W.config3(seed=seed, n=200, dx=0.4e-9)
+    a = B.voxelize(w)
+    b = oracle_mask(w)
+    assert a.any()
+    assert np.array_equal(a, b)
