@@ -51,6 +51,7 @@ def run_gpu(w, precision, steps, warmup):
     from paper_2005_06997_amd import binding
 
     sim = binding.Sim(w, precision=precision)
+    sim.tiling = sim.autotune(trial_steps=10)  # timed search over sweep tilings (state reset after)
     sim.run(warmup)
     sim.synchronize()
     torch.cuda.synchronize()
@@ -135,6 +136,7 @@ def main():
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": ejb, "avg_launch_ms": round(prof["ej"], 5)},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
+        "tiling": {k: sim.tiling[k] for k in ("ty", "kz", "xcd")},
         "h_roofline_frac": round(hb / (prof["h"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
     del sim

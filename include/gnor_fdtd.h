@@ -176,10 +176,27 @@ gnor_status gnor_load_state(gnor_sim *sim, const void *host_src, size_t bytes);
 gnor_status gnor_check_finite(gnor_sim *sim);
 
 /* Average device time per launch (ms) of each kernel over nsteps steps run
- * with events around every launch (no graphs):
- * ms[0] H update, ms[1] E/J update, ms[2] spectra, ms[3] auxiliary line
- * (both halves), ms[4] flux accumulation (per step, amortised). */
+ * with events around every launch on the bound stream (no graphs):
+ * ms[0] H sweep (with the auxiliary line's H half), ms[1] E/J sweep (with the
+ * auxiliary line's E half), ms[2] spectra and flux staging, ms[3] unused (0),
+ * ms[4] flux accumulation (per step, amortised).  count must be >= 5. */
 gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int32_t count);
+
+/* Sweep tiling: each block owns 64 (x) x ty (y) columns over kz planes;
+ * ty in {2, 4, 8}, 1 <= kz <= nz.  xcd_bands = 1 deals the tiles so that each
+ * of the 8 XCDs sweeps one contiguous band (neighbouring tiles share its L2);
+ * 0 keeps the natural order (tiles spread round-robin over the XCDs).
+ * Fields do not depend on the tiling; spectra only through FP64 summation
+ * order. */
+gnor_status gnor_set_tiling(gnor_sim *sim, int32_t ty, int32_t kz, int32_t xcd_bands);
+
+/* Autotuner: times every candidate tiling (ty in {2, 4, 8}, kz in {8, 16, 32,
+ * 64, nz}, xcd_bands in {0, 1}) over trial_steps directly launched steps and
+ * keeps the fastest.  Must be called at step index 0; the state is reset
+ * afterwards.  Outputs (any may be NULL): chosen ty, kz, xcd_bands and its
+ * ms per step. */
+gnor_status gnor_autotune(gnor_sim *sim, int32_t trial_steps, int32_t *ty, int32_t *kz,
+                          int32_t *xcd_bands, double *ms_per_step);
 
 /* Voxelisers.  Spheres: n spheres as (cx, cy, cz, r) in metres from node
  * (0,0,0); a P_c point is inside iff its squared distance to a centre is

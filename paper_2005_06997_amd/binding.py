@@ -98,6 +98,8 @@ def load() -> C.CDLL:
         "gnor_load_state": (i32, [vp, vp, sz]),
         "gnor_check_finite": (i32, [vp]),
         "gnor_profile_kernels": (i32, [vp, i64, dp, i32]),
+        "gnor_set_tiling": (i32, [vp, i32, i32, i32]),
+        "gnor_autotune": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp]),
         "gnor_voxelize_spheres": (i32, [i32, i32, i32, dbl, i32, vp, vp]),
         "gnor_voxelize_star": (i32, [i32, i32, i32, dbl, vp, i32, vp]),
         "gnor_status_string": (C.c_char_p, [i32]),
@@ -254,6 +256,40 @@ class Sim:
         self._check(self.L.gnor_load_state(self.h, (C.c_char * n).from_buffer(buf), n))
 
     def profile(self, nsteps: int) -> Dict[str, float]:
+        """Average ms per launch of the H sweep, E/J sweep, spectra+staging and
+        (amortised per step) flux accumulation, from HIP events."""
         ms = np.zeros(5)
         self._check(self.L.gnor_profile_kernels(self.h, int(nsteps), _dp(ms), 5))
-        return dict(h=ms[0], ej=ms[1], dft=ms[2], aux=ms[3], flux_acc=ms[4])
+        return dict(h=ms[0], ej=ms[1], dft=ms[2], flux_acc=ms[4])
+
+    def set_tiling(self, ty: int, kz: int, xcd: int = 0):
+        self._check(self.L.gnor_set_tiling(self.h, int(ty), int(kz), int(xcd)))
+
+    def autotune(self, trial_steps: int = 20, cache: Optional[str] = None):
+        """Pick the sweep tiling by timing every candidate (library autotuner);
+        results are cached in a JSON file keyed by grid shape, precision and
+        metal-cell count (default ~/.cache/gnorfdtd/tiling.json)."""
+        import json
+        path = cache or os.path.join(os.path.expanduser("~"), ".cache", "gnorfdtd", "tiling.json")
+        key = f"{self.w.nx}x{self.w.ny}x{self.w.nz}:{self.precision}:{int(np.count_nonzero(self.mask))}"
+        table = {}
+        if os.path.exists(path):
+            try:
+                table = json.load(open(path))
+            except (OSError, ValueError):
+                table = {}
+        if key in table:
+            e = table[key]
+            self.set_tiling(e["ty"], e["kz"], e["xcd"])
+            return dict(e, cached=True)
+        ty, kz, xcd, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        self._check(self.L.gnor_autotune(self.h, int(trial_steps), C.byref(ty), C.byref(kz),
+                                         C.byref(xcd), C.byref(ms)))
+        table[key] = dict(ty=ty.value, kz=kz.value, xcd=xcd.value, ms=ms.value)
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as fh:
+                json.dump(table, fh, indent=1)
+        except OSError:
+            pass
+        return dict(table[key], cached=False)

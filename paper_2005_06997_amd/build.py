@@ -17,7 +17,8 @@ COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
           "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 SOURCES = [
-    ("gnor_kernels.hip", []),
+    ("gnor_sweeps.hip", []),
+    ("gnor_spectra.hip", []),
     # the voxelisers' floating-point tests must not be contracted into FMAs
     ("gnor_runtime.cpp", ["-ffp-contract=off"]),
 ]

@@ -33,9 +33,11 @@ constexpr int kAuxPml = 20;
 constexpr int kAuxOff = 25;
 constexpr int kAuxSrc = 22;
 
-// Threads per block of the field sweeps (x, y).
+// Field sweeps: blocks of 64 (x, one wavefront) x TY (y) columns, each column
+// marching over kz planes.
 constexpr int kBX = 64;
-constexpr int kBY = 4;
+constexpr int kMaxFreq = 256;   // spectral frequencies per simulation
+constexpr int kFluxSlots = 64;  // flux staging depth (steps per accumulation)
 
 template <class T>
 struct CpmlAxis {
@@ -49,42 +51,15 @@ struct CpmlAxis {
   const T* kh;
 };
 
-// Device pointers and coefficients of one simulation (one precision).
-template <class T>
-struct Params {
-  int nx, ny, nz;
-  T S;            // Courant number: H coefficient
-  T SE;           // S / eps_b: vacuum E coefficient
-  // full-grid fields
-  T* E[3];        // E^n
-  T* O[3];        // E^{n-1} (read at metal points) -> E^{n+1} (written everywhere)
-  T* H[3];
-  // metal sub-grid [mlo, mlo + mn)
-  int mlo[3], mn[3];
-  const uint8_t* mask;  // sub-grid, bit c = P_c is metal
-  const float* rho;     // optional per-cell weight of wp^2, beta^2, D (sub-grid); null = 1
-  const T* Ji[3];
-  T* Jo[3];
-  const T* PPi;
-  T* PPo;
-  const T* PJi;
-  T* PJo;
-  T eps_inf, d3, agam, D2, g1, g2, ebd;  // ebd = eps_inf - eps_b
-  T cS, c3, c1, cJ, cG;                   // E metal coefficients divided by (eps_inf + d3)
-  // CPML memory: psi[axis][t], t = 0 for component (axis+2)%3, 1 for (axis+1)%3
-  T* psiE[3][2];
-  T* psiH[3][2];
-  CpmlAxis<T> cp[3];
-  // TF/SF
-  int tfsf;
-  int tf_lo[3], tf_hi[3];
-  const double* e1;
-  const double* h1;
-  // per-(plane, block) partial sums of the induced current for the spectra
-  double* jpart;      // [nz][nbxy]
-  int nbx, nby;
-  // step counter
-  const int64_t* step_base;
+// Tiling of a sweep: tiles of 64 x ty columns by kz planes, numbered x
+// fastest, then y, then z; tile t runs on block (t mod per) * 8 + t / per so
+// that each XCD (blocks are dealt to the 8 XCDs round-robin) owns a
+// contiguous band of tiles and neighbouring tiles share its L2.
+struct Tiling {
+  int ty, kz;
+  int xcd;        // 1: XCD bands as above; 0: natural order (round-robin over XCDs)
+  int nbx, nby, nbz;
+  int per;        // ceil(tiles / 8)
 };
 
 // Auxiliary line state (FP64 always).
@@ -103,16 +78,73 @@ struct AuxParams {
   const double* kh;
   int src_kind;
   double e0, omega_c, tau, t0, omega_max, dt;
+  // phase table of the step for the spectra: [cos tJ, sin tJ, cos tE, sin tE][nf]
+  int nf;
+  const double* omega;
+  double* phase;
+  int every;
   const int64_t* step_base;
 };
+
+// Device pointers and coefficients of one simulation (one precision).
+template <class T>
+struct Params {
+  int nx, ny, nz;
+  T S;            // Courant number: H coefficient
+  T SE;           // S / eps_b: vacuum E coefficient
+  // full-grid fields
+  T* E[3];        // E^n
+  T* O[3];        // E^{n-1} (read at metal points) -> E^{n+1} (written everywhere)
+  T* H[3];
+  // metal sub-grid [mlo, mlo + mn)
+  int any_metal;
+  int mlo[3], mn[3];
+  const uint8_t* mask;  // sub-grid, bit c = P_c is metal
+  const float* rho;     // optional per-cell weight of wp^2, beta^2, D (sub-grid); null = 1
+  const T* Ji[3];
+  T* Jo[3];
+  const T* PPi;
+  T* PPo;
+  const T* PJi;
+  T* PJo;
+  T* Q;                 // Q of the step's node scalars (written by k_h, read by k_ej)
+  T eps_inf, d3, agam, D2, g1, g2, ebd;  // ebd = eps_inf - eps_b
+  T cS, c3, c1, cJ, cG;                   // E metal coefficients divided by (eps_inf + d3)
+  // CPML memory: psi[axis][t], t = 0 for component (axis+2)%3, 1 for (axis+1)%3
+  T* psiE[3][2];
+  T* psiH[3][2];
+  CpmlAxis<T> cp[3];
+  // TF/SF
+  int tfsf;
+  int tf_lo[3], tf_hi[3];
+  const double* e1;
+  const double* h1;
+  // per-(plane, tile, wavefront) partial sums of the induced current J_x
+  double* jpart;      // [nz][nbx * nby * ty]
+  Tiling tl;
+  const int64_t* step_base;
+};
+
+// One face segment of the flux boxes: (E, H) sample pairs on a rectangle of
+// the face plane p (normal axis a); pair q of the segment lies at
+// inner = q % n_in, outer = q / n_in.
+struct FluxSeg {
+  int first;          // first pair index
+  int count;
+  int a, p;
+  int ecomp, hcomp;   // E component sampled on the face, H component averaged across it
+  int in_axis, out_axis;
+  int in_lo, out_lo, n_in;
+};
+constexpr int kMaxSeg = 24;
 
 struct DftParams {
   int nz, nf;
   int kz0, kz1;          // planes [kz0, kz1) carry induced current
   int nbxy;              // partial sums per plane
   const double* jpart;
-  const double* omega;
-  double dt, wdt;
+  const double* phase;   // [4][nf] from the auxiliary block of the E sweep
+  double wdt;
   int every;
   const double* e1;      // auxiliary line, E_inc^{n+1}
   double* a_re;          // [nz][nf]
@@ -122,36 +154,37 @@ struct DftParams {
   const int64_t* step_base;
 };
 
-// Flux monitors: staged samples, accumulated every `slots` steps.
+// Flux monitors: samples staged every step, accumulated every kFluxSlots.
+// Sample s < npairs is the E sample of pair s, s >= npairs the H sample of
+// pair s - npairs.
 struct FluxParams {
-  int nsamp;             // samples per step (both boxes)
+  int npairs, nsamp;     // nsamp = 2 npairs
   int nf;
-  int slots;             // staging depth
-  const int32_t* desc;   // per sample: kind and index (see runtime)
-  double* stage;         // [slots][nsamp]
+  int nseg;
+  FluxSeg seg[kMaxSeg];
+  int nx, ny;
+  double* stage;         // [kFluxSlots][nsamp]
   double* acc_re;        // [nf][nsamp]
   double* acc_im;
   const double* omega;
+  double* ptab;          // [nf][2 kinds][2 cos/sin][kFluxSlots]
   double dt, wdt;
-  int every;
   const int64_t* step_base;
 };
 
 template <class T>
-void launch_h(const Params<T>& p, int sub, hipStream_t s);
+void launch_h(const Params<T>& p, const AuxParams& a, hipStream_t s);
 template <class T>
-void launch_ej(const Params<T>& p, int sub, hipStream_t s);
-void launch_aux_h(const AuxParams& p, int sub, hipStream_t s);
-void launch_aux_e(const AuxParams& p, int sub, hipStream_t s);
-void launch_dft(const DftParams& p, int sub, hipStream_t s);
+void launch_ej(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s);
+template <class T>
+void launch_dft_stage(const DftParams& d, const FluxParams& f, const Params<T>& p, int sub,
+                      hipStream_t s);
 void launch_advance(int64_t* base, int64_t count, hipStream_t s);
-template <class T>
-void launch_flux_stage(const FluxParams& f, const Params<T>& p, const int64_t* sidx, int sub,
-                       hipStream_t s);
 void launch_flux_accumulate(const FluxParams& f, int* lo_ptr, int sub, hipStream_t s);
 void launch_flux_reduce(const double* acc_re, const double* acc_im, const double* pw, int npairs,
                         int npairs_box0, int nf, double* out, hipStream_t s);
 template <class T>
 void launch_nonfinite(const T* a, size_t n, int* flag, hipStream_t s);
+Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
 
 }  // namespace gnor

@@ -35,27 +35,31 @@ struct Err {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Region planner: assigns 256-byte aligned offsets.
+// Every region is followed by a 33 x 256-byte gap, so that equally sized
+// field arrays (e.g. 320^3 x 4 B = 2^17 x 1000 B) do not all start on the
+// same large power of two: the same cell of every array then maps to
+// different HBM channels.
 struct Planner {
   size_t off = 0;
   size_t take(size_t bytes) {
     const size_t o = off;
-    off += align_up(bytes);
+    off += align_up(bytes) + kSkew;
     return o;
   }
+  static constexpr size_t kSkew = 33 * 256;
 };
 
 struct Layout {
   // static region
-  size_t mask = 0, rho = 0, cpml[3] = {0, 0, 0}, aux_prof = 0, omega = 0, fdesc = 0, fsidx = 0,
-         fpw = 0, fbox = 0;
+  size_t mask = 0, rho = 0, cpml[3] = {0, 0, 0}, aux_prof = 0, omega = 0, fpw = 0;
   size_t static_end = 0;
   // state region
   size_t state_begin = 0;
   size_t E[2][3] = {{0}}, H[3] = {0, 0, 0};
-  size_t J[2][3] = {{0}}, PP[2] = {0, 0}, PJ[2] = {0, 0};
+  size_t J[2][3] = {{0}}, PP[2] = {0, 0}, PJ[2] = {0, 0}, Q = 0;
   size_t psiE[3][2] = {{0}}, psiH[3][2] = {{0}};
-  size_t aux = 0, jpart = 0, dft = 0, fstage = 0, facc = 0, step = 0, flux_lo = 0, flag = 0,
-         fsum = 0;
+  size_t aux = 0, phase = 0, jpart = 0, dft = 0, fstage = 0, facc = 0, ptab = 0, step = 0,
+         flux_lo = 0, flag = 0, fsum = 0;
   size_t state_end = 0;
 };
 
@@ -77,10 +81,10 @@ struct gnor_sim {
   int n1 = 0;
   int nbx = 0, nby = 0;
   // flux plan
-  int nsamp = 0, npairs = 0, npairs_box0 = 0, slots = 32;
-  std::vector<int32_t> fdesc;
-  std::vector<int64_t> fsidx;
+  int nsamp = 0, npairs = 0, npairs_box0 = 0, slots = gnor::kFluxSlots;
+  std::vector<gnor::FluxSeg> fseg;
   std::vector<double> fpw;
+  int tile_ty = 4, tile_kz = 32, tile_xcd = 0;   // sweep tiling (autotuned)
   Layout L;
   char* dev = nullptr;
   size_t dev_bytes = 0;
@@ -130,12 +134,16 @@ double layer_depth(double x, int n, int L) {
 }
 
 void plan_flux(gnor_sim* s) {
-  s->fdesc.clear(); s->fsidx.clear(); s->fpw.clear();
+  // Face segments of the two monitor boxes.  A segment is a rectangle of
+  // (E, H) sample pairs on one face; its inner index runs along x whenever x
+  // is tangential (coalesced staging loads).  Pair weights: outward sign x
+  // dx^2 x trapezoid weight along the face direction in which the samples sit
+  // on integer positions; E_b H_c pairs count +, E_c H_b pairs count -.
+  s->fseg.clear(); s->fpw.clear();
   s->nsamp = s->npairs = s->npairs_box0 = 0;
   if (!s->have_monitors || !s->mon.flux_enabled || s->mon.nfreq <= 0) return;
-  const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
-  const int64_t stride[3] = {1, (int64_t)n[0], (int64_t)n[0] * n[1]};
   const double h2 = s->g.dx * s->g.dx;
+  int first = 0;
   for (int box = 0; box < 2; ++box) {
     const int32_t* lo = box == 0 ? s->mon.abs_lo : s->mon.sca_lo;
     const int32_t* hi = box == 0 ? s->mon.abs_hi : s->mon.sca_hi;
@@ -143,35 +151,41 @@ void plan_flux(gnor_sim* s) {
       for (int side = -1; side <= 1; side += 2) {
         const int p = side < 0 ? lo[a] : hi[a];
         const int b = (a + 1) % 3, c = (a + 2) % 3;
-        auto lin = [&](int ib, int ic) {
-          int ii[3];
-          ii[a] = p; ii[b] = ib; ii[c] = ic;
-          return (int64_t)ii[0] + stride[1] * ii[1] + stride[2] * ii[2];
-        };
-        auto add_pair = [&](int ecomp, int hcomp, int64_t idx, double w) {
-          s->fdesc.insert(s->fdesc.end(), {0, ecomp, 0});
-          s->fsidx.push_back(idx);
-          s->fdesc.insert(s->fdesc.end(), {1, hcomp, (int32_t)stride[a]});
-          s->fsidx.push_back(idx);
-          s->fpw.push_back(w);
-        };
-        // E_b with H_c averaged across the face (trapezoid weights along c)
-        for (int kc = lo[c]; kc <= hi[c]; ++kc)
-          for (int jb = lo[b]; jb < hi[b]; ++jb) {
-            const double wt = (kc == lo[c] || kc == hi[c]) ? 0.5 : 1.0;
-            add_pair(b, c, lin(jb, kc), side * h2 * wt);
+        for (int kind = 0; kind < 2; ++kind) {
+          // kind 0: E_b at half-integer b, integer c, with H_c;
+          // kind 1: E_c at integer b, half-integer c, with H_b
+          gnor::FluxSeg g{};
+          g.a = a; g.p = p;
+          g.ecomp = kind == 0 ? b : c;
+          g.hcomp = kind == 0 ? c : b;
+          const int nb = kind == 0 ? hi[b] - lo[b] : hi[b] - lo[b] + 1;
+          const int nc = kind == 0 ? hi[c] - lo[c] + 1 : hi[c] - lo[c];
+          const bool inner_c = (c == 0);
+          g.in_axis = inner_c ? c : b;
+          g.out_axis = inner_c ? b : c;
+          g.in_lo = inner_c ? lo[c] : lo[b];
+          g.out_lo = inner_c ? lo[b] : lo[c];
+          g.n_in = inner_c ? nc : nb;
+          const int n_out = inner_c ? nb : nc;
+          g.first = first;
+          g.count = nb * nc;
+          for (int r = 0; r < g.count; ++r) {
+            const int ii = g.in_lo + r % g.n_in, oo = g.out_lo + r / g.n_in;
+            const int pb = inner_c ? oo : ii, pc = inner_c ? ii : oo;  // b and c coordinates
+            double wt;
+            if (kind == 0) wt = (pc == lo[c] || pc == hi[c]) ? 0.5 : 1.0;
+            else wt = (pb == lo[b] || pb == hi[b]) ? 0.5 : 1.0;
+            s->fpw.push_back((kind == 0 ? 1.0 : -1.0) * side * h2 * wt);
           }
-        // E_c with H_b averaged across the face (trapezoid weights along b)
-        for (int kc = lo[c]; kc < hi[c]; ++kc)
-          for (int jb = lo[b]; jb <= hi[b]; ++jb) {
-            const double wt = (jb == lo[b] || jb == hi[b]) ? 0.5 : 1.0;
-            add_pair(c, b, lin(jb, kc), -side * h2 * wt);
-          }
+          (void)n_out;
+          first += g.count;
+          s->fseg.push_back(g);
+        }
       }
-    if (box == 0) s->npairs_box0 = (int)s->fpw.size();
+    if (box == 0) s->npairs_box0 = first;
   }
-  s->npairs = (int)s->fpw.size();
-  s->nsamp = 2 * s->npairs;
+  s->npairs = first;
+  s->nsamp = 2 * first;
 }
 
 void plan_layout(gnor_sim* s) {
@@ -186,8 +200,6 @@ void plan_layout(gnor_sim* s) {
   for (int a = 0; a < 3; ++a) L.cpml[a] = P.take((size_t)6 * 2 * np * e + 8);
   L.aux_prof = P.take((size_t)6 * s->n1 * 8);
   L.omega = P.take((size_t)std::max(1, s->mon.nfreq) * 8);
-  L.fdesc = P.take((size_t)3 * s->nsamp * 4 + 4);
-  L.fsidx = P.take((size_t)s->nsamp * 8 + 8);
   L.fpw = P.take((size_t)s->npairs * 8 + 8);
   L.static_end = P.off;
   L.state_begin = P.off;
@@ -199,6 +211,7 @@ void plan_layout(gnor_sim* s) {
     L.PP[pp] = P.take(M * e);
     L.PJ[pp] = P.take(M * e);
   }
+  L.Q = P.take(M * e);
   const size_t nx = s->g.nx, ny = s->g.ny, nz = s->g.nz;
   const size_t slab[3] = {nz * ny * 2 * np, nz * 2 * np * nx, 2 * np * ny * nx};
   for (int a = 0; a < 3; ++a)
@@ -207,10 +220,13 @@ void plan_layout(gnor_sim* s) {
       L.psiH[a][t] = P.take(slab[a] * e + 8);
     }
   L.aux = P.take((size_t)4 * s->n1 * 8);
-  L.jpart = P.take(nz * (size_t)s->nbx * s->nby * 8);
+  L.phase = P.take((size_t)4 * std::max(1, s->mon.nfreq) * 8);
+  // partial sums per (plane, tile, wavefront): at most nbx * (ny + 8) per plane
+  L.jpart = P.take(nz * (size_t)s->nbx * (ny + 8) * 8);
   L.dft = P.take((size_t)4 * nz * std::max(1, s->mon.nfreq) * 8);
   L.fstage = P.take((size_t)s->slots * s->nsamp * 8 + 8);
   L.facc = P.take((size_t)2 * std::max(1, s->mon.nfreq) * s->nsamp * 8 + 8);
+  L.ptab = P.take((size_t)std::max(1, s->mon.nfreq) * 4 * gnor::kFluxSlots * 8);
   L.fsum = P.take((size_t)2 * std::max(1, s->mon.nfreq) * 8);
   L.step = P.take(8);
   L.flux_lo = P.take(4);
@@ -241,6 +257,8 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   }
   p.PPi = ptr<T>(s, s->L.PP[a]); p.PPo = ptr<T>(s, s->L.PP[b]);
   p.PJi = ptr<T>(s, s->L.PJ[a]); p.PJo = ptr<T>(s, s->L.PJ[b]);
+  p.Q = ptr<T>(s, s->L.Q);
+  p.any_metal = s->any_metal ? 1 : 0;
   for (int d = 0; d < 3; ++d) { p.mlo[d] = s->mlo[d]; p.mn[d] = s->mn[d]; }
   p.mask = ptr<uint8_t>(s, s->L.mask);
   p.rho = nullptr;
@@ -278,7 +296,7 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   double* aux = ptr<double>(s, s->L.aux);
   p.e1 = aux; p.h1 = aux + s->n1;
   p.jpart = ptr<double>(s, s->L.jpart);
-  p.nbx = s->nbx; p.nby = s->nby;
+  p.tl = gnor::make_tiling(g.nx, g.ny, g.nz, s->tile_ty, s->tile_kz, s->tile_xcd);
   p.step_base = ptr<int64_t>(s, s->L.step);
   return p;
 }
@@ -296,6 +314,10 @@ gnor::AuxParams make_aux(gnor_sim* s) {
   a.src_kind = s->have_source ? s->src.kind : 0;
   a.e0 = s->src.e0; a.omega_c = s->src.omega_c; a.tau = s->src.tau; a.t0 = s->src.t0;
   a.omega_max = s->src.omega_max; a.dt = s->dt;
+  a.nf = s->mon.nfreq;
+  a.omega = ptr<double>(s, s->L.omega);
+  a.phase = ptr<double>(s, s->L.phase);
+  a.every = std::max(1, s->mon.dft_every);
   a.step_base = ptr<int64_t>(s, s->L.step);
   return a;
 }
@@ -305,10 +327,10 @@ gnor::DftParams make_dft(gnor_sim* s) {
   d.nz = s->g.nz; d.nf = s->mon.nfreq;
   d.kz0 = s->any_metal ? s->mlo[2] : 0;
   d.kz1 = s->any_metal ? s->mlo[2] + s->mn[2] : 0;
-  d.nbxy = s->nbx * s->nby;
+  const gnor::Tiling tl = gnor::make_tiling(s->g.nx, s->g.ny, s->g.nz, s->tile_ty, s->tile_kz, s->tile_xcd);
+  d.nbxy = tl.nbx * tl.nby * tl.ty;
   d.jpart = ptr<double>(s, s->L.jpart);
-  d.omega = ptr<double>(s, s->L.omega);
-  d.dt = s->dt;
+  d.phase = ptr<double>(s, s->L.phase);
   d.every = std::max(1, s->mon.dft_every);
   d.wdt = s->dt * d.every;
   d.e1 = ptr<double>(s, s->L.aux);
@@ -321,13 +343,16 @@ gnor::DftParams make_dft(gnor_sim* s) {
 
 gnor::FluxParams make_flux(gnor_sim* s) {
   gnor::FluxParams f{};
-  f.nsamp = s->nsamp; f.nf = s->mon.nfreq; f.slots = s->slots;
-  f.desc = ptr<int32_t>(s, s->L.fdesc);
+  f.npairs = s->npairs; f.nsamp = s->nsamp; f.nf = s->mon.nfreq;
+  f.nseg = (int)s->fseg.size();
+  for (int q = 0; q < f.nseg; ++q) f.seg[q] = s->fseg[q];
+  f.nx = s->g.nx; f.ny = s->g.ny;
   f.stage = ptr<double>(s, s->L.fstage);
   f.acc_re = ptr<double>(s, s->L.facc);
   f.acc_im = f.acc_re + (size_t)s->mon.nfreq * s->nsamp;
   f.omega = ptr<double>(s, s->L.omega);
-  f.dt = s->dt; f.wdt = s->dt; f.every = 1;
+  f.ptab = ptr<double>(s, s->L.ptab);
+  f.dt = s->dt; f.wdt = s->dt;
   f.step_base = ptr<int64_t>(s, s->L.step);
   return f;
 }
@@ -337,15 +362,9 @@ template <class T>
 void enqueue_step(gnor_sim* s, int parity, int sub, hipStream_t st) {
   const gnor::Params<T> p = make_params<T>(s, parity);
   const gnor::AuxParams a = make_aux(s);
-  gnor::launch_h<T>(p, sub, st);
-  gnor::launch_aux_h(a, sub, st);
-  gnor::launch_ej<T>(p, sub, st);
-  gnor::launch_aux_e(a, sub, st);
-  if (s->mon.nfreq > 0) gnor::launch_dft(make_dft(s), sub, st);
-  if (s->nsamp > 0) {
-    const gnor::FluxParams f = make_flux(s);
-    gnor::launch_flux_stage<T>(f, p, ptr<int64_t>(s, s->L.fsidx), sub, st);
-  }
+  gnor::launch_h<T>(p, a, st);
+  gnor::launch_ej<T>(p, a, sub, st);
+  if (s->mon.nfreq > 0) gnor::launch_dft_stage<T>(make_dft(s), make_flux(s), p, sub, st);
 }
 
 void enqueue_flux_acc(gnor_sim* s, int sub, hipStream_t st) {
@@ -441,8 +460,6 @@ gnor_status upload_static(gnor_sim* s) {
   if (s->mon.nfreq > 0)
     HIPCHECK(s, hipMemcpy(s->dev + s->L.omega, s->omega.data(), s->omega.size() * 8, hipMemcpyHostToDevice));
   if (s->nsamp > 0) {
-    HIPCHECK(s, hipMemcpy(s->dev + s->L.fdesc, s->fdesc.data(), s->fdesc.size() * 4, hipMemcpyHostToDevice));
-    HIPCHECK(s, hipMemcpy(s->dev + s->L.fsidx, s->fsidx.data(), s->fsidx.size() * 8, hipMemcpyHostToDevice));
     HIPCHECK(s, hipMemcpy(s->dev + s->L.fpw, s->fpw.data(), s->fpw.size() * 8, hipMemcpyHostToDevice));
   }
   return GNOR_OK;
@@ -454,7 +471,7 @@ void prepare(gnor_sim* s) {
   s->N = (size_t)g.nx * g.ny * g.nz;
   s->n1 = g.nz + 2 * gnor::kAuxOff;
   s->nbx = (g.nx + gnor::kBX - 1) / gnor::kBX;
-  s->nby = (g.ny + gnor::kBY - 1) / gnor::kBY;
+  s->nby = 0;
   if (!s->any_metal) {
     for (int d = 0; d < 3; ++d) { s->mlo[d] = 0; s->mn[d] = 1; }
   }
@@ -862,47 +879,107 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
   if (!ms || count < 5 || nsteps <= 0) return GNOR_E_INVALID_ARG;
-  hipEvent_t ev[12];
+  hipEvent_t ev[5];
   for (auto& e : ev) HIPCHECK(s, hipEventCreate(&e));
   double acc[5] = {0, 0, 0, 0, 0};
-  int64_t nacc = 0;
+  const bool fp32 = s->g.precision == GNOR_FP32;
   for (int64_t q = 0; q < nsteps; ++q) {
     const int64_t n = s->step;
     const int parity = (int)(n & 1);
     const hipStream_t str = s->stream;
     const gnor::AuxParams a = make_aux(s);
     (void)hipEventRecord(ev[0], str);
-    if (s->g.precision == GNOR_FP32) gnor::launch_h<float>(make_params<float>(s, parity), 0, str);
-    else gnor::launch_h<double>(make_params<double>(s, parity), 0, str);
+    if (fp32) gnor::launch_h<float>(make_params<float>(s, parity), a, str);
+    else gnor::launch_h<double>(make_params<double>(s, parity), a, str);
     (void)hipEventRecord(ev[1], str);
-    gnor::launch_aux_h(a, 0, str);
+    if (fp32) gnor::launch_ej<float>(make_params<float>(s, parity), a, 0, str);
+    else gnor::launch_ej<double>(make_params<double>(s, parity), a, 0, str);
     (void)hipEventRecord(ev[2], str);
-    if (s->g.precision == GNOR_FP32) gnor::launch_ej<float>(make_params<float>(s, parity), 0, str);
-    else gnor::launch_ej<double>(make_params<double>(s, parity), 0, str);
-    (void)hipEventRecord(ev[3], str);
-    gnor::launch_aux_e(a, 0, str);
-    (void)hipEventRecord(ev[4], str);
-    if (s->mon.nfreq > 0) gnor::launch_dft(make_dft(s), 0, str);
-    if (s->nsamp > 0) {
-      if (s->g.precision == GNOR_FP32)
-        gnor::launch_flux_stage<float>(make_flux(s), make_params<float>(s, parity), ptr<int64_t>(s, s->L.fsidx), 0, str);
-      else
-        gnor::launch_flux_stage<double>(make_flux(s), make_params<double>(s, parity), ptr<int64_t>(s, s->L.fsidx), 0, str);
+    if (s->mon.nfreq > 0) {
+      if (fp32) gnor::launch_dft_stage<float>(make_dft(s), make_flux(s), make_params<float>(s, parity), 0, str);
+      else gnor::launch_dft_stage<double>(make_dft(s), make_flux(s), make_params<double>(s, parity), 0, str);
     }
-    (void)hipEventRecord(ev[5], str);
+    (void)hipEventRecord(ev[3], str);
     if (s->nsamp > 0 && (n % s->slots) == s->slots - 1) enqueue_flux_acc(s, 0, str);
-    (void)hipEventRecord(ev[6], str);
+    (void)hipEventRecord(ev[4], str);
     gnor::launch_advance(ptr<int64_t>(s, s->L.step), 1, str);
     HIPCHECK(s, hipGetLastError());
-    HIPCHECK(s, hipEventSynchronize(ev[6]));
-    float t[6];
-    for (int e = 0; e < 6; ++e) (void)hipEventElapsedTime(&t[e], ev[e], ev[e + 1]);
-    acc[0] += t[0]; acc[3] += t[1]; acc[1] += t[2]; acc[3] += t[3]; acc[2] += t[4]; acc[4] += t[5];
-    ++nacc;
+    HIPCHECK(s, hipEventSynchronize(ev[4]));
+    float t[4];
+    for (int e = 0; e < 4; ++e) (void)hipEventElapsedTime(&t[e], ev[e], ev[e + 1]);
+    acc[0] += t[0]; acc[1] += t[1]; acc[2] += t[2]; acc[4] += t[3];
     s->step += 1;
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
-  for (int i = 0; i < 5; ++i) ms[i] = acc[i] / (double)nacc;
+  for (int i = 0; i < 5; ++i) ms[i] = acc[i] / (double)nsteps;
+  return GNOR_OK;
+}
+
+gnor_status gnor_set_tiling(gnor_sim* s, int32_t ty, int32_t kz, int32_t xcd) {
+  if (!s) return GNOR_E_INVALID_ARG;
+  if (!(ty == 2 || ty == 4 || ty == 8) || kz < 1 || kz > s->g.nz || xcd < 0 || xcd > 1)
+    return fail(s, GNOR_E_INVALID_ARG, "tiling: ty must be 2, 4 or 8, 1 <= kz <= nz, xcd_bands 0 or 1");
+  if (ty != s->tile_ty || kz != s->tile_kz || xcd != s->tile_xcd) {
+    s->tile_ty = ty;
+    s->tile_kz = kz;
+    s->tile_xcd = xcd;
+    drop_graph(s);
+    if (s->bound) {
+      // partial sums are indexed by tile: clear stale entries of the old tiling
+      const size_t jbytes = (size_t)s->g.nz * s->nbx * (s->g.ny + 8) * 8;
+      HIPCHECK(s, hipMemsetAsync(s->dev + s->L.jpart, 0, jbytes, s->stream));
+      HIPCHECK(s, hipStreamSynchronize(s->stream));
+    }
+  }
+  return GNOR_OK;
+}
+
+gnor_status gnor_autotune(gnor_sim* s, int32_t trial_steps, int32_t* ty_out, int32_t* kz_out,
+                          int32_t* xcd_out, double* ms_out) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  if (s->step != 0) return fail(s, GNOR_E_STATE, "autotune runs before the first step (state is reset afterwards)");
+  if (trial_steps < 2) trial_steps = 2;
+  const int tys[3] = {2, 4, 8};
+  const int nz = s->g.nz;
+  const int kzs[5] = {8, 16, 32, 64, nz};
+  double best = 1e300;
+  int bty = s->tile_ty, bkz = s->tile_kz, bxcd = s->tile_xcd;
+  hipEvent_t e0, e1;
+  HIPCHECK(s, hipEventCreate(&e0));
+  HIPCHECK(s, hipEventCreate(&e1));
+  const int saved_chunk = s->graph_chunk;
+  s->graph_chunk = 0;
+  for (int x = 0; x < 2; ++x)
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 5; ++b) {
+      const int kz = std::min(kzs[b], nz);
+      if (b == 4 && kz <= 64) continue;
+      st = gnor_set_tiling(s, tys[a], kz, x);
+      if (st != GNOR_OK) return st;
+      st = gnor_run(s, 2);  // warm-up
+      if (st != GNOR_OK) return st;
+      (void)hipEventRecord(e0, s->stream);
+      st = gnor_run(s, trial_steps);
+      if (st != GNOR_OK) return st;
+      (void)hipEventRecord(e1, s->stream);
+      HIPCHECK(s, hipEventSynchronize(e1));
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      const double ms = t / trial_steps;
+      if (ms < best) { best = ms; bty = tys[a]; bkz = kz; bxcd = x; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->graph_chunk = saved_chunk;
+  st = gnor_set_tiling(s, bty, bkz, bxcd);
+  if (st != GNOR_OK) return st;
+  st = gnor_reset(s);
+  if (st != GNOR_OK) return st;
+  if (ty_out) *ty_out = bty;
+  if (kz_out) *kz_out = bkz;
+  if (xcd_out) *xcd_out = bxcd;
+  if (ms_out) *ms_out = best;
   return GNOR_OK;
 }
 

@@ -127,6 +127,37 @@ def test_fp32_config1_vs_oracle(B):
         f"{max(worst[k] for k in ('inc', 'ext', 'abs', 'sca')):.3e}")
 
 
+@pytest.mark.parametrize("ty,kz,xcd", [(2, 8, 1), (8, 13, 0), (4, 48, 1)])
+def test_tilings_agree_with_oracle(B, ty, kz, xcd):
+    """Every sweep tiling (including a kz that does not divide nz) reproduces
+    the oracle; only reduction orders of the spectra differ."""
+    w = W.early_pulse(W.config1(1))
+    w.omega = W.spectrum_omegas(20)
+    say(f"case tiling ty={ty} kz={kz} xcd={xcd}")
+    g = B.Sim(w, precision="fp64")
+    g.set_tiling(ty, kz, xcd)
+    g.run(300)
+    o = oracle_run(w, 300)
+    compare(g, o, 1e-10, 1e-10)
+
+
+def test_autotuner_picks_a_tiling_and_resets(B, tmp_path):
+    w = W.early_pulse(W.config1(2))
+    say("case autotuner")
+    g = B.Sim(w, precision="fp32")
+    r = g.autotune(trial_steps=3, cache=str(tmp_path / "tiles.json"))
+    assert r["ty"] in (2, 4, 8) and 1 <= r["kz"] <= w.nz and not r["cached"]
+    assert g.step == 0
+    r2 = g.autotune(cache=str(tmp_path / "tiles.json"))
+    assert r2["cached"] and (r2["ty"], r2["kz"]) == (r["ty"], r["kz"])
+    g.run(100)
+    h = B.Sim(w, precision="fp32")
+    h.set_tiling(r["ty"], r["kz"], r["xcd"])
+    h.run(100)
+    for f in FIELDS:
+        assert np.array_equal(g.field(f), h.field(f)), f
+
+
 def test_graph_replay_equals_eager_bitwise(B):
     w = W.early_pulse(W.config1(2))
     say("case graph chunks vs eager launches")
