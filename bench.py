@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--batch-steps", type=int, default=256,
+                    help="steps of the 64-instance batched sweep (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2 GiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -160,6 +162,25 @@ def main():
             err[k] = float(np.linalg.norm(spec32[k] - s64[k]) / den) if den > 0 else None
         out["fp32_vs_fp64_spectra_rel_l2"] = err
         del sim64
+        torch.cuda.empty_cache()
+    if args.batch_steps > 0:
+        from paper_2005_06997_amd import binding
+        ws = W.config4(seed=0, count=64)
+        sims = [binding.Sim(x, precision="fp32") for x in ws]
+        bt = binding.Batch(sims, tiling=(2, 8, 0))
+        bt.run(64)
+        bt.synchronize()
+        t0 = time.perf_counter()
+        bt.run(args.batch_steps)
+        bt.synchronize()
+        tb = time.perf_counter() - t0
+        out["batch"] = {"workload": "64 spheres / gap dimers, r 1-8 nm, grids 64^3-200^3, FP32, one "
+                                    "launch per phase over all instances",
+                        "value": round(bt.cells * args.batch_steps / tb / 1e9, 3),
+                        "unit": "Gcell-updates/s", "cells": bt.cells, "steps": args.batch_steps,
+                        "ms_per_step": round(tb / args.batch_steps * 1e3, 4)}
+        bt.close()
+        del sims
         torch.cuda.empty_cache()
     if not args.no_cpu:
         v, cores, secs = cpu_baseline(w, args.cpu_steps)

@@ -211,6 +211,21 @@ gnor_status gnor_voxelize_spheres(int32_t nx, int32_t ny, int32_t nz, double dx,
 gnor_status gnor_voxelize_star(int32_t nx, int32_t ny, int32_t nz, double dx, const double *desc,
                                int32_t desc_len, uint8_t *mask_out);
 
+/* Batches: n independent simulations (bound, same precision, same step
+ * index, same tile height) stepped in lockstep; every phase of a step is one
+ * launch over the tiles of all instances.  The batch enqueues on hip_stream
+ * (NULL: a stream of its own); call gnor_batch_synchronize before reading an
+ * instance.  Instances must not be stepped outside the batch while it is in
+ * use (GNOR_E_STATE).  The library allocates the batch's small parameter
+ * table (2 n records) with hipMalloc and frees it in gnor_batch_destroy.
+ * Results equal those of the instances run one by one. */
+gnor_status gnor_batch_create(int32_t n, gnor_sim *const *sims, void *hip_stream, gnor_batch **out);
+gnor_status gnor_batch_run(gnor_batch *batch, int64_t nsteps);
+gnor_status gnor_batch_synchronize(gnor_batch *batch);
+gnor_status gnor_batch_set_graph_chunk(gnor_batch *batch, int32_t steps);
+const char *gnor_batch_last_error(const gnor_batch *batch);
+void gnor_batch_destroy(gnor_batch *batch);
+
 const char *gnor_status_string(gnor_status s);
 const char *gnor_last_error(const gnor_sim *sim);
 

@@ -102,6 +102,12 @@ def load() -> C.CDLL:
         "gnor_autotune": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp]),
         "gnor_voxelize_spheres": (i32, [i32, i32, i32, dbl, i32, vp, vp]),
         "gnor_voxelize_star": (i32, [i32, i32, i32, dbl, vp, i32, vp]),
+        "gnor_batch_create": (i32, [i32, vp, vp, C.POINTER(vp)]),
+        "gnor_batch_run": (i32, [vp, i64]),
+        "gnor_batch_synchronize": (i32, [vp]),
+        "gnor_batch_set_graph_chunk": (i32, [vp, i32]),
+        "gnor_batch_last_error": (C.c_char_p, [vp]),
+        "gnor_batch_destroy": (None, [vp]),
         "gnor_status_string": (C.c_char_p, [i32]),
         "gnor_last_error": (C.c_char_p, [vp]),
     }
@@ -293,3 +299,45 @@ class Sim:
         except OSError:
             pass
         return dict(table[key], cached=False)
+
+
+class Batch:
+    """Independent simulations stepped in lockstep; each phase of a step is one
+    launch over the tiles of every instance (see gnor_batch_create)."""
+
+    def __init__(self, sims, tiling=(2, 8, 0), graph_chunk: int = 64):
+        L = load()
+        self.L = L
+        self.sims = list(sims)
+        for s in self.sims:
+            s.set_tiling(*tiling)
+        arr = (C.c_void_p * len(self.sims))(*[s.h.value for s in self.sims])
+        h = C.c_void_p()
+        st = L.gnor_batch_create(len(self.sims), arr, C.c_void_p(self.sims[0].stream.cuda_stream),
+                                 C.byref(h))
+        if st:
+            raise GnorError(st, "gnor_batch_create rejected the instances")
+        self.h = h
+        self._check(L.gnor_batch_set_graph_chunk(h, int(graph_chunk)))
+
+    def _check(self, st: int):
+        if st:
+            raise GnorError(st, self.L.gnor_batch_last_error(self.h).decode())
+
+    def run(self, nsteps: int):
+        self._check(self.L.gnor_batch_run(self.h, int(nsteps)))
+
+    def synchronize(self):
+        self._check(self.L.gnor_batch_synchronize(self.h))
+
+    @property
+    def cells(self) -> int:
+        return sum(s.w.cells for s in self.sims)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gnor_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -172,6 +172,30 @@ struct FluxParams {
   const int64_t* step_base;
 };
 
+// One instance of a batch: its parameters and its block ranges in the batched
+// sweep launches (hblk0 .. hblk0 + hnblk, tiles then the auxiliary-line block)
+// and in the batched spectra launch (dblk0 .. dblk0 + dnblk).
+template <class T>
+struct BatchEntry {
+  Params<T> p;
+  AuxParams a;
+  DftParams d;
+  FluxParams f;
+  int hblk0, hnblk;
+  int dblk0, dnblk;
+};
+
+template <class T>
+void launch_h_batch(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s);
+template <class T>
+void launch_ej_batch(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, hipStream_t s);
+template <class T>
+void launch_dft_batch(const BatchEntry<T>* e, int n, int blocks, int sub, hipStream_t s);
+template <class T>
+void launch_advance_batch(const BatchEntry<T>* e, int n, int64_t count, hipStream_t s);
+int sweep_blocks(const Tiling& t);
+int dft_blocks(const DftParams& d, const FluxParams& f);
+
 template <class T>
 void launch_h(const Params<T>& p, const AuxParams& a, hipStream_t s);
 template <class T>

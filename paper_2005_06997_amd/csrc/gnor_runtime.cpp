@@ -1057,3 +1057,199 @@ extern "C" gnor_status gnor_voxelize_star(int32_t nx, int32_t ny, int32_t nz, do
       }
   return GNOR_OK;
 }
+
+// ============================================================ batches
+// Many independent simulations stepped in lockstep: each phase of a step is
+// ONE launch over the tiles of every instance (block -> instance through a
+// device table of per-instance parameters, one table per ping-pong parity).
+struct gnor_batch {
+  std::vector<gnor_sim*> sims;
+  int n = 0;
+  bool fp32 = true;
+  int ty = 2;
+  char* tab = nullptr;       // two tables of n entries (parity 0, parity 1)
+  size_t entry_bytes = 0;
+  int hblocks = 0, dblocks = 0;
+  bool any_dft = false, any_flux = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipGraphExec_t graph = nullptr;
+  int graph_steps = 0, graph_chunk = 64;
+  int64_t step = 0;
+  std::string last_error;
+};
+
+namespace {
+
+gnor_status bfail(gnor_batch* b, gnor_status st, const std::string& m) {
+  if (b) b->last_error = m;
+  return st;
+}
+
+#define BHIPCHECK(b, call)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return bfail(b, GNOR_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+template <class T>
+gnor_status batch_tables(gnor_batch* b) {
+  std::vector<gnor::BatchEntry<T>> tab(2 * (size_t)b->n);
+  for (int parity = 0; parity < 2; ++parity) {
+    int h0 = 0, d0 = 0;
+    for (int q = 0; q < b->n; ++q) {
+      gnor_sim* s = b->sims[q];
+      gnor::BatchEntry<T>& e = tab[(size_t)parity * b->n + q];
+      e.p = make_params<T>(s, parity);
+      e.a = make_aux(s);
+      e.d = make_dft(s);
+      e.f = make_flux(s);
+      e.hblk0 = h0;
+      e.hnblk = gnor::sweep_blocks(e.p.tl);
+      h0 += e.hnblk;
+      e.dblk0 = d0;
+      e.dnblk = s->mon.nfreq > 0 ? gnor::dft_blocks(e.d, e.f) : 0;
+      d0 += e.dnblk;
+    }
+    b->hblocks = h0;
+    b->dblocks = d0;
+  }
+  b->entry_bytes = sizeof(gnor::BatchEntry<T>);
+  BHIPCHECK(b, hipMalloc(&b->tab, tab.size() * b->entry_bytes));
+  BHIPCHECK(b, hipMemcpy(b->tab, tab.data(), tab.size() * b->entry_bytes, hipMemcpyHostToDevice));
+  return GNOR_OK;
+}
+
+template <class T>
+void batch_enqueue(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st) {
+  const gnor::BatchEntry<T>* tabs = reinterpret_cast<const gnor::BatchEntry<T>*>(b->tab);
+  for (int64_t q = 0; q < count; ++q) {
+    const int64_t n = n0 + q;
+    const gnor::BatchEntry<T>* t = tabs + (size_t)(n & 1) * b->n;
+    const int sub = (int)q;
+    gnor::launch_h_batch<T>(t, b->n, b->hblocks, b->ty, st);
+    gnor::launch_ej_batch<T>(t, b->n, b->hblocks, b->ty, sub, st);
+    if (b->any_dft && b->dblocks > 0) gnor::launch_dft_batch<T>(t, b->n, b->dblocks, sub, st);
+    if (b->any_flux && (n % gnor::kFluxSlots) == gnor::kFluxSlots - 1)
+      for (gnor_sim* s : b->sims)
+        if (s->nsamp > 0) enqueue_flux_acc(s, sub, st);
+  }
+  gnor::launch_advance_batch<T>(tabs, b->n, count, st);
+}
+
+void batch_enqueue_any(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st) {
+  if (b->fp32) batch_enqueue<float>(b, n0, count, st);
+  else batch_enqueue<double>(b, n0, count, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, gnor_batch** out) {
+  if (!out || n < 1 || !sims) return GNOR_E_INVALID_ARG;
+  *out = nullptr;
+  gnor_batch* b = new (std::nothrow) gnor_batch();
+  if (!b) return GNOR_E_OUT_OF_MEMORY;
+  b->n = n;
+  for (int q = 0; q < n; ++q) {
+    gnor_sim* s = sims[q];
+    if (!s || !s->bound) { delete b; return GNOR_E_STATE; }
+    if (q > 0 && (s->g.precision != sims[0]->g.precision || s->step != sims[0]->step ||
+                  s->tile_ty != sims[0]->tile_ty)) {
+      delete b;
+      return GNOR_E_INVALID_ARG;  // one precision, one step index, one tile height
+    }
+    for (int r = 0; r < q; ++r)
+      if (sims[r] == s) { delete b; return GNOR_E_INVALID_ARG; }
+    b->sims.push_back(s);
+    b->any_dft = b->any_dft || s->mon.nfreq > 0;
+    b->any_flux = b->any_flux || s->nsamp > 0;
+  }
+  b->fp32 = sims[0]->g.precision == GNOR_FP32;
+  b->ty = sims[0]->tile_ty;
+  b->step = sims[0]->step;
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  if (!b->stream) {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) { delete b; return GNOR_E_DEVICE; }
+    b->own_stream = true;
+  }
+  // the instances' own queued work must be complete before the batch runs
+  for (gnor_sim* s : b->sims)
+    if (hipStreamSynchronize(s->stream) != hipSuccess) { delete b; return GNOR_E_DEVICE; }
+  const gnor_status st = b->fp32 ? batch_tables<float>(b) : batch_tables<double>(b);
+  if (st != GNOR_OK) { gnor_batch_destroy(b); return st; }
+  *out = b;
+  return GNOR_OK;
+}
+
+void gnor_batch_destroy(gnor_batch* b) {
+  if (!b) return;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->tab) (void)hipFree(b->tab);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+gnor_status gnor_batch_set_graph_chunk(gnor_batch* b, int32_t steps) {
+  if (!b || steps < 0 || (steps & 1)) return GNOR_E_INVALID_ARG;
+  b->graph_chunk = steps;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_steps = 0;
+  return GNOR_OK;
+}
+
+gnor_status gnor_batch_run(gnor_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return GNOR_E_INVALID_ARG;
+  for (gnor_sim* s : b->sims)
+    if (s->step != b->step) return bfail(b, GNOR_E_STATE, "an instance was stepped outside the batch");
+  const int align = b->any_flux ? gnor::kFluxSlots : 2;
+  int chunk = b->graph_chunk > 0 ? std::max(align, b->graph_chunk / align * align) : 0;
+  int64_t left = nsteps;
+  while (left > 0) {
+    if (chunk > 0 && (b->step % align) == 0 && left >= chunk) {
+      if (!b->graph || b->graph_steps != chunk) {
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        hipGraph_t gr = nullptr;
+        BHIPCHECK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        batch_enqueue_any(b, 0, chunk, b->stream);
+        BHIPCHECK(b, hipStreamEndCapture(b->stream, &gr));
+        const hipError_t e = hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) {
+          b->graph = nullptr;
+          return bfail(b, GNOR_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        b->graph_steps = chunk;
+      }
+      BHIPCHECK(b, hipGraphLaunch(b->graph, b->stream));
+      b->step += chunk;
+      left -= chunk;
+    } else {
+      int64_t m = left;
+      if (chunk > 0) {
+        const int64_t to_align = (align - (b->step % align)) % align;
+        m = to_align > 0 ? std::min(left, to_align) : left;
+      }
+      batch_enqueue_any(b, b->step, m, b->stream);
+      BHIPCHECK(b, hipGetLastError());
+      b->step += m;
+      left -= m;
+    }
+  }
+  for (gnor_sim* s : b->sims) s->step = b->step;
+  return GNOR_OK;
+}
+
+gnor_status gnor_batch_synchronize(gnor_batch* b) {
+  if (!b) return GNOR_E_INVALID_ARG;
+  BHIPCHECK(b, hipStreamSynchronize(b->stream));
+  return GNOR_OK;
+}
+
+const char* gnor_batch_last_error(const gnor_batch* b) { return b ? b->last_error.c_str() : "null batch"; }
+
+}  // extern "C"

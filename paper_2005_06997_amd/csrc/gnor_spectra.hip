@@ -19,11 +19,13 @@ namespace gnor {
 
 namespace {
 
+// Block blk of the spectra launch of one simulation.
 template <class T>
-__global__ void __launch_bounds__(256) k_dft(DftParams d, FluxParams f, Params<T> p, int sub) {
+__device__ __forceinline__ void dft_block(const DftParams& d, const FluxParams& f, const Params<T>& p,
+                                          int sub, int blk) {
   const int64_t n = d.step_base[0] + sub;
-  if ((int)blockIdx.x < d.nz) {
-    const int k = blockIdx.x;
+  if (blk < d.nz) {
+    const int k = blk;
     if (d.nf == 0 || (d.every > 1 && (n % d.every) != 0)) return;
     __shared__ double red[256];
     const bool has_j = k >= d.kz0 && k < d.kz1;
@@ -53,7 +55,7 @@ __global__ void __launch_bounds__(256) k_dft(DftParams d, FluxParams f, Params<T
     return;
   }
   // flux staging: pair q -> (segment, face point)
-  const int q = (blockIdx.x - d.nz) * 256 + threadIdx.x;
+  const int q = (blk - d.nz) * 256 + threadIdx.x;
   if (q >= f.npairs) return;
   int sgi = 0;
   while (sgi + 1 < f.nseg && q >= f.seg[sgi + 1].first) ++sgi;
@@ -73,8 +75,32 @@ __global__ void __launch_bounds__(256) k_dft(DftParams d, FluxParams f, Params<T
   f.stage[(size_t)slot * f.nsamp + f.npairs + q] = h;
 }
 
+template <class T>
+__global__ void __launch_bounds__(256) k_dft(DftParams d, FluxParams f, Params<T> p, int sub) {
+  dft_block<T>(d, f, p, sub, blockIdx.x);
+}
+
+// Batch: instance q owns blocks [dblk0, dblk0 + dnblk) of the launch.
+template <class T>
+__global__ void __launch_bounds__(256) k_dft_batch(const BatchEntry<T>* __restrict__ e, int n, int sub) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (e[mid].dblk0 <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchEntry<T>& en = e[lo];
+  dft_block<T>(en.d, en.f, en.p, sub, blockIdx.x - en.dblk0);
+}
+
 __global__ void k_advance(int64_t* base, int64_t count) {
   if (threadIdx.x == 0 && blockIdx.x == 0) base[0] += count;
+}
+
+template <class T>
+__global__ void k_advance_batch(const BatchEntry<T>* __restrict__ e, int n, int64_t count) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) const_cast<int64_t*>(e[q].p.step_base)[0] += count;
 }
 
 // ptab[m][kind][cos|sin][b] = wdt e^{i w_m t_b}; slot b of the window holds
@@ -168,12 +194,25 @@ __global__ void __launch_bounds__(256) k_nonfinite(const T* a, size_t n, int* fl
 
 }  // namespace
 
+int dft_blocks(const DftParams& d, const FluxParams& f) { return d.nz + (f.npairs + 255) / 256; }
+
 template <class T>
 void launch_dft_stage(const DftParams& d, const FluxParams& f, const Params<T>& p, int sub,
                       hipStream_t s) {
-  const int blocks = d.nz + (f.npairs + 255) / 256;
-  hipLaunchKernelGGL(k_dft<T>, dim3(blocks), dim3(256), 0, s, d, f, p, sub);
+  hipLaunchKernelGGL(k_dft<T>, dim3(dft_blocks(d, f)), dim3(256), 0, s, d, f, p, sub);
 }
+template <class T>
+void launch_dft_batch(const BatchEntry<T>* e, int n, int blocks, int sub, hipStream_t s) {
+  hipLaunchKernelGGL(k_dft_batch<T>, dim3(blocks), dim3(256), 0, s, e, n, sub);
+}
+template <class T>
+void launch_advance_batch(const BatchEntry<T>* e, int n, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance_batch<T>, dim3((n + 63) / 64), dim3(64), 0, s, e, n, count);
+}
+template void launch_dft_batch<float>(const BatchEntry<float>*, int, int, int, hipStream_t);
+template void launch_dft_batch<double>(const BatchEntry<double>*, int, int, int, hipStream_t);
+template void launch_advance_batch<float>(const BatchEntry<float>*, int, int64_t, hipStream_t);
+template void launch_advance_batch<double>(const BatchEntry<double>*, int, int64_t, hipStream_t);
 void launch_advance(int64_t* base, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, base, count);
 }

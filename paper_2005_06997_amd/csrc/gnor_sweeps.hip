@@ -122,14 +122,10 @@ struct HIn {
   T jx, jy, jz, jxm, jym, pp, pj;                  // node scalars' inputs at k
 };
 
+// One tile of the H sweep (blk: the block's index among the tiles).
 template <class T, int TY>
-__global__ void __launch_bounds__(kBX* TY) k_h(Params<T> p, AuxParams a) {
-  const int tid = threadIdx.y * kBX + threadIdx.x;
-  if ((int)blockIdx.x == (int)gridDim.x - 1) {
-    aux_h_block(a, tid, kBX * TY);
-    return;
-  }
-  const Tile tile = decode_tile(p.tl, blockIdx.x);
+__device__ __forceinline__ void h_tile(const Params<T>& p, int blk) {
+  const Tile tile = decode_tile(p.tl, blk);
   if (!tile.ok) return;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int i = tile.bx * kBX + threadIdx.x;
@@ -255,15 +251,11 @@ struct EIn {
   uint8_t mb;
 };
 
+// One tile of the E/J sweep.
 template <class T, int TY>
-__global__ void __launch_bounds__(kBX* TY) k_ej(Params<T> p, AuxParams a, int sub) {
+__device__ __forceinline__ void ej_tile(const Params<T>& p, int blk) {
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int tid = ty * kBX + tx;
-  if ((int)blockIdx.x == (int)gridDim.x - 1) {
-    aux_e_block(a, sub, tid, kBX * TY);
-    return;
-  }
-  const Tile tile = decode_tile(p.tl, blockIdx.x);
+  const Tile tile = decode_tile(p.tl, blk);
   if (!tile.ok) return;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int i = tile.bx * kBX + tx;
@@ -430,6 +422,64 @@ __global__ void __launch_bounds__(kBX* TY) k_ej(Params<T> p, AuxParams a, int su
   }
 }
 
+// ---------------------------------------------------------------- kernels
+// Single simulation: tiles, then the auxiliary-line block last.
+template <class T, int TY>
+__global__ void __launch_bounds__(kBX* TY) k_h(Params<T> p, AuxParams a) {
+  if ((int)blockIdx.x == (int)gridDim.x - 1) {
+    aux_h_block(a, threadIdx.y * kBX + threadIdx.x, kBX * TY);
+    return;
+  }
+  h_tile<T, TY>(p, blockIdx.x);
+}
+
+template <class T, int TY>
+__global__ void __launch_bounds__(kBX* TY) k_ej(Params<T> p, AuxParams a, int sub) {
+  if ((int)blockIdx.x == (int)gridDim.x - 1) {
+    aux_e_block(a, sub, threadIdx.y * kBX + threadIdx.x, kBX * TY);
+    return;
+  }
+  ej_tile<T, TY>(p, blockIdx.x);
+}
+
+// Batch: the blocks of all instances in one launch.  Instance q owns blocks
+// [blk0, blk0 + nblk) (its tiles, then its auxiliary-line block); a block
+// finds its instance by binary search over the table.
+template <class T>
+__device__ __forceinline__ int find_instance(const BatchEntry<T>* __restrict__ e, int n, int b,
+                                             bool dft) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((dft ? e[mid].dblk0 : e[mid].hblk0) <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class T, int TY>
+__global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __restrict__ e, int n) {
+  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, false)];
+  const int b = blockIdx.x - en.hblk0;
+  if (b == en.hnblk - 1) {
+    aux_h_block(en.a, threadIdx.y * kBX + threadIdx.x, kBX * TY);
+    return;
+  }
+  h_tile<T, TY>(en.p, b);
+}
+
+template <class T, int TY>
+__global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __restrict__ e, int n,
+                                                      int sub) {
+  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, false)];
+  const int b = blockIdx.x - en.hblk0;
+  if (b == en.hnblk - 1) {
+    aux_e_block(en.a, sub, threadIdx.y * kBX + threadIdx.x, kBX * TY);
+    return;
+  }
+  ej_tile<T, TY>(en.p, b);
+}
+
 }  // namespace
 
 Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd) {
@@ -464,6 +514,23 @@ void launch_ej(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s) {
   else if (p.tl.ty == 8) hipLaunchKernelGGL((k_ej<T, 8>), dim3(blocks), dim3(kBX, 8), 0, s, p, a, sub);
   else hipLaunchKernelGGL((k_ej<T, 2>), dim3(blocks), dim3(kBX, 2), 0, s, p, a, sub);
 }
+
+template <class T>
+void launch_h_batch(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s) {
+  if (ty == 4) hipLaunchKernelGGL((k_h_batch<T, 4>), dim3(blocks), dim3(kBX, 4), 0, s, e, n);
+  else if (ty == 8) hipLaunchKernelGGL((k_h_batch<T, 8>), dim3(blocks), dim3(kBX, 8), 0, s, e, n);
+  else hipLaunchKernelGGL((k_h_batch<T, 2>), dim3(blocks), dim3(kBX, 2), 0, s, e, n);
+}
+template <class T>
+void launch_ej_batch(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, hipStream_t s) {
+  if (ty == 4) hipLaunchKernelGGL((k_ej_batch<T, 4>), dim3(blocks), dim3(kBX, 4), 0, s, e, n, sub);
+  else if (ty == 8) hipLaunchKernelGGL((k_ej_batch<T, 8>), dim3(blocks), dim3(kBX, 8), 0, s, e, n, sub);
+  else hipLaunchKernelGGL((k_ej_batch<T, 2>), dim3(blocks), dim3(kBX, 2), 0, s, e, n, sub);
+}
+template void launch_h_batch<float>(const BatchEntry<float>*, int, int, int, hipStream_t);
+template void launch_h_batch<double>(const BatchEntry<double>*, int, int, int, hipStream_t);
+template void launch_ej_batch<float>(const BatchEntry<float>*, int, int, int, int, hipStream_t);
+template void launch_ej_batch<double>(const BatchEntry<double>*, int, int, int, int, hipStream_t);
 
 template void launch_h<float>(const Params<float>&, const AuxParams&, hipStream_t);
 template void launch_h<double>(const Params<double>&, const AuxParams&, hipStream_t);

@@ -1,0 +1,84 @@
+"""Batched launches over many instances (spheres and gap dimers of uneven
+grid sizes, per-instance beta and D) reproduce the instances run one by one
+bit for bit, and the batch reproduces the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2005_06997_amd import workloads as W
+from tests.helpers import oracle_mask, oracle_problem, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "Jx", "Jy", "Jz")
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2005_06997_amd import binding
+    return binding
+
+
+def instances(count=5, seed=0):
+    ws = [W.early_pulse(w) for w in W.config4(seed=seed, count=count)]
+    for q, w in enumerate(ws):
+        w.omega = W.spectrum_omegas(12 + 4 * q)  # uneven frequency counts
+        w.flux = (q % 2 == 1)
+    return ws
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_equals_individual_runs_bitwise(B, prec):
+    ws = instances()
+    print(f"case batch {prec}: sizes {[w.nx for w in ws]}", flush=True)
+    steps = 131  # odd: eager steps around graph chunks
+    solo = []
+    for w in ws:
+        s = B.Sim(w, precision=prec)
+        s.set_tiling(2, 8, 0)
+        s.run(steps)
+        solo.append(({f: s.field(f) for f in FIELDS}, s.spectra()))
+        s.close()
+    sims = [B.Sim(w, precision=prec) for w in ws]
+    bt = B.Batch(sims, tiling=(2, 8, 0))
+    bt.run(steps)
+    bt.synchronize()
+    for (fields, spec), s in zip(solo, sims):
+        assert s.step == steps
+        for f in FIELDS:
+            assert np.array_equal(s.field(f), fields[f]), (s.w.name, f)
+        sp = s.spectra()
+        for k in spec:
+            assert np.array_equal(sp[k], spec[k]), (s.w.name, k)
+
+
+def test_batch_instance_vs_oracle(B):
+    ws = instances(count=3, seed=1)
+    print("case batch fp64 vs oracle", flush=True)
+    sims = [B.Sim(w, precision="fp64") for w in ws]
+    bt = B.Batch(sims)
+    bt.run(120)
+    bt.synchronize()
+    w, s = ws[0], sims[0]
+    o = orc.OracleSim(oracle_problem(w, threads=8), oracle_mask(w))
+    o.run(120)
+    for f in ("Ex", "Hy", "Jx", "Jz"):
+        assert rel_l2(s.field(f), o.get(f)) <= 1e-10, f
+    assert rel_l2(s.spectra()["ext"], o.spectra()["ext"]) <= 1e-10
+
+
+def test_batch_rejects_mixed_precision_and_foreign_steps(B):
+    ws = instances(count=2)
+    a = B.Sim(ws[0], precision="fp32")
+    b = B.Sim(ws[1], precision="fp64")
+    with pytest.raises(B.GnorError):
+        B.Batch([a, b])
+    c = B.Sim(ws[1], precision="fp32")
+    bt = B.Batch([a, c])
+    bt.run(4)
+    bt.synchronize()
+    a.run(2)  # stepped outside the batch
+    with pytest.raises(B.GnorError):
+        bt.run(2)
