@@ -211,6 +211,27 @@ gnor_status gnor_voxelize_spheres(int32_t nx, int32_t ny, int32_t nz, double dx,
 gnor_status gnor_voxelize_star(int32_t nx, int32_t ny, int32_t nz, double dx, const double *desc,
                                int32_t desc_len, uint8_t *mask_out);
 
+/* Design region for gradients: cells [lo, hi) (node indices, x fastest) whose
+ * three P components are all treated as metal with per-cell density rho in
+ * [0, 1] scaling wp^2, beta^2 and D (gamma unchanged; rho = 0 leaves P = 0).
+ * The region replaces any fixed metal inside it and must lie 2 cells inside
+ * the TF box.  Call after gnor_set_material, before gnor_bind_memory;
+ * rho holds prod(hi - lo) floats.  gnor_update_design replaces the
+ * densities of a bound simulation (the state is not reset). */
+gnor_status gnor_set_design(gnor_sim *sim, const int32_t lo[3], const int32_t hi[3], const float *rho);
+gnor_status gnor_update_design(gnor_sim *sim, const float *rho);
+
+/* Objective sigma_ext(omega[m_target]) (as gnor_get_spectra) of nsteps steps
+ * from rest, and its exact discrete-adjoint gradient with respect to the
+ * design densities (grad: prod(hi - lo) doubles, x fastest).  Forward pass
+ * with a full-state checkpoint every ckpt_every steps; backward pass segment
+ * by segment with recomputation.  Needs dft_every = 1 and eps_inf =
+ * eps_background.  Allocates its workspace with hipMalloc (checkpoints,
+ * adjoint fields, per-segment design-region history) and frees it before
+ * returning; the simulation state afterwards is unspecified (gnor_reset). */
+gnor_status gnor_gradient(gnor_sim *sim, int64_t nsteps, int32_t ckpt_every, int32_t m_target,
+                          double *objective, double *grad);
+
 /* Batches: n independent simulations (bound, same precision, same step
  * index, same tile height) stepped in lockstep; every phase of a step is one
  * launch over the tiles of all instances.  The batch enqueues on hip_stream

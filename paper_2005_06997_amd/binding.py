@@ -102,6 +102,9 @@ def load() -> C.CDLL:
         "gnor_autotune": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp]),
         "gnor_voxelize_spheres": (i32, [i32, i32, i32, dbl, i32, vp, vp]),
         "gnor_voxelize_star": (i32, [i32, i32, i32, dbl, vp, i32, vp]),
+        "gnor_set_design": (i32, [vp, C.POINTER(i32), C.POINTER(i32), vp]),
+        "gnor_update_design": (i32, [vp, vp]),
+        "gnor_gradient": (i32, [vp, i64, i32, i32, dp, dp]),
         "gnor_batch_create": (i32, [i32, vp, vp, C.POINTER(vp)]),
         "gnor_batch_run": (i32, [vp, i64]),
         "gnor_batch_synchronize": (i32, [vp]),
@@ -167,6 +170,14 @@ class Sim:
         self.mask = voxelize(w) if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         mat = MaterialDesc(wp=w.wp, gamma=w.gamma, beta=w.beta, diffusion=w.diff, eps_inf=w.eps_inf)
         self._check(self.L.gnor_set_material(h, self.mask.ctypes.data, C.byref(mat)))
+        self.design_shape = None
+        if getattr(w, "design_lo", None) is not None:
+            lo = (C.c_int32 * 3)(*w.design_lo)
+            hi = (C.c_int32 * 3)(*w.design_hi)
+            rho = np.ascontiguousarray(w.rho, dtype=np.float32)
+            self.design_shape = tuple(int(b - a) for a, b in zip(w.design_lo[::-1], w.design_hi[::-1]))
+            assert rho.shape == self.design_shape, (rho.shape, self.design_shape)
+            self._check(self.L.gnor_set_design(h, lo, hi, rho.ctypes.data))
         src = SourceDesc(kind=w.src_kind, e0=w.e0, omega_c=w.omega_c, tau=w.tau, t0=w.t0,
                          omega_max=w.omega_max)
         self._check(self.L.gnor_set_source(h, C.byref(src)))
@@ -268,6 +279,20 @@ class Sim:
         self._check(self.L.gnor_profile_kernels(self.h, int(nsteps), _dp(ms), 5))
         return dict(h=ms[0], ej=ms[1], dft=ms[2], flux_acc=ms[4])
 
+    def update_design(self, rho):
+        """New design densities (z, y, x) in [0, 1]; the state is not reset."""
+        r = np.ascontiguousarray(rho, dtype=np.float32).reshape(self.design_shape)
+        self._check(self.L.gnor_update_design(self.h, r.ctypes.data))
+
+    def gradient(self, nsteps: int, ckpt_every: int, m_target: int):
+        """sigma_ext(omega[m_target]) of nsteps steps from rest and its exact
+        adjoint gradient w.r.t. the design densities, shape (z, y, x)."""
+        g = np.empty(self.design_shape, np.float64)
+        obj = C.c_double()
+        self._check(self.L.gnor_gradient(self.h, int(nsteps), int(ckpt_every), int(m_target),
+                                         C.byref(obj), _dp(g)))
+        return obj.value, g
+
     def set_tiling(self, ty: int, kz: int, xcd: int = 0):
         self._check(self.L.gnor_set_tiling(self.h, int(ty), int(kz), int(xcd)))
 
@@ -341,3 +366,24 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+def extinction_objective():
+    """A torch.autograd.Function: sigma_ext at one frequency as a function of
+    the design density tensor, differentiated by the library's adjoint."""
+    import torch
+
+    class ExtinctionObjective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, rho, sim, nsteps, ckpt_every, m_target):
+            sim.update_design(rho.detach().to("cpu", torch.float32).numpy())
+            obj, grad = sim.gradient(nsteps, ckpt_every, m_target)
+            ctx.save_for_backward(torch.from_numpy(grad).to(device=rho.device, dtype=rho.dtype))
+            return rho.new_tensor(obj)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (g,) = ctx.saved_tensors
+            return gout * g, None, None, None, None
+
+    return ExtinctionObjective

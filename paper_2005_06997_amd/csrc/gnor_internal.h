@@ -172,6 +172,42 @@ struct FluxParams {
   const int64_t* step_base;
 };
 
+// Adjoint state and workspace (all device pointers).
+template <class T>
+struct AdjParams {
+  Params<T> p;             // forward coefficients, masks, CPML profiles, Q
+  T* Eb[3];                // adjoint of E (full grid)
+  T* Hb[3];                // adjoint of H
+  T* Ob[3];                // adjoint of E^{n-1} at metal points (sub-grid)
+  T* Jb[3];                // adjoint of J (sub-grid)
+  T* PPb;                  // adjoints of the node scalars (sub-grid)
+  T* PJb;
+  T* phiJb;                // workspace: adjoint of Phi_J' of the step
+  T* dQb[3];               // workspace: adjoints of dQ_c at metal points
+  T* D[6];                 // workspace: adjoints of raw differences, [2 c + term]
+  T* psiEb[3][2];          // adjoint CPML memory
+  T* psiHb[3][2];
+  // design region (cells [dlo, dlo + dn)) and stored forward values
+  int dlo[3], dn[3];
+  const T* fE;             // [level][3][Nd] E at levels n0-1 .. n1 of a segment
+  const T* fdQ;            // [step][3][Nd] dQ_c of each step of the segment
+  int lev_base;            // level of E^n for the step being transposed
+  int t_idx;               // index of that step within the segment
+  double* grad;            // [Nd] d objective / d rho
+  // objective: sigma_ext(omega) = sum_n sum_k w_n(k) (plane sum of J~_x)
+  double dt, omega, CL;
+  const double* Bre;       // [nz] incident transform at omega
+  const double* Bim;
+};
+
+template <class T>
+void launch_adjoint_step(const AdjParams<T>& A, int64_t n_prev, hipStream_t s);
+template <class T>
+void launch_adjoint_source(const AdjParams<T>& A, int64_t n, hipStream_t s);
+template <class T>
+void launch_store_design(const AdjParams<T>& A, int store_e_only, const T* Ex, const T* Ey,
+                         const T* Ez, int lev, hipStream_t s);
+
 // One instance of a batch: its parameters and its block ranges in the batched
 // sweep launches (hblk0 .. hblk0 + hnblk, tiles then the auxiliary-line block)
 // and in the batched spectra launch (dblk0 .. dblk0 + dnblk).

@@ -75,6 +75,10 @@ struct gnor_sim {
   std::vector<uint8_t> mask;     // full grid
   int mlo[3] = {0, 0, 0}, mn[3] = {0, 0, 0};  // metal sub-grid (with halo)
   bool any_metal = false;
+  // design region [dlo, dhi) of cells with densities rho (x fastest)
+  bool design = false;
+  int dlo[3] = {0, 0, 0}, dhi[3] = {0, 0, 0};
+  std::vector<float> rho;
   size_t N = 0, M = 0;
   int elem = 8;                  // bytes per field value
   double dt = 0;
@@ -261,7 +265,7 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   p.any_metal = s->any_metal ? 1 : 0;
   for (int d = 0; d < 3; ++d) { p.mlo[d] = s->mlo[d]; p.mn[d] = s->mn[d]; }
   p.mask = ptr<uint8_t>(s, s->L.mask);
-  p.rho = nullptr;
+  p.rho = s->design ? ptr<float>(s, s->L.rho) : nullptr;
   // metal coefficients (Sec. III), scaled by eps0 and dx^2
   const double dt = s->dt, dx = g.dx;
   const double gam = s->mat.gamma, wp = s->mat.wp, beta = s->mat.beta, D = s->mat.diffusion;
@@ -416,6 +420,22 @@ gnor_status check_ready(gnor_sim* s) {
   return GNOR_OK;
 }
 
+// Per-cell weight of the metal's wp^2, beta^2 and D on the sub-grid: rho in
+// the design region, 1 elsewhere.
+gnor_status upload_rho(gnor_sim* s) {
+  std::vector<float> r(s->M, 1.0f);
+  const int dn[3] = {s->dhi[0] - s->dlo[0], s->dhi[1] - s->dlo[1], s->dhi[2] - s->dlo[2]};
+  for (int z = 0; z < dn[2]; ++z)
+    for (int y = 0; y < dn[1]; ++y)
+      for (int x = 0; x < dn[0]; ++x) {
+        const int lx = x + s->dlo[0] - s->mlo[0], ly = y + s->dlo[1] - s->mlo[1],
+                  lz = z + s->dlo[2] - s->mlo[2];
+        r[((size_t)lz * s->mn[1] + ly) * s->mn[0] + lx] = s->rho[((size_t)z * dn[1] + y) * dn[0] + x];
+      }
+  HIPCHECK(s, hipMemcpy(s->dev + s->L.rho, r.data(), r.size() * 4, hipMemcpyHostToDevice));
+  return GNOR_OK;
+}
+
 gnor_status upload_static(gnor_sim* s) {
   const gnor_grid_desc& g = s->g;
   // metal sub-grid mask
@@ -427,6 +447,10 @@ gnor_status upload_static(gnor_sim* s) {
         sub[((size_t)z * s->mn[1] + y) * s->mn[0] + x] = s->any_metal ? s->mask[gi] : 0;
       }
   HIPCHECK(s, hipMemcpy(s->dev + s->L.mask, sub.data(), s->M, hipMemcpyHostToDevice));
+  if (s->design) {
+    const gnor_status st = upload_rho(s);
+    if (st != GNOR_OK) return st;
+  }
   // CPML profiles per axis: be, ae, ke, bh, ah, kh over the 2 npml slab cells
   const int np = g.npml;
   const int nn[3] = {g.nx, g.ny, g.nz};
@@ -568,7 +592,53 @@ gnor_status gnor_set_material(gnor_sim* s, const uint8_t* mask, const gnor_mater
     for (int d = 0; d < 3; ++d) { s->mlo[d] = lo[d] - 1; s->mn[d] = hi[d] - lo[d] + 3; }
   s->mat = *m;
   s->have_material = true;
+  s->design = false;
   return GNOR_OK;
+}
+
+gnor_status gnor_set_design(gnor_sim* s, const int32_t* lo, const int32_t* hi, const float* rho) {
+  if (!s || !lo || !hi || !rho) return GNOR_E_INVALID_ARG;
+  if (!s->have_material) return fail(s, GNOR_E_STATE, "gnor_set_material must come first");
+  if (s->bound) return fail(s, GNOR_E_STATE, "the design region must be set before gnor_bind_memory");
+  const gnor_grid_desc& g = s->g;
+  size_t nd = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (hi[d] <= lo[d] || lo[d] < g.tf_lo[d] + 2 || hi[d] - 1 > g.tf_hi[d] - 2)
+      return fail(s, GNOR_E_INVALID_ARG,
+                  "design region must be non-empty and lie 2 cells inside the TF box");
+    nd *= (size_t)(hi[d] - lo[d]);
+  }
+  for (size_t q = 0; q < nd; ++q)
+    if (!(rho[q] >= 0.0f && rho[q] <= 1.0f)) return fail(s, GNOR_E_INVALID_ARG, "rho must lie in [0, 1]");
+  int mlo[3], mhi[3];
+  for (int d = 0; d < 3; ++d) {
+    mlo[d] = s->any_metal ? std::min(s->mlo[d] + 1, lo[d]) : lo[d];
+    mhi[d] = s->any_metal ? std::max(s->mlo[d] + s->mn[d] - 2, hi[d] - 1) : hi[d] - 1;
+  }
+  for (int k = lo[2]; k < hi[2]; ++k)
+    for (int j = lo[1]; j < hi[1]; ++j)
+      for (int i = lo[0]; i < hi[0]; ++i) s->mask[((size_t)k * g.ny + j) * g.nx + i] = 7;
+  s->any_metal = true;
+  for (int d = 0; d < 3; ++d) {
+    s->mlo[d] = mlo[d] - 1;
+    s->mn[d] = mhi[d] - mlo[d] + 3;
+    s->dlo[d] = lo[d];
+    s->dhi[d] = hi[d];
+  }
+  s->rho.assign(rho, rho + nd);
+  s->design = true;
+  return GNOR_OK;
+}
+
+gnor_status gnor_update_design(gnor_sim* s, const float* rho) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  if (!s->design || !rho) return fail(s, GNOR_E_STATE, "no design region");
+  for (size_t q = 0; q < s->rho.size(); ++q)
+    if (!(rho[q] >= 0.0f && rho[q] <= 1.0f)) return fail(s, GNOR_E_INVALID_ARG, "rho must lie in [0, 1]");
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  std::copy(rho, rho + s->rho.size(), s->rho.begin());
+  return upload_rho(s);
 }
 
 gnor_status gnor_set_source(gnor_sim* s, const gnor_source_desc* src) {
@@ -1253,3 +1323,158 @@ gnor_status gnor_batch_synchronize(gnor_batch* b) {
 const char* gnor_batch_last_error(const gnor_batch* b) { return b ? b->last_error.c_str() : "null batch"; }
 
 }  // extern "C"
+
+// ============================================================ gradients
+// Objective: sigma_ext(omega_m) of a run of nsteps steps from rest, as
+// returned by gnor_get_spectra.  Its gradient with respect to the design
+// densities is the exact discrete adjoint of the run: a forward pass keeps a
+// full-state checkpoint every ckpt_every steps; the backward pass, segment by
+// segment from the last, restores the segment's checkpoint, recomputes its
+// steps while storing the design region's E and dQ, then transposes the
+// segment's steps in reverse order (gnor_adjoint.hip).
+namespace {
+
+template <class T>
+gnor_status gradient_impl(gnor_sim* s, int64_t nsteps, int C, int m, double* objective,
+                          double* grad_out) {
+  const size_t N = s->N, M = s->M;
+  const gnor_grid_desc& g = s->g;
+  const int np = g.npml;
+  const int nz = g.nz, nf = s->mon.nfreq;
+  const int dn[3] = {s->dhi[0] - s->dlo[0], s->dhi[1] - s->dlo[1], s->dhi[2] - s->dlo[2]};
+  const size_t nd = (size_t)dn[0] * dn[1] * dn[2];
+  const size_t sbytes = s->L.state_end - s->L.state_begin;
+  const int nseg = (int)((nsteps + C - 1) / C);
+  const hipStream_t st = s->stream;
+  // workspace (library-allocated, freed before return)
+  Planner P;
+  const size_t o_ck = P.take(sbytes * (size_t)nseg);
+  const size_t o_zero = P.off;  // everything below is zeroed
+  size_t o_Eb[3], o_Hb[3], o_D[6], o_Ob[3], o_Jb[3], o_dQb[3], o_psiE[3][2], o_psiH[3][2];
+  for (int c = 0; c < 3; ++c) { o_Eb[c] = P.take(N * sizeof(T)); o_Hb[c] = P.take(N * sizeof(T)); }
+  for (int q = 0; q < 6; ++q) o_D[q] = P.take(N * sizeof(T));
+  for (int c = 0; c < 3; ++c) {
+    o_Ob[c] = P.take(M * sizeof(T)); o_Jb[c] = P.take(M * sizeof(T)); o_dQb[c] = P.take(M * sizeof(T));
+  }
+  const size_t o_PPb = P.take(M * sizeof(T)), o_PJb = P.take(M * sizeof(T)), o_phi = P.take(M * sizeof(T));
+  const size_t nxs = g.nx, nys = g.ny, nzs = g.nz;
+  const size_t slab[3] = {nzs * nys * 2 * np, nzs * 2 * np * nxs, 2 * np * nys * nxs};
+  for (int a = 0; a < 3; ++a)
+    for (int t = 0; t < 2; ++t) {
+      o_psiE[a][t] = P.take(slab[a] * sizeof(T) + 8);
+      o_psiH[a][t] = P.take(slab[a] * sizeof(T) + 8);
+    }
+  const size_t o_grad = P.take(nd * 8);
+  const size_t o_B = P.take((size_t)2 * nz * 8);
+  const size_t o_fE = P.take((size_t)(C + 2) * 3 * nd * sizeof(T));
+  const size_t o_fdQ = P.take((size_t)C * 3 * nd * sizeof(T));
+  const size_t total = P.off;
+  char* ws = nullptr;
+  HIPCHECK(s, hipMalloc(&ws, total));
+  struct Free {
+    char* p;
+    ~Free() { if (p) (void)hipFree(p); }
+  } guard{ws};
+  HIPCHECK(s, hipMemsetAsync(ws + o_zero, 0, total - o_zero, st));
+
+  // ---- forward pass with checkpoints
+  gnor_status rc = gnor_reset(s);
+  if (rc != GNOR_OK) return rc;
+  for (int seg = 0; seg < nseg; ++seg) {
+    const int64_t len = std::min<int64_t>(C, nsteps - (int64_t)seg * C);
+    HIPCHECK(s, hipMemcpyAsync(ws + o_ck + sbytes * seg, s->dev + s->L.state_begin, sbytes,
+                               hipMemcpyDeviceToDevice, st));
+    rc = gnor_run(s, len);
+    if (rc != GNOR_OK) return rc;
+  }
+  std::vector<double> ext(nf), are((size_t)nz * nf), aim((size_t)nz * nf), bre((size_t)nz * nf),
+      bim((size_t)nz * nf);
+  rc = gnor_get_spectra(s, nullptr, ext.data(), nullptr, nullptr);
+  if (rc != GNOR_OK) return rc;
+  rc = gnor_get_dft(s, are.data(), aim.data(), bre.data(), bim.data());
+  if (rc != GNOR_OK) return rc;
+  if (objective) *objective = ext[m];
+  std::vector<double> B(2 * (size_t)nz);
+  for (int k = 0; k < nz; ++k) {
+    B[k] = bre[(size_t)k * nf + m];
+    B[nz + k] = bim[(size_t)k * nf + m];
+  }
+  const double b2 = B[s->mon.norm_k] * B[s->mon.norm_k] + B[nz + s->mon.norm_k] * B[nz + s->mon.norm_k];
+  HIPCHECK(s, hipMemcpy(ws + o_B, B.data(), B.size() * 8, hipMemcpyHostToDevice));
+
+  // ---- adjoint
+  gnor::AdjParams<T> A{};
+  A.p = make_params<T>(s, 0);
+  for (int c = 0; c < 3; ++c) {
+    A.Eb[c] = reinterpret_cast<T*>(ws + o_Eb[c]);
+    A.Hb[c] = reinterpret_cast<T*>(ws + o_Hb[c]);
+    A.Ob[c] = reinterpret_cast<T*>(ws + o_Ob[c]);
+    A.Jb[c] = reinterpret_cast<T*>(ws + o_Jb[c]);
+    A.dQb[c] = reinterpret_cast<T*>(ws + o_dQb[c]);
+  }
+  for (int q = 0; q < 6; ++q) A.D[q] = reinterpret_cast<T*>(ws + o_D[q]);
+  A.PPb = reinterpret_cast<T*>(ws + o_PPb);
+  A.PJb = reinterpret_cast<T*>(ws + o_PJb);
+  A.phiJb = reinterpret_cast<T*>(ws + o_phi);
+  for (int a = 0; a < 3; ++a)
+    for (int t = 0; t < 2; ++t) {
+      A.psiEb[a][t] = reinterpret_cast<T*>(ws + o_psiE[a][t]);
+      A.psiHb[a][t] = reinterpret_cast<T*>(ws + o_psiH[a][t]);
+    }
+  for (int d = 0; d < 3; ++d) { A.dlo[d] = s->dlo[d]; A.dn[d] = dn[d]; }
+  A.fE = reinterpret_cast<const T*>(ws + o_fE);
+  A.fdQ = reinterpret_cast<const T*>(ws + o_fdQ);
+  A.grad = reinterpret_cast<double*>(ws + o_grad);
+  A.dt = s->dt;
+  A.omega = s->omega[m];
+  // sigma_ext = eta0 dx^3 sum_k Re(A conj B) / |B(norm_k)|^2 with A = (eps0/dt) sum_n dt e^{i w t} J~-sums
+  A.CL = eta0() * g.dx * g.dx * g.dx * s->dt * (eps0() / s->dt) / b2;
+  A.Bre = reinterpret_cast<const double*>(ws + o_B);
+  A.Bim = A.Bre + nz;
+  gnor::launch_adjoint_source<T>(A, nsteps - 1, st);
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t n0 = (int64_t)seg * C;
+    const int len = (int)std::min<int64_t>(C, nsteps - n0);
+    HIPCHECK(s, hipMemcpyAsync(s->dev + s->L.state_begin, ws + o_ck + sbytes * seg, sbytes,
+                               hipMemcpyDeviceToDevice, st));
+    s->step = n0;
+    const int par = (int)(n0 & 1);
+    gnor::launch_store_design<T>(A, 1, ptr<T>(s, s->L.E[par ^ 1][0]), ptr<T>(s, s->L.E[par ^ 1][1]),
+                                 ptr<T>(s, s->L.E[par ^ 1][2]), 0, st);
+    gnor::launch_store_design<T>(A, 1, ptr<T>(s, s->L.E[par][0]), ptr<T>(s, s->L.E[par][1]),
+                                 ptr<T>(s, s->L.E[par][2]), 1, st);
+    for (int t = 0; t < len; ++t) {
+      enqueue_steps_eager(s, s->step, 1, st);
+      s->step += 1;
+      const int q = (int)((n0 + t + 1) & 1);
+      A.t_idx = t;
+      gnor::launch_store_design<T>(A, 0, ptr<T>(s, s->L.E[q][0]), ptr<T>(s, s->L.E[q][1]),
+                                   ptr<T>(s, s->L.E[q][2]), t + 2, st);
+    }
+    for (int t = len - 1; t >= 0; --t) {
+      A.lev_base = t + 1;
+      A.t_idx = t;
+      gnor::launch_adjoint_step<T>(A, n0 + t - 1, st);
+    }
+    HIPCHECK(s, hipGetLastError());
+  }
+  HIPCHECK(s, hipStreamSynchronize(st));
+  HIPCHECK(s, hipMemcpy(grad_out, ws + o_grad, nd * 8, hipMemcpyDeviceToHost));
+  return GNOR_OK;
+}
+
+}  // namespace
+
+extern "C" gnor_status gnor_gradient(gnor_sim* s, int64_t nsteps, int32_t ckpt_every, int32_t m_target,
+                                     double* objective, double* grad) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  if (!s->design) return fail(s, GNOR_E_STATE, "no design region (gnor_set_design)");
+  if (!grad || nsteps < 1 || ckpt_every < 1) return fail(s, GNOR_E_INVALID_ARG, "bad gradient arguments");
+  if (m_target < 0 || m_target >= s->mon.nfreq) return fail(s, GNOR_E_INVALID_ARG, "m_target outside the frequency list");
+  if (s->mon.dft_every > 1) return fail(s, GNOR_E_INVALID_ARG, "gradients need dft_every = 1");
+  if (s->mat.eps_inf != s->g.eps_background)
+    return fail(s, GNOR_E_INVALID_ARG, "gradients need eps_inf = eps_background");
+  return s->g.precision == GNOR_FP32 ? gradient_impl<float>(s, nsteps, ckpt_every, m_target, objective, grad)
+                                     : gradient_impl<double>(s, nsteps, ckpt_every, m_target, objective, grad);
+}

@@ -267,7 +267,7 @@ def dimer_design(seed: int = 0, n: int = 160, dx: float = 0.25e-9, r: float = 5.
     lo = ci - design // 2
     w.design_lo = (lo, lo, lo)
     w.design_hi = (lo + design, lo + design, lo + design)
-    w.rho = g.uniform(0.0, 1.0, size=(design, design, design))
+    w.rho = g.uniform(0.0, 1.0, size=(design, design, design)).astype(np.float32)
     ext_lo = np.minimum(c - np.array([off + r, r, r]), np.array(w.design_lo) * dx)
     ext_hi = np.maximum(c + np.array([off + r, r, r]), np.array(w.design_hi) * dx)
     w.norm_k = int(round(c[2] / dx))
@@ -282,7 +282,7 @@ def config5(seed: int = 0) -> Workload:
 
 def config5_small(seed: int = 0) -> Workload:
     """48^3 copy of the design problem: same dx, geometry x 0.3, design 18^3."""
-    return dimer_design(seed, n=48, r=1.5e-9, gap=0.3e-9, design=18, npml=6, steps=6000,
+    return dimer_design(seed, n=48, r=1.5e-9, gap=0.3e-9, design=18, npml=4, steps=6000,
                         precision="fp64")
 
 

@@ -1,0 +1,101 @@
+"""Discrete-adjoint gradients of sigma_ext(omega) with respect to the design
+density, through the C-ABI:
+
+* FP64: <grad, v> equals the oracle's exact directional derivative (dual
+  numbers through every step of the literal P-form FDTD) along random v;
+* FP64: individual gradient entries equal central finite differences of the
+  GPU objective;
+* FP32 gradient vs FP64 gradient;
+* the torch.autograd.Function wrapper returns the same gradient.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2005_06997_amd import workloads as W
+from tests.helpers import oracle_mask_and_weight, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2005_06997_amd import binding
+    return binding
+
+
+def small_design(steps=500):
+    w = W.early_pulse(W.config5_small(0))
+    w.omega = W.spectrum_omegas(6, 2.0, 4.5)
+    w.steps = steps
+    return w
+
+
+def test_gradient_fp64_matches_oracle_directional_derivative(B):
+    w = small_design(500)
+    m = 3
+    print(f"case adjoint fp64 vs oracle dual numbers: {w.name}, design {w.rho.shape}", flush=True)
+    s = B.Sim(w, precision="fp64")
+    obj, g = s.gradient(w.steps, 128, m)
+    rng = np.random.default_rng(3)
+    mask, weight = oracle_mask_and_weight(w)
+    p = oracle_problem(w, threads=8)
+    (x0, y0, z0), (x1, y1, z1) = w.design_lo, w.design_hi
+    for trial in range(2):
+        v = rng.standard_normal(g.shape)
+        vfull = np.zeros_like(weight)
+        vfull[z0:z1, y0:y1, x0:x1] = v
+        val, der = orc.directional(p, mask, weight, vfull, w.steps, m)
+        gd = float(np.sum(g * v))
+        print(f"  L gpu {obj:.12e} oracle {val:.12e}; dL gpu {gd:.12e} oracle {der:.12e}", flush=True)
+        assert abs(obj - val) <= 1e-10 * abs(val)
+        assert abs(gd - der) <= 1e-8 * abs(der)
+    assert np.abs(g).max() > 0
+
+
+def test_gradient_fp64_matches_finite_differences(B):
+    w = small_design(400)
+    m = 2
+    print("case adjoint fp64 vs central differences", flush=True)
+    s = B.Sim(w, precision="fp64")
+    obj, g = s.gradient(w.steps, 100, m)
+    rho0 = np.array(w.rho, dtype=np.float32)
+    rng = np.random.default_rng(5)
+    idx = [tuple(rng.integers(0, n) for n in g.shape) for _ in range(4)]
+    idx.append(tuple(int(v) for v in np.unravel_index(np.argmax(np.abs(g)), g.shape)))
+    for q in idx:
+        # central difference inside [0, 1], divided by the actual FP32 step
+        h = min(1.0 / 256.0, float(rho0[q]) / 2, (1.0 - float(rho0[q])) / 2)
+        vals, pts = [], []
+        for sgn in (+1, -1):
+            r = rho0.copy()
+            r[q] = np.float32(rho0[q] + sgn * h)
+            pts.append(float(r[q]))
+            s.update_design(r)
+            s.reset()
+            s.run(w.steps)
+            vals.append(s.spectra()["ext"][m])
+        fd = (vals[0] - vals[1]) / (pts[0] - pts[1])
+        print(f"  voxel {q}: adjoint {g[q]:.10e} fd {fd:.10e}", flush=True)
+        assert abs(fd - g[q]) <= 1e-4 * np.abs(g).max()
+
+
+def test_gradient_fp32_close_to_fp64_and_autograd(B):
+    import torch
+    w = small_design(400)
+    m = 3
+    print("case adjoint fp32 vs fp64, autograd", flush=True)
+    s64 = B.Sim(w, precision="fp64")
+    _, g64 = s64.gradient(w.steps, 100, m)
+    s32 = B.Sim(w, precision="fp32")
+    _, g32 = s32.gradient(w.steps, 100, m)
+    err = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
+    print(f"  fp32 vs fp64 gradient rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-3
+    F = B.extinction_objective()
+    rho = torch.tensor(np.asarray(w.rho), dtype=torch.float64, requires_grad=True)
+    L = F.apply(rho, s64, w.steps, 100, m)
+    L.backward()
+    assert np.allclose(rho.grad.numpy(), g64, rtol=1e-12, atol=0)
