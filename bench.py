@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--adjoint-steps", type=int, default=6000,
+                    help="steps of the design-gradient run (forward + adjoint; 0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=256,
                     help="steps of the 64-instance batched sweep (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -181,6 +183,21 @@ def main():
                         "ms_per_step": round(tb / args.batch_steps * 1e3, 4)}
         bt.close()
         del sims
+        torch.cuda.empty_cache()
+    if args.adjoint_steps > 0:
+        from paper_2005_06997_amd import binding
+        wd = W.config5(0)
+        m = int(np.argmin(np.abs(wd.omega - W.ev_to_rad(2.5))))
+        sd = binding.Sim(wd, precision="fp32")
+        t0 = time.perf_counter()
+        obj, grad = sd.gradient(args.adjoint_steps, 500, m)
+        ta = time.perf_counter() - t0
+        out["adjoint"] = {"workload": "dimer r 5 nm, gap 1 nm, 160^3, 60^3 design region, FP32, "
+                                      "objective sigma_ext at 2.5 eV, checkpoints every 500 steps",
+                          "steps": args.adjoint_steps, "seconds": round(ta, 3),
+                          "gcell_steps_per_s": round(wd.cells * args.adjoint_steps / ta / 1e9, 3),
+                          "objective_m2": obj, "grad_norm": float(np.linalg.norm(grad))}
+        sd.close()
         torch.cuda.empty_cache()
     if not args.no_cpu:
         v, cores, secs = cpu_baseline(w, args.cpu_steps)
