@@ -57,9 +57,12 @@ struct CpmlAxis {
 // contiguous band of tiles and neighbouring tiles share its L2.
 struct Tiling {
   int ty, kz;
-  int xcd;        // 1: XCD bands as above; 0: natural order (round-robin over XCDs)
+  int xcd;        // 1: XCD bands as above; 0: natural order (round-robin over XCDs);
+                  // 2: chunks of q tiles dealt round-robin to the XCDs, each XCD
+                  //    sweeping its chunk's consecutive tiles (balanced and local)
   int nbx, nby, nbz;
-  int per;        // ceil(tiles / 8)
+  int per;        // tiles (mode 1) or chunks (mode 2) per XCD
+  int q;          // chunk size in tiles (8 rows of tiles)
 };
 
 // Auxiliary line state (FP64 always).

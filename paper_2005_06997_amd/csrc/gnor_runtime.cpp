@@ -987,8 +987,8 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
 
 gnor_status gnor_set_tiling(gnor_sim* s, int32_t ty, int32_t kz, int32_t xcd) {
   if (!s) return GNOR_E_INVALID_ARG;
-  if (!(ty == 2 || ty == 4 || ty == 8) || kz < 1 || kz > s->g.nz || xcd < 0 || xcd > 1)
-    return fail(s, GNOR_E_INVALID_ARG, "tiling: ty must be 2, 4 or 8, 1 <= kz <= nz, xcd_bands 0 or 1");
+  if (!(ty == 2 || ty == 4 || ty == 8) || kz < 1 || kz > s->g.nz || xcd < 0 || xcd > 2)
+    return fail(s, GNOR_E_INVALID_ARG, "tiling: ty must be 2, 4 or 8, 1 <= kz <= nz, tile order 0, 1 or 2");
   if (ty != s->tile_ty || kz != s->tile_kz || xcd != s->tile_xcd) {
     s->tile_ty = ty;
     s->tile_kz = kz;
@@ -1020,7 +1020,7 @@ gnor_status gnor_autotune(gnor_sim* s, int32_t trial_steps, int32_t* ty_out, int
   HIPCHECK(s, hipEventCreate(&e1));
   const int saved_chunk = s->graph_chunk;
   s->graph_chunk = 0;
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < 3; ++x)
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 5; ++b) {
       const int kz = std::min(kzs[b], nz);

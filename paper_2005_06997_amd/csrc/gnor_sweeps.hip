@@ -47,7 +47,13 @@ struct Tile {
 };
 __device__ __forceinline__ Tile decode_tile(const Tiling& tl, int b) {
   Tile r;
-  const int t = tl.xcd ? (b & 7) * tl.per + (b >> 3) : b;
+  int t = b;
+  if (tl.xcd == 1) {
+    t = (b & 7) * tl.per + (b >> 3);
+  } else if (tl.xcd == 2) {
+    const int rank = b >> 3;  // the block's rank on its XCD
+    t = ((rank / tl.q) * 8 + (b & 7)) * tl.q + rank % tl.q;
+  }
   r.ok = t < tl.nbx * tl.nby * tl.nbz;
   r.bx = t % tl.nbx;
   r.by = (t / tl.nbx) % tl.nby;
@@ -491,13 +497,16 @@ Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd) {
   t.nby = (ny + ty - 1) / ty;
   t.nbz = (nz + kz - 1) / kz;
   const int tiles = t.nbx * t.nby * t.nbz;
-  t.per = (tiles + 7) / 8;
+  t.q = t.nbx * 8;  // chunk: 8 rows of tiles
+  if (xcd == 2) t.per = ((tiles + t.q - 1) / t.q + 7) / 8;  // chunks per XCD
+  else t.per = (tiles + 7) / 8;
   return t;
 }
 
 int sweep_blocks(const Tiling& t) {
   // + the auxiliary-line block
-  return (t.xcd ? 8 * t.per : t.nbx * t.nby * t.nbz) + 1;
+  const int tiles = t.xcd == 1 ? 8 * t.per : (t.xcd == 2 ? 8 * t.per * t.q : t.nbx * t.nby * t.nbz);
+  return tiles + 1;
 }
 
 template <class T>

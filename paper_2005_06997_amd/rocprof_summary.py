@@ -1,0 +1,81 @@
+"""Summarise rocprofv3 CSV output of a bench.py run into a short Markdown
+report: average duration per kernel (kernel trace) and HBM bytes per dispatch
+(FETCH_SIZE and WRITE_SIZE counter runs), the latter scaled by what the same
+counters read for a plain device copy of known size.
+
+usage: python -m paper_2005_06997_amd.rocprof_summary TRACE_DIR FETCH_DIR WRITE_DIR
+           COPY_FETCH_DIR COPY_WRITE_DIR COPY_BYTES OUT.md "command 1" ["command 2" ...]
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _csv(d, suffix):
+    files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return list(csv.DictReader(open(files[0])))
+
+
+def short(name: str) -> str:
+    n = name.replace("(anonymous namespace)::", "")
+    n = n.split("(")[0]
+    for pre in ("void ", "gnor::"):
+        n = n.replace(pre, "")
+    return n.strip()
+
+
+def counters(d):
+    out = defaultdict(list)
+    for r in _csv(d, "counter_collection.csv"):
+        out[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return out
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main(argv):
+    trace, fetch, write, cfetch, cwrite, copy_bytes, out = argv[:7]
+    cmds = argv[7:]
+    copy_bytes = float(copy_bytes)
+    stats = _csv(trace, "kernel_stats.csv")
+    f, w = counters(fetch), counters(write)
+    cf, cw = counters(cfetch), counters(cwrite)
+    ckey = max(cf, key=lambda k: sum(cf[k]))
+    f_scale = copy_bytes / (sum(cf[ckey]) / len(cf[ckey]) * 1024.0)
+    w_scale = copy_bytes / (sum(cw[ckey]) / len(cw[ckey]) * 1024.0)
+    lines = ["# rocprofv3 summary: GNOR-FDTD step kernels", "",
+             f"library source hash (csrc/*): `{source_hash()}`", "", "Commands (repository root):", ""]
+    lines += [f"    {c}" for c in cmds]
+    lines += ["", f"Copy calibration ({copy_bytes / 2**30:.0f} GiB device copy): FETCH_SIZE scale "
+                  f"{f_scale:.4f}, WRITE_SIZE scale {w_scale:.4f} (true bytes / counter bytes).", "",
+              "| kernel | calls | avg us | FETCH MB/dispatch (scaled) | WRITE MB/dispatch (scaled) |"
+              " HBM GB/s |", "|---|---|---|---|---|---|"]
+    for r in stats[:12]:
+        k = short(r["Name"])
+        avg = float(r["AverageNs"])
+        fm = sum(f[k]) / len(f[k]) * 1024 * f_scale / 1e6 if k in f else float("nan")
+        wm = sum(w[k]) / len(w[k]) * 1024 * w_scale / 1e6 if k in w else float("nan")
+        bw = (fm + wm) * 1e6 / (avg * 1e-9) / 1e9 if avg > 0 else float("nan")
+        lines.append(f"| {k} | {r['Calls']} | {avg / 1e3:.1f} | {fm:.1f} | {wm:.1f} | {bw:.0f} |")
+        if k.startswith("k_ej") or k.startswith("k_h<") or k.startswith("k_h"):
+            lines.append(f"<!-- traffic {k.split('<')[0]} {fm * 1e6 + wm * 1e6:.0f} -->")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -127,7 +127,7 @@ def test_fp32_config1_vs_oracle(B):
         f"{max(worst[k] for k in ('inc', 'ext', 'abs', 'sca')):.3e}")
 
 
-@pytest.mark.parametrize("ty,kz,xcd", [(2, 8, 1), (8, 13, 0), (4, 48, 1)])
+@pytest.mark.parametrize("ty,kz,xcd", [(2, 8, 1), (8, 13, 0), (4, 48, 1), (4, 8, 2)])
 def test_tilings_agree_with_oracle(B, ty, kz, xcd):
     """Every sweep tiling (including a kz that does not divide nz) reproduces
     the oracle; only reduction orders of the spectra differ."""
