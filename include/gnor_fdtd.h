@@ -182,21 +182,32 @@ gnor_status gnor_check_finite(gnor_sim *sim);
  * ms[4] flux accumulation (per step, amortised).  count must be >= 5. */
 gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int32_t count);
 
+/* Each sweep runs as one launch per tile class: 0 tiles that meet neither
+ * the metal sub-grid nor a CPML slab, 1 tiles that meet a CPML slab only,
+ * 2 tiles that meet the metal sub-grid.  With count >= 11,
+ * gnor_profile_kernels also returns ms[5 + c] (H sweep, class c) and
+ * ms[8 + c] (E/J sweep, class c); class 0 includes the auxiliary line.
+ * gnor_tile_classes writes the number of tiles of each class of the current
+ * tiling to counts[0..2] (valid once the memory is bound). */
+gnor_status gnor_tile_classes(const gnor_sim *sim, int32_t *counts);
+
 /* Sweep tiling: each block owns 64 (x) x ty (y) columns over kz planes;
- * ty in {2, 4, 8}, 1 <= kz <= nz.  xcd_bands = 1 deals the tiles so that each
- * of the 8 XCDs sweeps one contiguous band (neighbouring tiles share its L2);
- * 0 keeps the natural order (tiles spread round-robin over the XCDs).
- * Fields do not depend on the tiling; spectra only through FP64 summation
- * order. */
-gnor_status gnor_set_tiling(gnor_sim *sim, int32_t ty, int32_t kz, int32_t xcd_bands);
+ * ty in {2, 4, 8}, 1 <= kz <= nz.  Blocks are dealt to the 8 XCDs
+ * round-robin; tile_order chooses which tiles a block takes within its
+ * class: 0 natural order (neighbouring tiles on different XCDs), 1 one
+ * contiguous band of tiles per XCD (neighbours share its L2), 2 chunks of 8
+ * tile rows dealt round-robin to the XCDs (balanced and local).  Fields do
+ * not depend on the tiling; spectra only through FP64 summation order.
+ * Errors: INVALID_ARG for other values. */
+gnor_status gnor_set_tiling(gnor_sim *sim, int32_t ty, int32_t kz, int32_t tile_order);
 
 /* Autotuner: times every candidate tiling (ty in {2, 4, 8}, kz in {8, 16, 32,
- * 64, nz}, xcd_bands in {0, 1}) over trial_steps directly launched steps and
- * keeps the fastest.  Must be called at step index 0; the state is reset
- * afterwards.  Outputs (any may be NULL): chosen ty, kz, xcd_bands and its
+ * 64, nz}, tile_order in {0, 1, 2}) over trial_steps directly launched steps
+ * and keeps the fastest.  Must be called at step index 0; the state is reset
+ * afterwards.  Outputs (any may be NULL): chosen ty, kz, tile_order and its
  * ms per step. */
 gnor_status gnor_autotune(gnor_sim *sim, int32_t trial_steps, int32_t *ty, int32_t *kz,
-                          int32_t *xcd_bands, double *ms_per_step);
+                          int32_t *tile_order, double *ms_per_step);
 
 /* Voxelisers.  Spheres: n spheres as (cx, cy, cz, r) in metres from node
  * (0,0,0); a P_c point is inside iff its squared distance to a centre is

@@ -98,6 +98,7 @@ def load() -> C.CDLL:
         "gnor_load_state": (i32, [vp, vp, sz]),
         "gnor_check_finite": (i32, [vp]),
         "gnor_profile_kernels": (i32, [vp, i64, dp, i32]),
+        "gnor_tile_classes": (i32, [vp, C.POINTER(C.c_int32)]),
         "gnor_set_tiling": (i32, [vp, i32, i32, i32]),
         "gnor_autotune": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp]),
         "gnor_voxelize_spheres": (i32, [i32, i32, i32, dbl, i32, vp, vp]),
@@ -275,9 +276,16 @@ class Sim:
     def profile(self, nsteps: int) -> Dict[str, float]:
         """Average ms per launch of the H sweep, E/J sweep, spectra+staging and
         (amortised per step) flux accumulation, from HIP events."""
-        ms = np.zeros(5)
-        self._check(self.L.gnor_profile_kernels(self.h, int(nsteps), _dp(ms), 5))
-        return dict(h=ms[0], ej=ms[1], dft=ms[2], flux_acc=ms[4])
+        ms = np.zeros(11)
+        self._check(self.L.gnor_profile_kernels(self.h, int(nsteps), _dp(ms), 11))
+        return dict(h=ms[0], ej=ms[1], dft=ms[2], flux_acc=ms[4],
+                    h_cls=[float(v) for v in ms[5:8]], ej_cls=[float(v) for v in ms[8:11]])
+
+    def tile_classes(self):
+        """Tiles per class (plain Yee, CPML, metal) of the current tiling."""
+        c = (C.c_int32 * 3)()
+        self._check(self.L.gnor_tile_classes(self.h, c))
+        return [int(v) for v in c]
 
     def update_design(self, rho):
         """New design densities (z, y, x) in [0, 1]; the state is not reset."""

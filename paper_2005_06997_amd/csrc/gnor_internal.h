@@ -24,6 +24,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace gnor {
 
@@ -52,17 +53,23 @@ struct CpmlAxis {
 };
 
 // Tiling of a sweep: tiles of 64 x ty columns by kz planes, numbered x
-// fastest, then y, then z; tile t runs on block (t mod per) * 8 + t / per so
-// that each XCD (blocks are dealt to the 8 XCDs round-robin) owns a
-// contiguous band of tiles and neighbouring tiles share its L2.
+// fastest, then y, then z, and split into three classes (plain Yee, CPML,
+// metal) that run as separate launches.  Within a class's launch, block b
+// takes a position in the class's tile list according to the tile order
+// (blocks are dealt to the 8 XCDs round-robin):
+//   0: natural order;
+//   1: XCD bands: position (b mod 8) * per + b / 8, so each XCD owns a
+//      contiguous band of the list and neighbouring tiles share its L2;
+//   2: chunks of q positions dealt round-robin to the XCDs, each XCD sweeping
+//      its chunk's consecutive positions (balanced and local).
 struct Tiling {
   int ty, kz;
-  int xcd;        // 1: XCD bands as above; 0: natural order (round-robin over XCDs);
-                  // 2: chunks of q tiles dealt round-robin to the XCDs, each XCD
-                  //    sweeping its chunk's consecutive tiles (balanced and local)
+  int xcd;        // tile order 0, 1 or 2 (above)
   int nbx, nby, nbz;
-  int per;        // tiles (mode 1) or chunks (mode 2) per XCD
-  int q;          // chunk size in tiles (8 rows of tiles)
+  int q;          // chunk size for order 2 (8 rows of tiles)
+  int cn[3];      // tiles per class
+  int coff[3];    // offset of each class's list in the tile list
+  int cper[3];    // positions (order 1) or chunks (order 2) per XCD, per class
 };
 
 // Auxiliary line state (FP64 always).
@@ -103,6 +110,7 @@ struct Params {
   int any_metal;
   int mlo[3], mn[3];
   const uint8_t* mask;  // sub-grid, bit c = P_c is metal
+  const int* colz;      // per sub-grid column: first and last plane of nodes on a metal edge
   const float* rho;     // optional per-cell weight of wp^2, beta^2, D (sub-grid); null = 1
   const T* Ji[3];
   T* Jo[3];
@@ -125,6 +133,7 @@ struct Params {
   // per-(plane, tile, wavefront) partial sums of the induced current J_x
   double* jpart;      // [nz][nbx * nby * ty]
   Tiling tl;
+  const int* tiles;   // tile lists of the three classes, back to back
   const int64_t* step_base;
 };
 
@@ -212,29 +221,37 @@ void launch_store_design(const AdjParams<T>& A, int store_e_only, const T* Ex, c
                          const T* Ez, int lev, hipStream_t s);
 
 // One instance of a batch: its parameters and its block ranges in the batched
-// sweep launches (hblk0 .. hblk0 + hnblk, tiles then the auxiliary-line block)
-// and in the batched spectra launch (dblk0 .. dblk0 + dnblk).
+// sweep launches of each tile class (blk0[c] .. blk0[c] + nblk[c]; class 0
+// ends with the instance's auxiliary-line block) and in the batched spectra
+// launch (dblk0 .. dblk0 + dnblk).
 template <class T>
 struct BatchEntry {
   Params<T> p;
   AuxParams a;
   DftParams d;
   FluxParams f;
-  int hblk0, hnblk;
+  int blk0[3], nblk[3];
   int dblk0, dnblk;
 };
 
 template <class T>
-void launch_h_batch(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s);
+void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[3], int ty, hipStream_t s);
 template <class T>
-void launch_ej_batch(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, hipStream_t s);
+void launch_ej_batch(const BatchEntry<T>* e, int n, const int blocks[3], int ty, int sub,
+                     hipStream_t s);
 template <class T>
 void launch_dft_batch(const BatchEntry<T>* e, int n, int blocks, int sub, hipStream_t s);
 template <class T>
 void launch_advance_batch(const BatchEntry<T>* e, int n, int64_t count, hipStream_t s);
-int sweep_blocks(const Tiling& t);
+// blocks of the class-c launch of one simulation (without the auxiliary block)
+int class_blocks(const Tiling& t, int c);
 int dft_blocks(const DftParams& d, const FluxParams& f);
 
+// one tile class of a sweep (class 0 also advances the auxiliary line)
+template <class T>
+void launch_h_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s);
+template <class T>
+void launch_ej_class(const Params<T>& p, const AuxParams& a, int sub, int c, hipStream_t s);
 template <class T>
 void launch_h(const Params<T>& p, const AuxParams& a, hipStream_t s);
 template <class T>
@@ -249,5 +266,10 @@ void launch_flux_reduce(const double* acc_re, const double* acc_im, const double
 template <class T>
 void launch_nonfinite(const T* a, size_t n, int* flag, hipStream_t s);
 Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
+// Classify the tiles (metal sub-grid [mlo, mlo + mn), CPML slabs of np cells)
+// and fill the class counts, offsets and per-XCD counts of t; list receives
+// the three class lists back to back.
+void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int mlo[3], const int mn[3],
+                    bool any_metal, std::vector<int>& list);
 
 }  // namespace gnor

@@ -51,7 +51,8 @@ struct Planner {
 
 struct Layout {
   // static region
-  size_t mask = 0, rho = 0, cpml[3] = {0, 0, 0}, aux_prof = 0, omega = 0, fpw = 0;
+  size_t mask = 0, rho = 0, cpml[3] = {0, 0, 0}, aux_prof = 0, omega = 0, fpw = 0, tiles = 0,
+         colz = 0;
   size_t static_end = 0;
   // state region
   size_t state_begin = 0;
@@ -89,6 +90,8 @@ struct gnor_sim {
   std::vector<gnor::FluxSeg> fseg;
   std::vector<double> fpw;
   int tile_ty = 4, tile_kz = 32, tile_xcd = 0;   // sweep tiling (autotuned)
+  gnor::Tiling tl{};                              // that tiling with its tile classes
+  std::vector<int> tile_list;                     // the classes' tile lists (host copy)
   Layout L;
   char* dev = nullptr;
   size_t dev_bytes = 0;
@@ -200,11 +203,14 @@ void plan_layout(gnor_sim* s) {
   const int e = s->elem;
   const int np = s->g.npml;
   L.mask = P.take(M);
+  L.colz = P.take((size_t)2 * s->mn[0] * s->mn[1] * 4);
   L.rho = P.take(M * sizeof(float));
   for (int a = 0; a < 3; ++a) L.cpml[a] = P.take((size_t)6 * 2 * np * e + 8);
   L.aux_prof = P.take((size_t)6 * s->n1 * 8);
   L.omega = P.take((size_t)std::max(1, s->mon.nfreq) * 8);
   L.fpw = P.take((size_t)s->npairs * 8 + 8);
+  // tile lists: room for the finest tiling (ty = 2, kz = 1)
+  L.tiles = P.take((size_t)s->nbx * ((s->g.ny + 1) / 2) * s->g.nz * 4 + 4);
   L.static_end = P.off;
   L.state_begin = P.off;
   for (int pp = 0; pp < 2; ++pp)
@@ -265,6 +271,7 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   p.any_metal = s->any_metal ? 1 : 0;
   for (int d = 0; d < 3; ++d) { p.mlo[d] = s->mlo[d]; p.mn[d] = s->mn[d]; }
   p.mask = ptr<uint8_t>(s, s->L.mask);
+  p.colz = ptr<int>(s, s->L.colz);
   p.rho = s->design ? ptr<float>(s, s->L.rho) : nullptr;
   // metal coefficients (Sec. III), scaled by eps0 and dx^2
   const double dt = s->dt, dx = g.dx;
@@ -300,7 +307,8 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   double* aux = ptr<double>(s, s->L.aux);
   p.e1 = aux; p.h1 = aux + s->n1;
   p.jpart = ptr<double>(s, s->L.jpart);
-  p.tl = gnor::make_tiling(g.nx, g.ny, g.nz, s->tile_ty, s->tile_kz, s->tile_xcd);
+  p.tl = s->tl;
+  p.tiles = ptr<int>(s, s->L.tiles);
   p.step_base = ptr<int64_t>(s, s->L.step);
   return p;
 }
@@ -436,6 +444,17 @@ gnor_status upload_rho(gnor_sim* s) {
   return GNOR_OK;
 }
 
+// Tile classes of the current tiling; uploaded when the memory is bound.
+gnor_status plan_tiles(gnor_sim* s) {
+  const gnor_grid_desc& g = s->g;
+  s->tl = gnor::make_tiling(g.nx, g.ny, g.nz, s->tile_ty, s->tile_kz, s->tile_xcd);
+  gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->mlo, s->mn, s->any_metal, s->tile_list);
+  if (s->bound && !s->tile_list.empty())
+    HIPCHECK(s, hipMemcpy(s->dev + s->L.tiles, s->tile_list.data(), s->tile_list.size() * 4,
+                          hipMemcpyHostToDevice));
+  return GNOR_OK;
+}
+
 gnor_status upload_static(gnor_sim* s) {
   const gnor_grid_desc& g = s->g;
   // metal sub-grid mask
@@ -447,6 +466,31 @@ gnor_status upload_static(gnor_sim* s) {
         sub[((size_t)z * s->mn[1] + y) * s->mn[0] + x] = s->any_metal ? s->mask[gi] : 0;
       }
   HIPCHECK(s, hipMemcpy(s->dev + s->L.mask, sub.data(), s->M, hipMemcpyHostToDevice));
+  // per sub-grid column, the first and last plane of nodes that touch a metal
+  // edge (E_a point with bit a set); node scalars elsewhere stay zero
+  {
+    const int m0 = s->mn[0], m1 = s->mn[1], m2 = s->mn[2];
+    std::vector<int> colz((size_t)2 * m0 * m1);
+    auto at = [&](int x, int y, int z) -> unsigned {
+      if (x < 0 || y < 0 || z < 0) return 0u;
+      return sub[((size_t)z * m1 + y) * m0 + x];
+    };
+    for (int y = 0; y < m1; ++y)
+      for (int x = 0; x < m0; ++x) {
+        int lo = 1, hi = 0;
+        for (int z = 0; z < m2; ++z) {
+          const bool act = at(x, y, z) != 0u || (at(x - 1, y, z) & 1u) || (at(x, y - 1, z) & 2u) ||
+                           (at(x, y, z - 1) & 4u);
+          if (act) {
+            if (lo > hi) lo = z;
+            hi = z;
+          }
+        }
+        colz[2 * ((size_t)y * m0 + x)] = lo;
+        colz[2 * ((size_t)y * m0 + x) + 1] = hi;
+      }
+    HIPCHECK(s, hipMemcpy(s->dev + s->L.colz, colz.data(), colz.size() * 4, hipMemcpyHostToDevice));
+  }
   if (s->design) {
     const gnor_status st = upload_rho(s);
     if (st != GNOR_OK) return st;
@@ -718,6 +762,8 @@ gnor_status gnor_bind_memory(gnor_sim* s, void* dptr, size_t bytes, void* stream
   s->bound = true;
   gnor_status st = upload_static(s);
   if (st != GNOR_OK) return st;
+  st = plan_tiles(s);
+  if (st != GNOR_OK) return st;
   return gnor_reset(s);
 }
 
@@ -949,9 +995,12 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
   if (!ms || count < 5 || nsteps <= 0) return GNOR_E_INVALID_ARG;
-  hipEvent_t ev[5];
+  // events: 0 | H class 0 | 1 | H class 1 | 2 | H class 2 | 3 | E/J 0 | 4 | E/J 1 | 5 | E/J 2 | 6
+  //         | spectra | 7 | flux accumulation | 8
+  constexpr int NE = 9;
+  hipEvent_t ev[NE];
   for (auto& e : ev) HIPCHECK(s, hipEventCreate(&e));
-  double acc[5] = {0, 0, 0, 0, 0};
+  double acc[NE - 1] = {0, 0, 0, 0, 0, 0, 0, 0};
   const bool fp32 = s->g.precision == GNOR_FP32;
   for (int64_t q = 0; q < nsteps; ++q) {
     const int64_t n = s->step;
@@ -959,29 +1008,52 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
     const hipStream_t str = s->stream;
     const gnor::AuxParams a = make_aux(s);
     (void)hipEventRecord(ev[0], str);
-    if (fp32) gnor::launch_h<float>(make_params<float>(s, parity), a, str);
-    else gnor::launch_h<double>(make_params<double>(s, parity), a, str);
-    (void)hipEventRecord(ev[1], str);
-    if (fp32) gnor::launch_ej<float>(make_params<float>(s, parity), a, 0, str);
-    else gnor::launch_ej<double>(make_params<double>(s, parity), a, 0, str);
-    (void)hipEventRecord(ev[2], str);
+    for (int c = 0; c < 3; ++c) {
+      if (fp32) gnor::launch_h_class<float>(make_params<float>(s, parity), a, c, str);
+      else gnor::launch_h_class<double>(make_params<double>(s, parity), a, c, str);
+      (void)hipEventRecord(ev[1 + c], str);
+    }
+    for (int c = 0; c < 3; ++c) {
+      if (fp32) gnor::launch_ej_class<float>(make_params<float>(s, parity), a, 0, c, str);
+      else gnor::launch_ej_class<double>(make_params<double>(s, parity), a, 0, c, str);
+      (void)hipEventRecord(ev[4 + c], str);
+    }
     if (s->mon.nfreq > 0) {
       if (fp32) gnor::launch_dft_stage<float>(make_dft(s), make_flux(s), make_params<float>(s, parity), 0, str);
       else gnor::launch_dft_stage<double>(make_dft(s), make_flux(s), make_params<double>(s, parity), 0, str);
     }
-    (void)hipEventRecord(ev[3], str);
+    (void)hipEventRecord(ev[7], str);
     if (s->nsamp > 0 && (n % s->slots) == s->slots - 1) enqueue_flux_acc(s, 0, str);
-    (void)hipEventRecord(ev[4], str);
+    (void)hipEventRecord(ev[8], str);
     gnor::launch_advance(ptr<int64_t>(s, s->L.step), 1, str);
     HIPCHECK(s, hipGetLastError());
-    HIPCHECK(s, hipEventSynchronize(ev[4]));
-    float t[4];
-    for (int e = 0; e < 4; ++e) (void)hipEventElapsedTime(&t[e], ev[e], ev[e + 1]);
-    acc[0] += t[0]; acc[1] += t[1]; acc[2] += t[2]; acc[4] += t[3];
+    HIPCHECK(s, hipEventSynchronize(ev[8]));
+    for (int e = 0; e < NE - 1; ++e) {
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, ev[e], ev[e + 1]);
+      acc[e] += t;
+    }
     s->step += 1;
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
-  for (int i = 0; i < 5; ++i) ms[i] = acc[i] / (double)nsteps;
+  const double inv = 1.0 / (double)nsteps;
+  double out[11];
+  out[0] = (acc[0] + acc[1] + acc[2]) * inv;
+  out[1] = (acc[3] + acc[4] + acc[5]) * inv;
+  out[2] = acc[6] * inv;
+  out[3] = 0.0;
+  out[4] = acc[7] * inv;
+  for (int c = 0; c < 3; ++c) {
+    out[5 + c] = acc[c] * inv;
+    out[8 + c] = acc[3 + c] * inv;
+  }
+  for (int i = 0; i < count && i < 11; ++i) ms[i] = out[i];
+  return GNOR_OK;
+}
+
+gnor_status gnor_tile_classes(const gnor_sim* s, int32_t* counts) {
+  if (!s || !counts) return GNOR_E_INVALID_ARG;
+  for (int c = 0; c < 3; ++c) counts[c] = s->tl.cn[c];
   return GNOR_OK;
 }
 
@@ -994,6 +1066,8 @@ gnor_status gnor_set_tiling(gnor_sim* s, int32_t ty, int32_t kz, int32_t xcd) {
     s->tile_kz = kz;
     s->tile_xcd = xcd;
     drop_graph(s);
+    const gnor_status st = plan_tiles(s);
+    if (st != GNOR_OK) return st;
     if (s->bound) {
       // partial sums are indexed by tile: clear stale entries of the old tiling
       const size_t jbytes = (size_t)s->g.nz * s->nbx * (s->g.ny + 8) * 8;
@@ -1139,7 +1213,8 @@ struct gnor_batch {
   int ty = 2;
   char* tab = nullptr;       // two tables of n entries (parity 0, parity 1)
   size_t entry_bytes = 0;
-  int hblocks = 0, dblocks = 0;
+  int hblocks[3] = {0, 0, 0}, dblocks = 0;
+  std::vector<int> tiling;   // (ty, kz, order) of every instance at creation
   bool any_dft = false, any_flux = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -1167,7 +1242,7 @@ template <class T>
 gnor_status batch_tables(gnor_batch* b) {
   std::vector<gnor::BatchEntry<T>> tab(2 * (size_t)b->n);
   for (int parity = 0; parity < 2; ++parity) {
-    int h0 = 0, d0 = 0;
+    int h0[3] = {0, 0, 0}, d0 = 0;
     for (int q = 0; q < b->n; ++q) {
       gnor_sim* s = b->sims[q];
       gnor::BatchEntry<T>& e = tab[(size_t)parity * b->n + q];
@@ -1175,14 +1250,16 @@ gnor_status batch_tables(gnor_batch* b) {
       e.a = make_aux(s);
       e.d = make_dft(s);
       e.f = make_flux(s);
-      e.hblk0 = h0;
-      e.hnblk = gnor::sweep_blocks(e.p.tl);
-      h0 += e.hnblk;
+      for (int c = 0; c < 3; ++c) {
+        e.blk0[c] = h0[c];
+        e.nblk[c] = gnor::class_blocks(e.p.tl, c) + (c == 0 ? 1 : 0);  // + auxiliary block
+        h0[c] += e.nblk[c];
+      }
       e.dblk0 = d0;
       e.dnblk = s->mon.nfreq > 0 ? gnor::dft_blocks(e.d, e.f) : 0;
       d0 += e.dnblk;
     }
-    b->hblocks = h0;
+    for (int c = 0; c < 3; ++c) b->hblocks[c] = h0[c];
     b->dblocks = d0;
   }
   b->entry_bytes = sizeof(gnor::BatchEntry<T>);
@@ -1234,6 +1311,7 @@ gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, gn
     for (int r = 0; r < q; ++r)
       if (sims[r] == s) { delete b; return GNOR_E_INVALID_ARG; }
     b->sims.push_back(s);
+    b->tiling.insert(b->tiling.end(), {s->tile_ty, s->tile_kz, s->tile_xcd});
     b->any_dft = b->any_dft || s->mon.nfreq > 0;
     b->any_flux = b->any_flux || s->nsamp > 0;
   }
@@ -1273,8 +1351,13 @@ gnor_status gnor_batch_set_graph_chunk(gnor_batch* b, int32_t steps) {
 
 gnor_status gnor_batch_run(gnor_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return GNOR_E_INVALID_ARG;
-  for (gnor_sim* s : b->sims)
+  for (size_t q = 0; q < b->sims.size(); ++q) {
+    const gnor_sim* s = b->sims[q];
     if (s->step != b->step) return bfail(b, GNOR_E_STATE, "an instance was stepped outside the batch");
+    if (s->tile_ty != b->tiling[3 * q] || s->tile_kz != b->tiling[3 * q + 1] ||
+        s->tile_xcd != b->tiling[3 * q + 2])
+      return bfail(b, GNOR_E_STATE, "an instance's tiling changed after the batch was created");
+  }
   const int align = b->any_flux ? gnor::kFluxSlots : 2;
   int chunk = b->graph_chunk > 0 ? std::max(align, b->graph_chunk / align * align) : 0;
   int64_t left = nsteps;

@@ -20,7 +20,9 @@
 // and stores (register double buffering); no barriers.
 #include "gnor_internal.h"
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace gnor {
 
@@ -45,16 +47,22 @@ struct Tile {
   int bx, by, bz;
   bool ok;
 };
-__device__ __forceinline__ Tile decode_tile(const Tiling& tl, int b) {
+// Block b of the launch for tile class c -> tile.  The class's tiles are
+// listed in natural order (x fastest, then y, then z); the position in the
+// list follows the tile order of the tiling (blocks are dealt round-robin to
+// the 8 XCDs).
+__device__ __forceinline__ Tile decode_tile(const Tiling& tl, const int* __restrict__ list, int c,
+                                            int b) {
   Tile r;
-  int t = b;
+  int pos = b;
   if (tl.xcd == 1) {
-    t = (b & 7) * tl.per + (b >> 3);
+    pos = (b & 7) * tl.cper[c] + (b >> 3);
   } else if (tl.xcd == 2) {
     const int rank = b >> 3;  // the block's rank on its XCD
-    t = ((rank / tl.q) * 8 + (b & 7)) * tl.q + rank % tl.q;
+    pos = ((rank / tl.q) * 8 + (b & 7)) * tl.q + rank % tl.q;
   }
-  r.ok = t < tl.nbx * tl.nby * tl.nbz;
+  r.ok = pos < tl.cn[c];
+  const int t = r.ok ? list[tl.coff[c] + pos] : 0;
   r.bx = t % tl.nbx;
   r.by = (t / tl.nbx) % tl.nby;
   r.bz = t / (tl.nbx * tl.nby);
@@ -65,14 +73,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
-}
-
-// CPML-stretched difference: kinv d + psi with psi <- b psi + a d (index units)
-template <class T>
-__device__ __forceinline__ T stretch(T* __restrict__ psi, size_t q, T b, T a, T ki, T d) {
-  const T ps = b * psi[q] + a * d;
-  psi[q] = ps;
-  return ki * d + ps;
 }
 
 // ------------------------------------------------------------ auxiliary line
@@ -121,18 +121,25 @@ __device__ void aux_e_block(const AuxParams& a, int sub, int tid, int nthr) {
   if (tid == 0) a.e1[kAuxSrc] += source_value(a, (double)(n + 1) * a.dt);
 }
 
-// ------------------------------------------------------------------ f1: H
-template <class T>
-struct HIn {
-  T ex1, ey1, ez, ezy, ezx, eyx, exy, hx, hy, hz;  // E at k+1 (own), E at k, H at k
-  T jx, jy, jz, jxm, jym, pp, pj;                  // node scalars' inputs at k
-};
+// ------------------------------------------------------------ tile classes
+// Each sweep runs as three launches, one per tile class, so that each class
+// gets the register budget (and hence the occupancy) its code needs:
+//   class 0: tiles that meet neither the metal sub-grid nor a CPML slab
+//            (the bulk of a large grid: the plain Yee update);
+//   class 1: tiles that meet a CPML slab but not the metal sub-grid;
+//   class 2: tiles that meet the metal sub-grid (CPML handled when the tile
+//            also meets a slab).
+// A wavefront marches its column over the tile's planes; every plane's loads
+// are issued together, then computed and stored.  Latency is hidden by the
+// other resident wavefronts.
+__device__ __forceinline__ bool range_in_slabs(int lo, int hi, int n, int np) {
+  // [lo, hi) meets [0, np) or [n - 1 - np, n)  (the E and H slabs of an axis)
+  return np > 0 && (lo < np || hi > n - 1 - np);
+}
 
-// One tile of the H sweep (blk: the block's index among the tiles).
-template <class T, int TY>
-__device__ __forceinline__ void h_tile(const Params<T>& p, int blk) {
-  const Tile tile = decode_tile(p.tl, blk);
-  if (!tile.ok) return;
+// ------------------------------------------------------------------ f1: H
+template <class T, int TY, bool METAL, bool PML>
+__device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool pml_tile) {
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int i = tile.bx * kBX + threadIdx.x;
   const int j = tile.by * TY + threadIdx.y;
@@ -152,68 +159,92 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, int blk) {
   const bool cx = i >= 1 && xin && yin;  // H_x columns
   const bool cy = xin && j >= 1 && yin;  // H_y
   const bool cz = xin && yin;            // H_z
-  const int sxh = np ? slab_h(i, nx, np) : -1;
-  const int syh = np ? slab_h(j, ny, np) : -1;
+  const int sxh = (PML && pml_tile) ? slab_h(i, nx, np) : -1;
+  const int syh = (PML && pml_tile) ? slab_h(j, ny, np) : -1;
+  const CpmlAxis<T>& Z = p.cp[2];
+  // the column's x- and y-slab coefficients, in registers for the whole
+  // march (the psi stores could alias them, so the compiler cannot hoist them)
+  T xb = T(0), xa = T(0), xk = T(1), yb = T(0), ya = T(0), yk = T(1);
+  if (sxh >= 0) { xb = p.cp[0].bh[sxh]; xa = p.cp[0].ah[sxh]; xk = p.cp[0].kh[sxh]; }
+  if (syh >= 0) { yb = p.cp[1].bh[syh]; ya = p.cp[1].ah[syh]; yk = p.cp[1].kh[syh]; }
   const bool tfx = p.tfsf && i >= p.tf_lo[0] && i <= p.tf_hi[0] - 1;
   const bool tfy_band = tfx && j >= p.tf_lo[1] && j <= p.tf_hi[1];
   const bool tfz_lo = tfx && j == p.tf_lo[1] - 1, tfz_hi = tfx && j == p.tf_hi[1];
   // node scalars: this column inside the metal sub-grid?
   const int lx = i - p.mlo[0], ly = j - p.mlo[1];
-  const bool col_sub = p.any_metal && lx >= 0 && ly >= 0 && lx < p.mn[0] && ly < p.mn[1];
+  const bool col_sub = METAL && lx >= 0 && ly >= 0 && lx < p.mn[0] && ly < p.mn[1];
   const size_t m1 = p.mn[0], m2 = (size_t)p.mn[0] * p.mn[1];
   const size_t lcol = col_sub ? (size_t)ly * m1 + lx : 0;
-
-  auto load = [&](int k, size_t id, HIn<T>& v) {
-    const bool zin = k <= nz - 2;
-    v.ex1 = zin ? Ex[id + sz] : T(0);
-    v.ey1 = zin ? Ey[id + sz] : T(0);
-    v.ez = Ez[id];
-    v.ezy = yin ? Ez[id + sy] : T(0);
-    v.ezx = xin ? Ez[id + 1] : T(0);
-    v.eyx = xin ? Ey[id + 1] : T(0);
-    v.exy = yin ? Ex[id + sy] : T(0);
-    v.hx = (cx && zin) ? Hx[id] : T(0);
-    v.hy = (cy && zin) ? Hy[id] : T(0);
-    v.hz = (cz && k >= 1 && zin) ? Hz[id] : T(0);
-    const int lz = k - p.mlo[2];
-    if (col_sub && lz >= 0 && lz < p.mn[2]) {
-      const size_t l = (size_t)lz * m2 + lcol;
-      v.jx = p.Ji[0][l]; v.jy = p.Ji[1][l]; v.jz = p.Ji[2][l];
-      v.jxm = lx > 0 ? p.Ji[0][l - 1] : T(0);
-      v.jym = ly > 0 ? p.Ji[1][l - m1] : T(0);
-      v.pp = p.PPi[l]; v.pj = p.PJi[l];
-    } else {
-      v.jx = v.jy = v.jz = v.jxm = v.jym = v.pp = v.pj = T(0);
-    }
-  };
+  // nodes of the column that touch a metal edge (sub-grid planes [zlo, zhi]);
+  // every other node keeps zero node scalars
+  int zlo = 1, zhi = 0;
+  if (METAL && col_sub) {
+    zlo = p.colz[2 * lcol];
+    zhi = p.colz[2 * lcol + 1];
+  }
 
   size_t id = (size_t)k0 * sz + (size_t)j * nx + i;
-  T ex0 = Ex[id], ey0 = Ey[id];
-  T jzm = T(0);  // J_z one plane below (own column)
-  if (col_sub) {
+  T ex0 = Ex[id], ey0 = Ey[id];  // E_x, E_y of plane k (carried up the column)
+  T jzm = T(0);                  // J_z one plane below (metal sub-grid)
+  if (METAL && col_sub) {
     const int lzm = k0 - 1 - p.mlo[2];
     if (lzm >= 0 && lzm < p.mn[2]) jzm = p.Ji[2][(size_t)lzm * m2 + lcol];
   }
-  HIn<T> cur, nxt;
-  load(k0, id, cur);
   for (int k = k0; k < k1; ++k, id += sz) {
-    if (k + 1 < k1) load(k + 1, id + sz, nxt);
     const bool zin = k <= nz - 2;
     const bool ux = cx && zin, uy = cy && zin, uz = cz && k >= 1 && zin;
-    T dyx = cur.ezy - cur.ez, dzx = cur.ey1 - ey0;   // H_x: dy Ez - dz Ey
-    T dzy = cur.ex1 - ex0, dxy = cur.ezx - cur.ez;   // H_y: dz Ex - dx Ez
-    T dxz = cur.eyx - ey0, dyz = cur.exy - ex0;      // H_z: dx Ey - dy Ex
-    if (np) {
+    // loads of the plane (one select per value: a branch that assigns
+    // several values on each side can leave them in scratch memory)
+    const T ex1 = zin ? Ex[id + sz] : T(0), ey1 = zin ? Ey[id + sz] : T(0);
+    const T ez = Ez[id];
+    const T ezy = yin ? Ez[id + sy] : T(0), exy = yin ? Ex[id + sy] : T(0);
+    const T ezx = xin ? Ez[id + 1] : T(0), eyx = xin ? Ey[id + 1] : T(0);
+    const T hx = ux ? Hx[id] : T(0), hy = uy ? Hy[id] : T(0), hz = uz ? Hz[id] : T(0);
+    T dyx = ezy - ez, dzx = ey1 - ey0;   // H_x: dy Ez - dz Ey
+    T dzy = ex1 - ex0, dxy = ezx - ez;   // H_y: dz Ex - dx Ez
+    T dxz = eyx - ey0, dyz = exy - ex0;  // H_z: dx Ey - dy Ex
+    if (PML && pml_tile) {
+      // CPML-stretched differences kinv d + psi with psi <- b psi + a d
       const int szh = slab_h(k, nz, np);
-      const CpmlAxis<T>& X = p.cp[0];
-      const CpmlAxis<T>& Y = p.cp[1];
-      const CpmlAxis<T>& Z = p.cp[2];
-      if (ux && syh >= 0) dyx = stretch(p.psiH[1][0], slab_index(1, syh, i, j, k, nx, ny, np), Y.bh[syh], Y.ah[syh], Y.kh[syh], dyx);
-      if (ux && szh >= 0) dzx = stretch(p.psiH[2][1], slab_index(2, szh, i, j, k, nx, ny, np), Z.bh[szh], Z.ah[szh], Z.kh[szh], dzx);
-      if (uy && szh >= 0) dzy = stretch(p.psiH[2][0], slab_index(2, szh, i, j, k, nx, ny, np), Z.bh[szh], Z.ah[szh], Z.kh[szh], dzy);
-      if (uy && sxh >= 0) dxy = stretch(p.psiH[0][1], slab_index(0, sxh, i, j, k, nx, ny, np), X.bh[sxh], X.ah[sxh], X.kh[sxh], dxy);
-      if (uz && sxh >= 0) dxz = stretch(p.psiH[0][0], slab_index(0, sxh, i, j, k, nx, ny, np), X.bh[sxh], X.ah[sxh], X.kh[sxh], dxz);
-      if (uz && syh >= 0) dyz = stretch(p.psiH[1][1], slab_index(1, syh, i, j, k, nx, ny, np), Y.bh[syh], Y.ah[syh], Y.kh[syh], dyz);
+      if (ux && syh >= 0) {
+        T* q = p.psiH[1][0] + slab_index(1, syh, i, j, k, nx, ny, np);
+        const T ps = yb * *q + ya * dyx;
+        *q = ps;
+        dyx = yk * dyx + ps;
+      }
+      if (szh >= 0) {
+        const T zb = Z.bh[szh], za = Z.ah[szh], zk = Z.kh[szh];
+        if (ux) {
+          T* q = p.psiH[2][1] + slab_index(2, szh, i, j, k, nx, ny, np);
+          const T ps = zb * *q + za * dzx;
+          *q = ps;
+          dzx = zk * dzx + ps;
+        }
+        if (uy) {
+          T* q = p.psiH[2][0] + slab_index(2, szh, i, j, k, nx, ny, np);
+          const T ps = zb * *q + za * dzy;
+          *q = ps;
+          dzy = zk * dzy + ps;
+        }
+      }
+      if (uy && sxh >= 0) {
+        T* q = p.psiH[0][1] + slab_index(0, sxh, i, j, k, nx, ny, np);
+        const T ps = xb * *q + xa * dxy;
+        *q = ps;
+        dxy = xk * dxy + ps;
+      }
+      if (uz && sxh >= 0) {
+        T* q = p.psiH[0][0] + slab_index(0, sxh, i, j, k, nx, ny, np);
+        const T ps = xb * *q + xa * dxz;
+        *q = ps;
+        dxz = xk * dxz + ps;
+      }
+      if (uz && syh >= 0) {
+        T* q = p.psiH[1][1] + slab_index(1, syh, i, j, k, nx, ny, np);
+        const T ps = yb * *q + ya * dyz;
+        *q = ps;
+        dyz = yk * dyz + ps;
+      }
     }
     T cyv = dzy - dxy;
     T czv = dxz - dyz;
@@ -226,49 +257,50 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, int blk) {
       const T inc = (T)p.e1[k + kAuxOff];
       czv += tfz_lo ? inc : -inc;
     }
-    if (ux) Hx[id] = cur.hx - S * (dyx - dzx);
-    if (uy) Hy[id] = cur.hy - S * cyv;
-    if (uz) Hz[id] = cur.hz - S * czv;
-    // node scalars of node (i, j, k) of the metal sub-grid
-    const int lz = k - p.mlo[2];
-    if (col_sub && lz >= 0 && lz < p.mn[2]) {
-      const T div = (cur.jx - cur.jxm) + (cur.jy - cur.jym) + (cur.jz - jzm);
-      const T phiP = cur.pp + div;
-      const size_t l = (size_t)lz * m2 + lcol;
-      p.PPo[l] = phiP;
-      p.PJo[l] = div;
-      p.Q[l] = p.g1 * phiP + p.g2 * (T(3) * div - cur.pj);
+    if (ux) Hx[id] = hx - S * (dyx - dzx);
+    if (uy) Hy[id] = hy - S * cyv;
+    if (uz) Hz[id] = hz - S * czv;
+    if (METAL) {
+      // node scalars of node (i, j, k) of the metal sub-grid
+      // J_z is carried from the plane below, so it is read one plane early
+      const int lz = k - p.mlo[2];
+      const bool sub = lz >= zlo && lz <= zhi;
+      const bool rd = lz >= zlo - 1 && lz <= zhi;
+      const size_t l = rd ? (size_t)lz * m2 + lcol : 0;
+      const T jx = sub ? p.Ji[0][l] : T(0);
+      const T jy = sub ? p.Ji[1][l] : T(0);
+      const T jz = rd ? p.Ji[2][l] : T(0);
+      const T jxm = (sub && lx > 0) ? p.Ji[0][l - 1] : T(0);
+      const T jym = (sub && ly > 0) ? p.Ji[1][l - m1] : T(0);
+      const T pp = sub ? p.PPi[l] : T(0);
+      const T pj = sub ? p.PJi[l] : T(0);
+      if (sub) {
+        const T div = (jx - jxm) + (jy - jym) + (jz - jzm);
+        const T phiP = pp + div;
+        p.PPo[l] = phiP;
+        p.PJo[l] = div;
+        p.Q[l] = p.g1 * phiP + p.g2 * (T(3) * div - pj);
+      }
+      jzm = jz;
     }
-    jzm = cur.jz;
-    ex0 = cur.ex1;
-    ey0 = cur.ey1;
-    cur = nxt;
+    ex0 = ex1;
+    ey0 = ey1;
   }
 }
 
 // ------------------------------------------------------- f2 + f4: E and J
-template <class T>
-struct EIn {
-  T hx, hy, hz, hzy, hzx, hyx, hxy;  // H at k (own and -x, -y neighbours)
-  T ex, ey, ez;                      // E^n
-  T emx, emy, emz;                   // E^{n-1} (metal)
-  T jx, jy, jz;                      // J^{n-1/2} (metal)
-  T q, qx, qy;                       // Q at node k, k + e_x, k + e_y (metal)
-  uint8_t mb;
-};
-
-// One tile of the E/J sweep.
-template <class T, int TY>
-__device__ __forceinline__ void ej_tile(const Params<T>& p, int blk) {
+template <class T, int TY, bool METAL, bool PML>
+__device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, bool pml_tile) {
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const Tile tile = decode_tile(p.tl, blk);
-  if (!tile.ok) return;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int i = tile.bx * kBX + tx;
   const int j = tile.by * TY + ty;
   const int k0 = tile.bz * p.tl.kz;
   const int k1 = min(nz, k0 + p.tl.kz);
+  // lanes outside the grid stay in metal tiles (the plane sums of J_x use
+  // whole wavefronts) but load and store nothing
   const bool active = i < nx && j < ny;
+  if (!METAL && !active) return;
   const size_t sy = nx, sz = (size_t)nx * ny;
   const T* __restrict__ Hx = p.H[0];
   const T* __restrict__ Hy = p.H[1];
@@ -284,86 +316,83 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, int blk) {
   const bool ax = active && i <= nx - 2 && j >= 1 && j <= ny - 2;
   const bool ay = active && i >= 1 && i <= nx - 2 && j <= ny - 2;
   const bool az = active && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
-  const int sxe = np ? slab_e(i, nx, np) : -1;
-  const int sye = np ? slab_e(j, ny, np) : -1;
+  const int sxe = (PML && pml_tile && active) ? slab_e(i, nx, np) : -1;
+  const int sye = (PML && pml_tile && active) ? slab_e(j, ny, np) : -1;
+  const CpmlAxis<T>& Z = p.cp[2];
+  T xb = T(0), xa = T(0), xk = T(1), yb = T(0), ya = T(0), yk = T(1);
+  if (sxe >= 0) { xb = p.cp[0].be[sxe]; xa = p.cp[0].ae[sxe]; xk = p.cp[0].ke[sxe]; }
+  if (sye >= 0) { yb = p.cp[1].be[sye]; ya = p.cp[1].ae[sye]; yk = p.cp[1].ke[sye]; }
   const bool tf_xband = p.tfsf && i >= p.tf_lo[0] && i <= p.tf_hi[0] - 1 && j >= p.tf_lo[1] &&
                         j <= p.tf_hi[1];
   const bool tf_zside = p.tfsf && j >= p.tf_lo[1] && j <= p.tf_hi[1] &&
                         (i == p.tf_lo[0] || i == p.tf_hi[0]);
-  const int x0 = tile.bx * kBX, y0 = tile.by * TY;
-  const bool metal_tile = p.any_metal && x0 < p.mlo[0] + p.mn[0] && x0 + kBX > p.mlo[0] &&
-                          y0 < p.mlo[1] + p.mn[1] && y0 + TY > p.mlo[1] &&
-                          k0 < p.mlo[2] + p.mn[2] && k1 > p.mlo[2];
   const int lx = i - p.mlo[0], ly = j - p.mlo[1];
-  const bool col_sub = metal_tile && active && lx >= 0 && ly >= 0 && lx < p.mn[0] && ly < p.mn[1];
+  const bool col_sub = METAL && active && lx >= 0 && ly >= 0 && lx < p.mn[0] && ly < p.mn[1];
   const size_t m1 = p.mn[0], m2 = (size_t)p.mn[0] * p.mn[1];
   const size_t lcol = col_sub ? (size_t)ly * m1 + lx : 0;
-  auto mask_at = [&](int k) -> uint8_t {
-    const int lz = k - p.mlo[2];
-    return (col_sub && k < k1 && lz >= 0 && lz < p.mn[2]) ? p.mask[(size_t)lz * m2 + lcol] : 0;
-  };
-  // E-type ranges in k: E_x, E_y need 1 <= k <= nz-2; E_z needs k <= nz-2
-  auto load = [&](int k, size_t id, uint8_t mb, EIn<T>& v) {
-    const bool zin = k >= 1 && k <= nz - 2;
-    v.hx = active ? Hx[id] : T(0);
-    v.hy = active ? Hy[id] : T(0);
-    v.hz = active ? Hz[id] : T(0);
-    v.hzy = (active && j >= 1) ? Hz[id - sy] : T(0);
-    v.hzx = (active && i >= 1) ? Hz[id - 1] : T(0);
-    v.hyx = (active && i >= 1) ? Hy[id - 1] : T(0);
-    v.hxy = (active && j >= 1) ? Hx[id - sy] : T(0);
-    v.ex = (ax && zin) ? Ex[id] : T(0);
-    v.ey = (ay && zin) ? Ey[id] : T(0);
-    v.ez = (az && k <= nz - 2) ? Ez[id] : T(0);
-    v.mb = mb;
-    if (mb) {
-      const size_t l = (size_t)(k - p.mlo[2]) * m2 + lcol;
-      v.emx = (mb & 1u) ? Ox[id] : T(0);
-      v.emy = (mb & 2u) ? Oy[id] : T(0);
-      v.emz = (mb & 4u) ? Oz[id] : T(0);
-      v.jx = (mb & 1u) ? p.Ji[0][l] : T(0);
-      v.jy = (mb & 2u) ? p.Ji[1][l] : T(0);
-      v.jz = (mb & 4u) ? p.Ji[2][l] : T(0);
-      // metal points lie >= 2 cells inside the sub-grid: +x, +y, +z nodes exist
-      v.q = p.Q[l];
-      v.qx = (mb & 1u) ? p.Q[l + 1] : T(0);
-      v.qy = (mb & 2u) ? p.Q[l + m1] : T(0);
-    } else {
-      v.emx = v.emy = v.emz = v.jx = v.jy = v.jz = v.q = v.qx = v.qy = T(0);
-    }
-  };
 
-  size_t id = (size_t)k0 * sz + (size_t)j * nx + i;
+  size_t id = (size_t)k0 * sz + (size_t)(active ? j : 0) * nx + (active ? i : 0);
   T hxm = T(0), hym = T(0);  // H at k-1 for the z differences
-  if (active && k0 >= 1) {
+  if (active && k0 >= 1 && k0 < k1) {
     hxm = Hx[id - sz];
     hym = Hy[id - sz];
   }
-  uint8_t mk1 = mask_at(k0 + 1);
-  EIn<T> cur, nxt;
-  load(k0, id, mask_at(k0), cur);
-  T qz = T(0);  // Q at node (i, j, k+1) for E_z
+  T qz = T(0);  // Q at node (i, j, k+1) for E_z (metal)
   for (int k = k0; k < k1; ++k, id += sz) {
-    const uint8_t mk2 = mask_at(k + 2);
-    if (k + 1 < k1) load(k + 1, id + sz, mk1, nxt);
-    if (cur.mb & 4u) qz = p.Q[(size_t)(k + 1 - p.mlo[2]) * m2 + lcol];
+    // E-type ranges in k: E_x, E_y need 1 <= k <= nz-2; E_z needs k <= nz-2
     const bool zin = k >= 1 && k <= nz - 2;
     const bool ux = ax && zin, uy = ay && zin, uz = az && k <= nz - 2;
+    const T hx = active ? Hx[id] : T(0), hy = active ? Hy[id] : T(0), hz = active ? Hz[id] : T(0);
+    const T hzy = (active && j >= 1) ? Hz[id - sy] : T(0);
+    const T hxy = (active && j >= 1) ? Hx[id - sy] : T(0);
+    const T hzx = (active && i >= 1) ? Hz[id - 1] : T(0);
+    const T hyx = (active && i >= 1) ? Hy[id - 1] : T(0);
+    const T ex = ux ? Ex[id] : T(0), ey = uy ? Ey[id] : T(0), ez = uz ? Ez[id] : T(0);
     // curl H (index units): E_x: dy Hz - dz Hy; E_y: dz Hx - dx Hz; E_z: dx Hy - dy Hx
-    T d_yx = cur.hz - cur.hzy, d_zx = cur.hy - hym;
-    T d_zy = cur.hx - hxm, d_xy = cur.hz - cur.hzx;
-    T d_xz = cur.hy - cur.hyx, d_yz = cur.hx - cur.hxy;
-    if (np) {
+    T d_yx = hz - hzy, d_zx = hy - hym;
+    T d_zy = hx - hxm, d_xy = hz - hzx;
+    T d_xz = hy - hyx, d_yz = hx - hxy;
+    if (PML && pml_tile) {
       const int sze = slab_e(k, nz, np);
-      const CpmlAxis<T>& X = p.cp[0];
-      const CpmlAxis<T>& Y = p.cp[1];
-      const CpmlAxis<T>& Z = p.cp[2];
-      if (ux && sye >= 0) d_yx = stretch(p.psiE[1][0], slab_index(1, sye, i, j, k, nx, ny, np), Y.be[sye], Y.ae[sye], Y.ke[sye], d_yx);
-      if (ux && sze >= 0) d_zx = stretch(p.psiE[2][1], slab_index(2, sze, i, j, k, nx, ny, np), Z.be[sze], Z.ae[sze], Z.ke[sze], d_zx);
-      if (uy && sze >= 0) d_zy = stretch(p.psiE[2][0], slab_index(2, sze, i, j, k, nx, ny, np), Z.be[sze], Z.ae[sze], Z.ke[sze], d_zy);
-      if (uy && sxe >= 0) d_xy = stretch(p.psiE[0][1], slab_index(0, sxe, i, j, k, nx, ny, np), X.be[sxe], X.ae[sxe], X.ke[sxe], d_xy);
-      if (uz && sxe >= 0) d_xz = stretch(p.psiE[0][0], slab_index(0, sxe, i, j, k, nx, ny, np), X.be[sxe], X.ae[sxe], X.ke[sxe], d_xz);
-      if (uz && sye >= 0) d_yz = stretch(p.psiE[1][1], slab_index(1, sye, i, j, k, nx, ny, np), Y.be[sye], Y.ae[sye], Y.ke[sye], d_yz);
+      if (ux && sye >= 0) {
+        T* q = p.psiE[1][0] + slab_index(1, sye, i, j, k, nx, ny, np);
+        const T ps = yb * *q + ya * d_yx;
+        *q = ps;
+        d_yx = yk * d_yx + ps;
+      }
+      if (sze >= 0) {
+        const T zb = Z.be[sze], za = Z.ae[sze], zk = Z.ke[sze];
+        if (ux) {
+          T* q = p.psiE[2][1] + slab_index(2, sze, i, j, k, nx, ny, np);
+          const T ps = zb * *q + za * d_zx;
+          *q = ps;
+          d_zx = zk * d_zx + ps;
+        }
+        if (uy) {
+          T* q = p.psiE[2][0] + slab_index(2, sze, i, j, k, nx, ny, np);
+          const T ps = zb * *q + za * d_zy;
+          *q = ps;
+          d_zy = zk * d_zy + ps;
+        }
+      }
+      if (uy && sxe >= 0) {
+        T* q = p.psiE[0][1] + slab_index(0, sxe, i, j, k, nx, ny, np);
+        const T ps = xb * *q + xa * d_xy;
+        *q = ps;
+        d_xy = xk * d_xy + ps;
+      }
+      if (uz && sxe >= 0) {
+        T* q = p.psiE[0][0] + slab_index(0, sxe, i, j, k, nx, ny, np);
+        const T ps = xb * *q + xa * d_xz;
+        *q = ps;
+        d_xz = xk * d_xz + ps;
+      }
+      if (uz && sye >= 0) {
+        T* q = p.psiE[1][1] + slab_index(1, sye, i, j, k, nx, ny, np);
+        const T ps = yb * *q + ya * d_yz;
+        *q = ps;
+        d_yz = yk * d_yz + ps;
+      }
     }
     T cxv = d_yx - d_zx, cyv = d_zy - d_xy, czv = d_xz - d_yz;
     // TF/SF: total-field E next to the box surface sees H_inc^{n+1/2} outside
@@ -375,172 +404,287 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, int blk) {
       const T inc = (T)p.h1[k + kAuxOff];
       czv += (i == p.tf_lo[0]) ? -inc : inc;
     }
-    T nx_ = cur.ex + SE * cxv, ny_ = cur.ey + SE * cyv, nz_ = cur.ez + SE * czv;
-    double jsum = 0.0;
-    const uint8_t mb = cur.mb;
-    if (mb) {
-      const size_t l = (size_t)(k - p.mlo[2]) * m2 + lcol;
-      T cS = p.cS, c3 = p.c3, c1 = p.c1, cJ = p.cJ, cG = p.cG, d3 = p.d3, r = T(1);
-      if (p.rho) {
-        r = (T)p.rho[l];
-        d3 = r * p.d3;
-        const T inv = T(1) / (p.eps_inf + d3);
-        cS = p.S * inv; c3 = T(3) * d3 * inv; c1 = d3 * inv; cJ = p.D2 * inv; cG = inv;
+    T nx_ = ex + SE * cxv, ny_ = ey + SE * cyv, nz_ = ez + SE * czv;
+    if (METAL) {
+      const int lz = k - p.mlo[2];
+      const bool zsub = lz >= 0 && lz < p.mn[2];
+      const size_t l = (col_sub && zsub) ? (size_t)lz * m2 + lcol : 0;
+      const uint32_t mb = (col_sub && zsub) ? p.mask[l] : 0u;
+      double jsum = 0.0;
+      if (mb) {
+        // metal points lie >= 2 cells inside the sub-grid: +x, +y, +z nodes exist
+        const bool b0 = mb & 1u, b1 = mb & 2u, b2 = mb & 4u;
+        const T emx = b0 ? Ox[id] : T(0), emy = b1 ? Oy[id] : T(0), emz = b2 ? Oz[id] : T(0);
+        const T jx = b0 ? p.Ji[0][l] : T(0), jy = b1 ? p.Ji[1][l] : T(0);
+        const T jz = b2 ? p.Ji[2][l] : T(0);
+        const T q = p.Q[l];
+        const T qx = b0 ? p.Q[l + 1] : T(0), qy = b1 ? p.Q[l + m1] : T(0);
+        qz = b2 ? p.Q[l + m2] : T(0);
+        T cS = p.cS, c3 = p.c3, c1 = p.c1, cJ = p.cJ, cG = p.cG, d3 = p.d3, r = T(1);
+        if (p.rho) {
+          r = (T)p.rho[l];
+          d3 = r * p.d3;
+          const T inv = T(1) / (p.eps_inf + d3);
+          cS = p.S * inv; c3 = T(3) * d3 * inv; c1 = d3 * inv; cJ = p.D2 * inv; cG = inv;
+        }
+        const T ag = p.agam;
+        if (b0) {
+          const T G = r * (qx - q);
+          const T en = ex + (cS * cxv - c3 * ex - c1 * emx + cJ * jx - cG * G);
+          const T jn = jx + (d3 * (emx + T(2) * ex + en) - ag * jx + G);
+          p.Jo[0][l] = jn;
+          jsum = (double)jn + (double)p.ebd * ((double)en - (double)ex);
+          nx_ = en;
+        }
+        if (b1) {
+          const T G = r * (qy - q);
+          const T en = ey + (cS * cyv - c3 * ey - c1 * emy + cJ * jy - cG * G);
+          p.Jo[1][l] = jy + (d3 * (emy + T(2) * ey + en) - ag * jy + G);
+          ny_ = en;
+        }
+        if (b2) {
+          const T G = r * (qz - q);
+          const T en = ez + (cS * czv - c3 * ez - c1 * emz + cJ * jz - cG * G);
+          p.Jo[2][l] = jz + (d3 * (emz + T(2) * ez + en) - ag * jz + G);
+          nz_ = en;
+        }
       }
-      const T ag = p.agam;
-      if (mb & 1u) {
-        const T G = r * (cur.qx - cur.q);
-        const T en = cur.ex + (cS * cxv - c3 * cur.ex - c1 * cur.emx + cJ * cur.jx - cG * G);
-        const T jn = cur.jx + (d3 * (cur.emx + T(2) * cur.ex + en) - ag * cur.jx + G);
-        p.Jo[0][l] = jn;
-        jsum = (double)jn + (double)p.ebd * ((double)en - (double)cur.ex);
-        nx_ = en;
-      }
-      if (mb & 2u) {
-        const T G = r * (cur.qy - cur.q);
-        const T en = cur.ey + (cS * cyv - c3 * cur.ey - c1 * cur.emy + cJ * cur.jy - cG * G);
-        p.Jo[1][l] = cur.jy + (d3 * (cur.emy + T(2) * cur.ey + en) - ag * cur.jy + G);
-        ny_ = en;
-      }
-      if (mb & 4u) {
-        const T G = r * (qz - cur.q);
-        const T en = cur.ez + (cS * czv - c3 * cur.ez - c1 * cur.emz + cJ * cur.jz - cG * G);
-        p.Jo[2][l] = cur.jz + (d3 * (cur.emz + T(2) * cur.ez + en) - ag * cur.jz + G);
-        nz_ = en;
+      // per-wavefront plane sum of J_x for the spectra (fixed order); a
+      // wavefront without metal in the plane keeps its zero entry
+      if (zsub && __any(mb != 0u)) {
+        const double s = wave_sum(jsum);
+        if (tx == 0) {
+          const int nbxy = p.tl.nbx * p.tl.nby * TY;
+          p.jpart[(size_t)k * nbxy + (tile.by * p.tl.nbx + tile.bx) * TY + ty] = s;
+        }
       }
     }
     if (ux) Ox[id] = nx_;
     if (uy) Oy[id] = ny_;
     if (uz) Oz[id] = nz_;
-    // per-wavefront plane sum of J_x for the spectra (fixed order)
-    const int lz = k - p.mlo[2];
-    if (metal_tile && lz >= 0 && lz < p.mn[2]) {
-      const double s = wave_sum(jsum);
-      if (tx == 0) {
-        const int nbxy = p.tl.nbx * p.tl.nby * TY;
-        p.jpart[(size_t)k * nbxy + (tile.by * p.tl.nbx + tile.bx) * TY + ty] = s;
-      }
-    }
-    hxm = cur.hx;
-    hym = cur.hy;
-    cur = nxt;
-    mk1 = mk2;
+    hxm = hx;
+    hym = hy;
   }
+}
+
+// Does a tile meet the metal sub-grid (the metal points' bounding box plus
+// one cell) or a CPML slab?
+template <class T, int TY>
+__device__ __forceinline__ bool tile_meets_pml(const Params<T>& p, const Tile& t) {
+  const int np = p.cp[0].np;
+  const int z0 = t.bz * p.tl.kz, z1 = min(p.nz, z0 + p.tl.kz);
+  return range_in_slabs(t.bx * kBX, t.bx * kBX + kBX, p.nx, np) ||
+         range_in_slabs(t.by * TY, t.by * TY + TY, p.ny, np) || range_in_slabs(z0, z1, p.nz, np);
+}
+
+template <class T, int TY, int CLS>
+__device__ __forceinline__ void h_class(const Params<T>& p, int b) {
+  const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
+  if (!tile.ok) return;
+  if (CLS == 0) h_tile<T, TY, false, false>(p, tile, false);
+  else if (CLS == 1) h_tile<T, TY, false, true>(p, tile, true);
+  else h_tile<T, TY, true, true>(p, tile, tile_meets_pml<T, TY>(p, tile));
+}
+template <class T, int TY, int CLS>
+__device__ __forceinline__ void ej_class(const Params<T>& p, int b) {
+  const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
+  if (!tile.ok) return;
+  if (CLS == 0) ej_tile<T, TY, false, false>(p, tile, false);
+  else if (CLS == 1) ej_tile<T, TY, false, true>(p, tile, true);
+  else ej_tile<T, TY, true, true>(p, tile, tile_meets_pml<T, TY>(p, tile));
 }
 
 // ---------------------------------------------------------------- kernels
-// Single simulation: tiles, then the auxiliary-line block last.
-template <class T, int TY>
+// Single simulation: one launch per tile class; the class-0 launch has one
+// extra block (the last) that advances the auxiliary line.
+template <class T, int TY, int CLS>
 __global__ void __launch_bounds__(kBX* TY) k_h(Params<T> p, AuxParams a) {
-  if ((int)blockIdx.x == (int)gridDim.x - 1) {
+  if (CLS == 0 && (int)blockIdx.x == (int)gridDim.x - 1) {
     aux_h_block(a, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  h_tile<T, TY>(p, blockIdx.x);
+  h_class<T, TY, CLS>(p, blockIdx.x);
 }
 
-template <class T, int TY>
+template <class T, int TY, int CLS>
 __global__ void __launch_bounds__(kBX* TY) k_ej(Params<T> p, AuxParams a, int sub) {
-  if ((int)blockIdx.x == (int)gridDim.x - 1) {
+  if (CLS == 0 && (int)blockIdx.x == (int)gridDim.x - 1) {
     aux_e_block(a, sub, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  ej_tile<T, TY>(p, blockIdx.x);
+  ej_class<T, TY, CLS>(p, blockIdx.x);
 }
 
-// Batch: the blocks of all instances in one launch.  Instance q owns blocks
-// [blk0, blk0 + nblk) (its tiles, then its auxiliary-line block); a block
-// finds its instance by binary search over the table.
+// Batch: the blocks of all instances in one launch per class.  Instance q
+// owns blocks [blk0[c], blk0[c] + nblk[c]) of class c (for class 0 its tiles,
+// then its auxiliary-line block); a block finds its instance by binary search.
 template <class T>
 __device__ __forceinline__ int find_instance(const BatchEntry<T>* __restrict__ e, int n, int b,
-                                             bool dft) {
+                                             int c) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if ((dft ? e[mid].dblk0 : e[mid].hblk0) <= b) lo = mid;
+    if ((c < 0 ? e[mid].dblk0 : e[mid].blk0[c]) <= b) lo = mid;
     else hi = mid - 1;
   }
   return lo;
 }
 
-template <class T, int TY>
+template <class T, int TY, int CLS>
 __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __restrict__ e, int n) {
-  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, false)];
-  const int b = blockIdx.x - en.hblk0;
-  if (b == en.hnblk - 1) {
+  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
+  const int b = blockIdx.x - en.blk0[CLS];
+  if (CLS == 0 && b == en.nblk[0] - 1) {
     aux_h_block(en.a, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  h_tile<T, TY>(en.p, b);
+  h_class<T, TY, CLS>(en.p, b);
 }
 
-template <class T, int TY>
+template <class T, int TY, int CLS>
 __global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __restrict__ e, int n,
                                                       int sub) {
-  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, false)];
-  const int b = blockIdx.x - en.hblk0;
-  if (b == en.hnblk - 1) {
+  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
+  const int b = blockIdx.x - en.blk0[CLS];
+  if (CLS == 0 && b == en.nblk[0] - 1) {
     aux_e_block(en.a, sub, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  ej_tile<T, TY>(en.p, b);
+  ej_class<T, TY, CLS>(en.p, b);
 }
 
 }  // namespace
 
+// ------------------------------------------------------------ host helpers
 Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd) {
-  Tiling t;
+  Tiling t{};
   t.ty = ty;
   t.kz = kz;
   t.xcd = xcd;
   t.nbx = (nx + kBX - 1) / kBX;
   t.nby = (ny + ty - 1) / ty;
   t.nbz = (nz + kz - 1) / kz;
-  const int tiles = t.nbx * t.nby * t.nbz;
   t.q = t.nbx * 8;  // chunk: 8 rows of tiles
-  if (xcd == 2) t.per = ((tiles + t.q - 1) / t.q + 7) / 8;  // chunks per XCD
-  else t.per = (tiles + 7) / 8;
   return t;
 }
 
-int sweep_blocks(const Tiling& t) {
-  // + the auxiliary-line block
-  const int tiles = t.xcd == 1 ? 8 * t.per : (t.xcd == 2 ? 8 * t.per * t.q : t.nbx * t.nby * t.nbz);
-  return tiles + 1;
+static bool tile_meets_metal_host(const Tiling& t, int tile, const int mlo[3], const int mn[3],
+                           bool any_metal, int nz) {
+  if (!any_metal) return false;
+  const int bx = tile % t.nbx, by = (tile / t.nbx) % t.nby, bz = tile / (t.nbx * t.nby);
+  const int x0 = bx * kBX, y0 = by * t.ty, z0 = bz * t.kz;
+  const int x1 = x0 + kBX, y1 = y0 + t.ty, z1 = std::min(nz, z0 + t.kz);
+  return x0 < mlo[0] + mn[0] && x1 > mlo[0] && y0 < mlo[1] + mn[1] && y1 > mlo[1] &&
+         z0 < mlo[2] + mn[2] && z1 > mlo[2];
 }
 
+void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int mlo[3], const int mn[3],
+                    bool any_metal, std::vector<int>& list) {
+  const int T = t.nbx * t.nby * t.nbz;
+  std::vector<int> cls[3];
+  auto slab = [&](int lo, int hi, int n) { return np > 0 && (lo < np || hi > n - 1 - np); };
+  for (int tile = 0; tile < T; ++tile) {
+    const int bx = tile % t.nbx, by = (tile / t.nbx) % t.nby, bz = tile / (t.nbx * t.nby);
+    const int z0 = bz * t.kz, z1 = std::min(nz, z0 + t.kz);
+    int c = 0;
+    if (tile_meets_metal_host(t, tile, mlo, mn, any_metal, nz)) c = 2;
+    else if (slab(bx * kBX, bx * kBX + kBX, nx) || slab(by * t.ty, by * t.ty + t.ty, ny) ||
+             slab(z0, z1, nz))
+      c = 1;
+    cls[c].push_back(tile);
+  }
+  list.clear();
+  for (int c = 0; c < 3; ++c) {
+    t.coff[c] = (int)list.size();
+    t.cn[c] = (int)cls[c].size();
+    list.insert(list.end(), cls[c].begin(), cls[c].end());
+    if (t.xcd == 1) t.cper[c] = (t.cn[c] + 7) / 8;
+    else if (t.xcd == 2) t.cper[c] = ((t.cn[c] + t.q - 1) / t.q + 7) / 8;  // chunks per XCD
+    else t.cper[c] = t.cn[c];
+  }
+}
+
+int class_blocks(const Tiling& t, int c) {
+  if (t.cn[c] == 0) return 0;
+  if (t.xcd == 1) return 8 * t.cper[c];
+  if (t.xcd == 2) return 8 * t.cper[c] * t.q;
+  return t.cn[c];
+}
+
+namespace {
+template <class T, int CLS>
+void launch_h_cls(const Params<T>& p, const AuxParams& a, hipStream_t s) {
+  const int blocks = class_blocks(p.tl, CLS) + (CLS == 0 ? 1 : 0);
+  if (blocks == 0) return;
+  if (p.tl.ty == 4) hipLaunchKernelGGL((k_h<T, 4, CLS>), dim3(blocks), dim3(kBX, 4), 0, s, p, a);
+  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_h<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, p, a);
+  else hipLaunchKernelGGL((k_h<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, p, a);
+}
+template <class T, int CLS>
+void launch_ej_cls(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s) {
+  const int blocks = class_blocks(p.tl, CLS) + (CLS == 0 ? 1 : 0);
+  if (blocks == 0) return;
+  if (p.tl.ty == 4) hipLaunchKernelGGL((k_ej<T, 4, CLS>), dim3(blocks), dim3(kBX, 4), 0, s, p, a, sub);
+  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_ej<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, p, a, sub);
+  else hipLaunchKernelGGL((k_ej<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, p, a, sub);
+}
+template <class T, int CLS>
+void launch_h_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s) {
+  if (blocks == 0) return;
+  if (ty == 4) hipLaunchKernelGGL((k_h_batch<T, 4, CLS>), dim3(blocks), dim3(kBX, 4), 0, s, e, n);
+  else if (ty == 8) hipLaunchKernelGGL((k_h_batch<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, e, n);
+  else hipLaunchKernelGGL((k_h_batch<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, e, n);
+}
+template <class T, int CLS>
+void launch_ej_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, hipStream_t s) {
+  if (blocks == 0) return;
+  if (ty == 4) hipLaunchKernelGGL((k_ej_batch<T, 4, CLS>), dim3(blocks), dim3(kBX, 4), 0, s, e, n, sub);
+  else if (ty == 8) hipLaunchKernelGGL((k_ej_batch<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, e, n, sub);
+  else hipLaunchKernelGGL((k_ej_batch<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, e, n, sub);
+}
+}  // namespace
+
+template <class T>
+void launch_h_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s) {
+  if (c == 0) launch_h_cls<T, 0>(p, a, s);
+  else if (c == 1) launch_h_cls<T, 1>(p, a, s);
+  else launch_h_cls<T, 2>(p, a, s);
+}
+template <class T>
+void launch_ej_class(const Params<T>& p, const AuxParams& a, int sub, int c, hipStream_t s) {
+  if (c == 0) launch_ej_cls<T, 0>(p, a, sub, s);
+  else if (c == 1) launch_ej_cls<T, 1>(p, a, sub, s);
+  else launch_ej_cls<T, 2>(p, a, sub, s);
+}
 template <class T>
 void launch_h(const Params<T>& p, const AuxParams& a, hipStream_t s) {
-  const int blocks = sweep_blocks(p.tl);
-  if (p.tl.ty == 4) hipLaunchKernelGGL((k_h<T, 4>), dim3(blocks), dim3(kBX, 4), 0, s, p, a);
-  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_h<T, 8>), dim3(blocks), dim3(kBX, 8), 0, s, p, a);
-  else hipLaunchKernelGGL((k_h<T, 2>), dim3(blocks), dim3(kBX, 2), 0, s, p, a);
+  for (int c = 0; c < 3; ++c) launch_h_class<T>(p, a, c, s);
 }
 template <class T>
 void launch_ej(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s) {
-  const int blocks = sweep_blocks(p.tl);
-  if (p.tl.ty == 4) hipLaunchKernelGGL((k_ej<T, 4>), dim3(blocks), dim3(kBX, 4), 0, s, p, a, sub);
-  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_ej<T, 8>), dim3(blocks), dim3(kBX, 8), 0, s, p, a, sub);
-  else hipLaunchKernelGGL((k_ej<T, 2>), dim3(blocks), dim3(kBX, 2), 0, s, p, a, sub);
+  for (int c = 0; c < 3; ++c) launch_ej_class<T>(p, a, sub, c, s);
 }
-
+template void launch_h_class<float>(const Params<float>&, const AuxParams&, int, hipStream_t);
+template void launch_h_class<double>(const Params<double>&, const AuxParams&, int, hipStream_t);
+template void launch_ej_class<float>(const Params<float>&, const AuxParams&, int, int, hipStream_t);
+template void launch_ej_class<double>(const Params<double>&, const AuxParams&, int, int, hipStream_t);
 template <class T>
-void launch_h_batch(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s) {
-  if (ty == 4) hipLaunchKernelGGL((k_h_batch<T, 4>), dim3(blocks), dim3(kBX, 4), 0, s, e, n);
-  else if (ty == 8) hipLaunchKernelGGL((k_h_batch<T, 8>), dim3(blocks), dim3(kBX, 8), 0, s, e, n);
-  else hipLaunchKernelGGL((k_h_batch<T, 2>), dim3(blocks), dim3(kBX, 2), 0, s, e, n);
+void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[3], int ty, hipStream_t s) {
+  launch_h_batch_cls<T, 0>(e, n, blocks[0], ty, s);
+  launch_h_batch_cls<T, 1>(e, n, blocks[1], ty, s);
+  launch_h_batch_cls<T, 2>(e, n, blocks[2], ty, s);
 }
 template <class T>
-void launch_ej_batch(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, hipStream_t s) {
-  if (ty == 4) hipLaunchKernelGGL((k_ej_batch<T, 4>), dim3(blocks), dim3(kBX, 4), 0, s, e, n, sub);
-  else if (ty == 8) hipLaunchKernelGGL((k_ej_batch<T, 8>), dim3(blocks), dim3(kBX, 8), 0, s, e, n, sub);
-  else hipLaunchKernelGGL((k_ej_batch<T, 2>), dim3(blocks), dim3(kBX, 2), 0, s, e, n, sub);
+void launch_ej_batch(const BatchEntry<T>* e, int n, const int blocks[3], int ty, int sub,
+                     hipStream_t s) {
+  launch_ej_batch_cls<T, 0>(e, n, blocks[0], ty, sub, s);
+  launch_ej_batch_cls<T, 1>(e, n, blocks[1], ty, sub, s);
+  launch_ej_batch_cls<T, 2>(e, n, blocks[2], ty, sub, s);
 }
-template void launch_h_batch<float>(const BatchEntry<float>*, int, int, int, hipStream_t);
-template void launch_h_batch<double>(const BatchEntry<double>*, int, int, int, hipStream_t);
-template void launch_ej_batch<float>(const BatchEntry<float>*, int, int, int, int, hipStream_t);
-template void launch_ej_batch<double>(const BatchEntry<double>*, int, int, int, int, hipStream_t);
-
+template void launch_h_batch<float>(const BatchEntry<float>*, int, const int[3], int, hipStream_t);
+template void launch_h_batch<double>(const BatchEntry<double>*, int, const int[3], int, hipStream_t);
+template void launch_ej_batch<float>(const BatchEntry<float>*, int, const int[3], int, int, hipStream_t);
+template void launch_ej_batch<double>(const BatchEntry<double>*, int, const int[3], int, int, hipStream_t);
 template void launch_h<float>(const Params<float>&, const AuxParams&, hipStream_t);
 template void launch_h<double>(const Params<double>&, const AuxParams&, hipStream_t);
 template void launch_ej<float>(const Params<float>&, const AuxParams&, int, hipStream_t);
