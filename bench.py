@@ -9,8 +9,11 @@ CPML), FP32 fields and currents with FP64 spectral accumulators.
 
 Prints one JSON line:  value = Gcell-updates/s (nx ny nz steps / time) of the
 FP32 path; roofline = achieved algorithmic HBM bytes / s of the dominant
-kernel (E/J update) from HIP events on the library's stream; cpu_baseline =
-the FP64 CPU oracle on the host cores on a 10-step sample of the same grid.
+kernel (the E/J sweep, one launch per tile class, timed as a whole) from HIP
+events on the library's stream; traffic = its measured HBM bytes per sweep
+from the committed rocprofv3 counter summary when that summary was taken on
+the current kernel sources (else null); cpu_baseline = the FP64 CPU oracle on
+the host cores on a short sample of the same grid.
 """
 from __future__ import annotations
 
@@ -26,6 +29,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "step_kernels_sphere320_fp32.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per sweep of `kernel` (sum over its tile-class launches) from
+    the rocprofv3 counter summary, or None if the summary is missing or was
+    taken on other kernel sources."""
+    try:
+        from paper_2005_06997_amd.rocprof_summary import source_hash
+        text = open(PROFILE_SUMMARY).read()
+    except (OSError, ImportError):
+        return None
+    import re
+    m = re.search(r"library source hash \(csrc/\*\): `([0-9a-f]+)`", text)
+    if not m or m.group(1) != source_hash():
+        return None
+    m = re.search(r"<!-- traffic " + re.escape(kernel) + r" sweep ([0-9.e+]+) -->", text)
+    return float(m.group(1)) if m else None
 
 
 def algorithmic_bytes(w, mask, word):
@@ -46,12 +67,16 @@ def algorithmic_bytes(w, mask, word):
     return h, ej, nm, cd
 
 
-def run_gpu(w, precision, steps, warmup):
+def run_gpu(w, precision, steps, warmup, tiling=None):
     import torch
     from paper_2005_06997_amd import binding
 
     sim = binding.Sim(w, precision=precision)
-    sim.tiling = sim.autotune(trial_steps=10)  # timed search over sweep tilings (state reset after)
+    if tiling is None:
+        sim.tiling = sim.autotune(trial_steps=10)  # timed search over sweep tilings (state reset after)
+    else:
+        sim.set_tiling(*tiling)
+        sim.tiling = dict(ty=tiling[0], kz=tiling[1], xcd=tiling[2], cached=False)
     sim.run(warmup)
     sim.synchronize()
     torch.cuda.synchronize()
@@ -91,6 +116,8 @@ def main():
                     help="steps of the design-gradient run (forward + adjoint; 0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=256,
                     help="steps of the 64-instance batched sweep (0 = skip)")
+    ap.add_argument("--tiling", type=str, default=None,
+                    help="ty,kz,order: fixed sweep tiling instead of the autotuner (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2 GiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -112,11 +139,16 @@ def main():
     from paper_2005_06997_amd import workloads as W
 
     w = W.config2("fp32")
-    sim, dt = run_gpu(w, "fp32", args.steps, args.warmup)
+    tiling = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
+    sim, dt = run_gpu(w, "fp32", args.steps, args.warmup, tiling)
     value = w.cells * args.steps / dt / 1e9
     ms_step = dt / args.steps * 1e3
     spec32 = sim.spectra()  # after warmup + steps, before profiling adds steps
     prof = sim.profile(args.profile_steps)
+    classes = sim.tile_classes()
+    sim.set_fused(True)
+    prof_fused = sim.profile(max(2, args.profile_steps // 4))
+    sim.set_fused(False)
     hb, ejb, nmetal, ncd = algorithmic_bytes(w, sim.mask, 4)
     ach = ejb / (prof["ej"] * 1e-3) / 1e9
     out = {
@@ -135,13 +167,20 @@ def main():
         "config": {"workload": "sphere_r10nm_320^3_dx0.1nm_gnor_fp32_fields_fp64_spectra",
                    "grid": [w.nx, w.ny, w.nz], "npml": w.npml, "metal_cells": nmetal,
                    "nfreq": int(len(w.omega)), "flux_boxes": bool(w.flux)},
-        "roofline": {"bound": "hbm", "kernel": "k_ej (E/J update)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_ej (E/J sweep = one launch per tile class, timed together)",
                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_ej"),
                      "bytes_per_launch": ejb, "avg_launch_ms": round(prof["ej"], 5)},
-        "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
+        "kernels_ms": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in prof.items()},
+        "tile_classes": {"plain": classes[0], "cpml": classes[1], "metal": classes[2]},
         "tiling": {k: sim.tiling[k] for k in ("ty", "kz", "xcd")},
         "h_roofline_frac": round(hb / (prof["h"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_roofline_frac": round((hb + ejb) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "fused_step": {"note": "one-pass H+E/J variant (12 instead of 18 field words per cell), "
+                               "not the default: slower here, see DESIGN.md",
+                       "step_ms": round(prof_fused["step"], 5),
+                       "classes_ms": [round(v, 5) for v in prof_fused["h_cls"]]},
     }
     del sim
     torch.cuda.empty_cache()

@@ -178,17 +178,27 @@ gnor_status gnor_check_finite(gnor_sim *sim);
 /* Average device time per launch (ms) of each kernel over nsteps steps run
  * with events around every launch on the bound stream (no graphs):
  * ms[0] H sweep (with the auxiliary line's H half), ms[1] E/J sweep (with the
- * auxiliary line's E half), ms[2] spectra and flux staging, ms[3] unused (0),
- * ms[4] flux accumulation (per step, amortised).  count must be >= 5. */
+ * auxiliary line's E half), ms[2] spectra and flux staging, ms[3] fused step
+ * (when fused; see below), ms[4] flux accumulation (per step, amortised).
+ * count must be >= 5; the state advances by nsteps. */
 gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int32_t count);
 
-/* Each sweep runs as one launch per tile class: 0 tiles that meet neither
- * the metal sub-grid nor a CPML slab, 1 tiles that meet a CPML slab only,
- * 2 tiles that meet the metal sub-grid.  With count >= 11,
- * gnor_profile_kernels also returns ms[5 + c] (H sweep, class c) and
- * ms[8 + c] (E/J sweep, class c); class 0 includes the auxiliary line.
+/* The field update runs as one launch per tile class: 0 tiles that meet
+ * neither the metal sub-grid nor a CPML slab, 1 tiles that meet a CPML slab
+ * only, 2 tiles that meet the metal sub-grid (a tile counts with a one-cell
+ * margin).  By default a step is the two-sweep form (H sweep, then E/J
+ * sweep); gnor_set_fused(sim, 1) selects one fused pass (H and E/J together,
+ * 12 instead of 18 field words moved per cell) plus a one-block launch that
+ * advances the auxiliary line.  Both give the same fields up to rounding;
+ * batches and gnor_gradient always use the two-sweep form.
+ * gnor_profile_kernels with count >= 12 returns, besides ms[0..4]:
+ * ms[5 + c] the H sweep's (or the fused step's) class c, ms[8 + c] the E/J
+ * sweep's class c, ms[11] the auxiliary-line launch; in fused form ms[0] =
+ * ms[1] = 0 and ms[3] holds the fused step (classes + auxiliary line).
  * gnor_tile_classes writes the number of tiles of each class of the current
- * tiling to counts[0..2] (valid once the memory is bound). */
+ * tiling to counts[0..2] (valid once the memory is bound).
+ * gnor_set_fused: on must be 0 or 1 (INVALID_ARG otherwise). */
+gnor_status gnor_set_fused(gnor_sim *sim, int32_t on);
 gnor_status gnor_tile_classes(const gnor_sim *sim, int32_t *counts);
 
 /* Sweep tiling: each block owns 64 (x) x ty (y) columns over kz planes;

@@ -99,6 +99,7 @@ def load() -> C.CDLL:
         "gnor_check_finite": (i32, [vp]),
         "gnor_profile_kernels": (i32, [vp, i64, dp, i32]),
         "gnor_tile_classes": (i32, [vp, C.POINTER(C.c_int32)]),
+        "gnor_set_fused": (i32, [vp, i32]),
         "gnor_set_tiling": (i32, [vp, i32, i32, i32]),
         "gnor_autotune": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp]),
         "gnor_voxelize_spheres": (i32, [i32, i32, i32, dbl, i32, vp, vp]),
@@ -276,10 +277,15 @@ class Sim:
     def profile(self, nsteps: int) -> Dict[str, float]:
         """Average ms per launch of the H sweep, E/J sweep, spectra+staging and
         (amortised per step) flux accumulation, from HIP events."""
-        ms = np.zeros(11)
-        self._check(self.L.gnor_profile_kernels(self.h, int(nsteps), _dp(ms), 11))
-        return dict(h=ms[0], ej=ms[1], dft=ms[2], flux_acc=ms[4],
-                    h_cls=[float(v) for v in ms[5:8]], ej_cls=[float(v) for v in ms[8:11]])
+        ms = np.zeros(12)
+        self._check(self.L.gnor_profile_kernels(self.h, int(nsteps), _dp(ms), 12))
+        return dict(h=ms[0], ej=ms[1], dft=ms[2], step=ms[3], flux_acc=ms[4],
+                    h_cls=[float(v) for v in ms[5:8]], ej_cls=[float(v) for v in ms[8:11]],
+                    aux=float(ms[11]), fused=bool(ms[3] > 0))
+
+    def set_fused(self, on: bool):
+        """One-pass fused step, or the two-sweep form (the default)."""
+        self._check(self.L.gnor_set_fused(self.h, 1 if on else 0))
 
     def tile_classes(self):
         """Tiles per class (plain Yee, CPML, metal) of the current tiling."""

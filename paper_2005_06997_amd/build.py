@@ -18,6 +18,7 @@ COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
 
 SOURCES = [
     ("gnor_sweeps.hip", []),
+    ("gnor_fused.hip", []),
     ("gnor_spectra.hip", []),
     ("gnor_adjoint.hip", []),
     # the voxelisers' floating-point tests must not be contracted into FMAs

@@ -1,0 +1,119 @@
+// Device helpers shared by the kernels of libgnorfdtd (not part of the ABI).
+#pragma once
+
+#include "gnor_internal.h"
+
+namespace gnor {
+namespace {
+
+__device__ __forceinline__ int slab_e(int g, int n, int np) {
+  return g < np ? g : (g >= n - np ? g - (n - 2 * np) : -1);
+}
+__device__ __forceinline__ int slab_h(int g, int n, int np) {
+  return g < np ? g : (g >= n - 1 - np ? g - (n - 1 - 2 * np) : -1);
+}
+// index into an axis-`a` slab array with slab coordinate s replacing axis a
+__device__ __forceinline__ size_t slab_index(int a, int s, int i, int j, int k, int nx, int ny,
+                                             int np) {
+  const int w = 2 * np;
+  if (a == 0) return ((size_t)k * ny + j) * w + s;
+  if (a == 1) return ((size_t)k * w + s) * nx + i;
+  return ((size_t)s * ny + j) * nx + i;
+}
+
+struct Tile {
+  int bx, by, bz;
+  bool ok;
+};
+// Block b of the launch for tile class c -> tile.  The class's tiles are
+// listed in natural order (x fastest, then y, then z); the position in the
+// list follows the tile order of the tiling (blocks are dealt round-robin to
+// the 8 XCDs).
+__device__ __forceinline__ Tile decode_tile(const Tiling& tl, const int* __restrict__ list, int c,
+                                            int b) {
+  Tile r;
+  int pos = b;
+  if (tl.xcd == 1) {
+    pos = (b & 7) * tl.cper[c] + (b >> 3);
+  } else if (tl.xcd == 2) {
+    const int rank = b >> 3;  // the block's rank on its XCD
+    pos = ((rank / tl.q) * 8 + (b & 7)) * tl.q + rank % tl.q;
+  }
+  r.ok = pos < tl.cn[c];
+  const int t = r.ok ? list[tl.coff[c] + pos] : 0;
+  r.bx = t % tl.nbx;
+  r.by = (t / tl.nbx) % tl.nby;
+  r.bz = t / (tl.nbx * tl.nby);
+  return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------ auxiliary line
+__device__ double source_value(const AuxParams& a, double t) {
+  if (a.src_kind == 1) {
+    const double u = (t - a.t0) / a.tau;
+    return a.e0 * exp(-u * u) * sin(a.omega_c * (t - a.t0));
+  }
+  if (a.src_kind == 2) {
+    if (t < 0.0 || t > 2.0 * M_PI / a.omega_max) return 0.0;
+    const double s = 0.5 * (1.0 - cos(a.omega_max * t));
+    return a.e0 * s * s * s;
+  }
+  return 0.0;
+}
+
+__device__ void aux_h_block(const AuxParams& a, int tid, int nthr) {
+  for (int q = tid; q <= a.n1 - 2; q += nthr) {
+    const double d = a.e1[q + 1] - a.e1[q];
+    const double ps = a.bh[q] * a.ph[q] + a.ah[q] * d;
+    a.ph[q] = ps;
+    a.h1[q] -= a.S * (a.kh[q] * d + ps);
+  }
+}
+
+__device__ void aux_e_block(const AuxParams& a, int sub, int tid, int nthr) {
+  for (int q = 1 + tid; q <= a.n1 - 2; q += nthr) {
+    const double d = a.h1[q] - a.h1[q - 1];
+    const double ps = a.be[q] * a.pe[q] + a.ae[q] * d;
+    a.pe[q] = ps;
+    a.e1[q] -= a.SE * (a.ke[q] * d + ps);
+  }
+  const int64_t n = a.step_base[0] + sub;
+  // phase table of this step for the running transforms (e^{+i w t})
+  const double tJ = ((double)n + 0.5) * a.dt, tE = ((double)n + 1.0) * a.dt;
+  for (int m = tid; m < a.nf; m += nthr) {
+    double s, c;
+    sincos(a.omega[m] * tJ, &s, &c);
+    a.phase[m] = c;
+    a.phase[a.nf + m] = s;
+    sincos(a.omega[m] * tE, &s, &c);
+    a.phase[2 * a.nf + m] = c;
+    a.phase[3 * a.nf + m] = s;
+  }
+  __syncthreads();
+  if (tid == 0) a.e1[kAuxSrc] += source_value(a, (double)(n + 1) * a.dt);
+}
+
+// [lo, hi) meets [0, np) or [n - 1 - np, n)  (the E and H slabs of an axis)
+__device__ __forceinline__ bool range_in_slabs(int lo, int hi, int n, int np) {
+  // [lo, hi) meets [0, np) or [n - 1 - np, n)  (the E and H slabs of an axis)
+  return np > 0 && (lo < np || hi > n - 1 - np);
+}
+
+// Does a tile (widened by one cell: the fused step's halo) meet a CPML slab?
+template <class T, int TY>
+__device__ __forceinline__ bool tile_meets_pml(const Params<T>& p, const Tile& t) {
+  const int np = p.cp[0].np;
+  const int z0 = t.bz * p.tl.kz, z1 = min(p.nz, z0 + p.tl.kz);
+  return range_in_slabs(t.bx * kBX - 1, t.bx * kBX + kBX + 1, p.nx, np) ||
+         range_in_slabs(t.by * TY - 1, t.by * TY + TY + 1, p.ny, np) ||
+         range_in_slabs(z0 - 1, z1 + 1, p.nz, np);
+}
+
+}  // namespace
+}  // namespace gnor

@@ -105,7 +105,8 @@ struct Params {
   // full-grid fields
   T* E[3];        // E^n
   T* O[3];        // E^{n-1} (read at metal points) -> E^{n+1} (written everywhere)
-  T* H[3];
+  const T* Hi[3]; // H^{n-1/2} (the step's input buffer)
+  T* H[3];        // H^{n+1/2} (the step's output buffer)
   // metal sub-grid [mlo, mlo + mn)
   int any_metal;
   int mlo[3], mn[3];
@@ -121,8 +122,10 @@ struct Params {
   T* Q;                 // Q of the step's node scalars (written by k_h, read by k_ej)
   T eps_inf, d3, agam, D2, g1, g2, ebd;  // ebd = eps_inf - eps_b
   T cS, c3, c1, cJ, cG;                   // E metal coefficients divided by (eps_inf + d3)
-  // CPML memory: psi[axis][t], t = 0 for component (axis+2)%3, 1 for (axis+1)%3
+  // CPML memory: psi[axis][t], t = 0 for component (axis+2)%3, 1 for (axis+1)%3;
+  // psi_E is updated in place, psi_H read from psiHi and written to psiH
   T* psiE[3][2];
+  const T* psiHi[3][2];
   T* psiH[3][2];
   CpmlAxis<T> cp[3];
   // TF/SF
@@ -252,6 +255,13 @@ template <class T>
 void launch_h_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s);
 template <class T>
 void launch_ej_class(const Params<T>& p, const AuxParams& a, int sub, int c, hipStream_t s);
+// fused step (H, E/J in one pass; one launch per tile class) and the
+// auxiliary line's step, which must follow it
+template <class T>
+void launch_step_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s);
+void launch_aux(const AuxParams& a, int sub, hipStream_t s);
+template <class T>
+void launch_step(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s);
 template <class T>
 void launch_h(const Params<T>& p, const AuxParams& a, hipStream_t s);
 template <class T>

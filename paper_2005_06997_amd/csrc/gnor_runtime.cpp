@@ -56,9 +56,9 @@ struct Layout {
   size_t static_end = 0;
   // state region
   size_t state_begin = 0;
-  size_t E[2][3] = {{0}}, H[3] = {0, 0, 0};
+  size_t E[2][3] = {{0}}, H[2][3] = {{0}};
   size_t J[2][3] = {{0}}, PP[2] = {0, 0}, PJ[2] = {0, 0}, Q = 0;
-  size_t psiE[3][2] = {{0}}, psiH[3][2] = {{0}};
+  size_t psiE[3][2] = {{0}}, psiH[2][3][2] = {{{0}}};
   size_t aux = 0, phase = 0, jpart = 0, dft = 0, fstage = 0, facc = 0, ptab = 0, step = 0,
          flux_lo = 0, flag = 0, fsum = 0;
   size_t state_end = 0;
@@ -89,14 +89,19 @@ struct gnor_sim {
   int nsamp = 0, npairs = 0, npairs_box0 = 0, slots = gnor::kFluxSlots;
   std::vector<gnor::FluxSeg> fseg;
   std::vector<double> fpw;
-  int tile_ty = 4, tile_kz = 32, tile_xcd = 0;   // sweep tiling (autotuned)
+  int tile_ty = 2, tile_kz = 8, tile_xcd = 2;    // sweep tiling (autotuned)
   gnor::Tiling tl{};                              // that tiling with its tile classes
   std::vector<int> tile_list;                     // the classes' tile lists (host copy)
+  bool fused = false;                             // one-pass step (else H and E/J sweeps)
   Layout L;
   char* dev = nullptr;
   size_t dev_bytes = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // the tile classes of a sweep run concurrently: class 0 on the bound
+  // stream, classes 1 and 2 on two side streams (fork / join by events)
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int64_t step = 0;
   int graph_chunk = 64;
   hipGraphExec_t graph = nullptr;
@@ -215,7 +220,9 @@ void plan_layout(gnor_sim* s) {
   L.state_begin = P.off;
   for (int pp = 0; pp < 2; ++pp)
     for (int c = 0; c < 3; ++c) L.E[pp][c] = P.take(N * e);
-  for (int c = 0; c < 3; ++c) L.H[c] = P.take(N * e);
+  // H^{n-1/2} in H[n mod 2]; a step writes H^{n+1/2} into the other buffer
+  for (int pp = 0; pp < 2; ++pp)
+    for (int c = 0; c < 3; ++c) L.H[pp][c] = P.take(N * e);
   for (int pp = 0; pp < 2; ++pp) {
     for (int c = 0; c < 3; ++c) L.J[pp][c] = P.take(M * e);
     L.PP[pp] = P.take(M * e);
@@ -227,7 +234,7 @@ void plan_layout(gnor_sim* s) {
   for (int a = 0; a < 3; ++a)
     for (int t = 0; t < 2; ++t) {
       L.psiE[a][t] = P.take(slab[a] * e + 8);
-      L.psiH[a][t] = P.take(slab[a] * e + 8);
+      for (int pp = 0; pp < 2; ++pp) L.psiH[pp][a][t] = P.take(slab[a] * e + 8);
     }
   L.aux = P.take((size_t)4 * s->n1 * 8);
   L.phase = P.take((size_t)4 * std::max(1, s->mon.nfreq) * 8);
@@ -261,7 +268,8 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   for (int c = 0; c < 3; ++c) {
     p.E[c] = ptr<T>(s, s->L.E[a][c]);
     p.O[c] = ptr<T>(s, s->L.E[b][c]);
-    p.H[c] = ptr<T>(s, s->L.H[c]);
+    p.Hi[c] = ptr<T>(s, s->L.H[a][c]);
+    p.H[c] = ptr<T>(s, s->L.H[b][c]);
     p.Ji[c] = ptr<T>(s, s->L.J[a][c]);
     p.Jo[c] = ptr<T>(s, s->L.J[b][c]);
   }
@@ -294,7 +302,8 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   for (int ax = 0; ax < 3; ++ax) {
     for (int t = 0; t < 2; ++t) {
       p.psiE[ax][t] = ptr<T>(s, s->L.psiE[ax][t]);
-      p.psiH[ax][t] = ptr<T>(s, s->L.psiH[ax][t]);
+      p.psiHi[ax][t] = ptr<T>(s, s->L.psiH[a][ax][t]);
+      p.psiH[ax][t] = ptr<T>(s, s->L.psiH[b][ax][t]);
     }
     gnor::CpmlAxis<T>& c = p.cp[ax];
     c.n = nn[ax]; c.np = np;
@@ -370,12 +379,34 @@ gnor::FluxParams make_flux(gnor_sim* s) {
 }
 
 // Enqueue one step; `sub` is the step's offset from the device step counter.
+// The three tile-class launches of a sweep, concurrently: class 0 on st,
+// classes 1 and 2 on the side streams, joined back into st.  (Also inside a
+// graph capture of st: the side streams join the capture through the fork
+// event.)  launch(c, stream) enqueues class c.
+template <class F>
+void enqueue_classes(gnor_sim* s, hipStream_t st, F launch) {
+  (void)hipEventRecord(s->ev_fork, st);
+  for (int q = 0; q < 2; ++q) (void)hipStreamWaitEvent(s->side[q], s->ev_fork, 0);
+  launch(0, st);
+  launch(1, s->side[0]);
+  launch(2, s->side[1]);
+  for (int q = 0; q < 2; ++q) {
+    (void)hipEventRecord(s->ev_join[q], s->side[q]);
+    (void)hipStreamWaitEvent(st, s->ev_join[q], 0);
+  }
+}
+
 template <class T>
-void enqueue_step(gnor_sim* s, int parity, int sub, hipStream_t st) {
+void enqueue_step(gnor_sim* s, int parity, int sub, bool fused, hipStream_t st) {
   const gnor::Params<T> p = make_params<T>(s, parity);
   const gnor::AuxParams a = make_aux(s);
-  gnor::launch_h<T>(p, a, st);
-  gnor::launch_ej<T>(p, a, sub, st);
+  if (fused) {
+    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_step_class<T>(p, a, c, q); });
+    gnor::launch_aux(a, sub, st);
+  } else {
+    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_h_class<T>(p, a, c, q); });
+    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_ej_class<T>(p, a, sub, c, q); });
+  }
   if (s->mon.nfreq > 0) gnor::launch_dft_stage<T>(make_dft(s), make_flux(s), p, sub, st);
 }
 
@@ -383,13 +414,15 @@ void enqueue_flux_acc(gnor_sim* s, int sub, hipStream_t st) {
   gnor::launch_flux_accumulate(make_flux(s), ptr<int>(s, s->L.flux_lo), sub, st);
 }
 
-void enqueue_steps_eager(gnor_sim* s, int64_t n0, int64_t count, hipStream_t st) {
+// fused: one-pass step kernels (the sim's setting), else the two sweeps (the
+// adjoint's forward recompute, which needs the stored Q)
+void enqueue_steps_eager(gnor_sim* s, int64_t n0, int64_t count, hipStream_t st, bool fused) {
   // steps n0 .. n0+count-1; the device counter holds n0 on entry
   for (int64_t q = 0; q < count; ++q) {
     const int64_t n = n0 + q;
     const int sub = (int)q;
-    if (s->g.precision == GNOR_FP32) enqueue_step<float>(s, (int)(n & 1), sub, st);
-    else enqueue_step<double>(s, (int)(n & 1), sub, st);
+    if (s->g.precision == GNOR_FP32) enqueue_step<float>(s, (int)(n & 1), sub, fused, st);
+    else enqueue_step<double>(s, (int)(n & 1), sub, fused, st);
     if (s->nsamp > 0 && (n % s->slots) == s->slots - 1) enqueue_flux_acc(s, sub, st);
   }
   gnor::launch_advance(ptr<int64_t>(s, s->L.step), count, st);
@@ -406,7 +439,7 @@ gnor_status build_graph(gnor_sim* s, int steps) {
   hipGraph_t gr = nullptr;
   HIPCHECK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
   // the chunk always starts at an even step aligned to the flux staging depth
-  enqueue_steps_eager(s, 0, steps, s->stream);
+  enqueue_steps_eager(s, 0, steps, s->stream, s->fused);
   HIPCHECK(s, hipStreamEndCapture(s->stream, &gr));
   hipError_t e = hipGraphInstantiate(&s->graph, gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
@@ -594,6 +627,11 @@ void gnor_destroy(gnor_sim* s) {
   if (!s) return;
   drop_graph(s);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  for (int q = 0; q < 2; ++q) {
+    if (s->side[q]) (void)hipStreamDestroy(s->side[q]);
+    if (s->ev_join[q]) (void)hipEventDestroy(s->ev_join[q]);
+  }
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   delete s;
 }
 
@@ -757,6 +795,13 @@ gnor_status gnor_bind_memory(gnor_sim* s, void* dptr, size_t bytes, void* stream
     HIPCHECK(s, hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
     s->own_stream = true;
   }
+  if (!s->side[0]) {
+    for (int q = 0; q < 2; ++q) {
+      HIPCHECK(s, hipStreamCreateWithFlags(&s->side[q], hipStreamNonBlocking));
+      HIPCHECK(s, hipEventCreateWithFlags(&s->ev_join[q], hipEventDisableTiming));
+    }
+    HIPCHECK(s, hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+  }
   s->dev = reinterpret_cast<char*>(dptr);
   s->dev_bytes = bytes;
   s->bound = true;
@@ -765,6 +810,15 @@ gnor_status gnor_bind_memory(gnor_sim* s, void* dptr, size_t bytes, void* stream
   st = plan_tiles(s);
   if (st != GNOR_OK) return st;
   return gnor_reset(s);
+}
+
+gnor_status gnor_set_fused(gnor_sim* s, int32_t on) {
+  if (!s || (on != 0 && on != 1)) return GNOR_E_INVALID_ARG;
+  if ((on != 0) != s->fused) {
+    s->fused = on != 0;
+    drop_graph(s);
+  }
+  return GNOR_OK;
 }
 
 gnor_status gnor_set_graph_chunk(gnor_sim* s, int32_t steps) {
@@ -801,7 +855,7 @@ gnor_status gnor_run(gnor_sim* s, int64_t nsteps) {
       n = to_align > 0 ? std::min(left, to_align) : std::min(left, (int64_t)chunk);
       if (to_align == 0 && left < chunk) n = left;
     }
-    enqueue_steps_eager(s, s->step, n, s->stream);
+    enqueue_steps_eager(s, s->step, n, s->stream, s->fused);
     HIPCHECK(s, hipGetLastError());
     s->step += n;
     left -= n;
@@ -907,7 +961,7 @@ gnor_status gnor_get_field(gnor_sim* s, int32_t which, double* dst, size_t count
     if (st != GNOR_OK) return st;
     std::memcpy(dst, v.data(), s->N * 8);
   } else if (which < 6) {
-    st = fetch(s->L.H[c], s->N, v);
+    st = fetch(s->L.H[s->step & 1][c], s->N, v);
     if (st != GNOR_OK) return st;
     const double k = 1.0 / eta0();
     for (size_t q = 0; q < s->N; ++q) dst[q] = v[q] * k;
@@ -979,10 +1033,10 @@ gnor_status gnor_check_finite(gnor_sim* s) {
   for (int c = 0; c < 3; ++c) {
     if (s->g.precision == GNOR_FP32) {
       gnor::launch_nonfinite<float>(ptr<float>(s, s->L.E[parity][c]), s->N, flag, s->stream);
-      gnor::launch_nonfinite<float>(ptr<float>(s, s->L.H[c]), s->N, flag, s->stream);
+      gnor::launch_nonfinite<float>(ptr<float>(s, s->L.H[s->step & 1][c]), s->N, flag, s->stream);
     } else {
       gnor::launch_nonfinite<double>(ptr<double>(s, s->L.E[parity][c]), s->N, flag, s->stream);
-      gnor::launch_nonfinite<double>(ptr<double>(s, s->L.H[c]), s->N, flag, s->stream);
+      gnor::launch_nonfinite<double>(ptr<double>(s, s->L.H[s->step & 1][c]), s->N, flag, s->stream);
     }
   }
   int h = 0;
@@ -995,13 +1049,15 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
   if (!ms || count < 5 || nsteps <= 0) return GNOR_E_INVALID_ARG;
-  // events: 0 | H class 0 | 1 | H class 1 | 2 | H class 2 | 3 | E/J 0 | 4 | E/J 1 | 5 | E/J 2 | 6
-  //         | spectra | 7 | flux accumulation | 8
-  constexpr int NE = 9;
+  // events around: class launches 0..2 of the first sweep (H, or the fused
+  // step), classes 0..2 of the E/J sweep (two-sweep form) or the auxiliary
+  // line (fused form), the spectra, the flux accumulation
+  constexpr int NE = 10;
   hipEvent_t ev[NE];
   for (auto& e : ev) HIPCHECK(s, hipEventCreate(&e));
-  double acc[NE - 1] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[NE - 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const bool fp32 = s->g.precision == GNOR_FP32;
+  const bool fused = s->fused;
   for (int64_t q = 0; q < nsteps; ++q) {
     const int64_t n = s->step;
     const int parity = (int)(n & 1);
@@ -1009,14 +1065,26 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
     const gnor::AuxParams a = make_aux(s);
     (void)hipEventRecord(ev[0], str);
     for (int c = 0; c < 3; ++c) {
-      if (fp32) gnor::launch_h_class<float>(make_params<float>(s, parity), a, c, str);
-      else gnor::launch_h_class<double>(make_params<double>(s, parity), a, c, str);
+      if (fused) {
+        if (fp32) gnor::launch_step_class<float>(make_params<float>(s, parity), a, c, str);
+        else gnor::launch_step_class<double>(make_params<double>(s, parity), a, c, str);
+      } else {
+        if (fp32) gnor::launch_h_class<float>(make_params<float>(s, parity), a, c, str);
+        else gnor::launch_h_class<double>(make_params<double>(s, parity), a, c, str);
+      }
       (void)hipEventRecord(ev[1 + c], str);
     }
-    for (int c = 0; c < 3; ++c) {
-      if (fp32) gnor::launch_ej_class<float>(make_params<float>(s, parity), a, 0, c, str);
-      else gnor::launch_ej_class<double>(make_params<double>(s, parity), a, 0, c, str);
-      (void)hipEventRecord(ev[4 + c], str);
+    if (fused) {
+      gnor::launch_aux(a, 0, str);
+      (void)hipEventRecord(ev[4], str);
+      (void)hipEventRecord(ev[5], str);
+      (void)hipEventRecord(ev[6], str);
+    } else {
+      for (int c = 0; c < 3; ++c) {
+        if (fp32) gnor::launch_ej_class<float>(make_params<float>(s, parity), a, 0, c, str);
+        else gnor::launch_ej_class<double>(make_params<double>(s, parity), a, 0, c, str);
+        (void)hipEventRecord(ev[4 + c], str);
+      }
     }
     if (s->mon.nfreq > 0) {
       if (fp32) gnor::launch_dft_stage<float>(make_dft(s), make_flux(s), make_params<float>(s, parity), 0, str);
@@ -1026,8 +1094,9 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
     if (s->nsamp > 0 && (n % s->slots) == s->slots - 1) enqueue_flux_acc(s, 0, str);
     (void)hipEventRecord(ev[8], str);
     gnor::launch_advance(ptr<int64_t>(s, s->L.step), 1, str);
+    (void)hipEventRecord(ev[9], str);
     HIPCHECK(s, hipGetLastError());
-    HIPCHECK(s, hipEventSynchronize(ev[8]));
+    HIPCHECK(s, hipEventSynchronize(ev[9]));
     for (int e = 0; e < NE - 1; ++e) {
       float t = 0.f;
       (void)hipEventElapsedTime(&t, ev[e], ev[e + 1]);
@@ -1037,17 +1106,19 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   const double inv = 1.0 / (double)nsteps;
-  double out[11];
-  out[0] = (acc[0] + acc[1] + acc[2]) * inv;
-  out[1] = (acc[3] + acc[4] + acc[5]) * inv;
+  const double first = (acc[0] + acc[1] + acc[2]) * inv, second = (acc[3] + acc[4] + acc[5]) * inv;
+  double out[12];
+  out[0] = fused ? 0.0 : first;
+  out[1] = fused ? 0.0 : second;
   out[2] = acc[6] * inv;
-  out[3] = 0.0;
+  out[3] = fused ? first + second : 0.0;
   out[4] = acc[7] * inv;
   for (int c = 0; c < 3; ++c) {
     out[5 + c] = acc[c] * inv;
-    out[8 + c] = acc[3 + c] * inv;
+    out[8 + c] = fused ? 0.0 : acc[3 + c] * inv;
   }
-  for (int i = 0; i < count && i < 11; ++i) ms[i] = out[i];
+  out[11] = fused ? second : 0.0;
+  for (int i = 0; i < count && i < 12; ++i) ms[i] = out[i];
   return GNOR_OK;
 }
 
@@ -1527,7 +1598,7 @@ gnor_status gradient_impl(gnor_sim* s, int64_t nsteps, int C, int m, double* obj
     gnor::launch_store_design<T>(A, 1, ptr<T>(s, s->L.E[par][0]), ptr<T>(s, s->L.E[par][1]),
                                  ptr<T>(s, s->L.E[par][2]), 1, st);
     for (int t = 0; t < len; ++t) {
-      enqueue_steps_eager(s, s->step, 1, st);
+      enqueue_steps_eager(s, s->step, 1, st, false);
       s->step += 1;
       const int q = (int)((n0 + t + 1) & 1);
       A.t_idx = t;
@@ -1558,6 +1629,12 @@ extern "C" gnor_status gnor_gradient(gnor_sim* s, int64_t nsteps, int32_t ckpt_e
   if (s->mon.dft_every > 1) return fail(s, GNOR_E_INVALID_ARG, "gradients need dft_every = 1");
   if (s->mat.eps_inf != s->g.eps_background)
     return fail(s, GNOR_E_INVALID_ARG, "gradients need eps_inf = eps_background");
-  return s->g.precision == GNOR_FP32 ? gradient_impl<float>(s, nsteps, ckpt_every, m_target, objective, grad)
-                                     : gradient_impl<double>(s, nsteps, ckpt_every, m_target, objective, grad);
+  // the backward pass needs the stored Q of each recomputed step, so the whole
+  // gradient (forward pass included) runs on the two-sweep kernels
+  const bool fused = s->fused;
+  if (fused) { s->fused = false; drop_graph(s); }
+  st = s->g.precision == GNOR_FP32 ? gradient_impl<float>(s, nsteps, ckpt_every, m_target, objective, grad)
+                                   : gradient_impl<double>(s, nsteps, ckpt_every, m_target, objective, grad);
+  if (fused) { s->fused = true; drop_graph(s); }
+  return st;
 }

@@ -1,24 +1,26 @@
-// Field sweeps of libgnorfdtd (gfx950): the two HBM-bound kernels of a step.
+// Field sweeps of libgnorfdtd (gfx950): the H and E/J updates as two
+// HBM-bound passes (used for batches, for the adjoint's forward recompute
+// and as the reference for the fused step).
 //
 //   k_h   f1 (Sec. III): H^{n+1/2} = H^{n-1/2} - S curl E^n with CPML and the
 //         TF/SF corrections that use E_inc^n.  Tiles over the metal sub-grid
 //         also evaluate the node scalars of the current form of Eq.
 //         (GNORUpdate): Phi_J^{n-1/2} = Div J^{n-1/2},
 //         Phi_P^n = Phi_P^{n-1} + Phi_J and Q = g1 Phi_P^n + g2 (3 Phi_J -
-//         Phi_J^{n-3/2}) (k_h does not read J, Phi or Q, so no halo is
-//         needed).  One extra block advances the auxiliary line's H half.
+//         Phi_J^{n-3/2}).  The class-0 launch also advances the auxiliary
+//         line's H half.
 //   k_ej  f2 + f4: E^{n+1} and, at metal points, J^{n+1/2} with
 //         G_a = Q(node + e_a) - Q(node) (= D_G1 GD^n + D_G2 BDF2(GD) of Eq.
 //         GNORUpdate, Eq. GradDiv being Grad of the node divergence), CPML,
 //         TF/SF corrections with H_inc^{n+1/2}, and per-wavefront plane sums
-//         of J_x for the spectra.  One extra block advances the auxiliary
-//         line's E half (soft source) and writes the step's DFT phase table.
+//         of J_x for the spectra.  The class-0 launch also advances the
+//         auxiliary line's E half (soft source) and writes the step's DFT
+//         phase table.
 //
 // A block owns 64 (x, one wavefront) x TY (y) columns and marches them over
-// kz planes.  Every iteration first issues the loads of the NEXT plane, then
-// computes and stores the current one, so memory latency overlaps compute
-// and stores (register double buffering); no barriers.
-#include "gnor_internal.h"
+// kz planes; H and the H-slab CPML memory are read from the step's input
+// buffers and written to its output buffers.
+#include "gnor_device.h"
 
 #include <algorithm>
 #include <cmath>
@@ -27,99 +29,6 @@
 namespace gnor {
 
 namespace {
-
-__device__ __forceinline__ int slab_e(int g, int n, int np) {
-  return g < np ? g : (g >= n - np ? g - (n - 2 * np) : -1);
-}
-__device__ __forceinline__ int slab_h(int g, int n, int np) {
-  return g < np ? g : (g >= n - 1 - np ? g - (n - 1 - 2 * np) : -1);
-}
-// index into an axis-`a` slab array with slab coordinate s replacing axis a
-__device__ __forceinline__ size_t slab_index(int a, int s, int i, int j, int k, int nx, int ny,
-                                             int np) {
-  const int w = 2 * np;
-  if (a == 0) return ((size_t)k * ny + j) * w + s;
-  if (a == 1) return ((size_t)k * w + s) * nx + i;
-  return ((size_t)s * ny + j) * nx + i;
-}
-
-struct Tile {
-  int bx, by, bz;
-  bool ok;
-};
-// Block b of the launch for tile class c -> tile.  The class's tiles are
-// listed in natural order (x fastest, then y, then z); the position in the
-// list follows the tile order of the tiling (blocks are dealt round-robin to
-// the 8 XCDs).
-__device__ __forceinline__ Tile decode_tile(const Tiling& tl, const int* __restrict__ list, int c,
-                                            int b) {
-  Tile r;
-  int pos = b;
-  if (tl.xcd == 1) {
-    pos = (b & 7) * tl.cper[c] + (b >> 3);
-  } else if (tl.xcd == 2) {
-    const int rank = b >> 3;  // the block's rank on its XCD
-    pos = ((rank / tl.q) * 8 + (b & 7)) * tl.q + rank % tl.q;
-  }
-  r.ok = pos < tl.cn[c];
-  const int t = r.ok ? list[tl.coff[c] + pos] : 0;
-  r.bx = t % tl.nbx;
-  r.by = (t / tl.nbx) % tl.nby;
-  r.bz = t / (tl.nbx * tl.nby);
-  return r;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// ------------------------------------------------------------ auxiliary line
-__device__ double source_value(const AuxParams& a, double t) {
-  if (a.src_kind == 1) {
-    const double u = (t - a.t0) / a.tau;
-    return a.e0 * exp(-u * u) * sin(a.omega_c * (t - a.t0));
-  }
-  if (a.src_kind == 2) {
-    if (t < 0.0 || t > 2.0 * M_PI / a.omega_max) return 0.0;
-    const double s = 0.5 * (1.0 - cos(a.omega_max * t));
-    return a.e0 * s * s * s;
-  }
-  return 0.0;
-}
-
-__device__ void aux_h_block(const AuxParams& a, int tid, int nthr) {
-  for (int q = tid; q <= a.n1 - 2; q += nthr) {
-    const double d = a.e1[q + 1] - a.e1[q];
-    const double ps = a.bh[q] * a.ph[q] + a.ah[q] * d;
-    a.ph[q] = ps;
-    a.h1[q] -= a.S * (a.kh[q] * d + ps);
-  }
-}
-
-__device__ void aux_e_block(const AuxParams& a, int sub, int tid, int nthr) {
-  for (int q = 1 + tid; q <= a.n1 - 2; q += nthr) {
-    const double d = a.h1[q] - a.h1[q - 1];
-    const double ps = a.be[q] * a.pe[q] + a.ae[q] * d;
-    a.pe[q] = ps;
-    a.e1[q] -= a.SE * (a.ke[q] * d + ps);
-  }
-  const int64_t n = a.step_base[0] + sub;
-  // phase table of this step for the running transforms (e^{+i w t})
-  const double tJ = ((double)n + 0.5) * a.dt, tE = ((double)n + 1.0) * a.dt;
-  for (int m = tid; m < a.nf; m += nthr) {
-    double s, c;
-    sincos(a.omega[m] * tJ, &s, &c);
-    a.phase[m] = c;
-    a.phase[a.nf + m] = s;
-    sincos(a.omega[m] * tE, &s, &c);
-    a.phase[2 * a.nf + m] = c;
-    a.phase[3 * a.nf + m] = s;
-  }
-  __syncthreads();
-  if (tid == 0) a.e1[kAuxSrc] += source_value(a, (double)(n + 1) * a.dt);
-}
 
 // ------------------------------------------------------------ tile classes
 // Each sweep runs as three launches, one per tile class, so that each class
@@ -132,10 +41,6 @@ __device__ void aux_e_block(const AuxParams& a, int sub, int tid, int nthr) {
 // A wavefront marches its column over the tile's planes; every plane's loads
 // are issued together, then computed and stored.  Latency is hidden by the
 // other resident wavefronts.
-__device__ __forceinline__ bool range_in_slabs(int lo, int hi, int n, int np) {
-  // [lo, hi) meets [0, np) or [n - 1 - np, n)  (the E and H slabs of an axis)
-  return np > 0 && (lo < np || hi > n - 1 - np);
-}
 
 // ------------------------------------------------------------------ f1: H
 template <class T, int TY, bool METAL, bool PML>
@@ -153,6 +58,9 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
   T* __restrict__ Hx = p.H[0];
   T* __restrict__ Hy = p.H[1];
   T* __restrict__ Hz = p.H[2];
+  const T* __restrict__ Hi0 = p.Hi[0];  // H^{n-1/2} (input buffer)
+  const T* __restrict__ Hi1 = p.Hi[1];
+  const T* __restrict__ Hi2 = p.Hi[2];
   const T S = p.S;
   const int np = p.cp[0].np;
   const bool xin = i <= nx - 2, yin = j <= ny - 2;
@@ -199,7 +107,7 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
     const T ez = Ez[id];
     const T ezy = yin ? Ez[id + sy] : T(0), exy = yin ? Ex[id + sy] : T(0);
     const T ezx = xin ? Ez[id + 1] : T(0), eyx = xin ? Ey[id + 1] : T(0);
-    const T hx = ux ? Hx[id] : T(0), hy = uy ? Hy[id] : T(0), hz = uz ? Hz[id] : T(0);
+    const T hx = ux ? Hi0[id] : T(0), hy = uy ? Hi1[id] : T(0), hz = uz ? Hi2[id] : T(0);
     T dyx = ezy - ez, dzx = ey1 - ey0;   // H_x: dy Ez - dz Ey
     T dzy = ex1 - ex0, dxy = ezx - ez;   // H_y: dz Ex - dx Ez
     T dxz = eyx - ey0, dyz = exy - ex0;  // H_z: dx Ey - dy Ex
@@ -207,42 +115,42 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
       // CPML-stretched differences kinv d + psi with psi <- b psi + a d
       const int szh = slab_h(k, nz, np);
       if (ux && syh >= 0) {
-        T* q = p.psiH[1][0] + slab_index(1, syh, i, j, k, nx, ny, np);
-        const T ps = yb * *q + ya * dyx;
-        *q = ps;
+        const size_t q = slab_index(1, syh, i, j, k, nx, ny, np);
+        const T ps = yb * p.psiHi[1][0][q] + ya * dyx;
+        p.psiH[1][0][q] = ps;
         dyx = yk * dyx + ps;
       }
       if (szh >= 0) {
         const T zb = Z.bh[szh], za = Z.ah[szh], zk = Z.kh[szh];
         if (ux) {
-          T* q = p.psiH[2][1] + slab_index(2, szh, i, j, k, nx, ny, np);
-          const T ps = zb * *q + za * dzx;
-          *q = ps;
+          const size_t q = slab_index(2, szh, i, j, k, nx, ny, np);
+          const T ps = zb * p.psiHi[2][1][q] + za * dzx;
+          p.psiH[2][1][q] = ps;
           dzx = zk * dzx + ps;
         }
         if (uy) {
-          T* q = p.psiH[2][0] + slab_index(2, szh, i, j, k, nx, ny, np);
-          const T ps = zb * *q + za * dzy;
-          *q = ps;
+          const size_t q = slab_index(2, szh, i, j, k, nx, ny, np);
+          const T ps = zb * p.psiHi[2][0][q] + za * dzy;
+          p.psiH[2][0][q] = ps;
           dzy = zk * dzy + ps;
         }
       }
       if (uy && sxh >= 0) {
-        T* q = p.psiH[0][1] + slab_index(0, sxh, i, j, k, nx, ny, np);
-        const T ps = xb * *q + xa * dxy;
-        *q = ps;
+        const size_t q = slab_index(0, sxh, i, j, k, nx, ny, np);
+        const T ps = xb * p.psiHi[0][1][q] + xa * dxy;
+        p.psiH[0][1][q] = ps;
         dxy = xk * dxy + ps;
       }
       if (uz && sxh >= 0) {
-        T* q = p.psiH[0][0] + slab_index(0, sxh, i, j, k, nx, ny, np);
-        const T ps = xb * *q + xa * dxz;
-        *q = ps;
+        const size_t q = slab_index(0, sxh, i, j, k, nx, ny, np);
+        const T ps = xb * p.psiHi[0][0][q] + xa * dxz;
+        p.psiH[0][0][q] = ps;
         dxz = xk * dxz + ps;
       }
       if (uz && syh >= 0) {
-        T* q = p.psiH[1][1] + slab_index(1, syh, i, j, k, nx, ny, np);
-        const T ps = yb * *q + ya * dyz;
-        *q = ps;
+        const size_t q = slab_index(1, syh, i, j, k, nx, ny, np);
+        const T ps = yb * p.psiHi[1][1][q] + ya * dyz;
+        p.psiH[1][1][q] = ps;
         dyz = yk * dyz + ps;
       }
     }
@@ -467,16 +375,6 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
   }
 }
 
-// Does a tile meet the metal sub-grid (the metal points' bounding box plus
-// one cell) or a CPML slab?
-template <class T, int TY>
-__device__ __forceinline__ bool tile_meets_pml(const Params<T>& p, const Tile& t) {
-  const int np = p.cp[0].np;
-  const int z0 = t.bz * p.tl.kz, z1 = min(p.nz, z0 + p.tl.kz);
-  return range_in_slabs(t.bx * kBX, t.bx * kBX + kBX, p.nx, np) ||
-         range_in_slabs(t.by * TY, t.by * TY + TY, p.ny, np) || range_in_slabs(z0, z1, p.nz, np);
-}
-
 template <class T, int TY, int CLS>
 __device__ __forceinline__ void h_class(const Params<T>& p, int b) {
   const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
@@ -572,8 +470,9 @@ static bool tile_meets_metal_host(const Tiling& t, int tile, const int mlo[3], c
                            bool any_metal, int nz) {
   if (!any_metal) return false;
   const int bx = tile % t.nbx, by = (tile / t.nbx) % t.nby, bz = tile / (t.nbx * t.nby);
-  const int x0 = bx * kBX, y0 = by * t.ty, z0 = bz * t.kz;
-  const int x1 = x0 + kBX, y1 = y0 + t.ty, z1 = std::min(nz, z0 + t.kz);
+  // the tile widened by one cell on every side (the fused step's halo)
+  const int x0 = bx * kBX - 1, y0 = by * t.ty - 1, z0 = bz * t.kz - 1;
+  const int x1 = bx * kBX + kBX + 1, y1 = by * t.ty + t.ty + 1, z1 = std::min(nz, bz * t.kz + t.kz) + 1;
   return x0 < mlo[0] + mn[0] && x1 > mlo[0] && y0 < mlo[1] + mn[1] && y1 > mlo[1] &&
          z0 < mlo[2] + mn[2] && z1 > mlo[2];
 }
@@ -586,10 +485,11 @@ void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int mlo[3],
   for (int tile = 0; tile < T; ++tile) {
     const int bx = tile % t.nbx, by = (tile / t.nbx) % t.nby, bz = tile / (t.nbx * t.nby);
     const int z0 = bz * t.kz, z1 = std::min(nz, z0 + t.kz);
+    // ranges widened by one cell: the fused step also touches the tile's halo
     int c = 0;
     if (tile_meets_metal_host(t, tile, mlo, mn, any_metal, nz)) c = 2;
-    else if (slab(bx * kBX, bx * kBX + kBX, nx) || slab(by * t.ty, by * t.ty + t.ty, ny) ||
-             slab(z0, z1, nz))
+    else if (slab(bx * kBX - 1, bx * kBX + kBX + 1, nx) ||
+             slab(by * t.ty - 1, by * t.ty + t.ty + 1, ny) || slab(z0 - 1, z1 + 1, nz))
       c = 1;
     cls[c].push_back(tile);
   }

@@ -64,15 +64,26 @@ def main(argv):
                   f"{f_scale:.4f}, WRITE_SIZE scale {w_scale:.4f} (true bytes / counter bytes).", "",
               "| kernel | calls | avg us | FETCH MB/dispatch (scaled) | WRITE MB/dispatch (scaled) |"
               " HBM GB/s |", "|---|---|---|---|---|---|"]
-    for r in stats[:12]:
+    fam = defaultdict(lambda: [0.0, 0.0, 0.0])  # sweep: avg us, fetch MB, write MB (sum of classes)
+    for r in stats[:16]:
         k = short(r["Name"])
         avg = float(r["AverageNs"])
         fm = sum(f[k]) / len(f[k]) * 1024 * f_scale / 1e6 if k in f else float("nan")
         wm = sum(w[k]) / len(w[k]) * 1024 * w_scale / 1e6 if k in w else float("nan")
         bw = (fm + wm) * 1e6 / (avg * 1e-9) / 1e9 if avg > 0 else float("nan")
         lines.append(f"| {k} | {r['Calls']} | {avg / 1e3:.1f} | {fm:.1f} | {wm:.1f} | {bw:.0f} |")
-        if k.startswith("k_ej") or k.startswith("k_h<") or k.startswith("k_h"):
-            lines.append(f"<!-- traffic {k.split('<')[0]} {fm * 1e6 + wm * 1e6:.0f} -->")
+        base = k.split("<")[0]
+        if base in ("k_h", "k_ej", "k_step"):
+            e = fam[base]
+            e[0] += avg / 1e3
+            e[1] += fm
+            e[2] += wm
+    lines += ["", "Sweeps (one launch per tile class, classes summed; each class runs once per sweep):", "",
+              "| sweep | avg us | FETCH MB | WRITE MB | HBM GB/s |", "|---|---|---|---|---|"]
+    for base, (us, fm, wm) in sorted(fam.items()):
+        lines.append(f"| {base} | {us:.1f} | {fm:.1f} | {wm:.1f} | {(fm + wm) * 1e6 / (us * 1e-6) / 1e9:.0f} |")
+        lines.append(f"<!-- traffic {base} sweep {(fm + wm) * 1e6:.0f} -->")
+        lines.append(f"<!-- time {base} sweep {us:.2f} -->")
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 

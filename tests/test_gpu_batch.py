@@ -34,12 +34,18 @@ def test_batch_equals_individual_runs_bitwise(B, prec):
     ws = instances()
     print(f"case batch {prec}: sizes {[w.nx for w in ws]}", flush=True)
     steps = 131  # odd: eager steps around graph chunks
-    solo = []
+    solo, fused = [], []
     for w in ws:
         s = B.Sim(w, precision=prec)
         s.set_tiling(2, 8, 0)
+        s.set_fused(False)  # batches run the two-sweep kernels
         s.run(steps)
         solo.append(({f: s.field(f) for f in FIELDS}, s.spectra()))
+        s.close()
+        s = B.Sim(w, precision=prec)
+        s.set_fused(True)
+        s.run(steps)
+        fused.append(s.spectra())
         s.close()
     sims = [B.Sim(w, precision=prec) for w in ws]
     bt = B.Batch(sims, tiling=(2, 8, 0))
@@ -52,6 +58,12 @@ def test_batch_equals_individual_runs_bitwise(B, prec):
         sp = s.spectra()
         for k in spec:
             assert np.array_equal(sp[k], spec[k]), (s.w.name, k)
+    # the fused one-pass step gives the same spectra up to rounding
+    tol = 1e-5 if prec == "fp32" else 1e-12
+    for f_spec, s in zip(fused, sims):
+        sp = s.spectra()
+        for k in ("inc", "ext"):
+            assert rel_l2(f_spec[k], sp[k]) <= tol, (s.w.name, k)
 
 
 def test_batch_instance_vs_oracle(B):

@@ -102,6 +102,37 @@ def test_fp64_ragged_grid_and_general_cpml(B):
     compare(g, o, 1e-10, 1e-10)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fused_and_two_sweep_forms_agree(B, prec):
+    """The one-pass fused step and the two-sweep form (H sweep, then E/J
+    sweep) compute the same update; both match the oracle."""
+    w = W.early_pulse(W.config1(0))
+    w.omega = W.spectrum_omegas(20)
+    steps = 300
+    say(f"case fused vs two-sweep, {prec}")
+    runs = []
+    for fused in (True, False):
+        g = B.Sim(w, precision=prec)
+        g.set_fused(fused)
+        g.run(steps)
+        runs.append(g)
+    o = oracle_run(w, steps)
+    tol = (1e-10, 1e-10) if prec == "fp64" else (1e-3, 1e-4)
+    for g in runs:
+        compare(g, o, *tol)
+    # relative to the largest component of the same field (a component that
+    # is rounding noise, e.g. H_x here, is compared at that scale)
+    agree = 1e-12 if prec == "fp64" else 1e-5
+    fa = {f: runs[0].field(f) for f in FIELDS}
+    fb = {f: runs[1].field(f) for f in FIELDS}
+    for f in FIELDS:
+        scale = max(np.linalg.norm(fb[g]) for g in FIELDS if g[0] == f[0])
+        d = np.linalg.norm(fa[f] - fb[f]) / scale
+        say(f"  {f}: fused vs two-sweep {d:.2e}")
+        assert d <= agree, f
+    assert runs[0].profile(2)["fused"] and not runs[1].profile(2)["fused"]
+
+
 def test_fp64_vacuum_no_metal(B):
     w = W.early_pulse(W.small_sphere(n=30, radius=1.0e-9, npml=4, seed=4))
     w.omega = W.spectrum_omegas(10)
