@@ -276,10 +276,11 @@ void launch_flux_reduce(const double* acc_re, const double* acc_im, const double
 template <class T>
 void launch_nonfinite(const T* a, size_t n, int* flag, hipStream_t s);
 Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
-// Classify the tiles (metal sub-grid [mlo, mlo + mn), CPML slabs of np cells)
-// and fill the class counts, offsets and per-XCD counts of t; list receives
-// the three class lists back to back.
-void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int mlo[3], const int mn[3],
-                    bool any_metal, std::vector<int>& list);
+// Classify the tiles (metal: a metal point within two cells, by the per-row
+// x extents rowx of the metal points, null = no metal; CPML: slabs of np
+// cells within one cell) and fill the class counts, offsets and per-XCD
+// counts of t; list receives the three class lists back to back.
+void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
+                    std::vector<int>& list);
 
 }  // namespace gnor

@@ -92,6 +92,7 @@ struct gnor_sim {
   int tile_ty = 2, tile_kz = 8, tile_xcd = 2;    // sweep tiling (autotuned)
   gnor::Tiling tl{};                              // that tiling with its tile classes
   std::vector<int> tile_list;                     // the classes' tile lists (host copy)
+  std::vector<int> rowx;                          // x extent of the metal points per (y, z) row
   bool fused = false;                             // one-pass step (else H and E/J sweeps)
   Layout L;
   char* dev = nullptr;
@@ -481,7 +482,23 @@ gnor_status upload_rho(gnor_sim* s) {
 gnor_status plan_tiles(gnor_sim* s) {
   const gnor_grid_desc& g = s->g;
   s->tl = gnor::make_tiling(g.nx, g.ny, g.nz, s->tile_ty, s->tile_kz, s->tile_xcd);
-  gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->mlo, s->mn, s->any_metal, s->tile_list);
+  if (s->any_metal && s->rowx.empty()) {
+    // x extent of the metal points of every (y, z) row
+    s->rowx.assign((size_t)2 * g.ny * g.nz, 0);
+    for (size_t r = 0; r < (size_t)g.ny * g.nz; ++r) {
+      const uint8_t* row = s->mask.data() + r * g.nx;
+      int lo = 1, hi = 0;
+      for (int x = 0; x < g.nx; ++x)
+        if (row[x]) {
+          if (lo > hi) lo = x;
+          hi = x;
+        }
+      s->rowx[2 * r] = lo;
+      s->rowx[2 * r + 1] = hi;
+    }
+  }
+  gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->any_metal ? s->rowx.data() : nullptr,
+                       s->tile_list);
   if (s->bound && !s->tile_list.empty())
     HIPCHECK(s, hipMemcpy(s->dev + s->L.tiles, s->tile_list.data(), s->tile_list.size() * 4,
                           hipMemcpyHostToDevice));
@@ -643,6 +660,7 @@ gnor_status gnor_set_material(gnor_sim* s, const uint8_t* mask, const gnor_mater
   const gnor_grid_desc& g = s->g;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
   s->mask.assign(N, 0);
+  s->rowx.clear();
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
   bool any = false;
   if (mask) {
@@ -700,6 +718,7 @@ gnor_status gnor_set_design(gnor_sim* s, const int32_t* lo, const int32_t* hi, c
   for (int k = lo[2]; k < hi[2]; ++k)
     for (int j = lo[1]; j < hi[1]; ++j)
       for (int i = lo[0]; i < hi[0]; ++i) s->mask[((size_t)k * g.ny + j) * g.nx + i] = 7;
+  s->rowx.clear();
   s->any_metal = true;
   for (int d = 0; d < 3; ++d) {
     s->mlo[d] = mlo[d] - 1;

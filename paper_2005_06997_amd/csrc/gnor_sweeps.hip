@@ -466,19 +466,27 @@ Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd) {
   return t;
 }
 
-static bool tile_meets_metal_host(const Tiling& t, int tile, const int mlo[3], const int mn[3],
-                           bool any_metal, int nz) {
-  if (!any_metal) return false;
+// Does the tile, widened by two cells on every side, contain a metal point?
+// (Metal work, node scalars and the fused step's Q halo all lie within that
+// distance of a metal point.)  rowx[2 (k ny + j)] .. [+1]: first and last x
+// of the metal points of row (j, k) (first > last: none).
+static bool tile_meets_metal_host(const Tiling& t, int tile, int nx, int ny, int nz,
+                                  const int* rowx) {
+  if (!rowx) return false;
   const int bx = tile % t.nbx, by = (tile / t.nbx) % t.nby, bz = tile / (t.nbx * t.nby);
-  // the tile widened by one cell on every side (the fused step's halo)
-  const int x0 = bx * kBX - 1, y0 = by * t.ty - 1, z0 = bz * t.kz - 1;
-  const int x1 = bx * kBX + kBX + 1, y1 = by * t.ty + t.ty + 1, z1 = std::min(nz, bz * t.kz + t.kz) + 1;
-  return x0 < mlo[0] + mn[0] && x1 > mlo[0] && y0 < mlo[1] + mn[1] && y1 > mlo[1] &&
-         z0 < mlo[2] + mn[2] && z1 > mlo[2];
+  const int x0 = bx * kBX - 2, x1 = std::min(nx, bx * kBX + kBX) + 1;
+  const int y0 = std::max(0, by * t.ty - 2), y1 = std::min(ny - 1, by * t.ty + t.ty + 1);
+  const int z0 = std::max(0, bz * t.kz - 2), z1 = std::min(nz - 1, std::min(nz, bz * t.kz + t.kz) + 1);
+  for (int k = z0; k <= z1; ++k)
+    for (int j = y0; j <= y1; ++j) {
+      const int* r = rowx + 2 * ((size_t)k * ny + j);
+      if (r[0] <= r[1] && r[0] <= x1 && r[1] >= x0) return true;
+    }
+  return false;
 }
 
-void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int mlo[3], const int mn[3],
-                    bool any_metal, std::vector<int>& list) {
+void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
+                    std::vector<int>& list) {
   const int T = t.nbx * t.nby * t.nbz;
   std::vector<int> cls[3];
   auto slab = [&](int lo, int hi, int n) { return np > 0 && (lo < np || hi > n - 1 - np); };
@@ -487,7 +495,7 @@ void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int mlo[3],
     const int z0 = bz * t.kz, z1 = std::min(nz, z0 + t.kz);
     // ranges widened by one cell: the fused step also touches the tile's halo
     int c = 0;
-    if (tile_meets_metal_host(t, tile, mlo, mn, any_metal, nz)) c = 2;
+    if (tile_meets_metal_host(t, tile, nx, ny, nz, rowx)) c = 2;
     else if (slab(bx * kBX - 1, bx * kBX + kBX + 1, nx) ||
              slab(by * t.ty - 1, by * t.ty + t.ty + 1, ny) || slab(z0 - 1, z1 + 1, nz))
       c = 1;
