@@ -67,11 +67,13 @@ def algorithmic_bytes(w, mask, word):
     return h, ej, nm, cd
 
 
-def run_gpu(w, precision, steps, warmup, tiling=None):
+def run_gpu(w, precision, steps, warmup, tiling=None, serial=False):
     import torch
     from paper_2005_06997_amd import binding
 
     sim = binding.Sim(w, precision=precision)
+    if serial:
+        sim.set_class_streams(False)
     if tiling is None:
         sim.tiling = sim.autotune(trial_steps=10)  # timed search over sweep tilings (state reset after)
     else:
@@ -118,6 +120,8 @@ def main():
                     help="steps of the 64-instance batched sweep (0 = skip)")
     ap.add_argument("--tiling", type=str, default=None,
                     help="ty,kz,order: fixed sweep tiling instead of the autotuner (profiling runs)")
+    ap.add_argument("--serial-classes", action="store_true",
+                    help="tile-class launches one after another (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2 GiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -140,7 +144,7 @@ def main():
 
     w = W.config2("fp32")
     tiling = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
-    sim, dt = run_gpu(w, "fp32", args.steps, args.warmup, tiling)
+    sim, dt = run_gpu(w, "fp32", args.steps, args.warmup, tiling, args.serial_classes)
     value = w.cells * args.steps / dt / 1e9
     ms_step = dt / args.steps * 1e3
     spec32 = sim.spectra()  # after warmup + steps, before profiling adds steps

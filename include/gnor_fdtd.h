@@ -199,6 +199,13 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * tiling to counts[0..2] (valid once the memory is bound).
  * gnor_set_fused: on must be 0 or 1 (INVALID_ARG otherwise). */
 gnor_status gnor_set_fused(gnor_sim *sim, int32_t on);
+
+/* The three tile-class launches of a sweep run concurrently (on = 1, the
+ * default: class 0 on the bound stream, classes 1 and 2 on two side streams
+ * of the library, joined back by events, also inside graphs) or one after
+ * another on the bound stream (on = 0; for profilers that time each
+ * launch).  INVALID_ARG unless on is 0 or 1. */
+gnor_status gnor_set_class_streams(gnor_sim *sim, int32_t on);
 gnor_status gnor_tile_classes(const gnor_sim *sim, int32_t *counts);
 
 /* Sweep tiling: each block owns 64 (x) x ty (y) columns over kz planes;

@@ -100,6 +100,7 @@ def load() -> C.CDLL:
         "gnor_profile_kernels": (i32, [vp, i64, dp, i32]),
         "gnor_tile_classes": (i32, [vp, C.POINTER(C.c_int32)]),
         "gnor_set_fused": (i32, [vp, i32]),
+        "gnor_set_class_streams": (i32, [vp, i32]),
         "gnor_set_tiling": (i32, [vp, i32, i32, i32]),
         "gnor_autotune": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp]),
         "gnor_voxelize_spheres": (i32, [i32, i32, i32, dbl, i32, vp, vp]),
@@ -282,6 +283,10 @@ class Sim:
         return dict(h=ms[0], ej=ms[1], dft=ms[2], step=ms[3], flux_acc=ms[4],
                     h_cls=[float(v) for v in ms[5:8]], ej_cls=[float(v) for v in ms[8:11]],
                     aux=float(ms[11]), fused=bool(ms[3] > 0))
+
+    def set_class_streams(self, on: bool):
+        """Concurrent tile-class launches (default) or one after another."""
+        self._check(self.L.gnor_set_class_streams(self.h, 1 if on else 0))
 
     def set_fused(self, on: bool):
         """One-pass fused step, or the two-sweep form (the default)."""

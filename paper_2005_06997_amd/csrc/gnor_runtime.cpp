@@ -103,6 +103,7 @@ struct gnor_sim {
   // stream, classes 1 and 2 on two side streams (fork / join by events)
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  bool concurrent = true;  // false: the class launches one after another on the bound stream
   int64_t step = 0;
   int graph_chunk = 64;
   hipGraphExec_t graph = nullptr;
@@ -386,6 +387,10 @@ gnor::FluxParams make_flux(gnor_sim* s) {
 // event.)  launch(c, stream) enqueues class c.
 template <class F>
 void enqueue_classes(gnor_sim* s, hipStream_t st, F launch) {
+  if (!s->concurrent) {
+    for (int c = 0; c < 3; ++c) launch(c, st);
+    return;
+  }
   (void)hipEventRecord(s->ev_fork, st);
   for (int q = 0; q < 2; ++q) (void)hipStreamWaitEvent(s->side[q], s->ev_fork, 0);
   launch(0, st);
@@ -829,6 +834,15 @@ gnor_status gnor_bind_memory(gnor_sim* s, void* dptr, size_t bytes, void* stream
   st = plan_tiles(s);
   if (st != GNOR_OK) return st;
   return gnor_reset(s);
+}
+
+gnor_status gnor_set_class_streams(gnor_sim* s, int32_t on) {
+  if (!s || (on != 0 && on != 1)) return GNOR_E_INVALID_ARG;
+  if ((on != 0) != s->concurrent) {
+    s->concurrent = on != 0;
+    drop_graph(s);
+  }
+  return GNOR_OK;
 }
 
 gnor_status gnor_set_fused(gnor_sim* s, int32_t on) {
