@@ -177,7 +177,8 @@ def main():
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_ej"),
                      "bytes_per_launch": ejb, "avg_launch_ms": round(prof["ej"], 5)},
         "kernels_ms": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in prof.items()},
-        "tile_classes": {"plain": classes[0], "cpml": classes[1], "metal": classes[2]},
+        "tile_classes": {"plain": classes[0], "cpml": classes[1], "metal": classes[2],
+                         "metal_cpml": classes[3]},
         "tiling": {k: sim.tiling[k] for k in ("ty", "kz", "xcd")},
         "h_roofline_frac": round(hb / (prof["h"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "step_roofline_frac": round((hb + ejb) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -184,19 +184,19 @@ gnor_status gnor_check_finite(gnor_sim *sim);
 gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int32_t count);
 
 /* The field update runs as one launch per tile class: 0 tiles that meet
- * neither the metal sub-grid nor a CPML slab, 1 tiles that meet a CPML slab
- * only, 2 tiles that meet the metal sub-grid (a tile counts with a one-cell
- * margin).  By default a step is the two-sweep form (H sweep, then E/J
+ * neither metal nor a CPML slab, 1 tiles that meet a CPML slab only, 2 tiles
+ * with a metal point within two cells, 3 tiles that are both 2 and 1 (a tile
+ * meets a slab with a one-cell margin).  By default a step is the two-sweep form (H sweep, then E/J
  * sweep); gnor_set_fused(sim, 1) selects one fused pass (H and E/J together,
  * 12 instead of 18 field words moved per cell) plus a one-block launch that
  * advances the auxiliary line.  Both give the same fields up to rounding;
  * batches and gnor_gradient always use the two-sweep form.
- * gnor_profile_kernels with count >= 12 returns, besides ms[0..4]:
- * ms[5 + c] the H sweep's (or the fused step's) class c, ms[8 + c] the E/J
- * sweep's class c, ms[11] the auxiliary-line launch; in fused form ms[0] =
+ * gnor_profile_kernels with count >= 14 returns, besides ms[0..4]:
+ * ms[5 + c] the H sweep's (or the fused step's) class c, ms[9 + c] the E/J
+ * sweep's class c, ms[13] the auxiliary-line launch; in fused form ms[0] =
  * ms[1] = 0 and ms[3] holds the fused step (classes + auxiliary line).
  * gnor_tile_classes writes the number of tiles of each class of the current
- * tiling to counts[0..2] (valid once the memory is bound).
+ * tiling to counts[0..3] (valid once the memory is bound).
  * gnor_set_fused: on must be 0 or 1 (INVALID_ARG otherwise). */
 gnor_status gnor_set_fused(gnor_sim *sim, int32_t on);
 

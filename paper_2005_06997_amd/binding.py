@@ -278,11 +278,11 @@ class Sim:
     def profile(self, nsteps: int) -> Dict[str, float]:
         """Average ms per launch of the H sweep, E/J sweep, spectra+staging and
         (amortised per step) flux accumulation, from HIP events."""
-        ms = np.zeros(12)
-        self._check(self.L.gnor_profile_kernels(self.h, int(nsteps), _dp(ms), 12))
-        return dict(h=ms[0], ej=ms[1], dft=ms[2], step=ms[3], flux_acc=ms[4],
-                    h_cls=[float(v) for v in ms[5:8]], ej_cls=[float(v) for v in ms[8:11]],
-                    aux=float(ms[11]), fused=bool(ms[3] > 0))
+        ms = np.zeros(14)
+        self._check(self.L.gnor_profile_kernels(self.h, int(nsteps), _dp(ms), 14))
+        return dict(h=float(ms[0]), ej=float(ms[1]), dft=float(ms[2]), step=float(ms[3]),
+                    flux_acc=float(ms[4]), h_cls=[float(v) for v in ms[5:9]],
+                    ej_cls=[float(v) for v in ms[9:13]], aux=float(ms[13]), fused=bool(ms[3] > 0))
 
     def set_class_streams(self, on: bool):
         """Concurrent tile-class launches (default) or one after another."""
@@ -293,8 +293,8 @@ class Sim:
         self._check(self.L.gnor_set_fused(self.h, 1 if on else 0))
 
     def tile_classes(self):
-        """Tiles per class (plain Yee, CPML, metal) of the current tiling."""
-        c = (C.c_int32 * 3)()
+        """Tiles per class (plain Yee, CPML, metal, metal + CPML) of the current tiling."""
+        c = (C.c_int32 * 4)()
         self._check(self.L.gnor_tile_classes(self.h, c))
         return [int(v) for v in c]
 

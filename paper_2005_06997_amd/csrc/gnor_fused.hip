@@ -582,9 +582,12 @@ __global__ void __launch_bounds__(kBX*(TY + 2)) k_step(Params<T> p, AuxParams a)
     step_tile<T, TY, false, false>(p, a, tile, false, L, nullptr);
   } else if constexpr (CLS == 1) {
     step_tile<T, TY, false, true>(p, a, tile, true, L, nullptr);
+  } else if constexpr (CLS == 2) {
+    __shared__ StepLdsQ<T, TY> LQ;
+    step_tile<T, TY, true, false>(p, a, tile, false, L, &LQ);
   } else {
     __shared__ StepLdsQ<T, TY> LQ;
-    step_tile<T, TY, true, true>(p, a, tile, tile_meets_pml<T, TY>(p, tile), L, &LQ);
+    step_tile<T, TY, true, true>(p, a, tile, true, L, &LQ);
   }
 }
 
@@ -611,14 +614,15 @@ template <class T>
 void launch_step_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s) {
   if (c == 0) launch_step_cls<T, 0>(p, a, s);
   else if (c == 1) launch_step_cls<T, 1>(p, a, s);
-  else launch_step_cls<T, 2>(p, a, s);
+  else if (c == 2) launch_step_cls<T, 2>(p, a, s);
+  else launch_step_cls<T, 3>(p, a, s);
 }
 void launch_aux(const AuxParams& a, int sub, hipStream_t s) {
   hipLaunchKernelGGL(k_aux, dim3(1), dim3(256), 0, s, a, sub);
 }
 template <class T>
 void launch_step(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s) {
-  for (int c = 0; c < 3; ++c) launch_step_class<T>(p, a, c, s);
+  for (int c = 0; c < kClasses; ++c) launch_step_class<T>(p, a, c, s);
   launch_aux(a, sub, s);
 }
 template void launch_step_class<float>(const Params<float>&, const AuxParams&, int, hipStream_t);

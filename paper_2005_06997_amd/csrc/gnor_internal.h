@@ -39,6 +39,7 @@ constexpr int kAuxSrc = 22;
 constexpr int kBX = 64;
 constexpr int kMaxFreq = 256;   // spectral frequencies per simulation
 constexpr int kFluxSlots = 64;  // flux staging depth (steps per accumulation)
+constexpr int kClasses = 4;     // tile classes of a sweep (plain, CPML, metal, metal + CPML)
 
 template <class T>
 struct CpmlAxis {
@@ -53,8 +54,8 @@ struct CpmlAxis {
 };
 
 // Tiling of a sweep: tiles of 64 x ty columns by kz planes, numbered x
-// fastest, then y, then z, and split into three classes (plain Yee, CPML,
-// metal) that run as separate launches.  Within a class's launch, block b
+// fastest, then y, then z, and split into kClasses classes (plain Yee, CPML,
+// metal, metal + CPML) that run as separate launches.  Within a class's launch, block b
 // takes a position in the class's tile list according to the tile order
 // (blocks are dealt to the 8 XCDs round-robin):
 //   0: natural order;
@@ -67,9 +68,9 @@ struct Tiling {
   int xcd;        // tile order 0, 1 or 2 (above)
   int nbx, nby, nbz;
   int q;          // chunk size for order 2 (8 rows of tiles)
-  int cn[3];      // tiles per class
-  int coff[3];    // offset of each class's list in the tile list
-  int cper[3];    // positions (order 1) or chunks (order 2) per XCD, per class
+  int cn[kClasses];    // tiles per class
+  int coff[kClasses];  // offset of each class's list in the tile list
+  int cper[kClasses];  // positions (order 1) or chunks (order 2) per XCD, per class
 };
 
 // Auxiliary line state (FP64 always).
@@ -136,7 +137,7 @@ struct Params {
   // per-(plane, tile, wavefront) partial sums of the induced current J_x
   double* jpart;      // [nz][nbx * nby * ty]
   Tiling tl;
-  const int* tiles;   // tile lists of the three classes, back to back
+  const int* tiles;   // tile lists of the classes, back to back
   const int64_t* step_base;
 };
 
@@ -233,14 +234,14 @@ struct BatchEntry {
   AuxParams a;
   DftParams d;
   FluxParams f;
-  int blk0[3], nblk[3];
+  int blk0[kClasses], nblk[kClasses];
   int dblk0, dnblk;
 };
 
 template <class T>
-void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[3], int ty, hipStream_t s);
+void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, hipStream_t s);
 template <class T>
-void launch_ej_batch(const BatchEntry<T>* e, int n, const int blocks[3], int ty, int sub,
+void launch_ej_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, int sub,
                      hipStream_t s);
 template <class T>
 void launch_dft_batch(const BatchEntry<T>* e, int n, int blocks, int sub, hipStream_t s);
@@ -278,8 +279,9 @@ void launch_nonfinite(const T* a, size_t n, int* flag, hipStream_t s);
 Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
 // Classify the tiles (metal: a metal point within two cells, by the per-row
 // x extents rowx of the metal points, null = no metal; CPML: slabs of np
-// cells within one cell) and fill the class counts, offsets and per-XCD
-// counts of t; list receives the three class lists back to back.
+// cells within one cell; classes 0 plain, 1 CPML, 2 metal, 3 metal + CPML)
+// and fill the class counts, offsets and per-XCD counts of t; list receives
+// the class lists back to back.
 void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
                     std::vector<int>& list);
 

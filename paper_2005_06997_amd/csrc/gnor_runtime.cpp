@@ -388,12 +388,13 @@ gnor::FluxParams make_flux(gnor_sim* s) {
 template <class F>
 void enqueue_classes(gnor_sim* s, hipStream_t st, F launch) {
   if (!s->concurrent) {
-    for (int c = 0; c < 3; ++c) launch(c, st);
+    for (int c = 0; c < gnor::kClasses; ++c) launch(c, st);
     return;
   }
   (void)hipEventRecord(s->ev_fork, st);
   for (int q = 0; q < 2; ++q) (void)hipStreamWaitEvent(s->side[q], s->ev_fork, 0);
   launch(0, st);
+  launch(3, st);  // metal + CPML: small grids (usually empty otherwise)
   launch(1, s->side[0]);
   launch(2, s->side[1]);
   for (int q = 0; q < 2; ++q) {
@@ -1082,13 +1083,15 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
   if (!ms || count < 5 || nsteps <= 0) return GNOR_E_INVALID_ARG;
-  // events around: class launches 0..2 of the first sweep (H, or the fused
-  // step), classes 0..2 of the E/J sweep (two-sweep form) or the auxiliary
-  // line (fused form), the spectra, the flux accumulation
-  constexpr int NE = 10;
+  constexpr int NC = gnor::kClasses;
+  // events around: the class launches of the first sweep (H, or the fused
+  // step), the class launches of the E/J sweep (two-sweep form) or the
+  // auxiliary line (fused form), the spectra, the flux accumulation, the
+  // step counter
+  constexpr int NE = 2 * NC + 4;
   hipEvent_t ev[NE];
   for (auto& e : ev) HIPCHECK(s, hipEventCreate(&e));
-  double acc[NE - 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[NE - 1] = {};
   const bool fp32 = s->g.precision == GNOR_FP32;
   const bool fused = s->fused;
   for (int64_t q = 0; q < nsteps; ++q) {
@@ -1097,7 +1100,7 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
     const hipStream_t str = s->stream;
     const gnor::AuxParams a = make_aux(s);
     (void)hipEventRecord(ev[0], str);
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NC; ++c) {
       if (fused) {
         if (fp32) gnor::launch_step_class<float>(make_params<float>(s, parity), a, c, str);
         else gnor::launch_step_class<double>(make_params<double>(s, parity), a, c, str);
@@ -1107,29 +1110,26 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       }
       (void)hipEventRecord(ev[1 + c], str);
     }
-    if (fused) {
-      gnor::launch_aux(a, 0, str);
-      (void)hipEventRecord(ev[4], str);
-      (void)hipEventRecord(ev[5], str);
-      (void)hipEventRecord(ev[6], str);
-    } else {
-      for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NC; ++c) {
+      if (fused) {
+        if (c == 0) gnor::launch_aux(a, 0, str);
+      } else {
         if (fp32) gnor::launch_ej_class<float>(make_params<float>(s, parity), a, 0, c, str);
         else gnor::launch_ej_class<double>(make_params<double>(s, parity), a, 0, c, str);
-        (void)hipEventRecord(ev[4 + c], str);
       }
+      (void)hipEventRecord(ev[1 + NC + c], str);
     }
     if (s->mon.nfreq > 0) {
       if (fp32) gnor::launch_dft_stage<float>(make_dft(s), make_flux(s), make_params<float>(s, parity), 0, str);
       else gnor::launch_dft_stage<double>(make_dft(s), make_flux(s), make_params<double>(s, parity), 0, str);
     }
-    (void)hipEventRecord(ev[7], str);
+    (void)hipEventRecord(ev[1 + 2 * NC], str);
     if (s->nsamp > 0 && (n % s->slots) == s->slots - 1) enqueue_flux_acc(s, 0, str);
-    (void)hipEventRecord(ev[8], str);
+    (void)hipEventRecord(ev[2 + 2 * NC], str);
     gnor::launch_advance(ptr<int64_t>(s, s->L.step), 1, str);
-    (void)hipEventRecord(ev[9], str);
+    (void)hipEventRecord(ev[3 + 2 * NC], str);
     HIPCHECK(s, hipGetLastError());
-    HIPCHECK(s, hipEventSynchronize(ev[9]));
+    HIPCHECK(s, hipEventSynchronize(ev[3 + 2 * NC]));
     for (int e = 0; e < NE - 1; ++e) {
       float t = 0.f;
       (void)hipEventElapsedTime(&t, ev[e], ev[e + 1]);
@@ -1139,25 +1139,29 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   const double inv = 1.0 / (double)nsteps;
-  const double first = (acc[0] + acc[1] + acc[2]) * inv, second = (acc[3] + acc[4] + acc[5]) * inv;
-  double out[12];
+  double first = 0.0, second = 0.0;
+  for (int c = 0; c < NC; ++c) {
+    first += acc[c] * inv;
+    second += acc[NC + c] * inv;
+  }
+  double out[6 + 2 * NC];
   out[0] = fused ? 0.0 : first;
   out[1] = fused ? 0.0 : second;
-  out[2] = acc[6] * inv;
+  out[2] = acc[2 * NC] * inv;
   out[3] = fused ? first + second : 0.0;
-  out[4] = acc[7] * inv;
-  for (int c = 0; c < 3; ++c) {
+  out[4] = acc[2 * NC + 1] * inv;
+  for (int c = 0; c < NC; ++c) {
     out[5 + c] = acc[c] * inv;
-    out[8 + c] = fused ? 0.0 : acc[3 + c] * inv;
+    out[5 + NC + c] = fused ? 0.0 : acc[NC + c] * inv;
   }
-  out[11] = fused ? second : 0.0;
-  for (int i = 0; i < count && i < 12; ++i) ms[i] = out[i];
+  out[5 + 2 * NC] = fused ? second : 0.0;
+  for (int i = 0; i < count && i < 6 + 2 * NC; ++i) ms[i] = out[i];
   return GNOR_OK;
 }
 
 gnor_status gnor_tile_classes(const gnor_sim* s, int32_t* counts) {
   if (!s || !counts) return GNOR_E_INVALID_ARG;
-  for (int c = 0; c < 3; ++c) counts[c] = s->tl.cn[c];
+  for (int c = 0; c < gnor::kClasses; ++c) counts[c] = s->tl.cn[c];
   return GNOR_OK;
 }
 
@@ -1317,7 +1321,7 @@ struct gnor_batch {
   int ty = 2;
   char* tab = nullptr;       // two tables of n entries (parity 0, parity 1)
   size_t entry_bytes = 0;
-  int hblocks[3] = {0, 0, 0}, dblocks = 0;
+  int hblocks[gnor::kClasses] = {0, 0, 0, 0}, dblocks = 0;
   std::vector<int> tiling;   // (ty, kz, order) of every instance at creation
   bool any_dft = false, any_flux = false;
   hipStream_t stream = nullptr;
@@ -1346,7 +1350,7 @@ template <class T>
 gnor_status batch_tables(gnor_batch* b) {
   std::vector<gnor::BatchEntry<T>> tab(2 * (size_t)b->n);
   for (int parity = 0; parity < 2; ++parity) {
-    int h0[3] = {0, 0, 0}, d0 = 0;
+    int h0[gnor::kClasses] = {0, 0, 0, 0}, d0 = 0;
     for (int q = 0; q < b->n; ++q) {
       gnor_sim* s = b->sims[q];
       gnor::BatchEntry<T>& e = tab[(size_t)parity * b->n + q];
@@ -1354,7 +1358,7 @@ gnor_status batch_tables(gnor_batch* b) {
       e.a = make_aux(s);
       e.d = make_dft(s);
       e.f = make_flux(s);
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < gnor::kClasses; ++c) {
         e.blk0[c] = h0[c];
         e.nblk[c] = gnor::class_blocks(e.p.tl, c) + (c == 0 ? 1 : 0);  // + auxiliary block
         h0[c] += e.nblk[c];
@@ -1363,7 +1367,7 @@ gnor_status batch_tables(gnor_batch* b) {
       e.dnblk = s->mon.nfreq > 0 ? gnor::dft_blocks(e.d, e.f) : 0;
       d0 += e.dnblk;
     }
-    for (int c = 0; c < 3; ++c) b->hblocks[c] = h0[c];
+    for (int c = 0; c < gnor::kClasses; ++c) b->hblocks[c] = h0[c];
     b->dblocks = d0;
   }
   b->entry_bytes = sizeof(gnor::BatchEntry<T>);

@@ -381,7 +381,8 @@ __device__ __forceinline__ void h_class(const Params<T>& p, int b) {
   if (!tile.ok) return;
   if (CLS == 0) h_tile<T, TY, false, false>(p, tile, false);
   else if (CLS == 1) h_tile<T, TY, false, true>(p, tile, true);
-  else h_tile<T, TY, true, true>(p, tile, tile_meets_pml<T, TY>(p, tile));
+  else if (CLS == 2) h_tile<T, TY, true, false>(p, tile, false);
+  else h_tile<T, TY, true, true>(p, tile, true);
 }
 template <class T, int TY, int CLS>
 __device__ __forceinline__ void ej_class(const Params<T>& p, int b) {
@@ -389,7 +390,8 @@ __device__ __forceinline__ void ej_class(const Params<T>& p, int b) {
   if (!tile.ok) return;
   if (CLS == 0) ej_tile<T, TY, false, false>(p, tile, false);
   else if (CLS == 1) ej_tile<T, TY, false, true>(p, tile, true);
-  else ej_tile<T, TY, true, true>(p, tile, tile_meets_pml<T, TY>(p, tile));
+  else if (CLS == 2) ej_tile<T, TY, true, false>(p, tile, false);
+  else ej_tile<T, TY, true, true>(p, tile, true);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -488,21 +490,20 @@ static bool tile_meets_metal_host(const Tiling& t, int tile, int nx, int ny, int
 void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
                     std::vector<int>& list) {
   const int T = t.nbx * t.nby * t.nbz;
-  std::vector<int> cls[3];
+  std::vector<int> cls[kClasses];
   auto slab = [&](int lo, int hi, int n) { return np > 0 && (lo < np || hi > n - 1 - np); };
   for (int tile = 0; tile < T; ++tile) {
     const int bx = tile % t.nbx, by = (tile / t.nbx) % t.nby, bz = tile / (t.nbx * t.nby);
     const int z0 = bz * t.kz, z1 = std::min(nz, z0 + t.kz);
     // ranges widened by one cell: the fused step also touches the tile's halo
-    int c = 0;
-    if (tile_meets_metal_host(t, tile, nx, ny, nz, rowx)) c = 2;
-    else if (slab(bx * kBX - 1, bx * kBX + kBX + 1, nx) ||
-             slab(by * t.ty - 1, by * t.ty + t.ty + 1, ny) || slab(z0 - 1, z1 + 1, nz))
-      c = 1;
+    const bool metal = tile_meets_metal_host(t, tile, nx, ny, nz, rowx);
+    const bool pml = slab(bx * kBX - 1, bx * kBX + kBX + 1, nx) ||
+                     slab(by * t.ty - 1, by * t.ty + t.ty + 1, ny) || slab(z0 - 1, z1 + 1, nz);
+    const int c = metal ? (pml ? 3 : 2) : (pml ? 1 : 0);
     cls[c].push_back(tile);
   }
   list.clear();
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < kClasses; ++c) {
     t.coff[c] = (int)list.size();
     t.cn[c] = (int)cls[c].size();
     list.insert(list.end(), cls[c].begin(), cls[c].end());
@@ -556,43 +557,47 @@ template <class T>
 void launch_h_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s) {
   if (c == 0) launch_h_cls<T, 0>(p, a, s);
   else if (c == 1) launch_h_cls<T, 1>(p, a, s);
-  else launch_h_cls<T, 2>(p, a, s);
+  else if (c == 2) launch_h_cls<T, 2>(p, a, s);
+  else launch_h_cls<T, 3>(p, a, s);
 }
 template <class T>
 void launch_ej_class(const Params<T>& p, const AuxParams& a, int sub, int c, hipStream_t s) {
   if (c == 0) launch_ej_cls<T, 0>(p, a, sub, s);
   else if (c == 1) launch_ej_cls<T, 1>(p, a, sub, s);
-  else launch_ej_cls<T, 2>(p, a, sub, s);
+  else if (c == 2) launch_ej_cls<T, 2>(p, a, sub, s);
+  else launch_ej_cls<T, 3>(p, a, sub, s);
 }
 template <class T>
 void launch_h(const Params<T>& p, const AuxParams& a, hipStream_t s) {
-  for (int c = 0; c < 3; ++c) launch_h_class<T>(p, a, c, s);
+  for (int c = 0; c < kClasses; ++c) launch_h_class<T>(p, a, c, s);
 }
 template <class T>
 void launch_ej(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s) {
-  for (int c = 0; c < 3; ++c) launch_ej_class<T>(p, a, sub, c, s);
+  for (int c = 0; c < kClasses; ++c) launch_ej_class<T>(p, a, sub, c, s);
 }
 template void launch_h_class<float>(const Params<float>&, const AuxParams&, int, hipStream_t);
 template void launch_h_class<double>(const Params<double>&, const AuxParams&, int, hipStream_t);
 template void launch_ej_class<float>(const Params<float>&, const AuxParams&, int, int, hipStream_t);
 template void launch_ej_class<double>(const Params<double>&, const AuxParams&, int, int, hipStream_t);
 template <class T>
-void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[3], int ty, hipStream_t s) {
+void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, hipStream_t s) {
   launch_h_batch_cls<T, 0>(e, n, blocks[0], ty, s);
   launch_h_batch_cls<T, 1>(e, n, blocks[1], ty, s);
   launch_h_batch_cls<T, 2>(e, n, blocks[2], ty, s);
+  launch_h_batch_cls<T, 3>(e, n, blocks[3], ty, s);
 }
 template <class T>
-void launch_ej_batch(const BatchEntry<T>* e, int n, const int blocks[3], int ty, int sub,
+void launch_ej_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, int sub,
                      hipStream_t s) {
   launch_ej_batch_cls<T, 0>(e, n, blocks[0], ty, sub, s);
   launch_ej_batch_cls<T, 1>(e, n, blocks[1], ty, sub, s);
   launch_ej_batch_cls<T, 2>(e, n, blocks[2], ty, sub, s);
+  launch_ej_batch_cls<T, 3>(e, n, blocks[3], ty, sub, s);
 }
-template void launch_h_batch<float>(const BatchEntry<float>*, int, const int[3], int, hipStream_t);
-template void launch_h_batch<double>(const BatchEntry<double>*, int, const int[3], int, hipStream_t);
-template void launch_ej_batch<float>(const BatchEntry<float>*, int, const int[3], int, int, hipStream_t);
-template void launch_ej_batch<double>(const BatchEntry<double>*, int, const int[3], int, int, hipStream_t);
+template void launch_h_batch<float>(const BatchEntry<float>*, int, const int[kClasses], int, hipStream_t);
+template void launch_h_batch<double>(const BatchEntry<double>*, int, const int[kClasses], int, hipStream_t);
+template void launch_ej_batch<float>(const BatchEntry<float>*, int, const int[kClasses], int, int, hipStream_t);
+template void launch_ej_batch<double>(const BatchEntry<double>*, int, const int[kClasses], int, int, hipStream_t);
 template void launch_h<float>(const Params<float>&, const AuxParams&, hipStream_t);
 template void launch_h<double>(const Params<double>&, const AuxParams&, hipStream_t);
 template void launch_ej<float>(const Params<float>&, const AuxParams&, int, hipStream_t);
