@@ -240,6 +240,12 @@ struct BatchEntry {
 
 template <class T>
 void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, hipStream_t s);
+// one class of the batched sweeps (blocks: that class's blocks of all instances)
+template <class T>
+void launch_h_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int c, hipStream_t s);
+template <class T>
+void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, int c,
+                           hipStream_t s);
 template <class T>
 void launch_ej_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, int sub,
                      hipStream_t s);

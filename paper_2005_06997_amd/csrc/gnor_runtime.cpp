@@ -1322,6 +1322,9 @@ struct gnor_batch {
   char* tab = nullptr;       // two tables of n entries (parity 0, parity 1)
   size_t entry_bytes = 0;
   int hblocks[gnor::kClasses] = {0, 0, 0, 0}, dblocks = 0;
+  // concurrent class launches, as for a single simulation
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   std::vector<int> tiling;   // (ty, kz, order) of every instance at creation
   bool any_dft = false, any_flux = false;
   hipStream_t stream = nullptr;
@@ -1383,8 +1386,24 @@ void batch_enqueue(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st) {
     const int64_t n = n0 + q;
     const gnor::BatchEntry<T>* t = tabs + (size_t)(n & 1) * b->n;
     const int sub = (int)q;
-    gnor::launch_h_batch<T>(t, b->n, b->hblocks, b->ty, st);
-    gnor::launch_ej_batch<T>(t, b->n, b->hblocks, b->ty, sub, st);
+    auto classes = [&](auto launch) {
+      (void)hipEventRecord(b->ev_fork, st);
+      for (int q2 = 0; q2 < 2; ++q2) (void)hipStreamWaitEvent(b->side[q2], b->ev_fork, 0);
+      launch(0, st);
+      launch(3, st);
+      launch(1, b->side[0]);
+      launch(2, b->side[1]);
+      for (int q2 = 0; q2 < 2; ++q2) {
+        (void)hipEventRecord(b->ev_join[q2], b->side[q2]);
+        (void)hipStreamWaitEvent(st, b->ev_join[q2], 0);
+      }
+    };
+    classes([&](int c, hipStream_t q2) {
+      gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, q2);
+    });
+    classes([&](int c, hipStream_t q2) {
+      gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, sub, c, q2);
+    });
     if (b->any_dft && b->dblocks > 0) gnor::launch_dft_batch<T>(t, b->n, b->dblocks, sub, st);
     if (b->any_flux && (n % gnor::kFluxSlots) == gnor::kFluxSlots - 1)
       for (gnor_sim* s : b->sims)
@@ -1431,6 +1450,17 @@ gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, gn
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) { delete b; return GNOR_E_DEVICE; }
     b->own_stream = true;
   }
+  for (int q = 0; q < 2; ++q) {
+    if (hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_join[q], hipEventDisableTiming) != hipSuccess) {
+      gnor_batch_destroy(b);
+      return GNOR_E_DEVICE;
+    }
+  }
+  if (hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) {
+    gnor_batch_destroy(b);
+    return GNOR_E_DEVICE;
+  }
   // the instances' own queued work must be complete before the batch runs
   for (gnor_sim* s : b->sims)
     if (hipStreamSynchronize(s->stream) != hipSuccess) { delete b; return GNOR_E_DEVICE; }
@@ -1445,6 +1475,11 @@ void gnor_batch_destroy(gnor_batch* b) {
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   if (b->tab) (void)hipFree(b->tab);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  for (int q = 0; q < 2; ++q) {
+    if (b->side[q]) (void)hipStreamDestroy(b->side[q]);
+    if (b->ev_join[q]) (void)hipEventDestroy(b->ev_join[q]);
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   delete b;
 }
 

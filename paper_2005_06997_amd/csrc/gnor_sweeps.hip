@@ -580,6 +580,25 @@ template void launch_h_class<double>(const Params<double>&, const AuxParams&, in
 template void launch_ej_class<float>(const Params<float>&, const AuxParams&, int, int, hipStream_t);
 template void launch_ej_class<double>(const Params<double>&, const AuxParams&, int, int, hipStream_t);
 template <class T>
+void launch_h_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int c, hipStream_t s) {
+  if (c == 0) launch_h_batch_cls<T, 0>(e, n, blocks, ty, s);
+  else if (c == 1) launch_h_batch_cls<T, 1>(e, n, blocks, ty, s);
+  else if (c == 2) launch_h_batch_cls<T, 2>(e, n, blocks, ty, s);
+  else launch_h_batch_cls<T, 3>(e, n, blocks, ty, s);
+}
+template <class T>
+void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, int c,
+                           hipStream_t s) {
+  if (c == 0) launch_ej_batch_cls<T, 0>(e, n, blocks, ty, sub, s);
+  else if (c == 1) launch_ej_batch_cls<T, 1>(e, n, blocks, ty, sub, s);
+  else if (c == 2) launch_ej_batch_cls<T, 2>(e, n, blocks, ty, sub, s);
+  else launch_ej_batch_cls<T, 3>(e, n, blocks, ty, sub, s);
+}
+template void launch_h_batch_class<float>(const BatchEntry<float>*, int, int, int, int, hipStream_t);
+template void launch_h_batch_class<double>(const BatchEntry<double>*, int, int, int, int, hipStream_t);
+template void launch_ej_batch_class<float>(const BatchEntry<float>*, int, int, int, int, int, hipStream_t);
+template void launch_ej_batch_class<double>(const BatchEntry<double>*, int, int, int, int, int, hipStream_t);
+template <class T>
 void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, hipStream_t s) {
   launch_h_batch_cls<T, 0>(e, n, blocks[0], ty, s);
   launch_h_batch_cls<T, 1>(e, n, blocks[1], ty, s);
