@@ -148,8 +148,11 @@ def main():
     value = w.cells * args.steps / dt / 1e9
     ms_step = dt / args.steps * 1e3
     spec32 = sim.spectra()  # after warmup + steps, before profiling adds steps
-    prof = sim.profile(args.profile_steps)
+    prof = sim.profile(args.profile_steps)  # each sweep timed as it runs (classes concurrent)
     classes = sim.tile_classes()
+    sim.set_class_streams(False)
+    prof_serial = sim.profile(max(2, args.profile_steps // 4))  # per-class breakdown
+    sim.set_class_streams(not args.serial_classes)
     sim.set_fused(True)
     prof_fused = sim.profile(max(2, args.profile_steps // 4))
     sim.set_fused(False)
@@ -176,7 +179,9 @@ def main():
                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_ej"),
                      "bytes_per_launch": ejb, "avg_launch_ms": round(prof["ej"], 5)},
-        "kernels_ms": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in prof.items()},
+        "kernels_ms": {k: round(prof[k], 5) for k in ("h", "ej", "dft", "flux_acc")},
+        "class_ms_serial": {"h": [round(v, 5) for v in prof_serial["h_cls"]],
+                            "ej": [round(v, 5) for v in prof_serial["ej_cls"]]},
         "tile_classes": {"plain": classes[0], "cpml": classes[1], "metal": classes[2],
                          "metal_cpml": classes[3]},
         "tiling": {k: sim.tiling[k] for k in ("ty", "kz", "xcd")},

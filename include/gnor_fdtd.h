@@ -191,10 +191,13 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * 12 instead of 18 field words moved per cell) plus a one-block launch that
  * advances the auxiliary line.  Both give the same fields up to rounding;
  * batches and gnor_gradient always use the two-sweep form.
- * gnor_profile_kernels with count >= 14 returns, besides ms[0..4]:
- * ms[5 + c] the H sweep's (or the fused step's) class c, ms[9 + c] the E/J
- * sweep's class c, ms[13] the auxiliary-line launch; in fused form ms[0] =
- * ms[1] = 0 and ms[3] holds the fused step (classes + auxiliary line).
+ * gnor_profile_kernels times each sweep as it runs: with concurrent class
+ * launches (the default, see gnor_set_class_streams) a sweep is timed from its
+ * fork to its join; with serial class launches, count >= 14 also returns
+ * ms[5 + c] the H sweep's (or the fused step's) class c and ms[9 + c] the E/J
+ * sweep's class c (0 otherwise); ms[13] is the auxiliary-line launch of the
+ * fused form.  In fused form ms[0] = ms[1] = 0 and ms[3] holds the fused step
+ * (classes + auxiliary line).
  * gnor_tile_classes writes the number of tiles of each class of the current
  * tiling to counts[0..3] (valid once the memory is bound).
  * gnor_set_fused: on must be 0 or 1 (INVALID_ARG otherwise). */

@@ -1100,7 +1100,32 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
     const hipStream_t str = s->stream;
     const gnor::AuxParams a = make_aux(s);
     (void)hipEventRecord(ev[0], str);
-    for (int c = 0; c < NC; ++c) {
+    if (s->concurrent) {
+      // each sweep timed as a whole, its classes running concurrently as in
+      // a normal run (per-class entries stay 0)
+      if (fused) {
+        enqueue_classes(s, str, [&](int c, hipStream_t q2) {
+          if (fp32) gnor::launch_step_class<float>(make_params<float>(s, parity), a, c, q2);
+          else gnor::launch_step_class<double>(make_params<double>(s, parity), a, c, q2);
+        });
+      } else {
+        enqueue_classes(s, str, [&](int c, hipStream_t q2) {
+          if (fp32) gnor::launch_h_class<float>(make_params<float>(s, parity), a, c, q2);
+          else gnor::launch_h_class<double>(make_params<double>(s, parity), a, c, q2);
+        });
+      }
+      for (int c = 0; c < NC; ++c) (void)hipEventRecord(ev[1 + c], str);
+      if (fused) {
+        gnor::launch_aux(a, 0, str);
+      } else {
+        enqueue_classes(s, str, [&](int c, hipStream_t q2) {
+          if (fp32) gnor::launch_ej_class<float>(make_params<float>(s, parity), a, 0, c, q2);
+          else gnor::launch_ej_class<double>(make_params<double>(s, parity), a, 0, c, q2);
+        });
+      }
+      for (int c = 0; c < NC; ++c) (void)hipEventRecord(ev[1 + NC + c], str);
+    }
+    for (int c = 0; c < NC && !s->concurrent; ++c) {
       if (fused) {
         if (fp32) gnor::launch_step_class<float>(make_params<float>(s, parity), a, c, str);
         else gnor::launch_step_class<double>(make_params<double>(s, parity), a, c, str);
@@ -1110,7 +1135,7 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       }
       (void)hipEventRecord(ev[1 + c], str);
     }
-    for (int c = 0; c < NC; ++c) {
+    for (int c = 0; c < NC && !s->concurrent; ++c) {
       if (fused) {
         if (c == 0) gnor::launch_aux(a, 0, str);
       } else {
@@ -1151,8 +1176,8 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   out[3] = fused ? first + second : 0.0;
   out[4] = acc[2 * NC + 1] * inv;
   for (int c = 0; c < NC; ++c) {
-    out[5 + c] = acc[c] * inv;
-    out[5 + NC + c] = fused ? 0.0 : acc[NC + c] * inv;
+    out[5 + c] = s->concurrent ? 0.0 : acc[c] * inv;
+    out[5 + NC + c] = (fused || s->concurrent) ? 0.0 : acc[NC + c] * inv;
   }
   out[5 + 2 * NC] = fused ? second : 0.0;
   for (int i = 0; i < count && i < 6 + 2 * NC; ++i) ms[i] = out[i];
