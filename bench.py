@@ -189,8 +189,7 @@ def main():
         "step_roofline_frac": round((hb + ejb) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "fused_step": {"note": "one-pass H+E/J variant (12 instead of 18 field words per cell), "
                                "not the default: slower here, see DESIGN.md",
-                       "step_ms": round(prof_fused["step"], 5),
-                       "classes_ms": [round(v, 5) for v in prof_fused["h_cls"]]},
+                       "step_ms": round(prof_fused["step"], 5)},
     }
     del sim
     torch.cuda.empty_cache()
