@@ -105,15 +105,5 @@ __device__ __forceinline__ bool range_in_slabs(int lo, int hi, int n, int np) {
   return np > 0 && (lo < np || hi > n - 1 - np);
 }
 
-// Does a tile (widened by one cell: the fused step's halo) meet a CPML slab?
-template <class T, int TY>
-__device__ __forceinline__ bool tile_meets_pml(const Params<T>& p, const Tile& t) {
-  const int np = p.cp[0].np;
-  const int z0 = t.bz * p.tl.kz, z1 = min(p.nz, z0 + p.tl.kz);
-  return range_in_slabs(t.bx * kBX - 1, t.bx * kBX + kBX + 1, p.nx, np) ||
-         range_in_slabs(t.by * TY - 1, t.by * TY + TY + 1, p.ny, np) ||
-         range_in_slabs(z0 - 1, z1 + 1, p.nz, np);
-}
-
 }  // namespace
 }  // namespace gnor

@@ -133,6 +133,28 @@ def test_fused_and_two_sweep_forms_agree(B, prec):
     assert runs[0].profile(2)["fused"] and not runs[1].profile(2)["fused"]
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_metal_across_x_tiles_vs_oracle(B, fused):
+    """A sphere straddling the boundary between x tiles 0 and 1 of a 128-wide
+    grid: tile 0 meets the CPML (class metal + CPML), tile 1 does not (class
+    metal)."""
+    n, dx, r = 128, 0.25e-9, 2.0e-9
+    c = np.array([60.3, 23.5, 23.2])
+    w = W.sphere_problem("wrap", n, dx, 8, c, r, steps=300)
+    w.ny = w.nz = 48
+    w = W._boxes(w, c * dx - r, c * dx + r)
+    w = W.early_pulse(w)
+    w.omega = W.spectrum_omegas(20)
+    say(f"case metal across x tiles 128x48x48, fused={fused}")
+    g = B.Sim(w, precision="fp64")
+    g.set_fused(fused)
+    g.set_tiling(4, 16, 2)
+    assert g.tile_classes()[3] > 0
+    g.run(w.steps)
+    o = oracle_run(w, w.steps)
+    compare(g, o, 1e-10, 1e-10)
+
+
 def test_fp64_vacuum_no_metal(B):
     w = W.early_pulse(W.small_sphere(n=30, radius=1.0e-9, npml=4, seed=4))
     w.omega = W.spectrum_omegas(10)
