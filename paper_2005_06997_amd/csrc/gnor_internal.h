@@ -38,7 +38,7 @@ constexpr int kAuxSrc = 22;
 // marching over kz planes.
 constexpr int kBX = 64;
 constexpr int kMaxFreq = 256;   // spectral frequencies per simulation
-constexpr int kFluxSlots = 64;  // flux staging depth (steps per accumulation)
+constexpr int kFluxSlots = 256;  // flux staging depth (steps per accumulation)
 constexpr int kClasses = 4;     // tile classes of a sweep (plain, CPML, metal, metal + CPML)
 
 template <class T>
@@ -183,7 +183,7 @@ struct FluxParams {
   double* acc_re;        // [nf][nsamp]
   double* acc_im;
   const double* omega;
-  double* ptab;          // [nf][2 kinds][2 cos/sin][kFluxSlots]
+  double* ptab;          // window phase factors as matrix fragments (flux_ptab_doubles)
   double dt, wdt;
   const int64_t* step_base;
 };
@@ -278,6 +278,7 @@ void launch_dft_stage(const DftParams& d, const FluxParams& f, const Params<T>& 
                       hipStream_t s);
 void launch_advance(int64_t* base, int64_t count, hipStream_t s);
 void launch_flux_accumulate(const FluxParams& f, int* lo_ptr, int sub, hipStream_t s);
+size_t flux_ptab_doubles(int nf);
 void launch_flux_reduce(const double* acc_re, const double* acc_im, const double* pw, int npairs,
                         int npairs_box0, int nf, double* out, hipStream_t s);
 template <class T>

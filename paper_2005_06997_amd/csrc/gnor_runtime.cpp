@@ -245,7 +245,7 @@ void plan_layout(gnor_sim* s) {
   L.dft = P.take((size_t)4 * nz * std::max(1, s->mon.nfreq) * 8);
   L.fstage = P.take((size_t)s->slots * s->nsamp * 8 + 8);
   L.facc = P.take((size_t)2 * std::max(1, s->mon.nfreq) * s->nsamp * 8 + 8);
-  L.ptab = P.take((size_t)std::max(1, s->mon.nfreq) * 4 * gnor::kFluxSlots * 8);
+  L.ptab = P.take(gnor::flux_ptab_doubles(std::max(1, s->mon.nfreq)) * 8);
   L.fsum = P.take((size_t)2 * std::max(1, s->mon.nfreq) * 8);
   L.step = P.take(8);
   L.flux_lo = P.take(4);

@@ -6,9 +6,11 @@
 //                  (n+1) dt), with the step's phase table from the E sweep;
 //                  blocks [nz, ...): staging of the flux-box samples (E on
 //                  the face, H averaged across it)
-//   k_flux_phase   phase table of one accumulation window
+//   k_flux_phase   phase table of one accumulation window (matrix-core
+//                  fragments)
 //   k_flux_acc     acc[m][s] += sum_b wdt e^{i w_m t_b} stage[b][s]: the
-//                  staged window folded into the flux-box transforms
+//                  staged window folded into the flux-box transforms, on the
+//                  FP64 matrix cores
 //   k_flux_reduce  sum over sample pairs of w_p Re(E conj(H)) per box and
 //                  frequency (fixed order)
 #include "gnor_internal.h"
@@ -103,52 +105,151 @@ __global__ void k_advance_batch(const BatchEntry<T>* __restrict__ e, int n, int6
   if (q < n) const_cast<int64_t*>(e[q].p.step_base)[0] += count;
 }
 
-// ptab[m][kind][cos|sin][b] = wdt e^{i w_m t_b}; slot b of the window holds
-// step w0 + b; E samples are stamped (n+1) dt, H samples (n+1/2) dt.
-__global__ void __launch_bounds__(2 * kFluxSlots) k_flux_phase(FluxParams f, int sub) {
-  const int m = blockIdx.x;
-  const int64_t n_last = f.step_base[0] + sub;
-  const int64_t w0 = n_last - (n_last % kFluxSlots);
-  const int b = threadIdx.x % kFluxSlots;
-  const int kind = threadIdx.x / kFluxSlots;
-  const double t = ((double)(w0 + b) + (kind == 0 ? 1.0 : 0.5)) * f.dt;
-  double s, c;
-  sincos(f.omega[m] * t, &s, &c);
-  double* out = f.ptab + ((size_t)m * 2 + kind) * 2 * kFluxSlots;
-  out[b] = f.wdt * c;
-  out[kFluxSlots + b] = f.wdt * s;
+// The window's fold acc += P_kind V is a matrix product: rows R = 2m + c of
+// P (c = 0: wdt cos(w_m t_b), c = 1: wdt sin(w_m t_b)), columns b = window
+// slots, V[b][s] = stage[b][s].  It runs on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: 16 rows x 16 samples x 4 slots per instruction).
+// Register layouts of that instruction, lane l of the wavefront:
+//   A (16 x 4):  A[l % 16][l / 16]
+//   B (4 x 16):  B[l / 16][l % 16]
+//   D (16 x 16): D[4 r + l / 16][l % 16] in element r of the double4.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kFluxKB = kFluxSlots / 4;  // 4-slot steps per window
+constexpr int kFluxTW = 13;              // row tiles per wavefront
+
+// row tiles of P (2 nf rows, 16 per tile), padded to whole wavefront groups
+__host__ __device__ __forceinline__ int flux_row_tiles(int nf) {
+  const int t = (nf + 7) / 8;
+  return (t + kFluxTW - 1) / kFluxTW * kFluxTW;
 }
 
-// acc[m][s] += sum_{b in [lo, hi)} ptab[m][kind(s)][.][b] stage[b][s]
-__global__ void __launch_bounds__(256) k_flux_acc(FluxParams f, const int* lo_ptr, int sub) {
-  const int s = blockIdx.x * 256 + threadIdx.x;
+// ptab[kind][g][kb][t][l] = A fragment of row tile g kFluxTW + t, slots
+// 4kb .. 4kb+3 (zero for rows past 2 nf and slots outside the unfolded part
+// [lo, hi) of the window): the fragments one wavefront loads per step are
+// contiguous.  Slot b holds step w0 + b; E samples are stamped (n+1) dt, H
+// samples (n+1/2) dt.
+__global__ void __launch_bounds__(256) k_flux_phase(FluxParams f, const int* lo_ptr, int sub) {
+  const int T = flux_row_tiles(f.nf);
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= 2 * T * kFluxKB * 64) return;
+  const int l = idx & 63;
+  const int q = idx >> 6;
+  const int kb = q / kFluxTW % kFluxKB;
+  const int gq = q / kFluxTW / kFluxKB;  // kind * (T / kFluxTW) + row group
+  const int t = (gq % (T / kFluxTW)) * kFluxTW + q % kFluxTW;
+  const int kind = gq / (T / kFluxTW);
+  const int b = 4 * kb + (l >> 4);
+  const int R = 16 * t + (l & 15);
+  const int m = R >> 1;
+  const int64_t n_last = f.step_base[0] + sub;
+  const int64_t w0 = n_last - (n_last % kFluxSlots);
+  const int hi = (int)(n_last % kFluxSlots) + 1;
+  const int lo = lo_ptr[0];
+  double v = 0.0;
+  if (m < f.nf && b >= lo && b < hi) {
+    const double tb = ((double)(w0 + b) + (kind == 0 ? 1.0 : 0.5)) * f.dt;
+    double sn, cs;
+    sincos(f.omega[m] * tb, &sn, &cs);
+    v = f.wdt * ((R & 1) ? sn : cs);
+  }
+  f.ptab[idx] = v;
+}
+
+// One wavefront: 16 samples (a column tile) of one kind x up to kFluxTW row
+// tiles.  Blocks of 4 wavefronts take 4 adjacent column tiles; the row groups
+// of a column group are consecutive blocks of one XCD (blocks are dealt
+// round-robin to the 8 XCDs), so the group's stage columns are read from
+// HBM once.
+__global__ void __launch_bounds__(256) k_flux_acc(FluxParams f, const int* lo_ptr, int sub, int ncg8) {
+  const int T = flux_row_tiles(f.nf);
+  const int WT = T / kFluxTW;
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, r = bid >> 3;
+  const int g = r % WT;
+  const int rest = r / WT;                  // [kind][column group / 8]
+  const int kind = rest / (ncg8 >> 3);
+  const int cg = (rest % (ncg8 >> 3)) * 8 + xcd;
+  const int l = threadIdx.x & 63;
+  const int ct = cg * 4 + (threadIdx.x >> 6);
+  const int col = ct * 16 + (l & 15);        // pair index of this lane's sample
+  if (kind > 1 || ct * 16 >= f.npairs) return;  // whole wavefront
+  const bool colok = col < f.npairs;
+  // lanes past the last pair read (and never store) the kind's first sample
+  const size_t s = (size_t)kind * f.npairs + (colok ? col : 0);
+  const int t0 = g * kFluxTW;
   const int64_t n_last = f.step_base[0] + sub;
   const int hi = (int)(n_last % kFluxSlots) + 1;
   const int lo = lo_ptr[0];
-  const bool ok = s < f.nsamp;
-  const int kind = (ok && s >= f.npairs) ? 1 : 0;
-  double v[kFluxSlots];
+  const size_t ns = f.nsamp;
+  // the window's sum, added to the running transforms at the end
+  dbl4 acc[kFluxTW];
 #pragma unroll
-  for (int b = 0; b < kFluxSlots; ++b)
-    v[b] = (ok && b >= lo && b < hi) ? f.stage[(size_t)b * f.nsamp + s] : 0.0;
-  __shared__ double ph[2][2][kFluxSlots];
-  for (int m = 0; m < f.nf; ++m) {
-    __syncthreads();
-    if (threadIdx.x < 4 * kFluxSlots) {
-      const double* src = f.ptab + (size_t)m * 4 * kFluxSlots;
-      (&ph[0][0][0])[threadIdx.x] = src[threadIdx.x];
-    }
-    __syncthreads();
-    double re = 0.0, im = 0.0;
+  for (int t = 0; t < kFluxTW; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const double* pa = f.ptab + (size_t)(kind * WT + g) * kFluxKB * kFluxTW * 64 + l;
+  // 4-slot steps covering [lo, hi), widened to whole groups of 8 steps
+  // inside the window (the extra steps have zero phase factors)
+  constexpr int G = 8;
+  int kb0 = lo >> 2, kb1 = (hi + 3) >> 2;
+  {
+    const int cnt = (kb1 - kb0 + G - 1) / G * G;
+    kb1 = min(kFluxKB, kb0 + cnt);
+    kb0 = kb1 - cnt;
+  }
+  if (kb0 == kb1) return;  // nothing staged since the last fold
+  // Operands of step kb: A fragments pa[(kb kFluxTW + t) 64] (phase table,
+  // cache-resident), loaded one fold ahead into two buffers in turn, and the
+  // B fragment from the staging ring (HBM).  The B fragments of a group of 8
+  // steps are loaded together one group ahead: memory counters retire in
+  // order, so a B load issued with each fold would hold up the next fold's A
+  // operands for a full HBM round trip.  Slots outside [lo, hi) meet zero
+  // phase factors; the ring holds finite values there (zeroed at reset,
+  // earlier samples after).
+  auto load_a = [&](int kb, double (&a)[kFluxTW]) {
 #pragma unroll
-    for (int b = 0; b < kFluxSlots; ++b) {
-      re += ph[kind][0][b] * v[b];
-      im += ph[kind][1][b] * v[b];
+    for (int t = 0; t < kFluxTW; ++t) a[t] = pa[((size_t)kb * kFluxTW + t) * 64];
+  };
+  auto load_b = [&](int kb, double (&b)[G]) {
+#pragma unroll
+    for (int j = 0; j < G; ++j) b[j] = f.stage[(size_t)(4 * (kb + j) + (l >> 4)) * ns + s];
+  };
+  auto fold = [&](const double (&a)[kFluxTW], double v) {
+#pragma unroll
+    for (int t = 0; t < kFluxTW; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], v, acc[t], 0, 0, 0);
+  };
+  double a0[kFluxTW], a1[kFluxTW], bq[G], bn[G];
+  load_b(kb0, bq);
+  load_a(kb0, a0);
+  // scheduling barriers keep each load group ahead of its use
+  for (int kb = kb0; kb < kb1; kb += G) {
+    const int nx = kb + G < kb1 ? kb + G : kb;  // the last group's reloads are not used
+    load_a(kb + 1, a1);
+    load_b(nx, bn);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < G; j += 2) {
+      fold(a0, bq[j]);
+      __builtin_amdgcn_sched_barrier(0);
+      load_a(j + 2 < G ? kb + j + 2 : nx, a0);
+      __builtin_amdgcn_sched_barrier(0);
+      fold(a1, bq[j + 1]);
+      __builtin_amdgcn_sched_barrier(0);
+      if (j + 3 < G) load_a(kb + j + 3, a1);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (ok) {
-      const size_t q = (size_t)m * f.nsamp + s;
-      f.acc_re[q] += re;
-      f.acc_im[q] += im;
+#pragma unroll
+    for (int j = 0; j < G; ++j) bq[j] = bn[j];
+  }
+#pragma unroll
+  for (int t = 0; t < kFluxTW; ++t) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int R = 16 * (t0 + t) + 4 * q + (l >> 4);
+      const int m = R >> 1;
+      if (colok && m < f.nf) {
+        double* dst = ((R & 1) ? f.acc_im : f.acc_re) + (size_t)m * ns + s;
+        __builtin_nontemporal_store(__builtin_nontemporal_load(dst) + acc[t][q], dst);
+      }
     }
   }
 }
@@ -216,9 +317,18 @@ template void launch_advance_batch<double>(const BatchEntry<double>*, int, int64
 void launch_advance(int64_t* base, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, base, count);
 }
+size_t flux_ptab_doubles(int nf) { return (size_t)2 * flux_row_tiles(nf) * kFluxKB * 64; }
+
 void launch_flux_accumulate(const FluxParams& f, int* lo_ptr, int sub, hipStream_t s) {
-  hipLaunchKernelGGL(k_flux_phase, dim3(f.nf), dim3(2 * kFluxSlots), 0, s, f, sub);
-  hipLaunchKernelGGL(k_flux_acc, dim3((f.nsamp + 255) / 256), dim3(256), 0, s, f, lo_ptr, sub);
+  const int T = flux_row_tiles(f.nf);
+  const int WT = T / kFluxTW;
+  const int nct = (f.npairs + 15) / 16;          // column tiles per kind
+  const int ncg8 = ((nct + 3) / 4 + 7) / 8 * 8;  // column groups per kind, padded to 8
+  const int phase_threads = 2 * T * kFluxKB * 64;
+  hipLaunchKernelGGL(k_flux_phase, dim3((phase_threads + 255) / 256), dim3(256), 0, s, f,
+                     (const int*)lo_ptr, sub);
+  hipLaunchKernelGGL(k_flux_acc, dim3(2 * ncg8 * WT), dim3(256), 0, s, f, (const int*)lo_ptr, sub,
+                     ncg8);
   hipLaunchKernelGGL(k_flux_set, dim3(1), dim3(64), 0, s, lo_ptr, f, sub);
 }
 void launch_flux_reduce(const double* are, const double* aim, const double* pw, int npairs,
