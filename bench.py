@@ -112,7 +112,7 @@ def main():
     # of the flux-box transforms per 256 steps, as in a full run)
     ap.add_argument("--steps", type=int, default=2048)
     ap.add_argument("--warmup", type=int, default=256)
-    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--profile-steps", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30)
