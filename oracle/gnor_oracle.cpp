@@ -10,7 +10,17 @@
 //
 // What it follows literally:
 //   * Yee positions of E, H and P: Sec. III, Table I.
-//   * Update order H -> E -> P_f (f1, f2, f4; no critical points): Sec. III.
+//   * Update order H -> E -> P_CP -> P_f (f1, f2, f3, f4): Sec. III.
+//   * N critical points (bound electrons), Eq. (CritPoint): the f3 update
+//     Eq. (critpointupdate) with C_p, C_1p .. C_5p, and their terms in the E
+//     update, obtained by putting Eq. (critpointupdate) into Eq.
+//     (discreteamperes) as Sec. III describes.  Two readings (the printed
+//     coefficients disagree with that derivation and with Eq. (CritPoint)):
+//     the sum of C_4p enters the E^n coefficient with a minus sign, and the
+//     sin(phi_p) part of C_3p and C_5p is eps0 A_p Omega_p sin(phi_p) /
+//     (dt C_p), which makes the discrete susceptibility tend to Eq.
+//     (CritPoint) as dt -> 0.  The poles act where P_f does (the metal), with
+//     the metal weight scaling A_p.
 //   * P_f update: Eq. (NonlocalUpdate) with D1, D2, D3, D_NL, D_d, and its
 //     GNOR form Eq. (GNORUpdate) with D_G1, D_G2 and the BDF2 time derivative
 //     of grad(div P): Sec. III.
@@ -109,6 +119,10 @@ typedef struct {
   int32_t flux;
   int32_t abs_lo[3], abs_hi[3], sca_lo[3], sca_hi[3];
   int32_t threads;
+  // critical points (Eq. CritPoint): ncp poles, A_p, Omega_p [rad/s],
+  // Gamma_p [rad/s], phi_p [rad]
+  int32_t ncp;
+  double cp_A[4], cp_Omega[4], cp_Gamma[4], cp_phi[4];
 } or_config;
 
 }  // extern "C"
@@ -127,6 +141,11 @@ struct Sim {
   std::vector<uint8_t> mask;  // bit c: P_c is updated at this Yee point
   std::vector<R> w;           // per-cell weight of the metal's wp^2, beta^2, D
   std::vector<R> E[3], Em[3], H[3], P[3], Pm[3], GD[3], GD1[3], GD2[3];
+  // critical points: P_CP,p^n and P_CP,p^{n-1}, and the coefficients of
+  // Eq. (critpointupdate)
+  int ncp = 0;
+  std::vector<R> PC[4][3], PCm[4][3];
+  double C1p[4] = {}, C2p[4] = {}, C3p[4] = {}, C4p[4] = {}, C5p[4] = {};
   std::vector<R> psiE[3][3], psiH[3][3];  // psi[component][derivative axis]
   // CPML coefficients per axis at integer (e) and half-integer (h) positions
   std::vector<double> be[3], ae[3], ke[3], bh[3], ah[3], kh[3];
@@ -208,6 +227,18 @@ struct Sim {
     eta = c.beta * c.beta + c.diff * c.gamma;
     DG1 = eta / Dd;
     DG2 = c.diff / (2.0 * dt * Dd);
+    // f3 coefficients, Eq. (critpointupdate) (sin term and sign: see top)
+    ncp = c.ncp < 0 ? 0 : (c.ncp > 4 ? 4 : c.ncp);
+    for (int q = 0; q < ncp; ++q) {
+      const double A = c.cp_A[q], Om = c.cp_Omega[q], Ga = c.cp_Gamma[q], ph = c.cp_phi[q];
+      const double s2 = Om * Om + Ga * Ga;
+      const double Cp = Ga / dt + 1.0 / (dt * dt) + s2 / 4.0;
+      C1p[q] = (2.0 / (dt * dt) - s2 / 2.0) / Cp;
+      C2p[q] = (Ga / dt - 1.0 / (dt * dt) - s2 / 4.0) / Cp;
+      C4p[q] = eps0() * A * Om * (Om * std::cos(ph) - Ga * std::sin(ph)) / Cp;
+      C3p[q] = C4p[q] / 2.0 - eps0() * A * Om * std::sin(ph) / (dt * Cp);
+      C5p[q] = C4p[q] / 2.0 + eps0() * A * Om * std::sin(ph) / (dt * Cp);
+    }
     mask.assign(m, m + N);
     w.assign(N, R(0.0));
     for (size_t p = 0; p < N; ++p) w[p] = weight ? weight[p] : R(mask[p] ? 1.0 : 0.0);
@@ -216,6 +247,7 @@ struct Sim {
       P[d].assign(N, R(0.0)); Pm[d].assign(N, R(0.0)); GD[d].assign(N, R(0.0));
       GD1[d].assign(N, R(0.0)); GD2[d].assign(N, R(0.0));
       for (int e = 0; e < 3; ++e) { psiE[d][e].assign(N, R(0.0)); psiH[d][e].assign(N, R(0.0)); }
+      for (int q = 0; q < ncp; ++q) { PC[q][d].assign(N, R(0.0)); PCm[q][d].assign(N, R(0.0)); }
     }
     const int L = c.periodic ? 0 : c.npml;
     const int ns[3] = {nx, ny, nz};
@@ -421,12 +453,34 @@ struct Sim {
                   ? (w[p] * DNL) * GD[comp][p]
                   : (w[p] * DG1) * GD[comp][p] +
                     (w[p] * DG2) * (3.0 * GD[comp][p] - 4.0 * GD1[comp][p] + GD2[comp][p]);
-              const R num = dt * curl + (e0ei - 2.0 * d3) * E[comp][p] - d3 * Em[comp][p] -
-                            (D1 - 1.0) * P[comp][p] - D2 * Pm[comp][p] - rhs_gd;
-              Enew[comp][p] = num / (e0ei + d3);
+              R num = dt * curl + (e0ei - 2.0 * d3) * E[comp][p] - d3 * Em[comp][p] -
+                      (D1 - 1.0) * P[comp][p] - D2 * Pm[comp][p] - rhs_gd;
+              R den = e0ei + d3;
+              for (int q = 0; q < ncp; ++q) {
+                num = num - (w[p] * C4p[q]) * E[comp][p] - (w[p] * C5p[q]) * Em[comp][p] -
+                      (C1p[q] - 1.0) * PC[q][comp][p] - C2p[q] * PCm[q][comp][p];
+                den = den + w[p] * C3p[q];
+              }
+              Enew[comp][p] = num / den;
             }
           }
     }
+    // f3: P_CP,p^{n+1}, Eq. (critpointupdate), where P_f is updated
+    for (int q = 0; q < ncp; ++q)
+      for (int comp = 0; comp < 3; ++comp) {
+        std::vector<R> Pn(N, R(0.0));
+#pragma omp parallel for schedule(static) num_threads(c.threads > 0 ? c.threads : 1)
+        for (int k = 0; k < nz; ++k)
+          for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+              const size_t p = id(i, j, k);
+              if (!active(comp, p)) continue;
+              Pn[p] = C1p[q] * PC[q][comp][p] + C2p[q] * PCm[q][comp][p] +
+                      w[p] * (C3p[q] * Enew[comp][p] + C4p[q] * E[comp][p] + C5p[q] * Em[comp][p]);
+            }
+        PCm[q][comp].swap(PC[q][comp]);
+        PC[q][comp].swap(Pn);
+      }
     // f4: P_f^{n+1} (Eqs. NonlocalUpdate / GNORUpdate) at metal points only
     std::vector<R> Pnew[3];
     for (int comp = 0; comp < 3; ++comp) {
@@ -485,14 +539,16 @@ struct Sim {
     }
     const double e0d = eps0() * (c.eps_inf - c.eps_b);
     for (int k = 0; k < nz; ++k) {
-      // induced current J_x^{n+1/2} = (P^{n+1}-P^n)/dt, plus the bound part
-      // eps0 (eps_inf - eps_b) dE/dt inside the metal, summed over the plane
+      // induced current J_x^{n+1/2} = (P^{n+1}-P^n)/dt, plus the bound parts
+      // eps0 (eps_inf - eps_b) dE/dt and dP_CP,p/dt inside the metal, summed
+      // over the plane
       R s(0.0);
       for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
           const size_t p = id(i, j, k);
           if (!active(0, p)) continue;
           s += (P[0][p] - Pm[0][p]) / dt + e0d * (E[0][p] - Em[0][p]) / dt;
+          for (int q = 0; q < ncp; ++q) s += (PC[q][0][p] - PCm[q][0][p]) / dt;
         }
       const double ei = (k + kAuxOff < n1) ? e1[k + kAuxOff] : 0.0;
       for (int m = 0; m < nf; ++m) {
@@ -701,11 +757,18 @@ long or_step_index(const or_sim* h) { return reinterpret_cast<const Sim<double>*
 double or_dt(const or_sim* h) { return reinterpret_cast<const Sim<double>*>(h)->dt; }
 
 // which: 0-2 E^n, 3-5 H^{n-1/2}, 6-8 J^{n-1/2} = (P^n - P^{n-1})/dt, 9-11 P^n,
-//        12-14 P^{n-1}, 15-17 E^{n-1}, 18-20 GD^{n-1}, 21-23 GD^{n-2}
+//        12-14 P^{n-1}, 15-17 E^{n-1}, 18-20 GD^{n-1}, 21-23 GD^{n-2},
+//        24 + 6q + (0-2) P_CP,q^n, 24 + 6q + (3-5) P_CP,q^{n-1}
 int or_get(const or_sim* h, int which, double* out) {
   const auto* s = reinterpret_cast<const Sim<double>*>(h);
   const int c = which % 3;
   const size_t N = s->N;
+  if (which >= 24) {
+    const int q = (which - 24) / 6, lev = (which - 24) % 6 / 3;
+    if (q >= s->ncp) return 1;
+    std::memcpy(out, (lev == 0 ? s->PC[q][c] : s->PCm[q][c]).data(), N * 8);
+    return 0;
+  }
   switch (which / 3) {
     case 0: std::memcpy(out, s->E[c].data(), N * 8); return 0;
     case 1: std::memcpy(out, s->H[c].data(), N * 8); return 0;
@@ -723,6 +786,13 @@ int or_set(or_sim* h, int which, const double* in) {
   const int c = which % 3;
   const size_t N = s->N;
   std::vector<double>* dst = nullptr;
+  if (which >= 24) {
+    const int q = (which - 24) / 6, lev = (which - 24) % 6 / 3;
+    if (q >= s->ncp) return 1;
+    dst = lev == 0 ? &s->PC[q][c] : &s->PCm[q][c];
+    std::memcpy(dst->data(), in, N * 8);
+    return 0;
+  }
   switch (which / 3) {
     case 0: dst = &s->E[c]; break;
     case 1: dst = &s->H[c]; break;

@@ -97,6 +97,9 @@ class OrConfig(C.Structure):
         ("abs_lo", C.c_int32 * 3), ("abs_hi", C.c_int32 * 3),
         ("sca_lo", C.c_int32 * 3), ("sca_hi", C.c_int32 * 3),
         ("threads", C.c_int32),
+        ("ncp", C.c_int32),
+        ("cp_A", C.c_double * 4), ("cp_Omega", C.c_double * 4),
+        ("cp_Gamma", C.c_double * 4), ("cp_phi", C.c_double * 4),
     ]
 
 
@@ -139,12 +142,23 @@ class Problem:
     sca_lo: Sequence[int] = (0, 0, 0)
     sca_hi: Sequence[int] = (0, 0, 0)
     threads: int = 0
+    # critical points, Eq. (CritPoint): up to 4 poles (A_p, Omega_p, Gamma_p, phi_p)
+    cp: Sequence[Sequence[float]] = ()
 
     def to_c(self) -> OrConfig:
         c = OrConfig()
         for name, _ in OrConfig._fields_:
             if name == "nfreq":
                 c.nfreq = int(len(self.omega))
+                continue
+            if name == "ncp":
+                if len(self.cp) > 4:
+                    raise ValueError("at most 4 critical points")
+                c.ncp = len(self.cp)
+                continue
+            if name.startswith("cp_"):
+                col = {"cp_A": 0, "cp_Omega": 1, "cp_Gamma": 2, "cp_phi": 3}[name]
+                getattr(c, name)[:] = [float(pole[col]) for pole in self.cp] + [0.0] * (4 - len(self.cp))
                 continue
             v = getattr(self, name)
             if name in ("tf_lo", "tf_hi", "abs_lo", "abs_hi", "sca_lo", "sca_hi"):
@@ -162,6 +176,11 @@ FIELD_INDEX = {
     "Emx": 15, "Emy": 16, "Emz": 17, "GD1x": 18, "GD1y": 19, "GD1z": 20,
     "GD2x": 21, "GD2y": 22, "GD2z": 23,
 }
+# critical-point polarisations: "PC<q><c>" (P_CP,q^n), "PCm<q><c>" (P_CP,q^{n-1})
+for _q in range(4):
+    for _i, _c in enumerate("xyz"):
+        FIELD_INDEX[f"PC{_q}{_c}"] = 24 + 6 * _q + _i
+        FIELD_INDEX[f"PCm{_q}{_c}"] = 27 + 6 * _q + _i
 
 
 def _ptr(a: np.ndarray):

@@ -86,15 +86,18 @@ def test_vacuum_flux_boxes_plane_wave():
 
 
 @pytest.mark.slow
-def test_extinction_equals_absorption_plus_scattering():
+@pytest.mark.parametrize("poles", [(), ((1.2, 4.0e15, 5.0e14, -0.6),)])
+def test_extinction_equals_absorption_plus_scattering(poles):
     """J-route extinction vs flux-box absorption + scattering on a strongly
-    damped sphere (fields decay within the run)."""
+    damped sphere (fields decay within the run).  With a critical point the
+    J-route must include the bound current dP_CP/dt."""
     n = 40
     dx = 1.0e-9
     w = W.sphere_problem("ext_balance", n, dx, 5, [(n - 1) / 2.0] * 3, 8.0e-9)
     w = W.early_pulse(w)
     om = W.spectrum_omegas(21, 2.0, 7.0)
-    p = oracle_problem(w, flux=True, omega=om, gamma=1.0e15, beta=0.0, diff=0.0, threads=8)
+    p = oracle_problem(w, flux=True, omega=om, gamma=1.0e15, beta=0.0, diff=0.0, threads=8,
+                       cp=poles)
     s = orc.OracleSim(p, oracle_mask(w))
     s.run(4000)
     sp = s.spectra()
