@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--adjoint-steps", type=int, default=6000,
                     help="steps of the design-gradient run (forward + adjoint; 0 = skip)")
+    ap.add_argument("--cp-steps", type=int, default=512,
+                    help="steps of the same sphere with two critical points (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=256,
                     help="steps of the 64-instance batched sweep (0 = skip)")
     ap.add_argument("--tiling", type=str, default=None,
@@ -214,6 +216,25 @@ def main():
             err[k] = float(np.linalg.norm(spec32[k] - s64[k]) / den) if den > 0 else None
         out["fp32_vs_fp64_spectra_rel_l2"] = err
         del sim64
+        torch.cuda.empty_cache()
+    if args.cp_steps > 0:
+        # bound electrons: the same sphere with two critical points (f3); the
+        # E/J sweep adds P_CP and its increment (read + write) per pole and
+        # component at the metal points
+        wc = W.with_critical_points(w)
+        tl = out["tiling"]
+        simc, dtc = run_gpu(wc, "fp32", args.cp_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]))
+        profc = simc.profile(max(2, args.profile_steps))
+        hbc, ejbc, nmc, _ = algorithmic_bytes(wc, simc.mask, 4)
+        ejbc += 4 * 12 * nmc * len(wc.cp)
+        out["critical_points"] = {
+            "workload": "the same sphere with 2 synthetic critical points, eps_inf 1.1, FP32",
+            "poles": len(wc.cp), "steps": args.cp_steps,
+            "value": round(wc.cells * args.cp_steps / dtc / 1e9, 3), "unit": "Gcell-updates/s",
+            "ms_per_step": round(dtc / args.cp_steps * 1e3, 5),
+            "ej_ms": round(profc["ej"], 5),
+            "ej_roofline_frac": round(ejbc / (profc["ej"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del simc
         torch.cuda.empty_cache()
     if args.batch_steps > 0:
         from paper_2005_06997_amd import binding

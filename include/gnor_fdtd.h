@@ -79,9 +79,19 @@ typedef struct {
 /* Free-electron metal (Sec. II): wp (rad/s), gamma (rad/s), beta (m/s; the
  * hydrodynamic pressure coefficient is beta^2), diffusion D (m^2/s; GNOR,
  * eta = beta^2 + D gamma), eps_inf (background permittivity of the metal).
- * beta = D = 0 is the local Drude model; D = 0 the nonlocal Drude model. */
+ * beta = D = 0 is the local Drude model; D = 0 the nonlocal Drude model.
+ *
+ * Bound electrons: ncp (0..4) critical points of Eq. (CritPoint), pole p
+ * with amplitude cp_A[p], frequency cp_Omega[p] (rad/s), width cp_Gamma[p]
+ * (rad/s) and phase cp_phi[p] (rad).  Their polarisation is updated at the
+ * metal points after E (f3, Eq. critpointupdate) and enters the E update and
+ * the extinction current.  With ncp > 0 the fused one-pass step and the
+ * design gradient are not available (GNOR_E_INVALID_ARG). */
+#define GNOR_MAX_CP 4
 typedef struct {
   double wp, gamma, beta, diffusion, eps_inf;
+  int32_t ncp;
+  double cp_A[GNOR_MAX_CP], cp_Omega[GNOR_MAX_CP], cp_Gamma[GNOR_MAX_CP], cp_phi[GNOR_MAX_CP];
 } gnor_material_desc;
 
 /* Plane-wave source: x-polarised, travelling along +z, injected through the
@@ -159,7 +169,9 @@ gnor_status gnor_get_spectra(gnor_sim *sim, double *inc, double *ext, double *ab
 gnor_status gnor_get_dft(gnor_sim *sim, double *a_re, double *a_im, double *b_re, double *b_im);
 
 /* Copy one field to host as nx*ny*nz doubles in SI units:
- * 0-2 E^n (V/m), 3-5 H^{n-1/2} (A/m), 6-8 J^{n-1/2} = dP_f/dt (A/m^2).
+ * 0-2 E^n (V/m), 3-5 H^{n-1/2} (A/m), 6-8 J^{n-1/2} = dP_f/dt (A/m^2),
+ * 9 + 3p + c (p < ncp): component c of the critical-point polarisation
+ * P_CP,p^n (C/m^2; zero outside the metal).
  * count must be nx*ny*nz.  Synchronises the stream. */
 gnor_status gnor_get_field(gnor_sim *sim, int32_t which, double *host_dst, size_t count);
 

@@ -22,6 +22,8 @@ GNOR_FP32, GNOR_FP64 = 0, 1
 STATUS = {0: "GNOR_OK", 1: "GNOR_E_INVALID_ARG", 2: "GNOR_E_UNSTABLE", 3: "GNOR_E_OUT_OF_MEMORY",
           4: "GNOR_E_DEVICE", 5: "GNOR_E_STATE", 6: "GNOR_E_BUFFER_TOO_SMALL", 7: "GNOR_E_NONFINITE"}
 FIELDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Hx": 3, "Hy": 4, "Hz": 5, "Jx": 6, "Jy": 7, "Jz": 8}
+# critical-point polarisation P_CP,p^n: "PC<p><c>"
+FIELDS.update({f"PC{p}{c}": 9 + 3 * p + i for p in range(4) for i, c in enumerate("xyz")})
 
 
 class GnorError(RuntimeError):
@@ -39,9 +41,15 @@ class GridDesc(C.Structure):
                 ("tf_lo", C.c_int32 * 3), ("tf_hi", C.c_int32 * 3), ("precision", C.c_int32)]
 
 
+MAX_CP = 4
+
+
 class MaterialDesc(C.Structure):
     _fields_ = [("wp", C.c_double), ("gamma", C.c_double), ("beta", C.c_double),
-                ("diffusion", C.c_double), ("eps_inf", C.c_double)]
+                ("diffusion", C.c_double), ("eps_inf", C.c_double),
+                ("ncp", C.c_int32),
+                ("cp_A", C.c_double * MAX_CP), ("cp_Omega", C.c_double * MAX_CP),
+                ("cp_Gamma", C.c_double * MAX_CP), ("cp_phi", C.c_double * MAX_CP)]
 
 
 class SourceDesc(C.Structure):
@@ -172,6 +180,12 @@ class Sim:
         self.h = h
         self.mask = voxelize(w) if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         mat = MaterialDesc(wp=w.wp, gamma=w.gamma, beta=w.beta, diffusion=w.diff, eps_inf=w.eps_inf)
+        cp = tuple(getattr(w, "cp", ()))
+        if len(cp) > MAX_CP:
+            raise ValueError(f"at most {MAX_CP} critical points")
+        mat.ncp = len(cp)
+        for u, (A, Om, Ga, ph) in enumerate(cp):
+            mat.cp_A[u], mat.cp_Omega[u], mat.cp_Gamma[u], mat.cp_phi[u] = A, Om, Ga, ph
         self._check(self.L.gnor_set_material(h, self.mask.ctypes.data, C.byref(mat)))
         self.design_shape = None
         if getattr(w, "design_lo", None) is not None:

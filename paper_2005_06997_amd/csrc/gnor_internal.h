@@ -38,6 +38,7 @@ constexpr int kAuxSrc = 22;
 // marching over kz planes.
 constexpr int kBX = 64;
 constexpr int kMaxFreq = 256;   // spectral frequencies per simulation
+constexpr int kMaxCP = 4;        // critical points per material
 constexpr int kFluxSlots = 256;  // flux staging depth (steps per accumulation)
 constexpr int kClasses = 4;     // tile classes of a sweep (plain, CPML, metal, metal + CPML)
 
@@ -122,7 +123,15 @@ struct Params {
   T* PJo;
   T* Q;                 // Q of the step's node scalars (written by k_h, read by k_ej)
   T eps_inf, d3, agam, D2, g1, g2, ebd;  // ebd = eps_inf - eps_b
-  T cS, c3, c1, cJ, cG;                   // E metal coefficients divided by (eps_inf + d3)
+  T cS, c3, c1, cJ, cG;                   // E metal coefficients divided by (eps_inf + d3 + c3sum)
+  // critical points (bound electrons) at the metal points, per pole u:
+  // P = P_CP/eps0 and its last increment Q on the sub-grid, updated in place;
+  // Q^{n+1} = cpa P + (1 - cpb) Q + cp4 (2 E^n) - cp5 (E^n - E^{n-1}) + cp3 (E^{n+1} - E^n)
+  int ncp;
+  T cpa[kMaxCP], cpb[kMaxCP], cp3[kMaxCP], cp4[kMaxCP], cp5[kMaxCP];
+  T c3sum;              // sum of cp3 (in the E divisor)
+  T* cpP[kMaxCP][3];
+  T* cpQ[kMaxCP][3];
   // CPML memory: psi[axis][t], t = 0 for component (axis+2)%3, 1 for (axis+1)%3;
   // psi_E is updated in place, psi_H read from psiHi and written to psiH
   T* psiE[3][2];
@@ -238,17 +247,12 @@ struct BatchEntry {
   int dblk0, dnblk;
 };
 
-template <class T>
-void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, hipStream_t s);
 // one class of the batched sweeps (blocks: that class's blocks of all instances)
 template <class T>
 void launch_h_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int c, hipStream_t s);
 template <class T>
-void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, int c,
+void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, int c, bool cp,
                            hipStream_t s);
-template <class T>
-void launch_ej_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, int sub,
-                     hipStream_t s);
 template <class T>
 void launch_dft_batch(const BatchEntry<T>* e, int n, int blocks, int sub, hipStream_t s);
 template <class T>

@@ -58,6 +58,7 @@ struct Layout {
   size_t state_begin = 0;
   size_t E[2][3] = {{0}}, H[2][3] = {{0}};
   size_t J[2][3] = {{0}}, PP[2] = {0, 0}, PJ[2] = {0, 0}, Q = 0;
+  size_t cpP[gnor::kMaxCP][3] = {{0}}, cpQ[gnor::kMaxCP][3] = {{0}};  // critical points
   size_t psiE[3][2] = {{0}}, psiH[2][3][2] = {{{0}}};
   size_t aux = 0, phase = 0, jpart = 0, dft = 0, fstage = 0, facc = 0, ptab = 0, step = 0,
          flux_lo = 0, flag = 0, fsum = 0;
@@ -231,6 +232,11 @@ void plan_layout(gnor_sim* s) {
     L.PJ[pp] = P.take(M * e);
   }
   L.Q = P.take(M * e);
+  for (int u = 0; u < s->mat.ncp; ++u)
+    for (int c = 0; c < 3; ++c) {
+      L.cpP[u][c] = P.take(M * e);
+      L.cpQ[u][c] = P.take(M * e);
+    }
   const size_t nx = s->g.nx, ny = s->g.ny, nz = s->g.nz;
   const size_t slab[3] = {nz * ny * 2 * np, nz * 2 * np * nx, 2 * np * ny * nx};
   for (int a = 0; a < 3; ++a)
@@ -294,7 +300,33 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   const double g1 = eta / Dd / (dx * dx);
   const double g2 = D / (2.0 * dt * Dd) / (dx * dx);
   const double ei = s->mat.eps_inf;
-  const double inv = 1.0 / (ei + d3);
+  // critical points, Eq. (critpointupdate) divided by eps0, as increments:
+  // Q = (P_CP^{n+1} - P_CP^n) / eps0 = a P + (1 - b) Q + c4 (2 E^n)
+  //   - c5 (E^n - E^{n-1}) + c3 (E^{n+1} - E^n), with a = C_1p + C_2p - 1 and
+  // b = 1 + C_2p (so that C_3p + C_4p + C_5p = 2 C_4p); the sin(phi) part of
+  // C_3p and C_5p is A Omega sin(phi) / (dt C_p)
+  double c3sum = 0.0;
+  p.ncp = s->mat.ncp;
+  for (int u = 0; u < s->mat.ncp; ++u) {
+    const double A = s->mat.cp_A[u], Om = s->mat.cp_Omega[u], Ga = s->mat.cp_Gamma[u];
+    const double ph = s->mat.cp_phi[u];
+    const double w2 = Om * Om + Ga * Ga;
+    const double Cp = Ga / dt + 1.0 / (dt * dt) + w2 / 4.0;
+    const double c4 = A * Om * (Om * std::cos(ph) - Ga * std::sin(ph)) / Cp;
+    const double sn = A * Om * std::sin(ph) / (dt * Cp);
+    p.cpa[u] = (T)(-w2 / Cp);
+    p.cpb[u] = (T)(2.0 * Ga / (dt * Cp));
+    p.cp3[u] = (T)(c4 / 2.0 - sn);
+    p.cp4[u] = (T)c4;
+    p.cp5[u] = (T)(c4 / 2.0 + sn);
+    c3sum += c4 / 2.0 - sn;
+    for (int c = 0; c < 3; ++c) {
+      p.cpP[u][c] = ptr<T>(s, s->L.cpP[u][c]);
+      p.cpQ[u][c] = ptr<T>(s, s->L.cpQ[u][c]);
+    }
+  }
+  p.c3sum = (T)c3sum;
+  const double inv = 1.0 / (ei + d3 + c3sum);
   p.eps_inf = (T)ei; p.d3 = (T)d3; p.agam = (T)agam; p.D2 = (T)D2; p.g1 = (T)g1; p.g2 = (T)g2;
   p.ebd = (T)(ei - g.eps_background);
   p.cS = (T)(S * inv); p.c3 = (T)(3.0 * d3 * inv); p.c1 = (T)(d3 * inv); p.cJ = (T)(D2 * inv);
@@ -663,6 +695,14 @@ gnor_status gnor_set_material(gnor_sim* s, const uint8_t* mask, const gnor_mater
   if (s->bound) return fail(s, GNOR_E_STATE, "material must be set before gnor_bind_memory");
   if (!(m->wp >= 0) || !(m->gamma >= 0) || !(m->beta >= 0) || !(m->diffusion >= 0) || !(m->eps_inf > 0))
     return fail(s, GNOR_E_INVALID_ARG, "material parameters must be non-negative (eps_inf > 0)");
+  if (m->ncp < 0 || m->ncp > gnor::kMaxCP)
+    return fail(s, GNOR_E_INVALID_ARG, "ncp must lie in [0, 4]");
+  for (int u = 0; u < m->ncp; ++u)
+    if (!std::isfinite(m->cp_A[u]) || !(m->cp_Omega[u] >= 0) || !(m->cp_Gamma[u] >= 0) ||
+        !std::isfinite(m->cp_phi[u]))
+      return fail(s, GNOR_E_INVALID_ARG, "critical points need finite A, phi and Omega, Gamma >= 0");
+  if (m->ncp > 0 && s->fused)
+    return fail(s, GNOR_E_INVALID_ARG, "the fused step has no critical-point terms (gnor_set_fused 0 first)");
   const gnor_grid_desc& g = s->g;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
   s->mask.assign(N, 0);
@@ -848,6 +888,8 @@ gnor_status gnor_set_class_streams(gnor_sim* s, int32_t on) {
 
 gnor_status gnor_set_fused(gnor_sim* s, int32_t on) {
   if (!s || (on != 0 && on != 1)) return GNOR_E_INVALID_ARG;
+  if (on && s->have_material && s->mat.ncp > 0)
+    return fail(s, GNOR_E_INVALID_ARG, "the fused step has no critical-point terms");
   if ((on != 0) != s->fused) {
     s->fused = on != 0;
     drop_graph(s);
@@ -973,7 +1015,7 @@ gnor_status gnor_get_field(gnor_sim* s, int32_t which, double* dst, size_t count
   if (st != GNOR_OK) return st;
   if (!dst) return GNOR_E_INVALID_ARG;
   if (count != s->N) return fail(s, GNOR_E_BUFFER_TOO_SMALL, "count must be nx*ny*nz");
-  if (which < 0 || which > 8) return fail(s, GNOR_E_INVALID_ARG, "field index out of range");
+  if (which < 0 || which >= 9 + 3 * s->mat.ncp) return fail(s, GNOR_E_INVALID_ARG, "field index out of range");
   HIPCHECK(s, hipStreamSynchronize(s->stream));
   const int parity = (int)(s->step & 1);
   const int c = which % 3;
@@ -1002,9 +1044,11 @@ gnor_status gnor_get_field(gnor_sim* s, int32_t which, double* dst, size_t count
   } else {
     std::memset(dst, 0, s->N * 8);
     if (s->any_metal) {
-      st = fetch(s->L.J[parity][c], s->M, v);
+      // J (sub-grid, scaled increment of P_f) or P_CP,u / eps0 (sub-grid)
+      const bool cp = which >= 9;
+      st = fetch(cp ? s->L.cpP[(which - 9) / 3][c] : s->L.J[parity][c], s->M, v);
       if (st != GNOR_OK) return st;
-      const double k = eps0() / s->dt;
+      const double k = cp ? eps0() : eps0() / s->dt;
       const gnor_grid_desc& g = s->g;
       for (int z = 0; z < s->mn[2]; ++z)
         for (int y = 0; y < s->mn[1]; ++y)
@@ -1351,7 +1395,7 @@ struct gnor_batch {
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   std::vector<int> tiling;   // (ty, kz, order) of every instance at creation
-  bool any_dft = false, any_flux = false;
+  bool any_dft = false, any_flux = false, any_cp = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipGraphExec_t graph = nullptr;
@@ -1427,7 +1471,7 @@ void batch_enqueue(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st) {
       gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, q2);
     });
     classes([&](int c, hipStream_t q2) {
-      gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, sub, c, q2);
+      gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, sub, c, b->any_cp, q2);
     });
     if (b->any_dft && b->dblocks > 0) gnor::launch_dft_batch<T>(t, b->n, b->dblocks, sub, st);
     if (b->any_flux && (n % gnor::kFluxSlots) == gnor::kFluxSlots - 1)
@@ -1466,6 +1510,7 @@ gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, gn
     b->tiling.insert(b->tiling.end(), {s->tile_ty, s->tile_kz, s->tile_xcd});
     b->any_dft = b->any_dft || s->mon.nfreq > 0;
     b->any_flux = b->any_flux || s->nsamp > 0;
+    b->any_cp = b->any_cp || s->mat.ncp > 0;
   }
   b->fp32 = sims[0]->g.precision == GNOR_FP32;
   b->ty = sims[0]->tile_ty;
@@ -1724,6 +1769,7 @@ extern "C" gnor_status gnor_gradient(gnor_sim* s, int64_t nsteps, int32_t ckpt_e
   if (!grad || nsteps < 1 || ckpt_every < 1) return fail(s, GNOR_E_INVALID_ARG, "bad gradient arguments");
   if (m_target < 0 || m_target >= s->mon.nfreq) return fail(s, GNOR_E_INVALID_ARG, "m_target outside the frequency list");
   if (s->mon.dft_every > 1) return fail(s, GNOR_E_INVALID_ARG, "gradients need dft_every = 1");
+  if (s->mat.ncp > 0) return fail(s, GNOR_E_INVALID_ARG, "gradients do not cover critical points");
   if (s->mat.eps_inf != s->g.eps_background)
     return fail(s, GNOR_E_INVALID_ARG, "gradients need eps_inf = eps_background");
   // the backward pass needs the stored Q of each recomputed step, so the whole

@@ -196,8 +196,45 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
   }
 }
 
+// Critical points of one E component at metal point l: the known part R_u of
+// each pole's increment (before E^{n+1}) and their sum, which enters the E
+// update; then the increments and polarisations after it (f3).
+template <class T>
+struct CpState {
+  T P[kMaxCP], R[kMaxCP];
+};
+template <class T>
+__device__ __forceinline__ T cp_known(const Params<T>& p, int c, size_t l, T r, T e, T em, CpState<T>& st) {
+  T sum = T(0);
+#pragma unroll
+  for (int u = 0; u < kMaxCP; ++u) {
+    if (u < p.ncp) {
+      st.P[u] = p.cpP[u][c][l];
+      const T q = p.cpQ[u][c][l];
+      st.R[u] = p.cpa[u] * st.P[u] + (q - p.cpb[u] * q) + r * (p.cp4[u] * (T(2) * e) - p.cp5[u] * (e - em));
+      sum += st.R[u];
+    }
+  }
+  return sum;
+}
+template <class T>
+__device__ __forceinline__ double cp_update(const Params<T>& p, int c, size_t l, T r, T de,
+                                            const CpState<T>& st) {
+  double inc = 0.0;
+#pragma unroll
+  for (int u = 0; u < kMaxCP; ++u) {
+    if (u < p.ncp) {
+      const T q = st.R[u] + r * p.cp3[u] * de;
+      p.cpQ[u][c][l] = q;
+      p.cpP[u][c][l] = st.P[u] + q;
+      inc += (double)q;
+    }
+  }
+  return inc;
+}
+
 // ------------------------------------------------------- f2 + f4: E and J
-template <class T, int TY, bool METAL, bool PML>
+template <class T, int TY, bool METAL, bool PML, bool CP>
 __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, bool pml_tile) {
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
@@ -332,28 +369,35 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
         if (p.rho) {
           r = (T)p.rho[l];
           d3 = r * p.d3;
-          const T inv = T(1) / (p.eps_inf + d3);
+          const T inv = T(1) / (p.eps_inf + d3 + (CP ? r * p.c3sum : T(0)));
           cS = p.S * inv; c3 = T(3) * d3 * inv; c1 = d3 * inv; cJ = p.D2 * inv; cG = inv;
         }
         const T ag = p.agam;
+        CpState<T> cps;
         if (b0) {
           const T G = r * (qx - q);
-          const T en = ex + (cS * cxv - c3 * ex - c1 * emx + cJ * jx - cG * G);
+          const T rs = CP ? cp_known(p, 0, l, r, ex, emx, cps) : T(0);
+          const T en = ex + (cS * cxv - c3 * ex - c1 * emx + cJ * jx - cG * (CP ? G + rs : G));
           const T jn = jx + (d3 * (emx + T(2) * ex + en) - ag * jx + G);
           p.Jo[0][l] = jn;
           jsum = (double)jn + (double)p.ebd * ((double)en - (double)ex);
+          if (CP) jsum += cp_update(p, 0, l, r, en - ex, cps);
           nx_ = en;
         }
         if (b1) {
           const T G = r * (qy - q);
-          const T en = ey + (cS * cyv - c3 * ey - c1 * emy + cJ * jy - cG * G);
+          const T rs = CP ? cp_known(p, 1, l, r, ey, emy, cps) : T(0);
+          const T en = ey + (cS * cyv - c3 * ey - c1 * emy + cJ * jy - cG * (CP ? G + rs : G));
           p.Jo[1][l] = jy + (d3 * (emy + T(2) * ey + en) - ag * jy + G);
+          if (CP) cp_update(p, 1, l, r, en - ey, cps);
           ny_ = en;
         }
         if (b2) {
           const T G = r * (qz - q);
-          const T en = ez + (cS * czv - c3 * ez - c1 * emz + cJ * jz - cG * G);
+          const T rs = CP ? cp_known(p, 2, l, r, ez, emz, cps) : T(0);
+          const T en = ez + (cS * czv - c3 * ez - c1 * emz + cJ * jz - cG * (CP ? G + rs : G));
           p.Jo[2][l] = jz + (d3 * (emz + T(2) * ez + en) - ag * jz + G);
+          if (CP) cp_update(p, 2, l, r, en - ez, cps);
           nz_ = en;
         }
       }
@@ -384,14 +428,14 @@ __device__ __forceinline__ void h_class(const Params<T>& p, int b) {
   else if (CLS == 2) h_tile<T, TY, true, false>(p, tile, false);
   else h_tile<T, TY, true, true>(p, tile, true);
 }
-template <class T, int TY, int CLS>
+template <class T, int TY, int CLS, bool CP>
 __device__ __forceinline__ void ej_class(const Params<T>& p, int b) {
   const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
   if (!tile.ok) return;
-  if (CLS == 0) ej_tile<T, TY, false, false>(p, tile, false);
-  else if (CLS == 1) ej_tile<T, TY, false, true>(p, tile, true);
-  else if (CLS == 2) ej_tile<T, TY, true, false>(p, tile, false);
-  else ej_tile<T, TY, true, true>(p, tile, true);
+  if (CLS == 0) ej_tile<T, TY, false, false, false>(p, tile, false);
+  else if (CLS == 1) ej_tile<T, TY, false, true, false>(p, tile, true);
+  else if (CLS == 2) ej_tile<T, TY, true, false, CP>(p, tile, false);
+  else ej_tile<T, TY, true, true, CP>(p, tile, true);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -406,13 +450,15 @@ __global__ void __launch_bounds__(kBX* TY) k_h(Params<T> p, AuxParams a) {
   h_class<T, TY, CLS>(p, blockIdx.x);
 }
 
-template <class T, int TY, int CLS>
+// CP: the metal classes with critical points (a separate variant, so the
+// plain metal code keeps its registers)
+template <class T, int TY, int CLS, bool CP>
 __global__ void __launch_bounds__(kBX* TY) k_ej(Params<T> p, AuxParams a, int sub) {
   if (CLS == 0 && (int)blockIdx.x == (int)gridDim.x - 1) {
     aux_e_block(a, sub, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  ej_class<T, TY, CLS>(p, blockIdx.x);
+  ej_class<T, TY, CLS, CP>(p, blockIdx.x);
 }
 
 // Batch: the blocks of all instances in one launch per class.  Instance q
@@ -441,7 +487,7 @@ __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __rest
   h_class<T, TY, CLS>(en.p, b);
 }
 
-template <class T, int TY, int CLS>
+template <class T, int TY, int CLS, bool CP>
 __global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __restrict__ e, int n,
                                                       int sub) {
   const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
@@ -450,7 +496,7 @@ __global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __res
     aux_e_block(en.a, sub, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  ej_class<T, TY, CLS>(en.p, b);
+  ej_class<T, TY, CLS, CP>(en.p, b);
 }
 
 }  // namespace
@@ -529,13 +575,13 @@ void launch_h_cls(const Params<T>& p, const AuxParams& a, hipStream_t s) {
   else if (p.tl.ty == 8) hipLaunchKernelGGL((k_h<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, p, a);
   else hipLaunchKernelGGL((k_h<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, p, a);
 }
-template <class T, int CLS>
+template <class T, int CLS, bool CP>
 void launch_ej_cls(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s) {
   const int blocks = class_blocks(p.tl, CLS) + (CLS == 0 ? 1 : 0);
   if (blocks == 0) return;
-  if (p.tl.ty == 4) hipLaunchKernelGGL((k_ej<T, 4, CLS>), dim3(blocks), dim3(kBX, 4), 0, s, p, a, sub);
-  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_ej<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, p, a, sub);
-  else hipLaunchKernelGGL((k_ej<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, p, a, sub);
+  if (p.tl.ty == 4) hipLaunchKernelGGL((k_ej<T, 4, CLS, CP>), dim3(blocks), dim3(kBX, 4), 0, s, p, a, sub);
+  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_ej<T, 8, CLS, CP>), dim3(blocks), dim3(kBX, 8), 0, s, p, a, sub);
+  else hipLaunchKernelGGL((k_ej<T, 2, CLS, CP>), dim3(blocks), dim3(kBX, 2), 0, s, p, a, sub);
 }
 template <class T, int CLS>
 void launch_h_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s) {
@@ -544,12 +590,12 @@ void launch_h_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, hipSt
   else if (ty == 8) hipLaunchKernelGGL((k_h_batch<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, e, n);
   else hipLaunchKernelGGL((k_h_batch<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, e, n);
 }
-template <class T, int CLS>
+template <class T, int CLS, bool CP>
 void launch_ej_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, hipStream_t s) {
   if (blocks == 0) return;
-  if (ty == 4) hipLaunchKernelGGL((k_ej_batch<T, 4, CLS>), dim3(blocks), dim3(kBX, 4), 0, s, e, n, sub);
-  else if (ty == 8) hipLaunchKernelGGL((k_ej_batch<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, e, n, sub);
-  else hipLaunchKernelGGL((k_ej_batch<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, e, n, sub);
+  if (ty == 4) hipLaunchKernelGGL((k_ej_batch<T, 4, CLS, CP>), dim3(blocks), dim3(kBX, 4), 0, s, e, n, sub);
+  else if (ty == 8) hipLaunchKernelGGL((k_ej_batch<T, 8, CLS, CP>), dim3(blocks), dim3(kBX, 8), 0, s, e, n, sub);
+  else hipLaunchKernelGGL((k_ej_batch<T, 2, CLS, CP>), dim3(blocks), dim3(kBX, 2), 0, s, e, n, sub);
 }
 }  // namespace
 
@@ -562,10 +608,11 @@ void launch_h_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s
 }
 template <class T>
 void launch_ej_class(const Params<T>& p, const AuxParams& a, int sub, int c, hipStream_t s) {
-  if (c == 0) launch_ej_cls<T, 0>(p, a, sub, s);
-  else if (c == 1) launch_ej_cls<T, 1>(p, a, sub, s);
-  else if (c == 2) launch_ej_cls<T, 2>(p, a, sub, s);
-  else launch_ej_cls<T, 3>(p, a, sub, s);
+  const bool cp = p.ncp > 0;
+  if (c == 0) launch_ej_cls<T, 0, false>(p, a, sub, s);
+  else if (c == 1) launch_ej_cls<T, 1, false>(p, a, sub, s);
+  else if (c == 2) cp ? launch_ej_cls<T, 2, true>(p, a, sub, s) : launch_ej_cls<T, 2, false>(p, a, sub, s);
+  else cp ? launch_ej_cls<T, 3, true>(p, a, sub, s) : launch_ej_cls<T, 3, false>(p, a, sub, s);
 }
 template <class T>
 void launch_h(const Params<T>& p, const AuxParams& a, hipStream_t s) {
@@ -587,36 +634,21 @@ void launch_h_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int
   else launch_h_batch_cls<T, 3>(e, n, blocks, ty, s);
 }
 template <class T>
-void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, int c,
+void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, int c, bool cp,
                            hipStream_t s) {
-  if (c == 0) launch_ej_batch_cls<T, 0>(e, n, blocks, ty, sub, s);
-  else if (c == 1) launch_ej_batch_cls<T, 1>(e, n, blocks, ty, sub, s);
-  else if (c == 2) launch_ej_batch_cls<T, 2>(e, n, blocks, ty, sub, s);
-  else launch_ej_batch_cls<T, 3>(e, n, blocks, ty, sub, s);
+  if (c == 0) launch_ej_batch_cls<T, 0, false>(e, n, blocks, ty, sub, s);
+  else if (c == 1) launch_ej_batch_cls<T, 1, false>(e, n, blocks, ty, sub, s);
+  else if (c == 2) cp ? launch_ej_batch_cls<T, 2, true>(e, n, blocks, ty, sub, s)
+                      : launch_ej_batch_cls<T, 2, false>(e, n, blocks, ty, sub, s);
+  else cp ? launch_ej_batch_cls<T, 3, true>(e, n, blocks, ty, sub, s)
+          : launch_ej_batch_cls<T, 3, false>(e, n, blocks, ty, sub, s);
 }
 template void launch_h_batch_class<float>(const BatchEntry<float>*, int, int, int, int, hipStream_t);
 template void launch_h_batch_class<double>(const BatchEntry<double>*, int, int, int, int, hipStream_t);
-template void launch_ej_batch_class<float>(const BatchEntry<float>*, int, int, int, int, int, hipStream_t);
-template void launch_ej_batch_class<double>(const BatchEntry<double>*, int, int, int, int, int, hipStream_t);
-template <class T>
-void launch_h_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, hipStream_t s) {
-  launch_h_batch_cls<T, 0>(e, n, blocks[0], ty, s);
-  launch_h_batch_cls<T, 1>(e, n, blocks[1], ty, s);
-  launch_h_batch_cls<T, 2>(e, n, blocks[2], ty, s);
-  launch_h_batch_cls<T, 3>(e, n, blocks[3], ty, s);
-}
-template <class T>
-void launch_ej_batch(const BatchEntry<T>* e, int n, const int blocks[kClasses], int ty, int sub,
-                     hipStream_t s) {
-  launch_ej_batch_cls<T, 0>(e, n, blocks[0], ty, sub, s);
-  launch_ej_batch_cls<T, 1>(e, n, blocks[1], ty, sub, s);
-  launch_ej_batch_cls<T, 2>(e, n, blocks[2], ty, sub, s);
-  launch_ej_batch_cls<T, 3>(e, n, blocks[3], ty, sub, s);
-}
-template void launch_h_batch<float>(const BatchEntry<float>*, int, const int[kClasses], int, hipStream_t);
-template void launch_h_batch<double>(const BatchEntry<double>*, int, const int[kClasses], int, hipStream_t);
-template void launch_ej_batch<float>(const BatchEntry<float>*, int, const int[kClasses], int, int, hipStream_t);
-template void launch_ej_batch<double>(const BatchEntry<double>*, int, const int[kClasses], int, int, hipStream_t);
+template void launch_ej_batch_class<float>(const BatchEntry<float>*, int, int, int, int, int, bool,
+                                           hipStream_t);
+template void launch_ej_batch_class<double>(const BatchEntry<double>*, int, int, int, int, int, bool,
+                                            hipStream_t);
 template void launch_h<float>(const Params<float>&, const AuxParams&, hipStream_t);
 template void launch_h<double>(const Params<double>&, const AuxParams&, hipStream_t);
 template void launch_ej<float>(const Params<float>&, const AuxParams&, int, hipStream_t);

@@ -30,6 +30,11 @@ WP = 1.37e16       # rad/s
 GAMMA = 1.06e14    # rad/s
 BETA = 1.0e6       # m/s (beta itself; beta^2 = 1e12 m^2/s^2)
 DIFF = 1.9e-4      # m^2/s
+# Two synthetic critical points (A, Omega [rad/s], Gamma [rad/s], phi [rad])
+# with the magnitudes of noble-metal interband fits (poles near 2.6 and 3.7
+# eV, widths of 0.4-1.2 eV, negative phases); not a fit to measured data.
+CP_SYNTH = ((0.65, 4.0e15, 6.5e14, -1.2), (1.4, 5.6e15, 1.9e15, -1.1))
+EPS_INF_SYNTH = 1.1
 
 
 def ev_to_rad(e: float) -> float:
@@ -64,6 +69,8 @@ class Workload:
     beta: float = BETA
     diff: float = DIFF
     eps_inf: float = 1.0
+    # critical points (Eq. CritPoint): (A, Omega, Gamma, phi) per pole
+    cp: Tuple = ()
     # source: 1 modulated Gaussian, 2 raised cosine
     src_kind: int = 1
     e0: float = 1.0
@@ -294,6 +301,13 @@ def small_sphere(n: int = 32, dx: float = 0.25e-9, radius: float = 1.2e-9, npml:
     centre = (n - 1) / 2.0 + off
     return sphere_problem(f"small_sphere_{n}^3_seed{seed}", n, dx, npml, centre, radius,
                           steps=steps, **kw)
+
+
+def with_critical_points(w: Workload, poles=CP_SYNTH, eps_inf: float = EPS_INF_SYNTH) -> Workload:
+    """The same problem with bound electrons: the two synthetic critical points
+    and eps_inf > 1 in the metal (eps_b stays 1)."""
+    return replace(w, name=w.name + "_cp", cp=tuple(tuple(float(x) for x in q) for q in poles),
+                   eps_inf=eps_inf)
 
 
 def early_pulse(w: Workload) -> Workload:

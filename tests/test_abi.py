@@ -106,3 +106,48 @@ def test_star_mask_bit_exact_vs_oracle(seed):
     b = oracle_mask(w)
     assert a.any()
     assert np.array_equal(a, b)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """sizeof and field offsets of the ABI structs as the C compiler lays them
+    out, against the ctypes mirrors in the binding."""
+    import os
+    import subprocess
+
+    structs = {"gnor_grid_desc": B.GridDesc, "gnor_material_desc": B.MaterialDesc,
+               "gnor_source_desc": B.SourceDesc, "gnor_monitor_desc": B.MonitorDesc}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gnor_fdtd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(out[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_material_rejects_bad_critical_points(lib):
+    w = W.config1(0)
+    st, h = _create(lib, _grid(w))
+    assert st == 0
+    mask = oracle_mask(w)
+    m = B.MaterialDesc(wp=w.wp, gamma=w.gamma, beta=w.beta, diffusion=w.diff, eps_inf=1.0)
+    m.ncp = 5
+    mp = mask.ctypes.data_as(C.c_void_p)
+    assert lib.gnor_set_material(h, mp, C.byref(m)) == 1  # GNOR_E_INVALID_ARG
+    m.ncp = 1
+    m.cp_A[0], m.cp_Omega[0], m.cp_Gamma[0], m.cp_phi[0] = 1.0, 4e15, -1.0, 0.0
+    assert lib.gnor_set_material(h, mp, C.byref(m)) == 1
+    m.cp_Gamma[0] = 5e14
+    assert lib.gnor_set_material(h, mp, C.byref(m)) == 0
+    assert lib.gnor_set_fused(h, 1) == 1
+    lib.gnor_destroy(h)
