@@ -43,6 +43,11 @@
 //     incident field, and of tangential E and H on two flux boxes
 //     (absorption: total field inside the TF box; scattering: scattered
 //     field outside it).
+//   * Near-field and free-electron density maps on one grid plane (the field
+//     and density distributions of Sec. V): running transforms of E_x, E_y,
+//     E_z at their Yee points of the plane (stamped (n+1) dt) and of the
+//     density n - n0 = div P_f / e of Eq. (Nsol) at its nodes (backward
+//     differences of P_f^n, stamped n dt), every map_every steps.
 // A templated scalar lets the same code run on dual numbers, which gives the
 // exact directional derivative of an objective with respect to the metal
 // weights (forward-mode differentiation).
@@ -123,6 +128,10 @@ typedef struct {
   // Gamma_p [rad/s], phi_p [rad]
   int32_t ncp;
   double cp_A[4], cp_Omega[4], cp_Gamma[4], cp_phi[4];
+  // maps: plane map_index normal to map_axis, nmap frequencies, every
+  // map_every steps
+  int32_t map_axis, map_index, nmap, map_every;
+  double map_omega[8];
 } or_config;
 
 }  // extern "C"
@@ -163,6 +172,10 @@ struct Sim {
     std::vector<R> Eb_re, Eb_im, Hc_re, Hc_im, Ec_re, Ec_im, Hb_re, Hb_im;
   };
   std::vector<Face> faces[2];       // 0: absorption box, 1: scattering box
+  // maps: [quantity][m][v][u], quantity Re/Im of E_x, E_y, E_z, n - n0
+  int nmap = 0, mu = 0, mv = 0;
+  std::vector<R> maps;
+  std::vector<double> map_inc;      // [m][re, im] incident transform at norm_k
 
   size_t id(int i, int j, int k) const { return ((size_t)k * ny + j) * nx + i; }
   int wrap(int i, int n) const { return c.periodic ? ((i % n) + n) % n : i; }
@@ -274,6 +287,11 @@ struct Sim {
       make_faces(0, c.abs_lo, c.abs_hi);
       make_faces(1, c.sca_lo, c.sca_hi);
     }
+    nmap = c.nmap < 0 ? 0 : (c.nmap > 8 ? 8 : c.nmap);
+    const int ua = c.map_axis == 0 ? 1 : 0, va = c.map_axis == 2 ? 1 : 2;
+    mu = ns[ua]; mv = ns[va];
+    maps.assign((size_t)8 * nmap * mu * mv, R(0.0));
+    map_inc.assign((size_t)2 * nmap, 0.0);
     step = 0;
   }
 
@@ -564,6 +582,48 @@ struct Sim {
       for (auto& f : faces[box]) accumulate_face(f, wdt, cE, sE, cJ, sJ);
   }
 
+  // P_f^n (held in Pm after a step) at index (i, j, k), zero off the grid
+  R pm_at(int comp, int i, int j, int k) const {
+    if (i < 0 || j < 0 || k < 0 || i >= nx || j >= ny || k >= nz) return R(0.0);
+    return Pm[comp][id(i, j, k)];
+  }
+
+  void accumulate_maps(long n) {
+    if (nmap <= 0) return;
+    const int every = c.map_every > 1 ? c.map_every : 1;
+    if (every > 1 && (n % every) != 0) return;
+    const double wdt = dt * every;
+    const double tE = (n + 1.0) * dt, tN = (double)n * dt;
+    const double qe = 1.602176634e-19;  // elementary charge (C), Eq. (Nsol)
+    const int ua = c.map_axis == 0 ? 1 : 0, va = c.map_axis == 2 ? 1 : 2;
+    for (int m = 0; m < nmap; ++m) {
+      const double w = c.map_omega[m];
+      const double ce = std::cos(w * tE), se = std::sin(w * tE);
+      const double cn = std::cos(w * tN), sn = std::sin(w * tN);
+      const size_t plane = (size_t)mu * mv;
+      for (int v = 0; v < mv; ++v)
+        for (int u = 0; u < mu; ++u) {
+          int ii[3];
+          ii[c.map_axis] = c.map_index; ii[ua] = u; ii[va] = v;
+          const int i = ii[0], j = ii[1], k = ii[2];
+          const size_t q = (size_t)v * mu + u;
+          for (int comp = 0; comp < 3; ++comp) {
+            const R e = E[comp][id(i, j, k)];
+            maps[(size_t)(2 * comp) * nmap * plane + m * plane + q] += (wdt * ce) * e;
+            maps[(size_t)(2 * comp + 1) * nmap * plane + m * plane + q] += (wdt * se) * e;
+          }
+          const R dens = ((pm_at(0, i, j, k) - pm_at(0, i - 1, j, k)) +
+                          (pm_at(1, i, j, k) - pm_at(1, i, j - 1, k)) +
+                          (pm_at(2, i, j, k) - pm_at(2, i, j, k - 1))) / (dx * qe);
+          maps[(size_t)6 * nmap * plane + m * plane + q] += (wdt * cn) * dens;
+          maps[(size_t)7 * nmap * plane + m * plane + q] += (wdt * sn) * dens;
+        }
+      const double ei = e1[c.norm_k + kAuxOff];
+      map_inc[2 * m] += wdt * ce * ei;
+      map_inc[2 * m + 1] += wdt * se * ei;
+    }
+  }
+
   R comp_at(const std::vector<R>* F, int comp, int a, int p, int b, int ib, int cc, int ic) const {
     int ii[3];
     ii[a] = p; ii[b] = ib; ii[cc] = ic;
@@ -665,6 +725,7 @@ struct Sim {
       update_e_p();                  // E^{n+1}, P^{n+1}; uses H_inc^{n+1/2}
       if (c.tfsf || c.src_kind) update_e1((n + 1) * dt);  // E_inc^{n+1}
       accumulate(n);
+      accumulate_maps(n);
       ++step;
     }
   }
@@ -826,6 +887,16 @@ double or_box_flux(const or_sim* h, int box, int m) {
 }
 double or_face_flux(const or_sim* h, int box, int face, int m) {
   return reinterpret_cast<const Sim<double>*>(h)->face_flux(box, face, m);
+}
+
+// Maps: fields [8][nmap][mv][mu] (Re/Im of E_x, E_y, E_z transforms, V s/m,
+// then of the density transform, s/m^3), inc [nmap][2].  Returns the plane
+// size mu * mv.
+long or_get_maps(const or_sim* h, double* fields, double* inc) {
+  const auto* s = reinterpret_cast<const Sim<double>*>(h);
+  if (fields) std::memcpy(fields, s->maps.data(), s->maps.size() * 8);
+  if (inc) std::memcpy(inc, s->map_inc.data(), s->map_inc.size() * 8);
+  return (long)s->mu * s->mv;
 }
 
 // Forward-mode derivative: the metal weight is w = weight + t * direction and

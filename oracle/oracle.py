@@ -60,6 +60,8 @@ def lib():
         L.or_aux_len.argtypes = [C.c_void_p]
         L.or_get_dft.argtypes = [C.c_void_p] + [C.c_void_p] * 4
         L.or_spectra.argtypes = [C.c_void_p] + [C.c_void_p] * 4
+        L.or_get_maps.restype = C.c_long
+        L.or_get_maps.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_box_flux.restype = C.c_double
         L.or_box_flux.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.or_face_flux.restype = C.c_double
@@ -100,6 +102,8 @@ class OrConfig(C.Structure):
         ("ncp", C.c_int32),
         ("cp_A", C.c_double * 4), ("cp_Omega", C.c_double * 4),
         ("cp_Gamma", C.c_double * 4), ("cp_phi", C.c_double * 4),
+        ("map_axis", C.c_int32), ("map_index", C.c_int32), ("nmap", C.c_int32),
+        ("map_every", C.c_int32), ("map_omega", C.c_double * 8),
     ]
 
 
@@ -144,6 +148,11 @@ class Problem:
     threads: int = 0
     # critical points, Eq. (CritPoint): up to 4 poles (A_p, Omega_p, Gamma_p, phi_p)
     cp: Sequence[Sequence[float]] = ()
+    # near-field / density maps on the plane map_index normal to map_axis
+    map_axis: int = 1
+    map_index: int = 0
+    map_every: int = 1
+    map_omega: np.ndarray = field(default_factory=lambda: np.zeros(0))
 
     def to_c(self) -> OrConfig:
         c = OrConfig()
@@ -155,6 +164,14 @@ class Problem:
                 if len(self.cp) > 4:
                     raise ValueError("at most 4 critical points")
                 c.ncp = len(self.cp)
+                continue
+            if name == "nmap":
+                if len(self.map_omega) > 8:
+                    raise ValueError("at most 8 map frequencies")
+                c.nmap = len(self.map_omega)
+                continue
+            if name == "map_omega":
+                c.map_omega[:] = [float(x) for x in self.map_omega] + [0.0] * (8 - len(self.map_omega))
                 continue
             if name.startswith("cp_"):
                 col = {"cp_A": 0, "cp_Omega": 1, "cp_Gamma": 2, "cp_phi": 3}[name]
@@ -242,6 +259,22 @@ class OracleSim:
         arrs = [np.empty((self.prob.nz, nf)) for _ in range(4)]
         lib().or_get_dft(self.h, *[_ptr(a) for a in arrs])
         return (arrs[0] + 1j * arrs[1], arrs[2] + 1j * arrs[3])
+
+    def maps(self):
+        """Map transforms: dict Ex, Ey, Ez, n -> complex (nmap, mv, mu) arrays,
+        and inc -> complex (nmap,) incident transforms at norm_k."""
+        p = self.prob
+        nm = len(p.map_omega)
+        ns = (p.nx, p.ny, p.nz)
+        ua = 1 if p.map_axis == 0 else 0
+        va = 1 if p.map_axis == 2 else 2
+        mu, mv = ns[ua], ns[va]
+        f = np.empty((8, nm, mv, mu))
+        inc = np.empty((nm, 2))
+        assert lib().or_get_maps(self.h, _ptr(f), _ptr(inc)) == mu * mv
+        out = {k: f[2 * q] + 1j * f[2 * q + 1] for q, k in enumerate(("Ex", "Ey", "Ez", "n"))}
+        out["inc"] = inc[:, 0] + 1j * inc[:, 1]
+        return out
 
     def spectra(self):
         nf = len(self._om)
