@@ -120,6 +120,8 @@ def main():
                     help="steps of the design-gradient run (forward + adjoint; 0 = skip)")
     ap.add_argument("--cp-steps", type=int, default=512,
                     help="steps of the same sphere with two critical points (0 = skip)")
+    ap.add_argument("--maps-steps", type=int, default=512,
+                    help="steps of the same sphere with near-field and density maps (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=256,
                     help="steps of the 64-instance batched sweep (0 = skip)")
     ap.add_argument("--tiling", type=str, default=None,
@@ -235,6 +237,21 @@ def main():
             "ej_ms": round(profc["ej"], 5),
             "ej_roofline_frac": round(ejbc / (profc["ej"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del simc
+        torch.cuda.empty_cache()
+    if args.maps_steps > 0:
+        # near-field and density maps: 4 frequencies on the xz plane through
+        # the sphere, every step (8 FP64 accumulators per point and frequency)
+        wm = W.with_maps(w, W.spectrum_omegas(4, 2.5, 4.0), every=1, axis=1)
+        tl = out["tiling"]
+        simm, dtm = run_gpu(wm, "fp32", args.maps_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]))
+        mp = simm.maps()
+        out["maps"] = {
+            "workload": "the same sphere with maps at 4 frequencies on the 320x320 xz plane, every step",
+            "steps": args.maps_steps, "value": round(wm.cells * args.maps_steps / dtm / 1e9, 3),
+            "unit": "Gcell-updates/s", "ms_per_step": round(dtm / args.maps_steps * 1e3, 5),
+            "overhead_ms_per_step": round(dtm / args.maps_steps * 1e3 - ms_step, 5),
+            "peak_density_m3s": float(np.abs(mp["n"]).max())}
+        del simm
         torch.cuda.empty_cache()
     if args.batch_steps > 0:
         from paper_2005_06997_amd import binding

@@ -168,6 +168,29 @@ gnor_status gnor_get_spectra(gnor_sim *sim, double *inc, double *ext, double *ab
  * nz * nfreq doubles each. */
 gnor_status gnor_get_dft(gnor_sim *sim, double *a_re, double *a_im, double *b_re, double *b_im);
 
+/* Near-field and free-electron density maps (the field and density
+ * distributions of Sec. V): running transforms (factor every*dt, e^{+i w t})
+ * on the grid plane `index` normal to `axis` (0 x, 1 y, 2 z) at nmap (<= 8)
+ * angular frequencies omega[] (rad/s).  E_x, E_y and E_z are taken at their
+ * Yee points of the plane and stamped (n+1) dt; the free-electron density
+ * n - n0 = div P_f / e (Eq. Nsol) at the plane's nodes, from P_f^n (backward
+ * differences), stamped n dt; every `every` steps (1 = each step).  Plane
+ * coordinates (u, v) are the two other axes in x, y, z order, u fastest.
+ * Set before gnor_bind_memory (nmap = 0 turns the maps off).  Not with
+ * batches or gnor_gradient (GNOR_E_STATE). */
+typedef struct {
+  int32_t axis, index, nmap, every;
+  const double *omega;
+} gnor_map_desc;
+gnor_status gnor_set_maps(gnor_sim *sim, const gnor_map_desc *maps);
+
+/* Map transforms: fields receives 8 * nmap * nu * nv doubles, [quantity][m]
+ * [v][u] with quantity = Re, Im of E_x, E_y, E_z (V s/m), then Re, Im of
+ * n - n0 (s/m^3); inc receives 2 * nmap doubles, [m][Re, Im] of the incident
+ * field's transform at plane norm_k (V s/m).  count = 8 * nmap * nu * nv.
+ * Synchronises the stream. */
+gnor_status gnor_get_maps(gnor_sim *sim, double *fields, double *inc, size_t count);
+
 /* Copy one field to host as nx*ny*nz doubles in SI units:
  * 0-2 E^n (V/m), 3-5 H^{n-1/2} (A/m), 6-8 J^{n-1/2} = dP_f/dt (A/m^2),
  * 9 + 3p + c (p < ncp): component c of the critical-point polarisation

@@ -52,6 +52,11 @@ class MaterialDesc(C.Structure):
                 ("cp_Gamma", C.c_double * MAX_CP), ("cp_phi", C.c_double * MAX_CP)]
 
 
+class MapDesc(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("index", C.c_int32), ("nmap", C.c_int32),
+                ("every", C.c_int32), ("omega", C.POINTER(C.c_double))]
+
+
 class SourceDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("e0", C.c_double), ("omega_c", C.c_double),
                 ("tau", C.c_double), ("t0", C.c_double), ("omega_max", C.c_double)]
@@ -90,6 +95,8 @@ def load() -> C.CDLL:
         "gnor_set_material": (i32, [vp, vp, C.POINTER(MaterialDesc)]),
         "gnor_set_source": (i32, [vp, C.POINTER(SourceDesc)]),
         "gnor_set_monitors": (i32, [vp, C.POINTER(MonitorDesc)]),
+        "gnor_set_maps": (i32, [vp, C.POINTER(MapDesc)]),
+        "gnor_get_maps": (i32, [vp, vp, vp, sz]),
         "gnor_required_bytes": (sz, [vp]),
         "gnor_bind_memory": (i32, [vp, vp, sz, vp]),
         "gnor_reset": (i32, [vp]),
@@ -204,6 +211,11 @@ class Sim:
         mon.abs_lo[:] = list(w.abs_lo); mon.abs_hi[:] = list(w.abs_hi)
         mon.sca_lo[:] = list(w.sca_lo); mon.sca_hi[:] = list(w.sca_hi)
         self._check(self.L.gnor_set_monitors(h, C.byref(mon)))
+        self._map_omega = np.ascontiguousarray(getattr(w, "map_omega", np.zeros(0)), dtype=np.float64)
+        if len(self._map_omega):
+            md = MapDesc(axis=w.map_axis, index=w.map_index, nmap=len(self._map_omega),
+                         every=w.map_every, omega=_dp(self._map_omega))
+            self._check(self.L.gnor_set_maps(h, C.byref(md)))
         nbytes = int(self.L.gnor_required_bytes(h))
         self.device = torch.device(device)
         self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -272,6 +284,20 @@ class Sim:
         a = [np.empty((self.w.nz, nf)) for _ in range(4)]
         self._check(self.L.gnor_get_dft(self.h, *[_dp(x) for x in a]))
         return a[0] + 1j * a[1], a[2] + 1j * a[3]
+
+    def maps(self) -> Dict[str, np.ndarray]:
+        """Map transforms: Ex, Ey, Ez, n -> complex (nmap, nv, nu); inc ->
+        complex (nmap,), the incident transform at norm_k."""
+        w = self.w
+        nm = len(self._map_omega)
+        n = (w.nx, w.ny, w.nz)
+        nu, nv = n[1 if w.map_axis == 0 else 0], n[1 if w.map_axis == 2 else 2]
+        f = np.empty((8, nm, nv, nu))
+        inc = np.empty((nm, 2))
+        self._check(self.L.gnor_get_maps(self.h, _dp(f), _dp(inc), f.size))
+        out = {k: f[2 * q] + 1j * f[2 * q + 1] for q, k in enumerate(("Ex", "Ey", "Ez", "n"))}
+        out["inc"] = inc[:, 0] + 1j * inc[:, 1]
+        return out
 
     def spectra(self) -> Dict[str, np.ndarray]:
         nf = len(self._omega)

@@ -197,6 +197,23 @@ struct FluxParams {
   const int64_t* step_base;
 };
 
+// Near-field and density maps on one grid plane (running transforms).
+template <class T>
+struct MapParams {
+  int axis, index, nmap, every;
+  int nu, nv, nx, ny;               // plane size; grid strides
+  const double* omega;              // [nmap]
+  double* acc;                      // [8][nmap][nv][nu]
+  double* inc;                      // [nmap][2]
+  double dt, nscale;                // nscale: Phi~_P -> n - n0 (eps0 / (dx e))
+  int mlo[3], mn[3];                // metal sub-grid
+  const T* E[3];                    // E^{n+1}
+  const T* PP;                      // Phi~_P^n on the sub-grid (this step's node scalars)
+  const double* e1;                 // auxiliary line (E_inc^{n+1})
+  int norm_k;
+  const int64_t* step_base;
+};
+
 // Adjoint state and workspace (all device pointers).
 template <class T>
 struct AdjParams {
@@ -283,6 +300,8 @@ void launch_dft_stage(const DftParams& d, const FluxParams& f, const Params<T>& 
 void launch_advance(int64_t* base, int64_t count, hipStream_t s);
 void launch_flux_accumulate(const FluxParams& f, int* lo_ptr, int sub, hipStream_t s);
 size_t flux_ptab_doubles(int nf);
+template <class T>
+void launch_maps(const MapParams<T>& m, int sub, hipStream_t s);
 void launch_flux_reduce(const double* acc_re, const double* acc_im, const double* pw, int npairs,
                         int npairs_box0, int nf, double* out, hipStream_t s);
 template <class T>

@@ -52,7 +52,7 @@ struct Planner {
 struct Layout {
   // static region
   size_t mask = 0, rho = 0, cpml[3] = {0, 0, 0}, aux_prof = 0, omega = 0, fpw = 0, tiles = 0,
-         colz = 0;
+         colz = 0, map_om = 0;
   size_t static_end = 0;
   // state region
   size_t state_begin = 0;
@@ -61,7 +61,7 @@ struct Layout {
   size_t cpP[gnor::kMaxCP][3] = {{0}}, cpQ[gnor::kMaxCP][3] = {{0}};  // critical points
   size_t psiE[3][2] = {{0}}, psiH[2][3][2] = {{{0}}};
   size_t aux = 0, phase = 0, jpart = 0, dft = 0, fstage = 0, facc = 0, ptab = 0, step = 0,
-         flux_lo = 0, flag = 0, fsum = 0;
+         flux_lo = 0, flag = 0, fsum = 0, maps = 0, map_inc = 0;
   size_t state_end = 0;
 };
 
@@ -95,6 +95,8 @@ struct gnor_sim {
   std::vector<int> tile_list;                     // the classes' tile lists (host copy)
   std::vector<int> rowx;                          // x extent of the metal points per (y, z) row
   bool fused = false;                             // one-pass step (else H and E/J sweeps)
+  gnor_map_desc maps{};                           // near-field / density maps (nmap = 0: off)
+  std::vector<double> map_omega;
   Layout L;
   char* dev = nullptr;
   size_t dev_bytes = 0;
@@ -203,6 +205,13 @@ void plan_flux(gnor_sim* s) {
   s->nsamp = 2 * first;
 }
 
+// points of the map plane
+size_t map_plane(const gnor_sim* s) {
+  const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
+  const int a = s->maps.axis;
+  return (size_t)n[a == 0 ? 1 : 0] * n[a == 2 ? 1 : 2];
+}
+
 void plan_layout(gnor_sim* s) {
   Layout& L = s->L;
   L = Layout();
@@ -219,6 +228,7 @@ void plan_layout(gnor_sim* s) {
   L.fpw = P.take((size_t)s->npairs * 8 + 8);
   // tile lists: room for the finest tiling (ty = 2, kz = 1)
   L.tiles = P.take((size_t)s->nbx * ((s->g.ny + 1) / 2) * s->g.nz * 4 + 4);
+  L.map_om = P.take((size_t)std::max(1, s->maps.nmap) * 8);
   L.static_end = P.off;
   L.state_begin = P.off;
   for (int pp = 0; pp < 2; ++pp)
@@ -253,6 +263,8 @@ void plan_layout(gnor_sim* s) {
   L.facc = P.take((size_t)2 * std::max(1, s->mon.nfreq) * s->nsamp * 8 + 8);
   L.ptab = P.take(gnor::flux_ptab_doubles(std::max(1, s->mon.nfreq)) * 8);
   L.fsum = P.take((size_t)2 * std::max(1, s->mon.nfreq) * 8);
+  L.maps = P.take((size_t)8 * s->maps.nmap * map_plane(s) * 8 + 8);
+  L.map_inc = P.take((size_t)2 * std::max(1, s->maps.nmap) * 8);
   L.step = P.take(8);
   L.flux_lo = P.take(4);
   L.flag = P.take(4);
@@ -412,6 +424,29 @@ gnor::FluxParams make_flux(gnor_sim* s) {
   return f;
 }
 
+template <class T>
+gnor::MapParams<T> make_maps(gnor_sim* s, int parity) {
+  gnor::MapParams<T> m{};
+  const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
+  m.axis = s->maps.axis; m.index = s->maps.index; m.nmap = s->maps.nmap;
+  m.every = std::max(1, s->maps.every);
+  m.nu = n[m.axis == 0 ? 1 : 0]; m.nv = n[m.axis == 2 ? 1 : 2];
+  m.nx = s->g.nx; m.ny = s->g.ny;
+  m.omega = ptr<double>(s, s->L.map_om);
+  m.acc = ptr<double>(s, s->L.maps);
+  m.inc = ptr<double>(s, s->L.map_inc);
+  m.dt = s->dt;
+  m.nscale = eps0() / (s->g.dx * 1.602176634e-19);  // Phi~_P = dx div P / eps0; n - n0 = div P / e
+  for (int d = 0; d < 3; ++d) { m.mlo[d] = s->mlo[d]; m.mn[d] = s->mn[d]; }
+  const int b = (parity & 1) ^ 1;
+  for (int c = 0; c < 3; ++c) m.E[c] = ptr<T>(s, s->L.E[b][c]);
+  m.PP = s->any_metal ? ptr<T>(s, s->L.PP[b]) : nullptr;
+  m.e1 = ptr<double>(s, s->L.aux);
+  m.norm_k = s->mon.norm_k;
+  m.step_base = ptr<int64_t>(s, s->L.step);
+  return m;
+}
+
 // Enqueue one step; `sub` is the step's offset from the device step counter.
 // The three tile-class launches of a sweep, concurrently: class 0 on st,
 // classes 1 and 2 on the side streams, joined back into st.  (Also inside a
@@ -447,6 +482,7 @@ void enqueue_step(gnor_sim* s, int parity, int sub, bool fused, hipStream_t st) 
     enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_ej_class<T>(p, a, sub, c, q); });
   }
   if (s->mon.nfreq > 0) gnor::launch_dft_stage<T>(make_dft(s), make_flux(s), p, sub, st);
+  if (s->maps.nmap > 0) gnor::launch_maps<T>(make_maps<T>(s, parity), sub, st);
 }
 
 void enqueue_flux_acc(gnor_sim* s, int sub, hipStream_t st) {
@@ -618,6 +654,9 @@ gnor_status upload_static(gnor_sim* s) {
   if (s->nsamp > 0) {
     HIPCHECK(s, hipMemcpy(s->dev + s->L.fpw, s->fpw.data(), s->fpw.size() * 8, hipMemcpyHostToDevice));
   }
+  if (s->maps.nmap > 0)
+    HIPCHECK(s, hipMemcpy(s->dev + s->L.map_om, s->map_omega.data(), s->map_omega.size() * 8,
+                          hipMemcpyHostToDevice));
   return GNOR_OK;
 }
 
@@ -822,6 +861,33 @@ gnor_status gnor_set_monitors(gnor_sim* s, const gnor_monitor_desc* m) {
   s->omega.assign(m->omega, m->omega + m->nfreq);
   s->mon.omega = nullptr;
   s->have_monitors = true;
+  return GNOR_OK;
+}
+
+gnor_status gnor_set_maps(gnor_sim* s, const gnor_map_desc* m) {
+  if (!s || !m) return GNOR_E_INVALID_ARG;
+  if (s->bound) return fail(s, GNOR_E_STATE, "maps must be set before gnor_bind_memory");
+  const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
+  if (m->nmap < 0 || m->nmap > 8 || (m->nmap > 0 && !m->omega))
+    return fail(s, GNOR_E_INVALID_ARG, "nmap must lie in [0, 8] with a frequency list");
+  if (m->axis < 0 || m->axis > 2) return fail(s, GNOR_E_INVALID_ARG, "map axis must be 0, 1 or 2");
+  if (m->index < 0 || m->index >= n[m->axis]) return fail(s, GNOR_E_INVALID_ARG, "map plane outside the grid");
+  if (m->every < 1) return fail(s, GNOR_E_INVALID_ARG, "map every must be >= 1");
+  s->maps = *m;
+  s->map_omega.assign(m->omega, m->omega + m->nmap);
+  s->maps.omega = nullptr;
+  return GNOR_OK;
+}
+
+gnor_status gnor_get_maps(gnor_sim* s, double* fields, double* inc, size_t count) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  const size_t nq = (size_t)8 * s->maps.nmap * map_plane(s);
+  if (count != nq) return fail(s, GNOR_E_BUFFER_TOO_SMALL, "count must be 8 * nmap * plane points");
+  if (nq == 0) return GNOR_OK;
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  if (fields) HIPCHECK(s, hipMemcpy(fields, s->dev + s->L.maps, nq * 8, hipMemcpyDeviceToHost));
+  if (inc) HIPCHECK(s, hipMemcpy(inc, s->dev + s->L.map_inc, (size_t)2 * s->maps.nmap * 8, hipMemcpyDeviceToHost));
   return GNOR_OK;
 }
 
@@ -1192,6 +1258,10 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       if (fp32) gnor::launch_dft_stage<float>(make_dft(s), make_flux(s), make_params<float>(s, parity), 0, str);
       else gnor::launch_dft_stage<double>(make_dft(s), make_flux(s), make_params<double>(s, parity), 0, str);
     }
+    if (s->maps.nmap > 0) {
+      if (fp32) gnor::launch_maps<float>(make_maps<float>(s, parity), 0, str);
+      else gnor::launch_maps<double>(make_maps<double>(s, parity), 0, str);
+    }
     (void)hipEventRecord(ev[1 + 2 * NC], str);
     if (s->nsamp > 0 && (n % s->slots) == s->slots - 1) enqueue_flux_acc(s, 0, str);
     (void)hipEventRecord(ev[2 + 2 * NC], str);
@@ -1498,7 +1568,7 @@ gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, gn
   b->n = n;
   for (int q = 0; q < n; ++q) {
     gnor_sim* s = sims[q];
-    if (!s || !s->bound) { delete b; return GNOR_E_STATE; }
+    if (!s || !s->bound || s->maps.nmap > 0) { delete b; return GNOR_E_STATE; }  // no maps in batches
     if (q > 0 && (s->g.precision != sims[0]->g.precision || s->step != sims[0]->step ||
                   s->tile_ty != sims[0]->tile_ty)) {
       delete b;
@@ -1770,6 +1840,7 @@ extern "C" gnor_status gnor_gradient(gnor_sim* s, int64_t nsteps, int32_t ckpt_e
   if (m_target < 0 || m_target >= s->mon.nfreq) return fail(s, GNOR_E_INVALID_ARG, "m_target outside the frequency list");
   if (s->mon.dft_every > 1) return fail(s, GNOR_E_INVALID_ARG, "gradients need dft_every = 1");
   if (s->mat.ncp > 0) return fail(s, GNOR_E_INVALID_ARG, "gradients do not cover critical points");
+  if (s->maps.nmap > 0) return fail(s, GNOR_E_STATE, "gradients replay steps: turn the maps off");
   if (s->mat.eps_inf != s->g.eps_background)
     return fail(s, GNOR_E_INVALID_ARG, "gradients need eps_inf = eps_background");
   // the backward pass needs the stored Q of each recomputed step, so the whole

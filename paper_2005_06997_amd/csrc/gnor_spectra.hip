@@ -13,6 +13,9 @@
 //                  FP64 matrix cores
 //   k_flux_reduce  sum over sample pairs of w_p Re(E conj(H)) per box and
 //                  frequency (fixed order)
+//   k_maps         near-field and density maps on one grid plane: running
+//                  transforms of E (stamped (n+1) dt) and of n - n0 from the
+//                  step's node scalars Phi~_P^n (stamped n dt)
 #include "gnor_internal.h"
 
 #include <cmath>
@@ -254,6 +257,55 @@ __global__ void __launch_bounds__(256) k_flux_acc(FluxParams f, const int* lo_pt
   }
 }
 
+// One thread per plane point; the block's phase factors of the step in LDS.
+template <class T>
+__global__ void __launch_bounds__(256) k_maps(MapParams<T> m, int sub) {
+  const int64_t n = m.step_base[0] + sub;
+  if (m.every > 1 && (n % m.every) != 0) return;  // the whole launch
+  __shared__ double ph[4][8];  // cos, sin of w t_E; cos, sin of w t_N
+  const int t = threadIdx.x;
+  if (t < m.nmap) {
+    double sn, cs;
+    sincos(m.omega[t] * ((double)(n + 1) * m.dt), &sn, &cs);
+    ph[0][t] = cs;
+    ph[1][t] = sn;
+    sincos(m.omega[t] * ((double)n * m.dt), &sn, &cs);
+    ph[2][t] = cs;
+    ph[3][t] = sn;
+  }
+  __syncthreads();
+  const double wdt = m.dt * (m.every > 1 ? m.every : 1);
+  if (blockIdx.x == 0 && t < m.nmap) {
+    const double ei = m.e1[m.norm_k + kAuxOff];
+    m.inc[2 * t] += wdt * ph[0][t] * ei;
+    m.inc[2 * t + 1] += wdt * ph[1][t] * ei;
+  }
+  const int plane = m.nu * m.nv;
+  const int q = blockIdx.x * 256 + t;
+  if (q >= plane) return;
+  const int ua = m.axis == 0 ? 1 : 0, va = m.axis == 2 ? 1 : 2;
+  int c[3];
+  c[m.axis] = m.index;
+  c[ua] = q % m.nu;
+  c[va] = q / m.nu;
+  const size_t id = ((size_t)c[2] * m.ny + c[1]) * m.nx + c[0];
+  const double e[3] = {(double)m.E[0][id], (double)m.E[1][id], (double)m.E[2][id]};
+  const int lx = c[0] - m.mlo[0], ly = c[1] - m.mlo[1], lz = c[2] - m.mlo[2];
+  double dens = 0.0;
+  if (m.PP && lx >= 0 && ly >= 0 && lz >= 0 && lx < m.mn[0] && ly < m.mn[1] && lz < m.mn[2])
+    dens = (double)m.PP[((size_t)lz * m.mn[1] + ly) * m.mn[0] + lx] * m.nscale;
+  const size_t qs = (size_t)m.nmap * plane;  // stride between quantities
+  for (int k = 0; k < m.nmap; ++k) {
+    const size_t o = (size_t)k * plane + q;
+    for (int a = 0; a < 3; ++a) {
+      m.acc[(2 * a) * qs + o] += (wdt * ph[0][k]) * e[a];
+      m.acc[(2 * a + 1) * qs + o] += (wdt * ph[1][k]) * e[a];
+    }
+    m.acc[6 * qs + o] += (wdt * ph[2][k]) * dens;
+    m.acc[7 * qs + o] += (wdt * ph[3][k]) * dens;
+  }
+}
+
 __global__ void k_flux_set(int* lo_ptr, FluxParams f, int sub) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int64_t n_last = f.step_base[0] + sub;
@@ -317,6 +369,14 @@ template void launch_advance_batch<double>(const BatchEntry<double>*, int, int64
 void launch_advance(int64_t* base, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, base, count);
 }
+template <class T>
+void launch_maps(const MapParams<T>& m, int sub, hipStream_t s) {
+  if (m.nmap <= 0) return;
+  hipLaunchKernelGGL(k_maps<T>, dim3((m.nu * m.nv + 255) / 256), dim3(256), 0, s, m, sub);
+}
+template void launch_maps<float>(const MapParams<float>&, int, hipStream_t);
+template void launch_maps<double>(const MapParams<double>&, int, hipStream_t);
+
 size_t flux_ptab_doubles(int nf) { return (size_t)2 * flux_row_tiles(nf) * kFluxKB * 64; }
 
 void launch_flux_accumulate(const FluxParams& f, int* lo_ptr, int sub, hipStream_t s) {

@@ -71,6 +71,11 @@ class Workload:
     eps_inf: float = 1.0
     # critical points (Eq. CritPoint): (A, Omega, Gamma, phi) per pole
     cp: Tuple = ()
+    # near-field / density maps on the plane map_index normal to map_axis
+    map_axis: int = 1
+    map_index: int = 0
+    map_every: int = 1
+    map_omega: np.ndarray = field(default_factory=lambda: np.zeros(0))
     # source: 1 modulated Gaussian, 2 raised cosine
     src_kind: int = 1
     e0: float = 1.0
@@ -308,6 +313,14 @@ def with_critical_points(w: Workload, poles=CP_SYNTH, eps_inf: float = EPS_INF_S
     and eps_inf > 1 in the metal (eps_b stays 1)."""
     return replace(w, name=w.name + "_cp", cp=tuple(tuple(float(x) for x in q) for q in poles),
                    eps_inf=eps_inf)
+
+
+def with_maps(w: Workload, omegas, every: int = 1, axis: int = 1) -> Workload:
+    """Maps on the plane through the first particle's centre, normal to
+    `axis` (the xz plane for axis 1: polarisation and propagation)."""
+    c = w.spheres[0, :3] if w.geometry == "spheres" else w.star[:3]
+    return replace(w, map_axis=axis, map_index=int(round(c[axis] / w.dx)), map_every=every,
+                   map_omega=np.asarray(omegas, dtype=np.float64))
 
 
 def early_pulse(w: Workload) -> Workload:

@@ -115,7 +115,8 @@ def test_binding_structs_match_the_header(tmp_path):
     import subprocess
 
     structs = {"gnor_grid_desc": B.GridDesc, "gnor_material_desc": B.MaterialDesc,
-               "gnor_source_desc": B.SourceDesc, "gnor_monitor_desc": B.MonitorDesc}
+               "gnor_source_desc": B.SourceDesc, "gnor_monitor_desc": B.MonitorDesc,
+               "gnor_map_desc": B.MapDesc}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gnor_fdtd.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
