@@ -103,6 +103,22 @@ def test_fp64_ragged_grid_and_general_cpml(B):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dielectric_background_n13(B, prec):
+    """A sphere in a background of index 1.3 (eps_b = 1.69, the setting of the
+    paper's Sec. V comparison with experiment): CPML, TF/SF line and the
+    vacuum update all take eps_b; the metal keeps eps_inf = 1."""
+    w = W.early_pulse(W.config1(4))
+    w.eps_b = 1.69
+    w.omega = W.spectrum_omegas(24)
+    say(f"case background n = 1.3, {prec}")
+    g = B.Sim(w, precision=prec)
+    g.run(w.steps)
+    o = oracle_run(w, w.steps)
+    tol = (1e-10, 1e-10) if prec == "fp64" else (1e-3, 1e-4)
+    compare(g, o, *tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_fused_and_two_sweep_forms_agree(B, prec):
     """The one-pass fused step and the two-sweep form (H sweep, then E/J
     sweep) compute the same update; both match the oracle."""

@@ -56,11 +56,15 @@ def yee_positions(shape, comp, kind="E"):
 
 
 # ---------------------------------------------------------------- P1 dispersion
-@pytest.mark.parametrize("kvec", [(1, 0, 0), (1, 2, 0), (1, 2, 3)])
-def test_vacuum_dispersion_closed_form(kvec):
+@pytest.mark.parametrize("kvec,eps_b", [((1, 0, 0), 1.0), ((1, 2, 0), 1.0), ((1, 2, 3), 1.0),
+                                         ((1, 2, 3), 1.69)])
+def test_vacuum_dispersion_closed_form(kvec, eps_b):
+    """Yee dispersion sin(w dt / 2) = (c dt / n) |sin(k dx / 2)| / dx in a
+    uniform background of index n = sqrt(eps_b) (n = 1.3: the background of
+    the paper's Sec. V comparison with experiment)."""
     n = (10, 10, 10)
     dx = 0.25e-9
-    p = periodic_problem(n, dx)
+    p = periodic_problem(n, dx, eps_b=eps_b)
     s = orc.OracleSim(p, np.zeros((n[2], n[1], n[0]), np.uint8))
     k = 2 * np.pi * np.array(kvec, float) / (np.array(n) * dx)
     K = 2 * np.sin(k * dx / 2) / dx
@@ -71,7 +75,7 @@ def test_vacuum_dispersion_closed_form(kvec):
         s.set(name, u[comp] * np.cos(k[0] * x * dx + k[1] * y * dx + k[2] * z * dx))
     dt = s.dt
     c0 = consts()["c0"]
-    sin_half = c0 * dt * math.sqrt(float(np.sum((np.sin(k * dx / 2) / dx) ** 2)))
+    sin_half = c0 * dt / math.sqrt(eps_b) * math.sqrt(float(np.sum((np.sin(k * dx / 2) / dx) ** 2)))
     w = 2 * math.asin(sin_half) / dt
     series = {nm: [] for nm in ("Ex", "Ey", "Ez")}
     for _ in range(400):
@@ -177,11 +181,13 @@ def test_divergence_invariants_with_metal_cpml_tfsf():
 
 
 # ------------------------------------------------------------ P4 TF/SF leakage
-def test_tfsf_no_leakage_and_tf_equals_incident():
+@pytest.mark.parametrize("eps_b", [1.0, 1.69])
+def test_tfsf_no_leakage_and_tf_equals_incident(eps_b):
     n = 30
     dx = 5e-9  # coarse cells so the pulse crosses the grid in a few hundred steps
     w = W.sphere_problem("vacuum_tfsf", n, dx, 4, [(n - 1) / 2.0] * 3, 3 * dx)
     w = W.early_pulse(w)
+    w.eps_b = eps_b
     p = oracle_problem(w, flux=False, omega=np.zeros(0))
     s = orc.OracleSim(p, np.zeros((n, n, n), np.uint8))
     lo, hi = w.tf_lo, w.tf_hi
