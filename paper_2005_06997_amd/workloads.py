@@ -44,7 +44,7 @@ def ev_to_rad(e: float) -> float:
 def spectrum_omegas(n: int = 100, e_lo: float = 1.0, e_hi: float = 6.0) -> np.ndarray:
     """omega_m = (e_lo + (e_hi - e_lo) m / (n - 1)) eV / hbar, m = 0 .. n-1."""
     m = np.arange(n, dtype=np.float64)
-    return (e_lo + (e_hi - e_lo) * m / (n - 1)) / HBAR_EV_S
+    return (e_lo + (e_hi - e_lo) * m / max(n - 1, 1)) / HBAR_EV_S
 
 
 @dataclass
