@@ -224,18 +224,24 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * meets a slab with a one-cell margin).  By default a step is the two-sweep form (H sweep, then E/J
  * sweep); gnor_set_fused(sim, 1) selects one fused pass (H and E/J together,
  * 12 instead of 18 field words moved per cell) plus a one-block launch that
- * advances the auxiliary line.  Both give the same fields up to rounding;
- * batches and gnor_gradient always use the two-sweep form.
+ * advances the auxiliary line; gnor_set_fused(sim, 2) the hybrid form: the
+ * fused pass for the tiles that meet no CPML slab (classes 0 and 2; class 2
+ * stays two-sweep with critical points), then the auxiliary line, then the
+ * E/J sweep of the CPML classes, whose H sweep ran alongside the fused
+ * tiles.  All forms give the same fields up to rounding; batches and
+ * gnor_gradient always use the two-sweep form.
  * gnor_profile_kernels times each sweep as it runs: with concurrent class
  * launches (the default, see gnor_set_class_streams) a sweep is timed from its
  * fork to its join; with serial class launches, count >= 14 also returns
  * ms[5 + c] the H sweep's (or the fused step's) class c and ms[9 + c] the E/J
  * sweep's class c (0 otherwise); ms[13] is the auxiliary-line launch of the
  * fused form.  In fused form ms[0] = ms[1] = 0 and ms[3] holds the fused step
- * (classes + auxiliary line).
+ * (classes + auxiliary line); in hybrid form ms[0] is the first phase (fused
+ * tiles and H sweeps) and ms[1] the second (auxiliary line and E/J sweeps).
  * gnor_tile_classes writes the number of tiles of each class of the current
  * tiling to counts[0..3] (valid once the memory is bound).
- * gnor_set_fused: on must be 0 or 1 (INVALID_ARG otherwise). */
+ * gnor_set_fused: on must be 0, 1 or 2 (INVALID_ARG otherwise; 1 also with
+ * critical points). */
 gnor_status gnor_set_fused(gnor_sim *sim, int32_t on);
 
 /* The three tile-class launches of a sweep run concurrently (on = 1, the

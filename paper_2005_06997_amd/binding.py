@@ -329,8 +329,13 @@ class Sim:
         self._check(self.L.gnor_set_class_streams(self.h, 1 if on else 0))
 
     def set_fused(self, on: bool):
-        """One-pass fused step, or the two-sweep form (the default)."""
+        """One-pass fused step, or the two-sweep form."""
         self._check(self.L.gnor_set_fused(self.h, 1 if on else 0))
+
+    def set_mode(self, mode: int):
+        """Step form: 0 two sweeps, 1 fused one-pass step, 2 hybrid (fused
+        where no CPML slab is met, two sweeps elsewhere)."""
+        self._check(self.L.gnor_set_fused(self.h, int(mode)))
 
     def tile_classes(self):
         """Tiles per class (plain Yee, CPML, metal, metal + CPML) of the current tiling."""

@@ -273,6 +273,7 @@ __device__ __forceinline__ void step_tile(const Params<T>& p, const AuxParams& a
           const size_t ll = (size_t)(k0 - p.mlo[2]) * m2 + lcol;
           p.PPo[ll] = pP;
           p.PJo[ll] = dv;
+          p.Q[ll] = qc;  // for two-sweep neighbours (hybrid form)
         }
         jcx = qv.act ? qv.jx : T(0);
         jcy = qv.act ? qv.jy : T(0);
@@ -445,6 +446,7 @@ __device__ __forceinline__ void step_tile(const Params<T>& p, const AuxParams& a
           const size_t ll = (size_t)(k + 1 - p.mlo[2]) * m2 + lcol;
           p.PPo[ll] = pP;
           p.PJo[ll] = dv;
+          p.Q[ll] = qn;
         }
         jnx = qv.act ? qv.jx : T(0);
         jny = qv.act ? qv.jy : T(0);

@@ -94,7 +94,7 @@ struct gnor_sim {
   gnor::Tiling tl{};                              // that tiling with its tile classes
   std::vector<int> tile_list;                     // the classes' tile lists (host copy)
   std::vector<int> rowx;                          // x extent of the metal points per (y, z) row
-  bool fused = false;                             // one-pass step (else H and E/J sweeps)
+  int mode = 0;  // step form: 0 H and E/J sweeps, 1 one-pass fused step, 2 hybrid (see hybrid_fused)
   gnor_map_desc maps{};                           // near-field / density maps (nmap = 0: off)
   std::vector<double> map_omega;
   Layout L;
@@ -470,17 +470,57 @@ void enqueue_classes(gnor_sim* s, hipStream_t st, F launch) {
   }
 }
 
+// Hybrid step form: the tile classes without CPML (plain, and metal unless
+// the material has critical points, which the fused kernel lacks) run the
+// one-pass fused step; the CPML classes run the two sweeps.  Order:
+//   1. fused classes and H sweeps of the others, concurrently (inputs E^n,
+//      H^{n-1/2} are never written in a step; the fused kernels evaluate
+//      H_inc^{n+1/2} from the line and store the node scalars Q their
+//      two-sweep neighbours read);
+//   2. the auxiliary line (after every reader of E_inc^n);
+//   3. E/J sweeps of the two-sweep classes (they read H^{n+1/2} of fused
+//      neighbours and H_inc^{n+1/2}).
+bool hybrid_fused(const gnor_sim* s, int c) { return c == 0 || (c == 2 && s->mat.ncp == 0); }
+
+// First half of a step: the H sweep (mode 0), the fused step (mode 1), or
+// phase 1 of the hybrid form.
 template <class T>
-void enqueue_step(gnor_sim* s, int parity, int sub, bool fused, hipStream_t st) {
-  const gnor::Params<T> p = make_params<T>(s, parity);
-  const gnor::AuxParams a = make_aux(s);
-  if (fused) {
+void enqueue_first(gnor_sim* s, const gnor::Params<T>& p, const gnor::AuxParams& a, int mode,
+                   hipStream_t st) {
+  if (mode == 1) {
     enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_step_class<T>(p, a, c, q); });
-    gnor::launch_aux(a, sub, st);
+  } else if (mode == 2) {
+    enqueue_classes(s, st, [&](int c, hipStream_t q) {
+      if (hybrid_fused(s, c)) gnor::launch_step_class<T>(p, a, c, q);
+      else gnor::launch_h_class<T>(p, a, c, q);
+    });
   } else {
     enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_h_class<T>(p, a, c, q); });
+  }
+}
+// Second half: the E/J sweep (mode 0), the auxiliary line (mode 1), or the
+// line and then the E/J sweeps of the two-sweep classes (mode 2).
+template <class T>
+void enqueue_second(gnor_sim* s, const gnor::Params<T>& p, const gnor::AuxParams& a, int sub, int mode,
+                    hipStream_t st) {
+  if (mode == 1) {
+    gnor::launch_aux(a, sub, st);
+  } else if (mode == 2) {
+    gnor::launch_aux(a, sub, st);
+    enqueue_classes(s, st, [&](int c, hipStream_t q) {
+      if (!hybrid_fused(s, c)) gnor::launch_ej_class<T>(p, a, sub, c, q);
+    });
+  } else {
     enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_ej_class<T>(p, a, sub, c, q); });
   }
+}
+
+template <class T>
+void enqueue_step(gnor_sim* s, int parity, int sub, int mode, hipStream_t st) {
+  const gnor::Params<T> p = make_params<T>(s, parity);
+  const gnor::AuxParams a = make_aux(s);
+  enqueue_first<T>(s, p, a, mode, st);
+  enqueue_second<T>(s, p, a, sub, mode, st);
   if (s->mon.nfreq > 0) gnor::launch_dft_stage<T>(make_dft(s), make_flux(s), p, sub, st);
   if (s->maps.nmap > 0) gnor::launch_maps<T>(make_maps<T>(s, parity), sub, st);
 }
@@ -489,15 +529,15 @@ void enqueue_flux_acc(gnor_sim* s, int sub, hipStream_t st) {
   gnor::launch_flux_accumulate(make_flux(s), ptr<int>(s, s->L.flux_lo), sub, st);
 }
 
-// fused: one-pass step kernels (the sim's setting), else the two sweeps (the
-// adjoint's forward recompute, which needs the stored Q)
-void enqueue_steps_eager(gnor_sim* s, int64_t n0, int64_t count, hipStream_t st, bool fused) {
+// mode: the step form (the sim's setting; the adjoint's forward recompute
+// uses the two sweeps, whose stored Q it needs everywhere)
+void enqueue_steps_eager(gnor_sim* s, int64_t n0, int64_t count, hipStream_t st, int mode) {
   // steps n0 .. n0+count-1; the device counter holds n0 on entry
   for (int64_t q = 0; q < count; ++q) {
     const int64_t n = n0 + q;
     const int sub = (int)q;
-    if (s->g.precision == GNOR_FP32) enqueue_step<float>(s, (int)(n & 1), sub, fused, st);
-    else enqueue_step<double>(s, (int)(n & 1), sub, fused, st);
+    if (s->g.precision == GNOR_FP32) enqueue_step<float>(s, (int)(n & 1), sub, mode, st);
+    else enqueue_step<double>(s, (int)(n & 1), sub, mode, st);
     if (s->nsamp > 0 && (n % s->slots) == s->slots - 1) enqueue_flux_acc(s, sub, st);
   }
   gnor::launch_advance(ptr<int64_t>(s, s->L.step), count, st);
@@ -514,7 +554,7 @@ gnor_status build_graph(gnor_sim* s, int steps) {
   hipGraph_t gr = nullptr;
   HIPCHECK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
   // the chunk always starts at an even step aligned to the flux staging depth
-  enqueue_steps_eager(s, 0, steps, s->stream, s->fused);
+  enqueue_steps_eager(s, 0, steps, s->stream, s->mode);
   HIPCHECK(s, hipStreamEndCapture(s->stream, &gr));
   hipError_t e = hipGraphInstantiate(&s->graph, gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
@@ -740,7 +780,7 @@ gnor_status gnor_set_material(gnor_sim* s, const uint8_t* mask, const gnor_mater
     if (!std::isfinite(m->cp_A[u]) || !(m->cp_Omega[u] >= 0) || !(m->cp_Gamma[u] >= 0) ||
         !std::isfinite(m->cp_phi[u]))
       return fail(s, GNOR_E_INVALID_ARG, "critical points need finite A, phi and Omega, Gamma >= 0");
-  if (m->ncp > 0 && s->fused)
+  if (m->ncp > 0 && s->mode == 1)
     return fail(s, GNOR_E_INVALID_ARG, "the fused step has no critical-point terms (gnor_set_fused 0 first)");
   const gnor_grid_desc& g = s->g;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
@@ -953,11 +993,11 @@ gnor_status gnor_set_class_streams(gnor_sim* s, int32_t on) {
 }
 
 gnor_status gnor_set_fused(gnor_sim* s, int32_t on) {
-  if (!s || (on != 0 && on != 1)) return GNOR_E_INVALID_ARG;
-  if (on && s->have_material && s->mat.ncp > 0)
+  if (!s || on < 0 || on > 2) return GNOR_E_INVALID_ARG;
+  if (on == 1 && s->have_material && s->mat.ncp > 0)
     return fail(s, GNOR_E_INVALID_ARG, "the fused step has no critical-point terms");
-  if ((on != 0) != s->fused) {
-    s->fused = on != 0;
+  if (on != s->mode) {
+    s->mode = on;
     drop_graph(s);
   }
   return GNOR_OK;
@@ -997,7 +1037,7 @@ gnor_status gnor_run(gnor_sim* s, int64_t nsteps) {
       n = to_align > 0 ? std::min(left, to_align) : std::min(left, (int64_t)chunk);
       if (to_align == 0 && left < chunk) n = left;
     }
-    enqueue_steps_eager(s, s->step, n, s->stream, s->fused);
+    enqueue_steps_eager(s, s->step, n, s->stream, s->mode);
     HIPCHECK(s, hipGetLastError());
     s->step += n;
     left -= n;
@@ -1203,39 +1243,26 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   for (auto& e : ev) HIPCHECK(s, hipEventCreate(&e));
   double acc[NE - 1] = {};
   const bool fp32 = s->g.precision == GNOR_FP32;
-  const bool fused = s->fused;
+  const int mode = s->mode;
+  const bool fused = mode == 1;
+  const bool whole = s->concurrent || mode == 2;  // each half timed as a whole
   for (int64_t q = 0; q < nsteps; ++q) {
     const int64_t n = s->step;
     const int parity = (int)(n & 1);
     const hipStream_t str = s->stream;
     const gnor::AuxParams a = make_aux(s);
     (void)hipEventRecord(ev[0], str);
-    if (s->concurrent) {
-      // each sweep timed as a whole, its classes running concurrently as in
-      // a normal run (per-class entries stay 0)
-      if (fused) {
-        enqueue_classes(s, str, [&](int c, hipStream_t q2) {
-          if (fp32) gnor::launch_step_class<float>(make_params<float>(s, parity), a, c, q2);
-          else gnor::launch_step_class<double>(make_params<double>(s, parity), a, c, q2);
-        });
-      } else {
-        enqueue_classes(s, str, [&](int c, hipStream_t q2) {
-          if (fp32) gnor::launch_h_class<float>(make_params<float>(s, parity), a, c, q2);
-          else gnor::launch_h_class<double>(make_params<double>(s, parity), a, c, q2);
-        });
-      }
+    if (whole) {
+      // each half of the step timed as a whole, its classes running
+      // concurrently as in a normal run (per-class entries stay 0)
+      if (fp32) enqueue_first<float>(s, make_params<float>(s, parity), a, mode, str);
+      else enqueue_first<double>(s, make_params<double>(s, parity), a, mode, str);
       for (int c = 0; c < NC; ++c) (void)hipEventRecord(ev[1 + c], str);
-      if (fused) {
-        gnor::launch_aux(a, 0, str);
-      } else {
-        enqueue_classes(s, str, [&](int c, hipStream_t q2) {
-          if (fp32) gnor::launch_ej_class<float>(make_params<float>(s, parity), a, 0, c, q2);
-          else gnor::launch_ej_class<double>(make_params<double>(s, parity), a, 0, c, q2);
-        });
-      }
+      if (fp32) enqueue_second<float>(s, make_params<float>(s, parity), a, 0, mode, str);
+      else enqueue_second<double>(s, make_params<double>(s, parity), a, 0, mode, str);
       for (int c = 0; c < NC; ++c) (void)hipEventRecord(ev[1 + NC + c], str);
     }
-    for (int c = 0; c < NC && !s->concurrent; ++c) {
+    for (int c = 0; c < NC && !whole; ++c) {
       if (fused) {
         if (fp32) gnor::launch_step_class<float>(make_params<float>(s, parity), a, c, str);
         else gnor::launch_step_class<double>(make_params<double>(s, parity), a, c, str);
@@ -1245,7 +1272,7 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       }
       (void)hipEventRecord(ev[1 + c], str);
     }
-    for (int c = 0; c < NC && !s->concurrent; ++c) {
+    for (int c = 0; c < NC && !whole; ++c) {
       if (fused) {
         if (c == 0) gnor::launch_aux(a, 0, str);
       } else {
@@ -1290,8 +1317,8 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   out[3] = fused ? first + second : 0.0;
   out[4] = acc[2 * NC + 1] * inv;
   for (int c = 0; c < NC; ++c) {
-    out[5 + c] = s->concurrent ? 0.0 : acc[c] * inv;
-    out[5 + NC + c] = (fused || s->concurrent) ? 0.0 : acc[NC + c] * inv;
+    out[5 + c] = whole ? 0.0 : acc[c] * inv;
+    out[5 + NC + c] = (fused || whole) ? 0.0 : acc[NC + c] * inv;
   }
   out[5 + 2 * NC] = fused ? second : 0.0;
   for (int i = 0; i < count && i < 6 + 2 * NC; ++i) ms[i] = out[i];
@@ -1845,10 +1872,10 @@ extern "C" gnor_status gnor_gradient(gnor_sim* s, int64_t nsteps, int32_t ckpt_e
     return fail(s, GNOR_E_INVALID_ARG, "gradients need eps_inf = eps_background");
   // the backward pass needs the stored Q of each recomputed step, so the whole
   // gradient (forward pass included) runs on the two-sweep kernels
-  const bool fused = s->fused;
-  if (fused) { s->fused = false; drop_graph(s); }
+  const int mode = s->mode;
+  if (mode != 0) { s->mode = 0; drop_graph(s); }
   st = s->g.precision == GNOR_FP32 ? gradient_impl<float>(s, nsteps, ckpt_every, m_target, objective, grad)
                                    : gradient_impl<double>(s, nsteps, ckpt_every, m_target, objective, grad);
-  if (fused) { s->fused = true; drop_graph(s); }
+  if (mode != 0) { s->mode = mode; drop_graph(s); }
   return st;
 }

@@ -84,7 +84,8 @@ def test_fp32_critical_points_vs_oracle(B):
     compare(g, o, w, 1e-3, 1e-4)
 
 
-def test_critical_points_in_metal_cpml_class(B):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_critical_points_in_metal_cpml_class(B, mode):
     """A sphere across x tiles 0 and 1 of a 160-wide grid: tile 0 holds the
     low x slab (metal + CPML class), tile 1 no slab (metal class), so both
     critical-point variants run; a ragged tiling; one pole with a positive
@@ -96,8 +97,9 @@ def test_critical_points_in_metal_cpml_class(B):
     w = W._boxes(w, c * dx - r, c * dx + r)
     w = W.with_critical_points(W.early_pulse(w), poles=((0.9, 4.5e15, 8.0e14, 0.7),), eps_inf=1.3)
     w.omega = W.spectrum_omegas(20)
-    say("case critical points across x tiles 160x48x48, tiling (4, 13, 2)")
+    say(f"case critical points across x tiles 160x48x48, tiling (4, 13, 2), step form {mode}")
     g = B.Sim(w, precision="fp64")
+    g.set_mode(mode)  # hybrid: the metal class stays two-sweep (no f3 in the fused kernel)
     g.set_tiling(4, 13, 2)
     assert g.tile_classes()[2] > 0 and g.tile_classes()[3] > 0
     g.run(w.steps)

@@ -149,11 +149,13 @@ def test_fused_and_two_sweep_forms_agree(B, prec):
     assert runs[0].profile(2)["fused"] and not runs[1].profile(2)["fused"]
 
 
-@pytest.mark.parametrize("fused", [False, True])
-def test_metal_across_x_tiles_vs_oracle(B, fused):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_metal_across_x_tiles_vs_oracle(B, mode):
     """A sphere straddling the boundary between x tiles 0 and 1 of a 160-wide
     grid: tile 0 holds the low x slab (class metal + CPML), tile 1 no slab
-    (class metal)."""
+    (class metal).  Step forms: two sweeps, fused, hybrid (the metal tile
+    fused, its metal + CPML neighbour two-sweep: each reads the other's H and
+    node scalars)."""
     n, dx, r = 160, 0.25e-9, 2.0e-9
     c = np.array([62.3, 23.5, 23.2])
     w = W.sphere_problem("wrap", n, dx, 8, c, r, steps=300)
@@ -161,14 +163,48 @@ def test_metal_across_x_tiles_vs_oracle(B, fused):
     w = W._boxes(w, c * dx - r, c * dx + r)
     w = W.early_pulse(w)
     w.omega = W.spectrum_omegas(20)
-    say(f"case metal across x tiles 160x48x48, fused={fused}")
+    say(f"case metal across x tiles 160x48x48, step form {mode}")
     g = B.Sim(w, precision="fp64")
-    g.set_fused(fused)
+    g.set_mode(mode)
     g.set_tiling(4, 16, 2)
     assert g.tile_classes()[2] > 0 and g.tile_classes()[3] > 0
     g.run(w.steps)
     o = oracle_run(w, w.steps)
     compare(g, o, 1e-10, 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_hybrid_and_two_sweep_forms_agree(B, prec):
+    """A 192 x 96 x 80 grid with a sphere across x tiles 0 and 1: every tile
+    class occurs; the hybrid form (fused where no CPML slab is met) and the
+    two-sweep form give the same fields and spectra up to rounding, through
+    graph chunks and eager steps."""
+    n, dx, r = 192, 0.25e-9, 3.0e-9
+    c = np.array([66.3, 47.6, 39.2])
+    w = W.sphere_problem("hybrid", n, dx, 8, c, r, steps=260)
+    w.ny, w.nz = 96, 80
+    w = W._boxes(w, c * dx - r, c * dx + r)
+    w = W.early_pulse(w)
+    w.omega = W.spectrum_omegas(16)
+    say(f"case hybrid vs two-sweep 192x96x80, {prec}")
+    runs = []
+    for mode in (0, 2):
+        g = B.Sim(w, precision=prec)
+        g.set_mode(mode)
+        g.run(w.steps)
+        runs.append(g)
+    assert min(runs[1].tile_classes()) > 0
+    agree = 1e-12 if prec == "fp64" else 1e-5
+    fa = {f: runs[0].field(f) for f in FIELDS}
+    fb = {f: runs[1].field(f) for f in FIELDS}
+    for f in FIELDS:
+        scale = max(np.linalg.norm(fa[g]) for g in FIELDS if g[0] == f[0])
+        d = np.linalg.norm(fa[f] - fb[f]) / scale
+        say(f"  {f}: hybrid vs two-sweep {d:.2e}")
+        assert d <= agree, f
+    sa, sb = runs[0].spectra(), runs[1].spectra()
+    for k in ("inc", "ext", "abs", "sca"):
+        assert rel_l2(sb[k], sa[k]) <= agree, k
 
 
 def test_fp64_vacuum_no_metal(B):
