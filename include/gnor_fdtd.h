@@ -211,7 +211,9 @@ gnor_status gnor_load_state(gnor_sim *sim, const void *host_src, size_t bytes);
 gnor_status gnor_check_finite(gnor_sim *sim);
 
 /* Average device time per launch (ms) of each kernel over nsteps steps run
- * with events around every launch on the bound stream (no graphs):
+ * with events around every launch on the bound stream (no graphs; the host
+ * waits once, after the last step, so the queue never drains; 1 <= nsteps
+ * <= 4096, INVALID_ARG otherwise):
  * ms[0] H sweep (with the auxiliary line's H half), ms[1] E/J sweep (with the
  * auxiliary line's E half), ms[2] spectra and flux staging, ms[3] fused step
  * (when fused; see below), ms[4] flux accumulation (per step, amortised).
@@ -244,8 +246,8 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * critical points). */
 gnor_status gnor_set_fused(gnor_sim *sim, int32_t on);
 
-/* The three tile-class launches of a sweep run concurrently (on = 1, the
- * default: class 0 on the bound stream, classes 1 and 2 on two side streams
+/* The four tile-class launches of a sweep run concurrently (on = 1, the
+ * default: classes 0 and 3 on the bound stream, classes 1 and 2 on two side streams
  * of the library, joined back by events, also inside graphs) or one after
  * another on the bound stream (on = 0; for profilers that time each
  * launch).  INVALID_ARG unless on is 0 or 1. */

@@ -448,10 +448,15 @@ gnor::MapParams<T> make_maps(gnor_sim* s, int parity) {
 }
 
 // Enqueue one step; `sub` is the step's offset from the device step counter.
-// The three tile-class launches of a sweep, concurrently: class 0 on st,
-// classes 1 and 2 on the side streams, joined back into st.  (Also inside a
+// The four tile-class launches of a sweep, concurrently: classes 0 and 3 on
+// st, classes 1 and 2 on the side streams, joined back into st.  (Also inside a
 // graph capture of st: the side streams join the capture through the fork
 // event.)  launch(c, stream) enqueues class c.
+// Fork/join events order the class streams of one device: no timing and no
+// system-scope fence (the kernels' own completion makes their writes visible
+// on the device; only the host reads results, after a stream synchronize).
+constexpr unsigned kJoinEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
+
 template <class F>
 void enqueue_classes(gnor_sim* s, hipStream_t st, F launch) {
   if (!s->concurrent) {
@@ -969,9 +974,9 @@ gnor_status gnor_bind_memory(gnor_sim* s, void* dptr, size_t bytes, void* stream
   if (!s->side[0]) {
     for (int q = 0; q < 2; ++q) {
       HIPCHECK(s, hipStreamCreateWithFlags(&s->side[q], hipStreamNonBlocking));
-      HIPCHECK(s, hipEventCreateWithFlags(&s->ev_join[q], hipEventDisableTiming));
+      HIPCHECK(s, hipEventCreateWithFlags(&s->ev_join[q], kJoinEventFlags));
     }
-    HIPCHECK(s, hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    HIPCHECK(s, hipEventCreateWithFlags(&s->ev_fork, kJoinEventFlags));
   }
   s->dev = reinterpret_cast<char*>(dptr);
   s->dev_bytes = bytes;
@@ -1238,9 +1243,13 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   // step), the class launches of the E/J sweep (two-sweep form) or the
   // auxiliary line (fused form), the spectra, the flux accumulation, the
   // step counter
+  // Every step gets its own events and the host synchronizes once at the end,
+  // so the queue never drains and no interval holds host launch latency.
   constexpr int NE = 2 * NC + 4;
-  hipEvent_t ev[NE];
-  for (auto& e : ev) HIPCHECK(s, hipEventCreate(&e));
+  if (nsteps > 4096) return fail(s, GNOR_E_INVALID_ARG, "profile: at most 4096 steps");
+  std::vector<hipEvent_t> evs((size_t)nsteps * NE);
+  // timing only: no system-scope fence (no L2 write-back inside the intervals)
+  for (auto& e : evs) HIPCHECK(s, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   double acc[NE - 1] = {};
   const bool fp32 = s->g.precision == GNOR_FP32;
   const int mode = s->mode;
@@ -1251,16 +1260,17 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
     const int parity = (int)(n & 1);
     const hipStream_t str = s->stream;
     const gnor::AuxParams a = make_aux(s);
+    hipEvent_t* ev = evs.data() + (size_t)q * NE;
     (void)hipEventRecord(ev[0], str);
     if (whole) {
       // each half of the step timed as a whole, its classes running
       // concurrently as in a normal run (per-class entries stay 0)
       if (fp32) enqueue_first<float>(s, make_params<float>(s, parity), a, mode, str);
       else enqueue_first<double>(s, make_params<double>(s, parity), a, mode, str);
-      for (int c = 0; c < NC; ++c) (void)hipEventRecord(ev[1 + c], str);
+      (void)hipEventRecord(ev[NC], str);
       if (fp32) enqueue_second<float>(s, make_params<float>(s, parity), a, 0, mode, str);
       else enqueue_second<double>(s, make_params<double>(s, parity), a, 0, mode, str);
-      for (int c = 0; c < NC; ++c) (void)hipEventRecord(ev[1 + NC + c], str);
+      (void)hipEventRecord(ev[2 * NC], str);
     }
     for (int c = 0; c < NC && !whole; ++c) {
       if (fused) {
@@ -1295,15 +1305,25 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
     gnor::launch_advance(ptr<int64_t>(s, s->L.step), 1, str);
     (void)hipEventRecord(ev[3 + 2 * NC], str);
     HIPCHECK(s, hipGetLastError());
-    HIPCHECK(s, hipEventSynchronize(ev[3 + 2 * NC]));
-    for (int e = 0; e < NE - 1; ++e) {
-      float t = 0.f;
-      (void)hipEventElapsedTime(&t, ev[e], ev[e + 1]);
-      acc[e] += t;
-    }
     s->step += 1;
   }
-  for (auto& e : ev) (void)hipEventDestroy(e);
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  for (int64_t q = 0; q < nsteps; ++q) {
+    const hipEvent_t* ev = evs.data() + (size_t)q * NE;
+    auto elapsed = [&](int from, int to) {
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, ev[from], ev[to]);
+      return (double)t;
+    };
+    if (whole) {  // ev[0], ev[NC] and ev[2 NC] bound the halves
+      acc[NC - 1] += elapsed(0, NC);
+      acc[2 * NC - 1] += elapsed(NC, 2 * NC);
+    } else {
+      for (int e = 0; e < 2 * NC; ++e) acc[e] += elapsed(e, e + 1);
+    }
+    for (int e = 2 * NC; e < NE - 1; ++e) acc[e] += elapsed(e, e + 1);
+  }
+  for (auto& e : evs) (void)hipEventDestroy(e);
   const double inv = 1.0 / (double)nsteps;
   double first = 0.0, second = 0.0;
   for (int c = 0; c < NC; ++c) {
@@ -1619,12 +1639,12 @@ gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, gn
   }
   for (int q = 0; q < 2; ++q) {
     if (hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_join[q], hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->ev_join[q], kJoinEventFlags) != hipSuccess) {
       gnor_batch_destroy(b);
       return GNOR_E_DEVICE;
     }
   }
-  if (hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&b->ev_fork, kJoinEventFlags) != hipSuccess) {
     gnor_batch_destroy(b);
     return GNOR_E_DEVICE;
   }
