@@ -17,6 +17,7 @@ term, a wrong sign or index, a transposed operand) would break:
 * linearity in the source amplitude.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -43,16 +44,27 @@ def periodic_problem(n, dx=0.25e-9, **kw):
     return p
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def yee_table():
+    """{(field, component): (x, y, z) offset in cells}, from the paper's
+    table of Yee cell positions (Sec. 3, Table 1), stored as a fixture."""
+    out = {}
+    for line in open(os.path.join(GOLDEN, "yee_cell_positions.txt")):
+        line = line.split("#")[0].split()
+        if line:
+            out[(line[0], "xyz".index(line[1]))] = tuple(float(v) for v in line[2:5])
+    return out
+
+
 def yee_positions(shape, comp, kind="E"):
-    """Index-space Yee coordinates (x, y, z) of a component, arrays (nz, ny, nx)."""
+    """Index-space Yee coordinates (x, y, z) of a component of field `kind`
+    (E, H or P), arrays (nz, ny, nx)."""
     nz, ny, nx = shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    x = x.astype(float); y = y.astype(float); z = z.astype(float)
-    if kind == "E":
-        if comp == 0: x = x + 0.5
-        if comp == 1: y = y + 0.5
-        if comp == 2: z = z + 0.5
-    return x, y, z
+    ox, oy, oz = yee_table()[(kind, comp)]
+    return x + ox, y + oy, z + oz
 
 
 # ---------------------------------------------------------------- P1 dispersion
@@ -88,6 +100,32 @@ def test_vacuum_dispersion_closed_form(kvec, eps_b):
         sr = np.array(sr)
         res = sr[2:] + sr[:-2] - 2 * cw * sr[1:-1]
         assert np.abs(res).max() <= 1e-12 * scale, (nm, np.abs(res).max() / scale)
+
+
+def test_first_half_step_puts_h_at_the_table_positions():
+    """From E = u cos(k.r) (r at the table's E positions) and H = 0, the first
+    H half step gives H = (dt / mu0) (K x u) sin(k.r_H) with r_H the table's
+    H positions and K = 2 sin(k dx / 2) / dx: the centred differences of the
+    curl land exactly on those points.  A wrong staggering, sign or curl
+    term leaves a cosine part or a wrong amplitude."""
+    n = (10, 12, 14)
+    dx = 0.25e-9
+    p = periodic_problem(n, dx)
+    s = orc.OracleSim(p, np.zeros((n[2], n[1], n[0]), np.uint8))
+    k = 2 * np.pi * np.array((1, 2, 3), float) / (np.array(n) * dx)
+    K = 2 * np.sin(k * dx / 2) / dx
+    u = np.cross(K, [1.0, 0.0, 0.0])  # transverse: div E = 0
+    shape = (n[2], n[1], n[0])
+    for comp, name in enumerate(["Ex", "Ey", "Ez"]):
+        x, y, z = yee_positions(shape, comp, "E")
+        s.set(name, u[comp] * np.cos(k[0] * x * dx + k[1] * y * dx + k[2] * z * dx))
+    s.run(1)
+    amp = s.dt / consts()["mu0"] * np.cross(K, u)
+    for comp, name in enumerate(["Hx", "Hy", "Hz"]):
+        x, y, z = yee_positions(shape, comp, "H")
+        want = amp[comp] * np.sin(k[0] * x * dx + k[1] * y * dx + k[2] * z * dx)
+        got = s.get(name)
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(amp).max(), name
 
 
 # ---------------------------------------------------------- P2 energy (PEC box)
@@ -220,7 +258,7 @@ def _bulk_mode_series(beta, gamma, diff, kvec, nsteps=600, n=8, dx=0.25e-9, wp=1
     u = K / np.linalg.norm(K)  # longitudinal
     shape = (n, n, n)
     for comp, c in enumerate("xyz"):
-        x, y, z = yee_positions(shape, comp)
+        x, y, z = yee_positions(shape, comp, "P")
         P0 = 1e-12 * u[comp] * np.cos(k[0] * x * dx + k[1] * y * dx + k[2] * z * dx)
         s.set("P" + c, P0); s.set("Pm" + c, P0)
         s.set("E" + c, -P0 / eps0); s.set("Em" + c, -P0 / eps0)
