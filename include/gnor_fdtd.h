@@ -264,11 +264,12 @@ gnor_status gnor_tile_classes(const gnor_sim *sim, int32_t *counts);
  * Errors: INVALID_ARG for other values. */
 gnor_status gnor_set_tiling(gnor_sim *sim, int32_t ty, int32_t kz, int32_t tile_order);
 
-/* Autotuner: times every candidate tiling (ty in {2, 4, 8}, kz in {8, 16, 32,
- * 64, nz}, tile_order in {0, 1, 2}) over trial_steps directly launched steps
- * and keeps the fastest.  Must be called at step index 0; the state is reset
- * afterwards.  Outputs (any may be NULL): chosen ty, kz, tile_order and its
- * ms per step. */
+/* Autotuner: times every candidate tiling (ty in {2, 4, 8}, kz in {2, 3, 4,
+ * 8, 16, 32, 64, nz} clamped to nz, tile_order in {0, 1, 2}) over
+ * trial_steps directly launched steps, times the four fastest again over
+ * 4 * trial_steps steps and keeps the fastest of those.  Must be called at
+ * step index 0; the state is reset afterwards.  Outputs (any may be NULL):
+ * chosen ty, kz, tile_order and its ms per step (from the second timing). */
 gnor_status gnor_autotune(gnor_sim *sim, int32_t trial_steps, int32_t *ty, int32_t *kz,
                           int32_t *tile_order, double *ms_per_step);
 

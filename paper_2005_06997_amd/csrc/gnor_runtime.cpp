@@ -1380,33 +1380,50 @@ gnor_status gnor_autotune(gnor_sim* s, int32_t trial_steps, int32_t* ty_out, int
   if (trial_steps < 2) trial_steps = 2;
   const int tys[3] = {2, 4, 8};
   const int nz = s->g.nz;
-  const int kzs[5] = {8, 16, 32, 64, nz};
-  double best = 1e300;
-  int bty = s->tile_ty, bkz = s->tile_kz, bxcd = s->tile_xcd;
+  const int kzs[8] = {2, 3, 4, 8, 16, 32, 64, nz};
   hipEvent_t e0, e1;
   HIPCHECK(s, hipEventCreate(&e0));
   HIPCHECK(s, hipEventCreate(&e1));
   const int saved_chunk = s->graph_chunk;
   s->graph_chunk = 0;
+  // ms per step of one tiling over `steps` steps (after two warm-up steps)
+  auto trial = [&](int ty, int kz, int x, int steps, double* ms) -> gnor_status {
+    gnor_status r = gnor_set_tiling(s, ty, kz, x);
+    if (r == GNOR_OK) r = gnor_run(s, 2);
+    if (r != GNOR_OK) return r;
+    (void)hipEventRecord(e0, s->stream);
+    r = gnor_run(s, steps);
+    if (r != GNOR_OK) return r;
+    (void)hipEventRecord(e1, s->stream);
+    HIPCHECK(s, hipEventSynchronize(e1));
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    *ms = t / steps;
+    return GNOR_OK;
+  };
+  // every candidate once, then the four fastest again over four times the
+  // steps (single short trials differ by a few per cent from run to run)
+  struct Cand { double ms; int ty, kz, x; };
+  std::vector<Cand> cands;
   for (int x = 0; x < 3; ++x)
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 5; ++b) {
-      const int kz = std::min(kzs[b], nz);
-      if (b == 4 && kz <= 64) continue;
-      st = gnor_set_tiling(s, tys[a], kz, x);
-      if (st != GNOR_OK) return st;
-      st = gnor_run(s, 2);  // warm-up
-      if (st != GNOR_OK) return st;
-      (void)hipEventRecord(e0, s->stream);
-      st = gnor_run(s, trial_steps);
-      if (st != GNOR_OK) return st;
-      (void)hipEventRecord(e1, s->stream);
-      HIPCHECK(s, hipEventSynchronize(e1));
-      float t = 0.f;
-      (void)hipEventElapsedTime(&t, e0, e1);
-      const double ms = t / trial_steps;
-      if (ms < best) { best = ms; bty = tys[a]; bkz = kz; bxcd = x; }
-    }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 8; ++b) {
+        const int kz = std::min(kzs[b], nz);
+        if (b > 0 && kz <= std::min(kzs[b - 1], nz)) continue;  // clamped duplicate
+        Cand c{0.0, tys[a], kz, x};
+        st = trial(c.ty, c.kz, c.x, trial_steps, &c.ms);
+        if (st != GNOR_OK) return st;
+        cands.push_back(c);
+      }
+  std::sort(cands.begin(), cands.end(), [](const Cand& u, const Cand& v) { return u.ms < v.ms; });
+  double best = 1e300;
+  int bty = s->tile_ty, bkz = s->tile_kz, bxcd = s->tile_xcd;
+  for (size_t q = 0; q < cands.size() && q < 4; ++q) {
+    double ms = 0.0;
+    st = trial(cands[q].ty, cands[q].kz, cands[q].x, 4 * trial_steps, &ms);
+    if (st != GNOR_OK) return st;
+    if (ms < best) { best = ms; bty = cands[q].ty; bkz = cands[q].kz; bxcd = cands[q].x; }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   s->graph_chunk = saved_chunk;

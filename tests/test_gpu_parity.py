@@ -232,7 +232,8 @@ def test_fp32_config1_vs_oracle(B):
         f"{max(worst[k] for k in ('inc', 'ext', 'abs', 'sca')):.3e}")
 
 
-@pytest.mark.parametrize("ty,kz,xcd", [(2, 8, 1), (8, 13, 0), (4, 48, 1), (4, 8, 2)])
+@pytest.mark.parametrize("ty,kz,xcd", [(2, 8, 1), (8, 13, 0), (4, 48, 1), (4, 8, 2), (2, 2, 2),
+                                        (4, 5, 2)])
 def test_tilings_agree_with_oracle(B, ty, kz, xcd):
     """Every sweep tiling (including a kz that does not divide nz) reproduces
     the oracle; only reduction orders of the spectra differ."""
@@ -294,6 +295,39 @@ def test_resume_from_snapshot_is_bitwise(B):
         assert np.array_equal(b.field(f), ref[f]), f
     for k, v in b.spectra().items():
         assert np.array_equal(v, sref[k]), k
+
+
+def test_step_forms_switch_mid_run_and_resume(B):
+    """Switching step forms at odd and even steps keeps every double-buffered
+    state array (fields, currents, node scalars, CPML memories) where the
+    next form reads it (against the oracle), and a snapshot taken in the
+    fused form resumes bit for bit in a fresh simulation that continues in
+    the hybrid and two-sweep forms."""
+    w = W.early_pulse(W.config1(1))
+    w.omega = W.spectrum_omegas(16)
+    say("case step forms 0 -> 1 (step 101) -> snapshot (160) -> 2 -> 0 (212), fp64")
+    g = B.Sim(w, precision="fp64")
+    g.run(101)
+    g.set_mode(1)
+    g.run(59)
+    snap = g.save_state()
+    g.set_mode(2)
+    g.run(52)
+    g.set_mode(0)
+    g.run(88)
+    compare(g, oracle_run(w, 300), 1e-10, 1e-10)
+    h = B.Sim(w, precision="fp64")
+    h.load_state(snap)
+    assert h.step == 160
+    h.set_mode(2)
+    h.run(52)
+    h.set_mode(0)
+    h.run(88)
+    for f in FIELDS:
+        assert np.array_equal(h.field(f), g.field(f)), f
+    sg, sh = g.spectra(), h.spectra()
+    for k in sg:
+        assert np.array_equal(sh[k], sg[k]), k
 
 
 def test_nonfinite_watchdog(B):
