@@ -311,8 +311,10 @@ Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
 // x extents rowx of the metal points, null = no metal; CPML: slabs of np
 // cells within one cell; classes 0 plain, 1 CPML, 2 metal, 3 metal + CPML)
 // and fill the class counts, offsets and per-XCD counts of t; list receives
-// the class lists back to back.
+// the class lists back to back.  merge_x: tiles without metal that meet only
+// an x slab go to class 0, whose two-sweep kernels update the x-slab psi of
+// such tiles (the fused kernels of class 0 have no CPML: false for them).
 void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
-                    std::vector<int>& list);
+                    std::vector<int>& list, bool merge_x);
 
 }  // namespace gnor

@@ -597,7 +597,8 @@ gnor_status upload_rho(gnor_sim* s) {
   return GNOR_OK;
 }
 
-// Tile classes of the current tiling; uploaded when the memory is bound.
+// Tile classes of the current tiling and step form; uploaded when the memory
+// is bound (after the stream's queued steps, which read the old lists).
 gnor_status plan_tiles(gnor_sim* s) {
   const gnor_grid_desc& g = s->g;
   s->tl = gnor::make_tiling(g.nx, g.ny, g.nz, s->tile_ty, s->tile_kz, s->tile_xcd);
@@ -616,12 +617,25 @@ gnor_status plan_tiles(gnor_sim* s) {
       s->rowx[2 * r + 1] = hi;
     }
   }
+  // x-slab tiles join the plain class only in the two-sweep form: the fused
+  // and hybrid forms run class 0 on the fused kernel, which has no CPML
   gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->any_metal ? s->rowx.data() : nullptr,
-                       s->tile_list);
-  if (s->bound && !s->tile_list.empty())
+                       s->tile_list, s->mode == 0);
+  if (s->bound && !s->tile_list.empty()) {
+    HIPCHECK(s, hipStreamSynchronize(s->stream));
     HIPCHECK(s, hipMemcpy(s->dev + s->L.tiles, s->tile_list.data(), s->tile_list.size() * 4,
                           hipMemcpyHostToDevice));
+  }
   return GNOR_OK;
+}
+
+// Change the step form; the class lists depend on it (see plan_tiles).
+gnor_status set_mode(gnor_sim* s, int mode) {
+  if (mode == s->mode) return GNOR_OK;
+  const bool replan = (mode == 0) != (s->mode == 0);
+  s->mode = mode;
+  drop_graph(s);
+  return replan ? plan_tiles(s) : GNOR_OK;
 }
 
 gnor_status upload_static(gnor_sim* s) {
@@ -1001,11 +1015,7 @@ gnor_status gnor_set_fused(gnor_sim* s, int32_t on) {
   if (!s || on < 0 || on > 2) return GNOR_E_INVALID_ARG;
   if (on == 1 && s->have_material && s->mat.ncp > 0)
     return fail(s, GNOR_E_INVALID_ARG, "the fused step has no critical-point terms");
-  if (on != s->mode) {
-    s->mode = on;
-    drop_graph(s);
-  }
-  return GNOR_OK;
+  return set_mode(s, on);
 }
 
 gnor_status gnor_set_graph_chunk(gnor_sim* s, int32_t steps) {
@@ -1910,9 +1920,10 @@ extern "C" gnor_status gnor_gradient(gnor_sim* s, int64_t nsteps, int32_t ckpt_e
   // the backward pass needs the stored Q of each recomputed step, so the whole
   // gradient (forward pass included) runs on the two-sweep kernels
   const int mode = s->mode;
-  if (mode != 0) { s->mode = 0; drop_graph(s); }
+  st = set_mode(s, 0);
+  if (st != GNOR_OK) return st;
   st = s->g.precision == GNOR_FP32 ? gradient_impl<float>(s, nsteps, ckpt_every, m_target, objective, grad)
                                    : gradient_impl<double>(s, nsteps, ckpt_every, m_target, objective, grad);
-  if (mode != 0) { s->mode = mode; drop_graph(s); }
-  return st;
+  const gnor_status st2 = set_mode(s, mode);
+  return st != GNOR_OK ? st : st2;
 }

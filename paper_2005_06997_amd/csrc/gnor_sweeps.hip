@@ -43,8 +43,20 @@ namespace {
 // other resident wavefronts.
 
 // ------------------------------------------------------------------ f1: H
-template <class T, int TY, bool METAL, bool PML>
+// Does the tile, widened by one cell, meet an x slab?  (The host's
+// classification makes the same test.)
+template <class T>
+__device__ __forceinline__ bool tile_meets_x_slab(const Params<T>& p, const Tile& t) {
+  const int np = p.cp[0].np;
+  return np > 0 && (t.bx * kBX - 1 < np || t.bx * kBX + kBX + 1 > p.nx - 1 - np);
+}
+
+// PM: 0 no CPML; 1 any slab (pml_tile: the tile meets one); 2 at most an x
+// slab (the plain class in the two-sweep form, which also takes the tiles
+// that meet only an x slab: the y and z parts compile away)
+template <class T, int TY, bool METAL, int PM>
 __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool pml_tile) {
+  constexpr bool PML = PM != 0, PYZ = PM == 1;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int i = tile.bx * kBX + threadIdx.x;
   const int j = tile.by * TY + threadIdx.y;
@@ -68,7 +80,7 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
   const bool cy = xin && j >= 1 && yin;  // H_y
   const bool cz = xin && yin;            // H_z
   const int sxh = (PML && pml_tile) ? slab_h(i, nx, np) : -1;
-  const int syh = (PML && pml_tile) ? slab_h(j, ny, np) : -1;
+  const int syh = (PYZ && pml_tile) ? slab_h(j, ny, np) : -1;
   const CpmlAxis<T>& Z = p.cp[2];
   // the column's x- and y-slab coefficients, in registers for the whole
   // march (the psi stores could alias them, so the compiler cannot hoist them)
@@ -113,8 +125,8 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
     T dxz = eyx - ey0, dyz = exy - ex0;  // H_z: dx Ey - dy Ex
     if (PML && pml_tile) {
       // CPML-stretched differences kinv d + psi with psi <- b psi + a d
-      const int szh = slab_h(k, nz, np);
-      if (ux && syh >= 0) {
+      const int szh = PYZ ? slab_h(k, nz, np) : -1;
+      if (PYZ && ux && syh >= 0) {
         const size_t q = slab_index(1, syh, i, j, k, nx, ny, np);
         const T ps = yb * p.psiHi[1][0][q] + ya * dyx;
         p.psiH[1][0][q] = ps;
@@ -147,7 +159,7 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
         p.psiH[0][0][q] = ps;
         dxz = xk * dxz + ps;
       }
-      if (uz && syh >= 0) {
+      if (PYZ && uz && syh >= 0) {
         const size_t q = slab_index(1, syh, i, j, k, nx, ny, np);
         const T ps = yb * p.psiHi[1][1][q] + ya * dyz;
         p.psiH[1][1][q] = ps;
@@ -234,8 +246,9 @@ __device__ __forceinline__ double cp_update(const Params<T>& p, int c, size_t l,
 }
 
 // ------------------------------------------------------- f2 + f4: E and J
-template <class T, int TY, bool METAL, bool PML, bool CP>
+template <class T, int TY, bool METAL, int PM, bool CP>
 __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, bool pml_tile) {
+  constexpr bool PML = PM != 0, PYZ = PM == 1;  // PM as for h_tile
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int i = tile.bx * kBX + tx;
@@ -262,7 +275,7 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
   const bool ay = active && i >= 1 && i <= nx - 2 && j <= ny - 2;
   const bool az = active && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
   const int sxe = (PML && pml_tile && active) ? slab_e(i, nx, np) : -1;
-  const int sye = (PML && pml_tile && active) ? slab_e(j, ny, np) : -1;
+  const int sye = (PYZ && pml_tile && active) ? slab_e(j, ny, np) : -1;
   const CpmlAxis<T>& Z = p.cp[2];
   T xb = T(0), xa = T(0), xk = T(1), yb = T(0), ya = T(0), yk = T(1);
   if (sxe >= 0) { xb = p.cp[0].be[sxe]; xa = p.cp[0].ae[sxe]; xk = p.cp[0].ke[sxe]; }
@@ -298,8 +311,8 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
     T d_zy = hx - hxm, d_xy = hz - hzx;
     T d_xz = hy - hyx, d_yz = hx - hxy;
     if (PML && pml_tile) {
-      const int sze = slab_e(k, nz, np);
-      if (ux && sye >= 0) {
+      const int sze = PYZ ? slab_e(k, nz, np) : -1;
+      if (PYZ && ux && sye >= 0) {
         T* q = p.psiE[1][0] + slab_index(1, sye, i, j, k, nx, ny, np);
         const T ps = yb * *q + ya * d_yx;
         *q = ps;
@@ -332,7 +345,7 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
         *q = ps;
         d_xz = xk * d_xz + ps;
       }
-      if (uz && sye >= 0) {
+      if (PYZ && uz && sye >= 0) {
         T* q = p.psiE[1][1] + slab_index(1, sye, i, j, k, nx, ny, np);
         const T ps = yb * *q + ya * d_yz;
         *q = ps;
@@ -423,19 +436,19 @@ template <class T, int TY, int CLS>
 __device__ __forceinline__ void h_class(const Params<T>& p, int b) {
   const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
   if (!tile.ok) return;
-  if (CLS == 0) h_tile<T, TY, false, false>(p, tile, false);
-  else if (CLS == 1) h_tile<T, TY, false, true>(p, tile, true);
-  else if (CLS == 2) h_tile<T, TY, true, false>(p, tile, false);
-  else h_tile<T, TY, true, true>(p, tile, true);
+  if (CLS == 0) h_tile<T, TY, false, 2>(p, tile, tile_meets_x_slab(p, tile));
+  else if (CLS == 1) h_tile<T, TY, false, 1>(p, tile, true);
+  else if (CLS == 2) h_tile<T, TY, true, 0>(p, tile, false);
+  else h_tile<T, TY, true, 1>(p, tile, true);
 }
 template <class T, int TY, int CLS, bool CP>
 __device__ __forceinline__ void ej_class(const Params<T>& p, int b) {
   const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
   if (!tile.ok) return;
-  if (CLS == 0) ej_tile<T, TY, false, false, false>(p, tile, false);
-  else if (CLS == 1) ej_tile<T, TY, false, true, false>(p, tile, true);
-  else if (CLS == 2) ej_tile<T, TY, true, false, CP>(p, tile, false);
-  else ej_tile<T, TY, true, true, CP>(p, tile, true);
+  if (CLS == 0) ej_tile<T, TY, false, 2, false>(p, tile, tile_meets_x_slab(p, tile));
+  else if (CLS == 1) ej_tile<T, TY, false, 1, false>(p, tile, true);
+  else if (CLS == 2) ej_tile<T, TY, true, 0, CP>(p, tile, false);
+  else ej_tile<T, TY, true, 1, CP>(p, tile, true);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -534,7 +547,7 @@ static bool tile_meets_metal_host(const Tiling& t, int tile, int nx, int ny, int
 }
 
 void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
-                    std::vector<int>& list) {
+                    std::vector<int>& list, bool merge_x) {
   const int T = t.nbx * t.nby * t.nbz;
   std::vector<int> cls[kClasses];
   auto slab = [&](int lo, int hi, int n) { return np > 0 && (lo < np || hi > n - 1 - np); };
@@ -543,9 +556,9 @@ void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
     const int z0 = bz * t.kz, z1 = std::min(nz, z0 + t.kz);
     // ranges widened by one cell: the fused step also touches the tile's halo
     const bool metal = tile_meets_metal_host(t, tile, nx, ny, nz, rowx);
-    const bool pml = slab(bx * kBX - 1, bx * kBX + kBX + 1, nx) ||
-                     slab(by * t.ty - 1, by * t.ty + t.ty + 1, ny) || slab(z0 - 1, z1 + 1, nz);
-    const int c = metal ? (pml ? 3 : 2) : (pml ? 1 : 0);
+    const bool px = slab(bx * kBX - 1, bx * kBX + kBX + 1, nx);
+    const bool pyz = slab(by * t.ty - 1, by * t.ty + t.ty + 1, ny) || slab(z0 - 1, z1 + 1, nz);
+    const int c = metal ? (px || pyz ? 3 : 2) : (pyz || (px && !merge_x) ? 1 : 0);
     cls[c].push_back(tile);
   }
   list.clear();
