@@ -1,5 +1,10 @@
-"""Checks at the benchmark configurations' full sizes, where the oracle is too
-slow to run: properties that hold at any size and FP32-vs-FP64 agreement.
+"""Checks at the benchmark configurations' full sizes: a short run of the
+320^3 grid against the oracle, element by element, and, where the oracle is
+too slow, properties that hold at any size and FP32-vs-FP64 agreement.
+
+* 320^3 grid in the benchmark's launch configuration, sphere moved down in z
+  so the pulse reaches it within 100 steps: FP64 and FP32 paths against the
+  FP64 oracle, every element of E, H and J and the spectra.
 
 * 320^3 sphere (the benchmark workload, autotuned launch configuration):
   FP32 spectra within 1e-4 of the FP64 GPU path; div H invariant in the FP64
@@ -24,6 +29,62 @@ def B():
     assert torch.cuda.is_available()
     from paper_2005_06997_amd import binding
     return binding
+
+
+def test_sphere320_vs_oracle_in_the_benchmark_launch(B):
+    """The benchmark grid (320^3, dx = 0.1 nm, 12-cell CPML, r = 10 nm sphere,
+    GNOR metal) in the benchmark's launch configuration: tiling (2, 3, 2),
+    graph chunks of 64 steps, concurrent tile classes.  The sphere sits as
+    low in z as the monitor boxes allow (scattering box one cell above the
+    CPML), so the incident pulse, launched three cells below the grid, enters
+    the TF box after about 36 steps and the metal after about 43; 100 steps
+    then exercise every tile class.  The oracle takes about a minute for
+    them on 16 host threads."""
+    import torch
+    from oracle import oracle as orc
+    from tests.helpers import oracle_problem
+    n, dx, r = 320, 0.1e-9, 10.0e-9
+    c = [(n - 1) / 2.0, (n - 1) / 2.0, 118.5]
+    w = W.early_pulse(W.sphere_problem("sphere_r10nm_320^3_low", n, dx, 12, c, r, steps=100,
+                                       precision="fp64"))
+    w.omega = W.spectrum_omegas(20)
+    w.norm_k = 20  # a plane the pulse has crossed (the centre plane has not seen it yet)
+    assert w.sca_lo[2] == w.npml + 1
+    steps = 100
+    fields = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "Jx", "Jy", "Jz")
+    print(f"case 320^3 low sphere vs oracle, {steps} steps, tiling (2, 3, 2)", flush=True)
+    o = orc.OracleSim(oracle_problem(w, threads=16), oracle_mask(w))
+    o.run(steps)
+    ref = {f: o.get(f) for f in fields}
+    sref = o.spectra()
+    o.close()
+    assert np.abs(ref["Jx"]).max() > 0  # the field has reached the metal
+    assert np.abs(sref["inc"]).min() > 0
+    # FP32 spectra: 1e-3 here.  After 100 steps the scattered flux is barely
+    # above the FP32 rounding of the total-minus-incident cancellation at the
+    # TF surface (measured 1.3e-4 for sigma_sca, 1e-8 for ext and abs); the
+    # 1e-4 bound of full-length runs is checked below at 2400 steps.
+    for prec, ftol, stol in (("fp64", 1e-10, 1e-10), ("fp32", 1e-3, 1e-3)):
+        g = B.Sim(w, precision=prec)
+        g.set_tiling(2, 3, 2)
+        cls = g.tile_classes()
+        assert all(v > 0 for v in cls), cls
+        g.run(steps)
+        worst = {}
+        for f in fields:
+            a, b = g.field(f), ref[f]
+            kin = max(np.linalg.norm(ref[h]) for h in fields if h[0] == f[0])
+            worst[f] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-3 * kin))
+        sg = g.spectra()
+        for k in ("inc", "ext", "abs", "sca"):
+            worst[k] = rel_l2(sg[k], sref[k])
+        print(f"  {prec} rel-L2: " + ", ".join(f"{k} {v:.1e}" for k, v in worst.items()), flush=True)
+        for f in fields:
+            assert worst[f] <= ftol, (prec, f, worst[f])
+        for k in ("inc", "ext", "abs", "sca"):
+            assert worst[k] <= stol, (prec, k, worst[k])
+        g.close()
+        torch.cuda.empty_cache()
 
 
 def test_sphere320_fp32_vs_fp64_and_div_h(B):
