@@ -177,9 +177,9 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
       const T inc = (T)p.e1[k + kAuxOff];
       czv += tfz_lo ? inc : -inc;
     }
-    if (ux) Hx[id] = hx - S * (dyx - dzx);
-    if (uy) Hy[id] = hy - S * cyv;
-    if (uz) Hz[id] = hz - S * czv;
+    if (ux) __builtin_nontemporal_store(hx - S * (dyx - dzx), &Hx[id]);
+    if (uy) __builtin_nontemporal_store(hy - S * cyv, &Hy[id]);
+    if (uz) __builtin_nontemporal_store(hz - S * czv, &Hz[id]);
     if (METAL) {
       // node scalars of node (i, j, k) of the metal sub-grid
       // J_z is carried from the plane below, so it is read one plane early
@@ -424,9 +424,9 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
         }
       }
     }
-    if (ux) Ox[id] = nx_;
-    if (uy) Oy[id] = ny_;
-    if (uz) Oz[id] = nz_;
+    if (ux) __builtin_nontemporal_store(nx_, &Ox[id]);
+    if (uy) __builtin_nontemporal_store(ny_, &Oy[id]);
+    if (uz) __builtin_nontemporal_store(nz_, &Oz[id]);
     hxm = hx;
     hym = hy;
   }
