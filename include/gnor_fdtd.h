@@ -121,7 +121,9 @@ typedef struct {
   int32_t sca_lo[3], sca_hi[3];
 } gnor_monitor_desc;
 
-/* Create a simulation for a grid.  Checks sizes and the Courant number
+/* Create a simulation for a grid.  Checks sizes (each of nx, ny, nz >= 4;
+ * at most 4e9 cells, since the sweeps index cells with 32-bit integers; the
+ * TF box and the CPML as described above) and the Courant number
  * (GNOR_E_UNSTABLE if S >= 1/sqrt(3)).  *out receives an opaque handle. */
 gnor_status gnor_create(const gnor_grid_desc *grid, gnor_sim **out);
 void gnor_destroy(gnor_sim *sim);

@@ -760,6 +760,7 @@ gnor_status gnor_create(const gnor_grid_desc* g, gnor_sim** out) {
   *out = nullptr;
   if (g->nx < 4 || g->ny < 4 || g->nz < 4 || !(g->dx > 0.0) || !(g->eps_background > 0.0))
     return GNOR_E_INVALID_ARG;
+  // at most 4e9 cells: the sweeps index cells with 32-bit integers
   if ((double)g->nx * g->ny * g->nz > 4.0e9) return GNOR_E_INVALID_ARG;
   if (g->precision != GNOR_FP32 && g->precision != GNOR_FP64) return GNOR_E_INVALID_ARG;
   if (!(g->courant > 0.0) || g->courant >= 1.0 / std::sqrt(3.0)) return GNOR_E_UNSTABLE;

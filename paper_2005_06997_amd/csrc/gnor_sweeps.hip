@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 namespace gnor {
@@ -43,6 +44,13 @@ namespace {
 // other resident wavefronts.
 
 // ------------------------------------------------------------------ f1: H
+// Cell index of the sweeps: 32-bit in the metal classes and in FP64 (fewer
+// registers for addresses: 67 -> 46 VGPRs in the FP32 metal E/J kernel),
+// 64-bit elsewhere, which measured faster there.  gnor_create admits at most
+// 4e9 < 2^32 cells, and every index a sweep dereferences lies below N.
+template <class T, bool METAL>
+using CellIdx = typename std::conditional<METAL || sizeof(T) == 8, uint32_t, size_t>::type;
+
 // Does the tile, widened by one cell, meet an x slab?  (The host's
 // classification makes the same test.)
 template <class T>
@@ -103,7 +111,8 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
     zhi = p.colz[2 * lcol + 1];
   }
 
-  size_t id = (size_t)k0 * sz + (size_t)j * nx + i;
+  using Idx = CellIdx<T, METAL>;
+  Idx id = (Idx)k0 * (Idx)sz + (Idx)j * nx + i;
   T ex0 = Ex[id], ey0 = Ey[id];  // E_x, E_y of plane k (carried up the column)
   T jzm = T(0);                  // J_z one plane below (metal sub-grid)
   if (METAL && col_sub) {
@@ -289,7 +298,8 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
   const size_t m1 = p.mn[0], m2 = (size_t)p.mn[0] * p.mn[1];
   const size_t lcol = col_sub ? (size_t)ly * m1 + lx : 0;
 
-  size_t id = (size_t)k0 * sz + (size_t)(active ? j : 0) * nx + (active ? i : 0);
+  using Idx = CellIdx<T, METAL>;
+  Idx id = (Idx)k0 * (Idx)sz + (Idx)(active ? j : 0) * nx + (active ? i : 0);
   T hxm = T(0), hym = T(0);  // H at k-1 for the z differences
   if (active && k0 >= 1 && k0 < k1) {
     hxm = Hx[id - sz];
