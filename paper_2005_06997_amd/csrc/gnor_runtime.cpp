@@ -297,6 +297,7 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   p.PJi = ptr<T>(s, s->L.PJ[a]); p.PJo = ptr<T>(s, s->L.PJ[b]);
   p.Q = ptr<T>(s, s->L.Q);
   p.any_metal = s->any_metal ? 1 : 0;
+  p.stream_stores = 9.0 * (double)s->N * sizeof(T) > gnor::kStreamStoreBytes ? 1 : 0;
   for (int d = 0; d < 3; ++d) { p.mlo[d] = s->mlo[d]; p.mn[d] = s->mn[d]; }
   p.mask = ptr<uint8_t>(s, s->L.mask);
   p.colz = ptr<int>(s, s->L.colz);
@@ -1541,6 +1542,7 @@ struct gnor_batch {
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   std::vector<int> tiling;   // (ty, kz, order) of every instance at creation
   bool any_dft = false, any_flux = false, any_cp = false;
+  bool stream_stores = false;  // nontemporal field stores (by the batch's total size)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipGraphExec_t graph = nullptr;
@@ -1566,12 +1568,18 @@ gnor_status bfail(gnor_batch* b, gnor_status st, const std::string& m) {
 template <class T>
 gnor_status batch_tables(gnor_batch* b) {
   std::vector<gnor::BatchEntry<T>> tab(2 * (size_t)b->n);
+  // one launch sweeps every instance: stream the field stores by the total
+  double cells = 0.0;
+  for (int q = 0; q < b->n; ++q) cells += (double)b->sims[q]->N;
+  const int stream = 9.0 * cells * sizeof(T) > gnor::kStreamStoreBytes ? 1 : 0;
+  b->stream_stores = stream != 0;
   for (int parity = 0; parity < 2; ++parity) {
     int h0[gnor::kClasses] = {0, 0, 0, 0}, d0 = 0;
     for (int q = 0; q < b->n; ++q) {
       gnor_sim* s = b->sims[q];
       gnor::BatchEntry<T>& e = tab[(size_t)parity * b->n + q];
       e.p = make_params<T>(s, parity);
+      e.p.stream_stores = stream;
       e.a = make_aux(s);
       e.d = make_dft(s);
       e.f = make_flux(s);
@@ -1613,10 +1621,11 @@ void batch_enqueue(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st) {
       }
     };
     classes([&](int c, hipStream_t q2) {
-      gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, q2);
+      gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
     });
     classes([&](int c, hipStream_t q2) {
-      gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, sub, c, b->any_cp, q2);
+      gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, sub, c, b->any_cp,
+                                     b->stream_stores, q2);
     });
     if (b->any_dft && b->dblocks > 0) gnor::launch_dft_batch<T>(t, b->n, b->dblocks, sub, st);
     if (b->any_flux && (n % gnor::kFluxSlots) == gnor::kFluxSlots - 1)

@@ -51,6 +51,15 @@ namespace {
 template <class T, bool METAL>
 using CellIdx = typename std::conditional<METAL || sizeof(T) == 8, uint32_t, size_t>::type;
 
+// Store of a field output: nontemporal for sweeps larger than the Infinity
+// Cache.  A compile-time choice: the compiler merges the two stores of a
+// run-time branch into one plain store.
+template <bool NT, class T>
+__device__ __forceinline__ void store_field(T* a, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, a);
+  else *a = v;
+}
+
 // Does the tile, widened by one cell, meet an x slab?  (The host's
 // classification makes the same test.)
 template <class T>
@@ -62,7 +71,7 @@ __device__ __forceinline__ bool tile_meets_x_slab(const Params<T>& p, const Tile
 // PM: 0 no CPML; 1 any slab (pml_tile: the tile meets one); 2 at most an x
 // slab (the plain class in the two-sweep form, which also takes the tiles
 // that meet only an x slab: the y and z parts compile away)
-template <class T, int TY, bool METAL, int PM>
+template <class T, int TY, bool METAL, int PM, bool NT>
 __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool pml_tile) {
   constexpr bool PML = PM != 0, PYZ = PM == 1;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
@@ -186,9 +195,9 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
       const T inc = (T)p.e1[k + kAuxOff];
       czv += tfz_lo ? inc : -inc;
     }
-    if (ux) __builtin_nontemporal_store(hx - S * (dyx - dzx), &Hx[id]);
-    if (uy) __builtin_nontemporal_store(hy - S * cyv, &Hy[id]);
-    if (uz) __builtin_nontemporal_store(hz - S * czv, &Hz[id]);
+    if (ux) store_field<NT>(&Hx[id], hx - S * (dyx - dzx));
+    if (uy) store_field<NT>(&Hy[id], hy - S * cyv);
+    if (uz) store_field<NT>(&Hz[id], hz - S * czv);
     if (METAL) {
       // node scalars of node (i, j, k) of the metal sub-grid
       // J_z is carried from the plane below, so it is read one plane early
@@ -255,7 +264,7 @@ __device__ __forceinline__ double cp_update(const Params<T>& p, int c, size_t l,
 }
 
 // ------------------------------------------------------- f2 + f4: E and J
-template <class T, int TY, bool METAL, int PM, bool CP>
+template <class T, int TY, bool METAL, int PM, bool CP, bool NT>
 __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, bool pml_tile) {
   constexpr bool PML = PM != 0, PYZ = PM == 1;  // PM as for h_tile
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -434,54 +443,55 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
         }
       }
     }
-    if (ux) __builtin_nontemporal_store(nx_, &Ox[id]);
-    if (uy) __builtin_nontemporal_store(ny_, &Oy[id]);
-    if (uz) __builtin_nontemporal_store(nz_, &Oz[id]);
+    if (ux) store_field<NT>(&Ox[id], nx_);
+    if (uy) store_field<NT>(&Oy[id], ny_);
+    if (uz) store_field<NT>(&Oz[id], nz_);
     hxm = hx;
     hym = hy;
   }
 }
 
-template <class T, int TY, int CLS>
+template <class T, int TY, int CLS, bool NT>
 __device__ __forceinline__ void h_class(const Params<T>& p, int b) {
   const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
   if (!tile.ok) return;
-  if (CLS == 0) h_tile<T, TY, false, 2>(p, tile, tile_meets_x_slab(p, tile));
-  else if (CLS == 1) h_tile<T, TY, false, 1>(p, tile, true);
-  else if (CLS == 2) h_tile<T, TY, true, 0>(p, tile, false);
-  else h_tile<T, TY, true, 1>(p, tile, true);
+  if (CLS == 0) h_tile<T, TY, false, 2, NT>(p, tile, tile_meets_x_slab(p, tile));
+  else if (CLS == 1) h_tile<T, TY, false, 1, NT>(p, tile, true);
+  else if (CLS == 2) h_tile<T, TY, true, 0, NT>(p, tile, false);
+  else h_tile<T, TY, true, 1, NT>(p, tile, true);
 }
-template <class T, int TY, int CLS, bool CP>
+template <class T, int TY, int CLS, bool CP, bool NT>
 __device__ __forceinline__ void ej_class(const Params<T>& p, int b) {
   const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
   if (!tile.ok) return;
-  if (CLS == 0) ej_tile<T, TY, false, 2, false>(p, tile, tile_meets_x_slab(p, tile));
-  else if (CLS == 1) ej_tile<T, TY, false, 1, false>(p, tile, true);
-  else if (CLS == 2) ej_tile<T, TY, true, 0, CP>(p, tile, false);
-  else ej_tile<T, TY, true, 1, CP>(p, tile, true);
+  if (CLS == 0) ej_tile<T, TY, false, 2, false, NT>(p, tile, tile_meets_x_slab(p, tile));
+  else if (CLS == 1) ej_tile<T, TY, false, 1, false, NT>(p, tile, true);
+  else if (CLS == 2) ej_tile<T, TY, true, 0, CP, NT>(p, tile, false);
+  else ej_tile<T, TY, true, 1, CP, NT>(p, tile, true);
 }
 
 // ---------------------------------------------------------------- kernels
 // Single simulation: one launch per tile class; the class-0 launch has one
 // extra block (the last) that advances the auxiliary line.
-template <class T, int TY, int CLS>
+// NT: nontemporal field stores (chosen by the host per launch: Params::stream_stores)
+template <class T, int TY, int CLS, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_h(Params<T> p, AuxParams a) {
   if (CLS == 0 && (int)blockIdx.x == (int)gridDim.x - 1) {
     aux_h_block(a, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  h_class<T, TY, CLS>(p, blockIdx.x);
+  h_class<T, TY, CLS, NT>(p, blockIdx.x);
 }
 
 // CP: the metal classes with critical points (a separate variant, so the
 // plain metal code keeps its registers)
-template <class T, int TY, int CLS, bool CP>
+template <class T, int TY, int CLS, bool CP, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_ej(Params<T> p, AuxParams a, int sub) {
   if (CLS == 0 && (int)blockIdx.x == (int)gridDim.x - 1) {
     aux_e_block(a, sub, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  ej_class<T, TY, CLS, CP>(p, blockIdx.x);
+  ej_class<T, TY, CLS, CP, NT>(p, blockIdx.x);
 }
 
 // Batch: the blocks of all instances in one launch per class.  Instance q
@@ -499,7 +509,7 @@ __device__ __forceinline__ int find_instance(const BatchEntry<T>* __restrict__ e
   return lo;
 }
 
-template <class T, int TY, int CLS>
+template <class T, int TY, int CLS, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __restrict__ e, int n) {
   const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
   const int b = blockIdx.x - en.blk0[CLS];
@@ -507,10 +517,10 @@ __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __rest
     aux_h_block(en.a, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  h_class<T, TY, CLS>(en.p, b);
+  h_class<T, TY, CLS, NT>(en.p, b);
 }
 
-template <class T, int TY, int CLS, bool CP>
+template <class T, int TY, int CLS, bool CP, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __restrict__ e, int n,
                                                       int sub) {
   const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
@@ -519,7 +529,7 @@ __global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __res
     aux_e_block(en.a, sub, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
   }
-  ej_class<T, TY, CLS, CP>(en.p, b);
+  ej_class<T, TY, CLS, CP, NT>(en.p, b);
 }
 
 }  // namespace
@@ -590,35 +600,55 @@ int class_blocks(const Tiling& t, int c) {
 }
 
 namespace {
+template <class T, int CLS, bool NT>
+void launch_h_cls_nt(const Params<T>& p, const AuxParams& a, int blocks, hipStream_t s) {
+  if (p.tl.ty == 4) hipLaunchKernelGGL((k_h<T, 4, CLS, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p, a);
+  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_h<T, 8, CLS, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p, a);
+  else hipLaunchKernelGGL((k_h<T, 2, CLS, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p, a);
+}
 template <class T, int CLS>
 void launch_h_cls(const Params<T>& p, const AuxParams& a, hipStream_t s) {
   const int blocks = class_blocks(p.tl, CLS) + (CLS == 0 ? 1 : 0);
   if (blocks == 0) return;
-  if (p.tl.ty == 4) hipLaunchKernelGGL((k_h<T, 4, CLS>), dim3(blocks), dim3(kBX, 4), 0, s, p, a);
-  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_h<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, p, a);
-  else hipLaunchKernelGGL((k_h<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, p, a);
+  if (p.stream_stores) launch_h_cls_nt<T, CLS, true>(p, a, blocks, s);
+  else launch_h_cls_nt<T, CLS, false>(p, a, blocks, s);
+}
+template <class T, int CLS, bool CP, bool NT>
+void launch_ej_cls_nt(const Params<T>& p, const AuxParams& a, int sub, int blocks, hipStream_t s) {
+  if (p.tl.ty == 4) hipLaunchKernelGGL((k_ej<T, 4, CLS, CP, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p, a, sub);
+  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_ej<T, 8, CLS, CP, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p, a, sub);
+  else hipLaunchKernelGGL((k_ej<T, 2, CLS, CP, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p, a, sub);
 }
 template <class T, int CLS, bool CP>
 void launch_ej_cls(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s) {
   const int blocks = class_blocks(p.tl, CLS) + (CLS == 0 ? 1 : 0);
   if (blocks == 0) return;
-  if (p.tl.ty == 4) hipLaunchKernelGGL((k_ej<T, 4, CLS, CP>), dim3(blocks), dim3(kBX, 4), 0, s, p, a, sub);
-  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_ej<T, 8, CLS, CP>), dim3(blocks), dim3(kBX, 8), 0, s, p, a, sub);
-  else hipLaunchKernelGGL((k_ej<T, 2, CLS, CP>), dim3(blocks), dim3(kBX, 2), 0, s, p, a, sub);
+  if (p.stream_stores) launch_ej_cls_nt<T, CLS, CP, true>(p, a, sub, blocks, s);
+  else launch_ej_cls_nt<T, CLS, CP, false>(p, a, sub, blocks, s);
+}
+template <class T, int CLS, bool NT>
+void launch_h_batch_cls_nt(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s) {
+  if (ty == 4) hipLaunchKernelGGL((k_h_batch<T, 4, CLS, NT>), dim3(blocks), dim3(kBX, 4), 0, s, e, n);
+  else if (ty == 8) hipLaunchKernelGGL((k_h_batch<T, 8, CLS, NT>), dim3(blocks), dim3(kBX, 8), 0, s, e, n);
+  else hipLaunchKernelGGL((k_h_batch<T, 2, CLS, NT>), dim3(blocks), dim3(kBX, 2), 0, s, e, n);
 }
 template <class T, int CLS>
-void launch_h_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s) {
+void launch_h_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, bool nt, hipStream_t s) {
   if (blocks == 0) return;
-  if (ty == 4) hipLaunchKernelGGL((k_h_batch<T, 4, CLS>), dim3(blocks), dim3(kBX, 4), 0, s, e, n);
-  else if (ty == 8) hipLaunchKernelGGL((k_h_batch<T, 8, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, e, n);
-  else hipLaunchKernelGGL((k_h_batch<T, 2, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, e, n);
+  if (nt) launch_h_batch_cls_nt<T, CLS, true>(e, n, blocks, ty, s);
+  else launch_h_batch_cls_nt<T, CLS, false>(e, n, blocks, ty, s);
+}
+template <class T, int CLS, bool CP, bool NT>
+void launch_ej_batch_cls_nt(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, hipStream_t s) {
+  if (ty == 4) hipLaunchKernelGGL((k_ej_batch<T, 4, CLS, CP, NT>), dim3(blocks), dim3(kBX, 4), 0, s, e, n, sub);
+  else if (ty == 8) hipLaunchKernelGGL((k_ej_batch<T, 8, CLS, CP, NT>), dim3(blocks), dim3(kBX, 8), 0, s, e, n, sub);
+  else hipLaunchKernelGGL((k_ej_batch<T, 2, CLS, CP, NT>), dim3(blocks), dim3(kBX, 2), 0, s, e, n, sub);
 }
 template <class T, int CLS, bool CP>
-void launch_ej_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, hipStream_t s) {
+void launch_ej_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, bool nt, hipStream_t s) {
   if (blocks == 0) return;
-  if (ty == 4) hipLaunchKernelGGL((k_ej_batch<T, 4, CLS, CP>), dim3(blocks), dim3(kBX, 4), 0, s, e, n, sub);
-  else if (ty == 8) hipLaunchKernelGGL((k_ej_batch<T, 8, CLS, CP>), dim3(blocks), dim3(kBX, 8), 0, s, e, n, sub);
-  else hipLaunchKernelGGL((k_ej_batch<T, 2, CLS, CP>), dim3(blocks), dim3(kBX, 2), 0, s, e, n, sub);
+  if (nt) launch_ej_batch_cls_nt<T, CLS, CP, true>(e, n, blocks, ty, sub, s);
+  else launch_ej_batch_cls_nt<T, CLS, CP, false>(e, n, blocks, ty, sub, s);
 }
 }  // namespace
 
@@ -650,27 +680,28 @@ template void launch_h_class<double>(const Params<double>&, const AuxParams&, in
 template void launch_ej_class<float>(const Params<float>&, const AuxParams&, int, int, hipStream_t);
 template void launch_ej_class<double>(const Params<double>&, const AuxParams&, int, int, hipStream_t);
 template <class T>
-void launch_h_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int c, hipStream_t s) {
-  if (c == 0) launch_h_batch_cls<T, 0>(e, n, blocks, ty, s);
-  else if (c == 1) launch_h_batch_cls<T, 1>(e, n, blocks, ty, s);
-  else if (c == 2) launch_h_batch_cls<T, 2>(e, n, blocks, ty, s);
-  else launch_h_batch_cls<T, 3>(e, n, blocks, ty, s);
+void launch_h_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int c, bool nt,
+                          hipStream_t s) {
+  if (c == 0) launch_h_batch_cls<T, 0>(e, n, blocks, ty, nt, s);
+  else if (c == 1) launch_h_batch_cls<T, 1>(e, n, blocks, ty, nt, s);
+  else if (c == 2) launch_h_batch_cls<T, 2>(e, n, blocks, ty, nt, s);
+  else launch_h_batch_cls<T, 3>(e, n, blocks, ty, nt, s);
 }
 template <class T>
 void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, int c, bool cp,
-                           hipStream_t s) {
-  if (c == 0) launch_ej_batch_cls<T, 0, false>(e, n, blocks, ty, sub, s);
-  else if (c == 1) launch_ej_batch_cls<T, 1, false>(e, n, blocks, ty, sub, s);
-  else if (c == 2) cp ? launch_ej_batch_cls<T, 2, true>(e, n, blocks, ty, sub, s)
-                      : launch_ej_batch_cls<T, 2, false>(e, n, blocks, ty, sub, s);
-  else cp ? launch_ej_batch_cls<T, 3, true>(e, n, blocks, ty, sub, s)
-          : launch_ej_batch_cls<T, 3, false>(e, n, blocks, ty, sub, s);
+                           bool nt, hipStream_t s) {
+  if (c == 0) launch_ej_batch_cls<T, 0, false>(e, n, blocks, ty, sub, nt, s);
+  else if (c == 1) launch_ej_batch_cls<T, 1, false>(e, n, blocks, ty, sub, nt, s);
+  else if (c == 2) cp ? launch_ej_batch_cls<T, 2, true>(e, n, blocks, ty, sub, nt, s)
+                      : launch_ej_batch_cls<T, 2, false>(e, n, blocks, ty, sub, nt, s);
+  else cp ? launch_ej_batch_cls<T, 3, true>(e, n, blocks, ty, sub, nt, s)
+          : launch_ej_batch_cls<T, 3, false>(e, n, blocks, ty, sub, nt, s);
 }
-template void launch_h_batch_class<float>(const BatchEntry<float>*, int, int, int, int, hipStream_t);
-template void launch_h_batch_class<double>(const BatchEntry<double>*, int, int, int, int, hipStream_t);
-template void launch_ej_batch_class<float>(const BatchEntry<float>*, int, int, int, int, int, bool,
+template void launch_h_batch_class<float>(const BatchEntry<float>*, int, int, int, int, bool, hipStream_t);
+template void launch_h_batch_class<double>(const BatchEntry<double>*, int, int, int, int, bool, hipStream_t);
+template void launch_ej_batch_class<float>(const BatchEntry<float>*, int, int, int, int, int, bool, bool,
                                            hipStream_t);
-template void launch_ej_batch_class<double>(const BatchEntry<double>*, int, int, int, int, int, bool,
+template void launch_ej_batch_class<double>(const BatchEntry<double>*, int, int, int, int, int, bool, bool,
                                             hipStream_t);
 template void launch_h<float>(const Params<float>&, const AuxParams&, hipStream_t);
 template void launch_h<double>(const Params<double>&, const AuxParams&, hipStream_t);
