@@ -66,6 +66,37 @@ def test_batch_equals_individual_runs_bitwise(B, prec):
             assert rel_l2(f_spec[k], sp[k]) <= tol, (s.w.name, k)
 
 
+def test_batch_with_streamed_stores_bitwise(B):
+    """A batch whose field traffic exceeds the Infinity Cache runs the
+    streaming-store sweep variants for every instance (the small instance
+    alone would not); results are unchanged, bit for bit."""
+    ws = []
+    for q, (n, r) in enumerate(((200, 5.0e-9), (96, 3.0e-9))):
+        c = [(n - 1) / 2.0 + 0.3 * q] * 3
+        w = W.early_pulse(W.sphere_problem(f"sphere_{n}", n, 0.25e-9, 8, c, r, steps=220))
+        w.omega = W.spectrum_omegas(10)
+        ws.append(w)
+    steps = 220  # the pulse enters the 200^3 TF box after about 160 steps
+    print(f"case streamed batch: sizes {[w.nx for w in ws]}", flush=True)
+    solo = []
+    for w in ws:
+        s = B.Sim(w, precision="fp32")
+        s.set_tiling(2, 8, 0)
+        s.run(steps)
+        solo.append(({f: s.field(f) for f in FIELDS}, s.spectra()))
+        s.close()
+    sims = [B.Sim(w, precision="fp32") for w in ws]
+    bt = B.Batch(sims, tiling=(2, 8, 0))
+    bt.run(steps)
+    bt.synchronize()
+    for (fields, spec), s in zip(solo, sims):
+        for f in FIELDS:
+            assert np.array_equal(s.field(f), fields[f]), (s.w.name, f)
+        for k, v in s.spectra().items():
+            assert np.array_equal(v, spec[k]), (s.w.name, k)
+    assert np.abs(solo[0][0]["Jx"]).max() > 0
+
+
 def test_batch_instance_vs_oracle(B):
     ws = instances(count=3, seed=1)
     print("case batch fp64 vs oracle", flush=True)
