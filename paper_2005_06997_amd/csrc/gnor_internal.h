@@ -37,7 +37,6 @@ constexpr int kAuxSrc = 22;
 // Field sweeps: blocks of 64 (x, one wavefront) x TY (y) columns, each column
 // marching over kz planes.
 constexpr int kBX = 64;
-constexpr int kMaxFreq = 256;   // spectral frequencies per simulation
 constexpr int kMaxCP = 4;        // critical points per material
 constexpr int kFluxSlots = 256;  // flux staging depth (steps per accumulation)
 // Field stores of a sweep go nontemporal when its field traffic (9 words per
