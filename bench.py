@@ -132,7 +132,7 @@ def main():
                     help="only run a plain device copy of 2 GiB (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU sharding); use --gpus 1",
+        print("bench.py runs on one GPU (there is no multi-GPU sharding); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
