@@ -1259,7 +1259,16 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   // so the queue never drains and no interval holds host launch latency.
   constexpr int NE = 2 * NC + 4;
   if (nsteps > 4096) return fail(s, GNOR_E_INVALID_ARG, "profile: at most 4096 steps");
-  std::vector<hipEvent_t> evs((size_t)nsteps * NE);
+  // the events are destroyed on every return path
+  struct Events {
+    std::vector<hipEvent_t> v;
+    ~Events() {
+      for (hipEvent_t e : v)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } events;
+  events.v.assign((size_t)nsteps * NE, nullptr);
+  std::vector<hipEvent_t>& evs = events.v;
   // timing only: no system-scope fence (no L2 write-back inside the intervals)
   for (auto& e : evs) HIPCHECK(s, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   double acc[NE - 1] = {};
@@ -1335,7 +1344,6 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
     }
     for (int e = 2 * NC; e < NE - 1; ++e) acc[e] += elapsed(e, e + 1);
   }
-  for (auto& e : evs) (void)hipEventDestroy(e);
   const double inv = 1.0 / (double)nsteps;
   double first = 0.0, second = 0.0;
   for (int c = 0; c < NC; ++c) {
@@ -1393,10 +1401,23 @@ gnor_status gnor_autotune(gnor_sim* s, int32_t trial_steps, int32_t* ty_out, int
   const int tys[3] = {2, 4, 8};
   const int nz = s->g.nz;
   const int kzs[8] = {2, 3, 4, 8, 16, 32, 64, nz};
-  hipEvent_t e0, e1;
-  HIPCHECK(s, hipEventCreate(&e0));
-  HIPCHECK(s, hipEventCreate(&e1));
-  const int saved_chunk = s->graph_chunk;
+  // on every return path: the events destroyed, the graph chunk restored,
+  // and (on failure) the tiling the search started from set back
+  struct Restore {
+    gnor_sim* s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int chunk, ty, kz, xcd;
+    bool done = false;
+    ~Restore() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      s->graph_chunk = chunk;
+      if (!done) (void)gnor_set_tiling(s, ty, kz, xcd);
+    }
+  } guard{s, nullptr, nullptr, s->graph_chunk, s->tile_ty, s->tile_kz, s->tile_xcd};
+  HIPCHECK(s, hipEventCreate(&guard.e0));
+  HIPCHECK(s, hipEventCreate(&guard.e1));
+  hipEvent_t e0 = guard.e0, e1 = guard.e1;
   s->graph_chunk = 0;
   // ms per step of one tiling over `steps` steps (after two warm-up steps)
   auto trial = [&](int ty, int kz, int x, int steps, double* ms) -> gnor_status {
@@ -1436,11 +1457,10 @@ gnor_status gnor_autotune(gnor_sim* s, int32_t trial_steps, int32_t* ty_out, int
     if (st != GNOR_OK) return st;
     if (ms < best) { best = ms; bty = cands[q].ty; bkz = cands[q].kz; bxcd = cands[q].x; }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  s->graph_chunk = saved_chunk;
+  s->graph_chunk = guard.chunk;
   st = gnor_set_tiling(s, bty, bkz, bxcd);
   if (st != GNOR_OK) return st;
+  guard.done = true;
   st = gnor_reset(s);
   if (st != GNOR_OK) return st;
   if (ty_out) *ty_out = bty;

@@ -99,3 +99,17 @@ def test_ninth_map_frequency_is_refused(B):
     base = W.early_pulse(W.config1(0))
     with pytest.raises(B.GnorError):
         B.Sim(W.with_maps(base, W.spectrum_omegas(9, 2.0, 5.0)), precision="fp32")
+
+
+def test_profile_refuses_more_than_4096_steps(B):
+    """gnor_profile_kernels takes at most 4096 steps (one set of events per
+    step); the simulation stays usable after the refusal."""
+    w = W.early_pulse(W.config1(0))
+    g = B.Sim(w, precision="fp32")
+    with pytest.raises(B.GnorError):
+        g.profile(4097)
+    assert g.step == 0
+    pr = g.profile(8)
+    assert pr["h"] > 0 and pr["ej"] > 0 and g.step == 8
+    g.run(16)
+    assert g.check_finite()
