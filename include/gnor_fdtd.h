@@ -225,7 +225,9 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
 /* The field update runs as one launch per tile class: 0 tiles that meet
  * neither metal nor a CPML slab, 1 tiles that meet a CPML slab only, 2 tiles
  * with a metal point within two cells, 3 tiles that are both 2 and 1 (a tile
- * meets a slab with a one-cell margin).  By default a step is the two-sweep form (H sweep, then E/J
+ * meets a slab with a one-cell margin); in the two-sweep form class 0 also
+ * takes the tiles that meet only an x slab (gnor_tile_classes counts them
+ * there).  By default a step is the two-sweep form (H sweep, then E/J
  * sweep); gnor_set_fused(sim, 1) selects one fused pass (H and E/J together,
  * 12 instead of 18 field words moved per cell) plus a one-block launch that
  * advances the auxiliary line; gnor_set_fused(sim, 2) the hybrid form: the

@@ -32,13 +32,15 @@ namespace gnor {
 namespace {
 
 // ------------------------------------------------------------ tile classes
-// Each sweep runs as three launches, one per tile class, so that each class
+// Each sweep runs as four launches, one per tile class, so that each class
 // gets the register budget (and hence the occupancy) its code needs:
-//   class 0: tiles that meet neither the metal sub-grid nor a CPML slab
-//            (the bulk of a large grid: the plain Yee update);
-//   class 1: tiles that meet a CPML slab but not the metal sub-grid;
-//   class 2: tiles that meet the metal sub-grid (CPML handled when the tile
-//            also meets a slab).
+//   class 0: tiles that meet neither metal nor a CPML slab (the bulk of a
+//            large grid: the plain Yee update), and in the two-sweep form
+//            also the tiles that meet only an x slab (their slab lanes
+//            update the x-slab psi behind a tile-uniform branch);
+//   class 1: tiles that meet a CPML slab but no metal;
+//   class 2: tiles with a metal point within two cells and no slab;
+//   class 3: tiles that are both 1 and 2.
 // A wavefront marches its column over the tile's planes; every plane's loads
 // are issued together, then computed and stored.  Latency is hidden by the
 // other resident wavefronts.
