@@ -74,6 +74,18 @@ typedef struct {
   double eps_background;
   int32_t tf_lo[3], tf_hi[3];
   int32_t precision; /* gnor_precision */
+  /* Dielectric substrate: with eps_substrate > 0 the half-space beyond node
+   * plane substrate_k (z > substrate_k dx) has relative permittivity
+   * eps_substrate; E_x and E_y on that plane take the mean of the two, E_z
+   * half a cell above a node takes the permittivity of its side.  The 1D
+   * incident line carries the same layers, so the TF/SF source injects the
+   * layered (Fresnel) plane wave at normal incidence.  0 = no substrate.
+   * With a substrate: every metal point must lie below plane substrate_k
+   * (in eps_background), and the fused and hybrid step forms and the design
+   * gradient are refused (GNOR_E_INVALID_ARG).  The CPML keeps the
+   * eps_background grading on both sides. */
+  double eps_substrate;
+  int32_t substrate_k;
 } gnor_grid_desc;
 
 /* Free-electron metal (Sec. II): wp (rad/s), gamma (rad/s), beta (m/s; the
@@ -270,8 +282,8 @@ gnor_status gnor_set_tiling(gnor_sim *sim, int32_t ty, int32_t kz, int32_t tile_
 
 /* Autotuner: times every candidate tiling (ty in {2, 4, 8}, kz in {2, 3, 4,
  * 8, 16, 32, 64, nz} clamped to nz, tile_order in {0, 1, 2}) over
- * trial_steps directly launched steps, times the four fastest again over
- * 4 * trial_steps steps and keeps the fastest of those.  Must be called at
+ * trial_steps directly launched steps, times the four fastest three more
+ * times over 4 * trial_steps steps and keeps the fastest of those timings.  Must be called at
  * step index 0; the state is reset afterwards.  Outputs (any may be NULL):
  * chosen ty, kz, tile_order and its ms per step (from the second timing). */
 gnor_status gnor_autotune(gnor_sim *sim, int32_t trial_steps, int32_t *ty, int32_t *kz,

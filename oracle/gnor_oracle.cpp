@@ -132,6 +132,10 @@ typedef struct {
   // map_every steps
   int32_t map_axis, map_index, nmap, map_every;
   double map_omega[8];
+  // dielectric substrate: the half-space z > sub_k (node planes) has relative
+  // permittivity eps_sub when eps_sub > 0 (0: uniform background eps_b)
+  double eps_sub;
+  int32_t sub_k;
 } or_config;
 
 }  // extern "C"
@@ -210,6 +214,17 @@ struct Sim {
     if (x < L) d = L - x;
     if (x > (n - 1 - L)) d = x - (n - 1 - L);
     return d;
+  }
+
+  // Background permittivity at an E point: eps_b, or eps_sub beyond the
+  // substrate plane.  E_x and E_y lie on the node planes (on the interface
+  // plane itself: the mean of the two), E_z half a cell above its node.
+  double eps_at(int comp, int k) const {
+    if (!(c.eps_sub > 0.0)) return c.eps_b;
+    if (comp == 2) return (k + 0.5 > c.sub_k) ? c.eps_sub : c.eps_b;
+    if (k > c.sub_k) return c.eps_sub;
+    if (k == c.sub_k) return 0.5 * (c.eps_b + c.eps_sub);
+    return c.eps_b;
   }
 
   double source(double t) const {
@@ -396,8 +411,9 @@ struct Sim {
   }
   // 1D auxiliary line: E_inc^{n+1} from H_inc^{n+1/2}, then the soft source
   void update_e1(double t_next) {
-    const double ce = dt / (eps0() * c.eps_b * dx);
     for (int q = 1; q <= n1 - 2; ++q) {
+      // line cell q carries E_x of grid plane q - kAuxOff (layered like the grid)
+      const double ce = dt / (eps0() * eps_at(0, q - kAuxOff) * dx);
       const double d = h1[q] - h1[q - 1];
       pe1[q] = be1[q] * pe1[q] + ae1[q] * d;
       e1[q] -= ce * (ke1[q] * d + pe1[q]);
@@ -437,7 +453,6 @@ struct Sim {
             GD[comp][p] = active(comp, p) ? grad_div(comp, i, j, k, P) : R(0.0);
           }
     }
-    const double ce_vac = dt / (eps0() * c.eps_b);
     const double hinc_scale = 1.0 / dx;
     const double e0ei = eps0() * c.eps_inf;
     std::vector<R> Enew[3];
@@ -464,7 +479,7 @@ struct Sim {
             R curl = (ke[a1][ii[a1]] * d1 + s1) - (ke[a2][ii[a2]] * d2 + s2);
             if (c.tfsf && !c.periodic) curl += tfsf_e(comp, i, j, k) * hinc_scale;
             if (!active(comp, p)) {
-              Enew[comp][p] = E[comp][p] + ce_vac * curl;
+              Enew[comp][p] = E[comp][p] + dt / (eps0() * eps_at(comp, k)) * curl;
             } else {
               const R d3 = w[p] * D3;
               const R rhs_gd = (c.model == 1)

@@ -104,6 +104,7 @@ class OrConfig(C.Structure):
         ("cp_Gamma", C.c_double * 4), ("cp_phi", C.c_double * 4),
         ("map_axis", C.c_int32), ("map_index", C.c_int32), ("nmap", C.c_int32),
         ("map_every", C.c_int32), ("map_omega", C.c_double * 8),
+        ("eps_sub", C.c_double), ("sub_k", C.c_int32),
     ]
 
 
@@ -153,6 +154,10 @@ class Problem:
     map_index: int = 0
     map_every: int = 1
     map_omega: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    # dielectric substrate: the half-space z > sub_k has permittivity eps_sub
+    # (0: none)
+    eps_sub: float = 0.0
+    sub_k: int = 0
 
     def to_c(self) -> OrConfig:
         c = OrConfig()

@@ -38,7 +38,8 @@ class GridDesc(C.Structure):
                 ("pml_order", C.c_double), ("pml_sigma_scale", C.c_double),
                 ("pml_kappa_max", C.c_double), ("pml_alpha_max", C.c_double),
                 ("eps_background", C.c_double),
-                ("tf_lo", C.c_int32 * 3), ("tf_hi", C.c_int32 * 3), ("precision", C.c_int32)]
+                ("tf_lo", C.c_int32 * 3), ("tf_hi", C.c_int32 * 3), ("precision", C.c_int32),
+                ("eps_substrate", C.c_double), ("substrate_k", C.c_int32)]
 
 
 MAX_CP = 4
@@ -177,7 +178,8 @@ class Sim:
         g = GridDesc(nx=w.nx, ny=w.ny, nz=w.nz, dx=w.dx, courant=w.courant, npml=w.npml,
                      pml_order=w.pml_order, pml_sigma_scale=w.pml_sigma_scale,
                      pml_kappa_max=w.pml_kappa_max, pml_alpha_max=w.pml_alpha_max,
-                     eps_background=w.eps_b, precision=GNOR_FP32 if prec == "fp32" else GNOR_FP64)
+                     eps_background=w.eps_b, precision=GNOR_FP32 if prec == "fp32" else GNOR_FP64,
+                     eps_substrate=getattr(w, "eps_sub", 0.0), substrate_k=getattr(w, "sub_k", 0))
         g.tf_lo[:] = list(w.tf_lo)
         g.tf_hi[:] = list(w.tf_hi)
         h = C.c_void_p()

@@ -81,7 +81,10 @@ __device__ void aux_e_block(const AuxParams& a, int sub, int tid, int nthr) {
     const double d = a.h1[q] - a.h1[q - 1];
     const double ps = a.be[q] * a.pe[q] + a.ae[q] * d;
     a.pe[q] = ps;
-    a.e1[q] -= a.SE * (a.ke[q] * d + ps);
+    // line cell q carries E_x of plane k = q - kAuxOff, layered like the grid
+    const int k = q - kAuxOff;
+    const double se = k < a.sub_k ? a.SE : (k == a.sub_k ? a.se_avg : a.se_sub);
+    a.e1[q] -= se * (a.ke[q] * d + ps);
   }
   const int64_t n = a.step_base[0] + sub;
   // phase table of this step for the running transforms (e^{+i w t})

@@ -83,6 +83,9 @@ struct Tiling {
 struct AuxParams {
   int n1;
   double S, SE;
+  // substrate (see Params::sub_k): line cell q carries plane q - kAuxOff
+  int sub_k;
+  double se_avg, se_sub;
   double* e1;
   double* h1;
   double* pe;
@@ -109,6 +112,11 @@ struct Params {
   int nx, ny, nz;
   T S;            // Courant number: H coefficient
   T SE;           // S / eps_b: vacuum E coefficient
+  // dielectric substrate: E_x, E_y on planes k > sub_k and E_z on planes
+  // k >= sub_k use se_sub = S / eps_sub, E_x, E_y on plane sub_k use se_avg
+  // (the mean permittivity); sub_k = nz + 1 without a substrate
+  int sub_k;
+  T se_avg, se_sub;
   // full-grid fields
   T* E[3];        // E^n
   T* O[3];        // E^{n-1} (read at metal points) -> E^{n+1} (written everywhere)

@@ -383,7 +383,11 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
       const T inc = (T)p.h1[k + kAuxOff];
       czv += (i == p.tf_lo[0]) ? -inc : inc;
     }
-    T nx_ = ex + SE * cxv, ny_ = ey + SE * cyv, nz_ = ez + SE * czv;
+    // background coefficients of the plane: E_x, E_y on node plane k, E_z
+    // half a cell above it (a substrate beyond plane sub_k; see Params)
+    const T sexy = k < p.sub_k ? SE : (k == p.sub_k ? p.se_avg : p.se_sub);
+    const T sez = k < p.sub_k ? SE : p.se_sub;
+    T nx_ = ex + sexy * cxv, ny_ = ey + sexy * cyv, nz_ = ez + sez * czv;
     if (METAL) {
       const int lz = k - p.mlo[2];
       const bool zsub = lz >= 0 && lz < p.mn[2];

@@ -61,6 +61,10 @@ class Workload:
     pml_kappa_max: float = 1.0
     pml_alpha_max: float = 0.0
     eps_b: float = 1.0
+    # dielectric substrate: the half-space z > sub_k (node planes) has relative
+    # permittivity eps_sub (0: none)
+    eps_sub: float = 0.0
+    sub_k: int = 0
     tf_lo: Tuple[int, int, int] = (0, 0, 0)
     tf_hi: Tuple[int, int, int] = (0, 0, 0)
     # material

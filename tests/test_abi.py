@@ -66,6 +66,12 @@ def test_create_rejects_bad_sizes_and_boxes(lib):
     g = _grid(w)
     g.tf_lo[0] = w.npml  # TF box touching the CPML
     assert _create(lib, g)[0] == 1
+    # substrate: negative permittivity or a plane outside the grid
+    assert _create(lib, _grid(w, eps_substrate=-1.0))[0] == 1
+    assert _create(lib, _grid(w, eps_substrate=2.25, substrate_k=w.nz))[0] == 1
+    st, h = _create(lib, _grid(w, eps_substrate=2.25, substrate_k=w.nz - 1))
+    assert st == 0
+    lib.gnor_destroy(h)
 
 
 def test_material_outside_tf_rejected_and_run_before_bind(lib):
