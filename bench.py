@@ -122,6 +122,9 @@ def main():
                     help="steps of the same sphere with two critical points (0 = skip)")
     ap.add_argument("--maps-steps", type=int, default=512,
                     help="steps of the same sphere with near-field and density maps (0 = skip)")
+    ap.add_argument("--substrate-steps", type=int, default=512,
+                    help="steps of the same sphere in an n = 1.3 background on an eps 2.25 substrate "
+                         "(0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=256,
                     help="steps of the 64-instance batched sweep (0 = skip)")
     ap.add_argument("--tiling", type=str, default=None,
@@ -252,6 +255,22 @@ def main():
             "overhead_ms_per_step": round(dtm / args.maps_steps * 1e3 - ms_step, 5),
             "peak_density_m3s": float(np.abs(mp["n"]).max())}
         del simm
+        torch.cuda.empty_cache()
+    if args.substrate_steps > 0:
+        # the same sphere in an n = 1.3 background, resting on an eps 2.25
+        # half-space that starts right above its top metal plane
+        from dataclasses import replace
+        ws_ = replace(w, eps_b=1.69, eps_sub=2.25,
+                      sub_k=int(round((w.spheres[0, 2] + w.spheres[0, 3]) / w.dx)) + 1)
+        tl = out["tiling"]
+        sims_, dts = run_gpu(ws_, "fp32", args.substrate_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]))
+        out["substrate"] = {
+            "workload": "the same sphere in an n = 1.3 background on an eps 2.25 substrate (plane "
+                        f"{ws_.sub_k}), FP32",
+            "steps": args.substrate_steps,
+            "value": round(ws_.cells * args.substrate_steps / dts / 1e9, 3), "unit": "Gcell-updates/s",
+            "ms_per_step": round(dts / args.substrate_steps * 1e3, 5)}
+        del sims_
         torch.cuda.empty_cache()
     if args.batch_steps > 0:
         from paper_2005_06997_amd import binding
