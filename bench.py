@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--substrate-steps", type=int, default=512,
                     help="steps of the same sphere in an n = 1.3 background on an eps 2.25 substrate "
                          "(0 = skip)")
+    ap.add_argument("--star-steps", type=int, default=256,
+                    help="steps of the 640^3 star particle (FP32, 100 frequencies, flux boxes; 0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=256,
                     help="steps of the 64-instance batched sweep (0 = skip)")
     ap.add_argument("--tiling", type=str, default=None,
@@ -271,6 +273,21 @@ def main():
             "value": round(ws_.cells * args.substrate_steps / dts / 1e9, 3), "unit": "Gcell-updates/s",
             "ms_per_step": round(dts / args.substrate_steps * 1e3, 5)}
         del sims_
+        torch.cuda.empty_cache()
+    if args.star_steps > 0:
+        # the star particle: R = 15 nm sphere with six capped cones, 640^3 at
+        # 0.2 nm, 12-cell CPML (run at the sphere's tiling)
+        wst = W.config3(seed=0)
+        tl = out["tiling"]
+        simst, dtst = run_gpu(wst, "fp32", args.star_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]))
+        out["star"] = {
+            "workload": "640^3 star particle (sphere R 15 nm + 6 cones), dx 0.2 nm, 12-cell CPML, "
+                        "100 frequencies with flux boxes, FP32",
+            "steps": args.star_steps,
+            "value": round(wst.cells * args.star_steps / dtst / 1e9, 3), "unit": "Gcell-updates/s",
+            "ms_per_step": round(dtst / args.star_steps * 1e3, 5)}
+        simst.close()
+        del simst
         torch.cuda.empty_cache()
     if args.batch_steps > 0:
         from paper_2005_06997_amd import binding
