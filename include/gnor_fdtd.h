@@ -325,7 +325,8 @@ gnor_status gnor_gradient(gnor_sim *sim, int64_t nsteps, int32_t ckpt_every, int
 
 /* Batches: n independent simulations (bound, same precision, same step
  * index, same tile height) stepped in lockstep; every phase of a step is one
- * launch over the tiles of all instances.  The batch enqueues on hip_stream
+ * launch per tile class over the tiles of all instances (and one launch
+ * advances every instance's incident line).  The batch enqueues on hip_stream
  * (NULL: a stream of its own); call gnor_batch_synchronize before reading an
  * instance.  Instances must not be stepped outside the batch while it is in
  * use (GNOR_E_STATE).  The library allocates the batch's small parameter

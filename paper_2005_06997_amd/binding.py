@@ -396,7 +396,7 @@ class Batch:
     """Independent simulations stepped in lockstep; each phase of a step is one
     launch over the tiles of every instance (see gnor_batch_create)."""
 
-    def __init__(self, sims, tiling=(2, 8, 0), graph_chunk: int = 64):
+    def __init__(self, sims, tiling=(2, 5, 2), graph_chunk: int = 64):
         L = load()
         self.L = L
         self.sims = list(sims)

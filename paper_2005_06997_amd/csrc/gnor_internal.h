@@ -39,6 +39,7 @@ constexpr int kAuxSrc = 22;
 constexpr int kBX = 64;
 constexpr int kMaxCP = 4;        // critical points per material
 constexpr int kFluxSlots = 256;  // flux staging depth (steps per accumulation)
+constexpr int kAuxThreads = 256;  // threads of a batch's auxiliary-line block
 // Field stores of a sweep go nontemporal when its field traffic (9 words per
 // cell) exceeds this: larger sweeps cycle the 256 MB Infinity Cache anyway,
 // and keeping their one-shot outputs out of it leaves it to the re-read halo
@@ -283,8 +284,12 @@ template <class T>
 void launch_h_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int c, bool nt,
                           hipStream_t s);
 template <class T>
-void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, int c, bool cp,
-                           bool nt, hipStream_t s);
+void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int c, bool cp, bool nt,
+                           hipStream_t s);
+// the auxiliary lines' E update of every instance (one block each), step sub
+// of the chunk: after the H sweep, before the spectra
+template <class T>
+void launch_aux_e_batch(const BatchEntry<T>* e, int n, int sub, hipStream_t s);
 template <class T>
 void launch_dft_batch(const BatchEntry<T>* e, int n, int blocks, int sub, hipStream_t s);
 template <class T>

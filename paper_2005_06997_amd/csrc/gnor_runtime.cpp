@@ -1621,9 +1621,12 @@ gnor_status batch_tables(gnor_batch* b) {
       e.d = make_dft(s);
       e.f = make_flux(s);
       for (int c = 0; c < gnor::kClasses; ++c) {
-        e.blk0[c] = h0[c];
+        // XCD-aware tile orders: the instance's first chunk goes to XCD q % 8
+        // (its tiles keep their grouping by XCD under any start; the rotation
+        // spreads the partly filled chunks of small instances over the XCDs)
+        e.blk0[c] = e.p.tl.xcd != 0 ? (h0[c] + 7) / 8 * 8 + q % 8 : h0[c];
         e.nblk[c] = gnor::class_blocks(e.p.tl, c) + (c == 0 ? 1 : 0);  // + auxiliary block
-        h0[c] += e.nblk[c];
+        h0[c] = e.blk0[c] + e.nblk[c];
       }
       e.dblk0 = d0;
       e.dnblk = s->mon.nfreq > 0 ? gnor::dft_blocks(e.d, e.f) : 0;
@@ -1661,8 +1664,9 @@ void batch_enqueue(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st) {
       gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
     });
     classes([&](int c, hipStream_t q2) {
-      gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, sub, c, b->any_cp,
-                                     b->stream_stores, q2);
+      gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->any_cp, b->stream_stores, q2);
+      // the lines' E beside the sweep, after the short metal class
+      if (c == 2) gnor::launch_aux_e_batch<T>(t, b->n, sub, q2);
     });
     if (b->any_dft && b->dblocks > 0) gnor::launch_dft_batch<T>(t, b->n, b->dblocks, sub, st);
     if (b->any_flux && (n % gnor::kFluxSlots) == gnor::kFluxSlots - 1)

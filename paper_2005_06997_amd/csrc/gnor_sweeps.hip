@@ -503,6 +503,8 @@ __global__ void __launch_bounds__(kBX* TY) k_ej(Params<T> p, AuxParams a, int su
 // Batch: the blocks of all instances in one launch per class.  Instance q
 // owns blocks [blk0[c], blk0[c] + nblk[c]) of class c (for class 0 its tiles,
 // then its auxiliary-line block); a block finds its instance by binary search.
+// With an XCD-aware tile order the ranges are spaced so that instance q's
+// first chunk runs on XCD q % 8; the blocks between the ranges exit at once.
 template <class T>
 __device__ __forceinline__ int find_instance(const BatchEntry<T>* __restrict__ e, int n, int b,
                                              int c) {
@@ -519,6 +521,7 @@ template <class T, int TY, int CLS, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __restrict__ e, int n) {
   const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
   const int b = blockIdx.x - en.blk0[CLS];
+  if (b >= en.nblk[CLS]) return;
   if (CLS == 0 && b == en.nblk[0] - 1) {
     aux_h_block(en.a, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
@@ -526,16 +529,24 @@ __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __rest
   h_class<T, TY, CLS, NT>(en.p, b);
 }
 
+// Class 0's last block of each instance is idle in the E/J sweep: the lines'
+// E update is k_aux_e_batch.
 template <class T, int TY, int CLS, bool CP, bool NT>
-__global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __restrict__ e, int n,
-                                                      int sub) {
+__global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __restrict__ e, int n) {
   const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
   const int b = blockIdx.x - en.blk0[CLS];
-  if (CLS == 0 && b == en.nblk[0] - 1) {
-    aux_e_block(en.a, sub, threadIdx.y * kBX + threadIdx.x, kBX * TY);
-    return;
-  }
+  if (b >= en.nblk[CLS] || (CLS == 0 && b == en.nblk[0] - 1)) return;
   ej_class<T, TY, CLS, CP, NT>(en.p, b);
+}
+
+// The auxiliary lines' E update of a batch, one block per instance.  A kernel
+// of its own rather than a block of the class-0 sweep (as for one
+// simulation): there its FP64 source and phase evaluation, reached through
+// the instance table, doubled the sweep kernel's registers and halved its
+// occupancy.
+template <class T>
+__global__ void __launch_bounds__(kAuxThreads) k_aux_e_batch(const BatchEntry<T>* __restrict__ e, int sub) {
+  aux_e_block(e[blockIdx.x].a, sub, threadIdx.x, kAuxThreads);
 }
 
 }  // namespace
@@ -645,16 +656,16 @@ void launch_h_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, bool 
   else launch_h_batch_cls_nt<T, CLS, false>(e, n, blocks, ty, s);
 }
 template <class T, int CLS, bool CP, bool NT>
-void launch_ej_batch_cls_nt(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, hipStream_t s) {
-  if (ty == 4) hipLaunchKernelGGL((k_ej_batch<T, 4, CLS, CP, NT>), dim3(blocks), dim3(kBX, 4), 0, s, e, n, sub);
-  else if (ty == 8) hipLaunchKernelGGL((k_ej_batch<T, 8, CLS, CP, NT>), dim3(blocks), dim3(kBX, 8), 0, s, e, n, sub);
-  else hipLaunchKernelGGL((k_ej_batch<T, 2, CLS, CP, NT>), dim3(blocks), dim3(kBX, 2), 0, s, e, n, sub);
+void launch_ej_batch_cls_nt(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s) {
+  if (ty == 4) hipLaunchKernelGGL((k_ej_batch<T, 4, CLS, CP, NT>), dim3(blocks), dim3(kBX, 4), 0, s, e, n);
+  else if (ty == 8) hipLaunchKernelGGL((k_ej_batch<T, 8, CLS, CP, NT>), dim3(blocks), dim3(kBX, 8), 0, s, e, n);
+  else hipLaunchKernelGGL((k_ej_batch<T, 2, CLS, CP, NT>), dim3(blocks), dim3(kBX, 2), 0, s, e, n);
 }
 template <class T, int CLS, bool CP>
-void launch_ej_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, bool nt, hipStream_t s) {
+void launch_ej_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, bool nt, hipStream_t s) {
   if (blocks == 0) return;
-  if (nt) launch_ej_batch_cls_nt<T, CLS, CP, true>(e, n, blocks, ty, sub, s);
-  else launch_ej_batch_cls_nt<T, CLS, CP, false>(e, n, blocks, ty, sub, s);
+  if (nt) launch_ej_batch_cls_nt<T, CLS, CP, true>(e, n, blocks, ty, s);
+  else launch_ej_batch_cls_nt<T, CLS, CP, false>(e, n, blocks, ty, s);
 }
 }  // namespace
 
@@ -694,21 +705,27 @@ void launch_h_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int
   else launch_h_batch_cls<T, 3>(e, n, blocks, ty, nt, s);
 }
 template <class T>
-void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int sub, int c, bool cp,
-                           bool nt, hipStream_t s) {
-  if (c == 0) launch_ej_batch_cls<T, 0, false>(e, n, blocks, ty, sub, nt, s);
-  else if (c == 1) launch_ej_batch_cls<T, 1, false>(e, n, blocks, ty, sub, nt, s);
-  else if (c == 2) cp ? launch_ej_batch_cls<T, 2, true>(e, n, blocks, ty, sub, nt, s)
-                      : launch_ej_batch_cls<T, 2, false>(e, n, blocks, ty, sub, nt, s);
-  else cp ? launch_ej_batch_cls<T, 3, true>(e, n, blocks, ty, sub, nt, s)
-          : launch_ej_batch_cls<T, 3, false>(e, n, blocks, ty, sub, nt, s);
+void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int c, bool cp, bool nt,
+                           hipStream_t s) {
+  if (c == 0) launch_ej_batch_cls<T, 0, false>(e, n, blocks, ty, nt, s);
+  else if (c == 1) launch_ej_batch_cls<T, 1, false>(e, n, blocks, ty, nt, s);
+  else if (c == 2) cp ? launch_ej_batch_cls<T, 2, true>(e, n, blocks, ty, nt, s)
+                      : launch_ej_batch_cls<T, 2, false>(e, n, blocks, ty, nt, s);
+  else cp ? launch_ej_batch_cls<T, 3, true>(e, n, blocks, ty, nt, s)
+          : launch_ej_batch_cls<T, 3, false>(e, n, blocks, ty, nt, s);
+}
+template <class T>
+void launch_aux_e_batch(const BatchEntry<T>* e, int n, int sub, hipStream_t s) {
+  hipLaunchKernelGGL((k_aux_e_batch<T>), dim3(n), dim3(kAuxThreads), 0, s, e, sub);
 }
 template void launch_h_batch_class<float>(const BatchEntry<float>*, int, int, int, int, bool, hipStream_t);
 template void launch_h_batch_class<double>(const BatchEntry<double>*, int, int, int, int, bool, hipStream_t);
-template void launch_ej_batch_class<float>(const BatchEntry<float>*, int, int, int, int, int, bool, bool,
+template void launch_ej_batch_class<float>(const BatchEntry<float>*, int, int, int, int, bool, bool,
                                            hipStream_t);
-template void launch_ej_batch_class<double>(const BatchEntry<double>*, int, int, int, int, int, bool, bool,
+template void launch_ej_batch_class<double>(const BatchEntry<double>*, int, int, int, int, bool, bool,
                                             hipStream_t);
+template void launch_aux_e_batch<float>(const BatchEntry<float>*, int, int, hipStream_t);
+template void launch_aux_e_batch<double>(const BatchEntry<double>*, int, int, hipStream_t);
 template void launch_h<float>(const Params<float>&, const AuxParams&, hipStream_t);
 template void launch_h<double>(const Params<double>&, const AuxParams&, hipStream_t);
 template void launch_ej<float>(const Params<float>&, const AuxParams&, int, hipStream_t);

@@ -3,8 +3,11 @@ report: average duration per kernel (kernel trace) and HBM bytes per dispatch
 (FETCH_SIZE and WRITE_SIZE counter runs), the latter scaled by what the same
 counters read for a plain device copy of known size.
 
-usage: python -m paper_2005_06997_amd.rocprof_summary TRACE_DIR FETCH_DIR WRITE_DIR
-           COPY_FETCH_DIR COPY_WRITE_DIR COPY_BYTES OUT.md "command 1" ["command 2" ...]
+usage: python -m paper_2005_06997_amd.rocprof_summary [--only=K1,K2,...] TRACE_DIR FETCH_DIR
+           WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR COPY_BYTES OUT.md "command 1" ["command 2" ...]
+
+--only keeps the kernels whose name (template arguments dropped) is listed,
+e.g. the batched kernels of a run that also steps single simulations.
 """
 from __future__ import annotations
 
@@ -16,6 +19,16 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+# kernel families launched once per tile class, the classes of one sweep
+# back to back (or concurrently)
+SWEEPS = ("k_h", "k_ej", "k_step", "k_h_batch", "k_ej_batch")
+# kernels launched inside a sweep's fork/join, counted with that sweep
+MEMBER_OF = {"k_aux_e_batch": "k_ej_batch"}
+
+
+def family(kernel: str) -> str:
+    base = kernel.split("<")[0]
+    return MEMBER_OF.get(base, base)
 
 
 def _csv(d, suffix):
@@ -41,17 +54,17 @@ def counters(d):
 
 
 def sweep_spans(trace_dir):
-    """Per sweep family (k_h, k_ej, k_step): number of sweeps and the mean span
+    """Per sweep family (SWEEPS): number of sweeps and the mean span
     (us) from the first start to the last end of each run of that family's
     class launches, with the dispatches of the whole run in start order."""
     rows = _csv(trace_dir, "kernel_trace.csv")
-    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(r["Kernel_Name"]).split("<")[0])
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), family(short(r["Kernel_Name"])))
                 for r in rows)
     out = defaultdict(list)
     cur, lo, hi = None, 0, 0
     for st, en, base in ev + [(0, 0, None)]:
         if base != cur:
-            if cur in ("k_h", "k_ej", "k_step"):
+            if cur in SWEEPS:
                 out[cur].append((hi - lo) / 1e3)
             cur, lo, hi = base, st, en
         else:
@@ -67,16 +80,23 @@ def source_hash() -> str:
 
 
 def main(argv):
+    only = None
+    if argv and argv[0].startswith("--only="):
+        only = set(argv[0][len("--only="):].split(","))
+        argv = argv[1:]
     trace, fetch, write, cfetch, cwrite, copy_bytes, out = argv[:7]
     cmds = argv[7:]
     copy_bytes = float(copy_bytes)
     stats = _csv(trace, "kernel_stats.csv")
+    if only is not None:
+        stats = [r for r in stats if short(r["Name"]).split("<")[0] in only]
     f, w = counters(fetch), counters(write)
     cf, cw = counters(cfetch), counters(cwrite)
     ckey = max(cf, key=lambda k: sum(cf[k]))
     f_scale = copy_bytes / (sum(cf[ckey]) / len(cf[ckey]) * 1024.0)
     w_scale = copy_bytes / (sum(cw[ckey]) / len(cw[ckey]) * 1024.0)
-    lines = ["# rocprofv3 summary: GNOR-FDTD step kernels", "",
+    title = "GNOR-FDTD step kernels" if only is None else "GNOR-FDTD kernels " + ", ".join(sorted(only))
+    lines = ["# rocprofv3 summary: " + title, "",
              f"library source hash (csrc/*): `{source_hash()}`", "", "Commands (repository root):", ""]
     lines += [f"    {c}" for c in cmds]
     lines += ["", f"Copy calibration ({copy_bytes / 2**30:.0f} GiB device copy): FETCH_SIZE scale "
@@ -91,8 +111,8 @@ def main(argv):
         wm = sum(w[k]) / len(w[k]) * 1024 * w_scale / 1e6 if k in w else float("nan")
         bw = (fm + wm) * 1e6 / (avg * 1e-9) / 1e9 if avg > 0 else float("nan")
         lines.append(f"| {k} | {r['Calls']} | {avg / 1e3:.1f} | {fm:.1f} | {wm:.1f} | {bw:.0f} |")
-        base = k.split("<")[0]
-        if base in ("k_h", "k_ej", "k_step"):
+        base = family(k)
+        if base in SWEEPS:
             e = fam[base]
             e[0] += avg / 1e3
             e[1] += fm
@@ -100,7 +120,9 @@ def main(argv):
     spans = sweep_spans(trace)
     lines += ["", "Sweeps (one launch per tile class, the classes of a sweep running concurrently).",
               "Span = first start to last end of a sweep's class launches, averaged over the sweeps;",
-              "bytes = per-dispatch counters summed over the classes (each runs once per sweep):", "",
+              "bytes = per-dispatch counters summed over the classes (each runs once per sweep)",
+              "and over the kernels launched inside the sweep (" +
+              ", ".join(f"{k} in {v}" for k, v in MEMBER_OF.items()) + "):", "",
               "| sweep | sweeps | avg span us | FETCH MB | WRITE MB | HBM GB/s over the span |",
               "|---|---|---|---|---|---|"]
     for base, (us, fm, wm) in sorted(fam.items()):

@@ -29,15 +29,18 @@ def instances(count=5, seed=0):
     return ws
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_batch_equals_individual_runs_bitwise(B, prec):
+@pytest.mark.parametrize("prec,tiling", [("fp32", (2, 8, 0)), ("fp64", (2, 8, 0)),
+                                         ("fp32", (2, 3, 2)), ("fp32", (4, 4, 1))])
+def test_batch_equals_individual_runs_bitwise(B, prec, tiling):
+    """Also with the XCD-aware tile orders 1 and 2, under which the
+    instances' block ranges are spaced apart by idle blocks."""
     ws = instances()
-    print(f"case batch {prec}: sizes {[w.nx for w in ws]}", flush=True)
+    print(f"case batch {prec} tiling {tiling}: sizes {[w.nx for w in ws]}", flush=True)
     steps = 131  # odd: eager steps around graph chunks
     solo, fused = [], []
     for w in ws:
         s = B.Sim(w, precision=prec)
-        s.set_tiling(2, 8, 0)
+        s.set_tiling(*tiling)
         s.set_fused(False)  # batches run the two-sweep kernels
         s.run(steps)
         solo.append(({f: s.field(f) for f in FIELDS}, s.spectra()))
@@ -48,7 +51,7 @@ def test_batch_equals_individual_runs_bitwise(B, prec):
         fused.append(s.spectra())
         s.close()
     sims = [B.Sim(w, precision=prec) for w in ws]
-    bt = B.Batch(sims, tiling=(2, 8, 0))
+    bt = B.Batch(sims, tiling=tiling)
     bt.run(steps)
     bt.synchronize()
     for (fields, spec), s in zip(solo, sims):
