@@ -128,3 +128,34 @@ def test_batch_rejects_mixed_precision_and_foreign_steps(B):
     a.run(2)  # stepped outside the batch
     with pytest.raises(B.GnorError):
         bt.run(2)
+
+
+def test_batch_mixes_substrate_and_background_bitwise(B):
+    """Instances that differ in their dielectric surroundings (one resting on
+    an eps 2.25 half-space whose plane lies just above its particle, one in
+    an n = 1.3 background, one in vacuum) batch together and reproduce their
+    single runs bit for bit, once the pulse has crossed the substrate plane."""
+    ws = instances(count=3, seed=1)
+    top = int(np.nonzero(oracle_mask(ws[0]).any(axis=(1, 2)))[0].max())
+    ws[0].eps_sub, ws[0].sub_k = 2.25, top + 1
+    ws[1].eps_b = 1.69
+    steps = 300
+    print(f"case mixed batch: sizes {[w.nx for w in ws]}, substrate plane {ws[0].sub_k}", flush=True)
+    solo = []
+    for w in ws:
+        s = B.Sim(w, precision="fp32")
+        s.set_tiling(2, 5, 2)
+        s.run(steps)
+        solo.append(({f: s.field(f) for f in FIELDS}, s.spectra()))
+        s.close()
+    sims = [B.Sim(w, precision="fp32") for w in ws]
+    bt = B.Batch(sims, tiling=(2, 5, 2))
+    bt.run(steps)
+    bt.synchronize()
+    for (fields, spec), s in zip(solo, sims):
+        for f in FIELDS:
+            assert np.array_equal(s.field(f), fields[f]), (s.w.name, f)
+        for k, v in s.spectra().items():
+            assert np.array_equal(v, spec[k]), (s.w.name, k)
+    assert np.abs(solo[0][0]["Ex"][ws[0].sub_k + 1:]).max() > 0  # the pulse reached the substrate
+    assert np.abs(solo[0][0]["Jx"]).max() > 0
