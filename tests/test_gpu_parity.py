@@ -278,6 +278,35 @@ def test_graph_replay_equals_eager_bitwise(B):
         assert np.array_equal(sa[k], sb[k]), k
 
 
+def test_serial_classes_profiled_steps_and_reset_are_bitwise_neutral(B):
+    """The tile classes of a sweep update disjoint tiles: launching them one
+    after another instead of concurrently on their streams, stepping through
+    the profiler (events around every sweep) and rerunning after gnor_reset
+    change no bit of the fields or spectra."""
+    w = W.early_pulse(W.config1(1))
+    w.omega = W.spectrum_omegas(16)
+    steps = w.steps
+    say(f"case serial classes, profiled steps and reset vs concurrent classes, {steps} steps")
+    ref = B.Sim(w, precision="fp32")
+    ref.run(steps)
+    want = ({f: ref.field(f) for f in FIELDS}, ref.spectra())
+    ser = B.Sim(w, precision="fp32")
+    ser.set_class_streams(False)
+    ser.run(steps)
+    pro = B.Sim(w, precision="fp32")
+    pr = pro.profile(steps)
+    assert pro.step == steps and pr["h"] > 0
+    ref.reset()
+    assert ref.step == 0
+    ref.run(steps)
+    for name, s in (("serial", ser), ("profiled", pro), ("reset", ref)):
+        for f in FIELDS:
+            assert np.array_equal(s.field(f), want[0][f]), (name, f)
+        for k, v in s.spectra().items():
+            assert np.array_equal(v, want[1][k]), (name, k)
+    assert np.abs(want[0]["Jx"]).max() > 0
+
+
 def test_resume_from_snapshot_is_bitwise(B):
     w = W.early_pulse(W.config1(3))
     say("case save/load state resume")
