@@ -30,15 +30,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "step_kernels_sphere320_fp32.md")
+PROFILE_SUMMARY_FP64 = os.path.join(ROOT, "profiles", "step_kernels_sphere320_fp64.md")
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, summary=PROFILE_SUMMARY):
     """HBM bytes per sweep of `kernel` (sum over its tile-class launches) from
-    the rocprofv3 counter summary, or None if the summary is missing or was
+    a rocprofv3 counter summary, or None if the summary is missing or was
     taken on other kernel sources."""
     try:
         from paper_2005_06997_amd.rocprof_summary import source_hash
-        text = open(PROFILE_SUMMARY).read()
+        text = open(summary).read()
     except (OSError, ImportError):
         return None
     import re
@@ -206,12 +207,14 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_fp64:
         steps64 = max(2, args.steps // 2)
-        sim64, dt64 = run_gpu(w, "fp64", steps64, args.warmup)
+        sim64, dt64 = run_gpu(w, "fp64", steps64, args.warmup, tiling, args.serial_classes)
         v64 = w.cells * steps64 / dt64 / 1e9
         prof64 = sim64.profile(max(2, args.profile_steps // 2))
         _, ejb64, _, _ = algorithmic_bytes(w, sim64.mask, 8)
         out["fp64"] = {"value": round(v64, 3), "ms_per_step": round(dt64 / steps64 * 1e3, 5),
                        "roofline_frac": round(ejb64 / (prof64["ej"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "traffic": measured_traffic("k_ej", PROFILE_SUMMARY_FP64),
+                       "tiling": {k: sim64.tiling[k] for k in ("ty", "kz", "xcd")},
                        "fp32_speedup": round(value / v64, 3)}
         # FP32 and FP64 runs of equal length, compared spectrum by spectrum
         sim64.reset()

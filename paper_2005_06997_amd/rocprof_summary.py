@@ -8,6 +8,8 @@ usage: python -m paper_2005_06997_amd.rocprof_summary [--only=K1,K2,...] TRACE_D
 
 --only keeps the kernels whose name (template arguments dropped) is listed,
 e.g. the batched kernels of a run that also steps single simulations.
+--type=T keeps the kernels whose first template argument is T (float or
+double), e.g. the FP64 sweeps of a run that also steps in FP32.
 """
 from __future__ import annotations
 
@@ -29,6 +31,15 @@ MEMBER_OF = {"k_aux_e_batch": "k_ej_batch"}
 def family(kernel: str) -> str:
     base = kernel.split("<")[0]
     return MEMBER_OF.get(base, base)
+
+
+def of_type(kernel: str, typ) -> bool:
+    """True when typ is None or the kernel's first template argument is typ."""
+    if typ is None:
+        return True
+    if "<" not in kernel:
+        return False
+    return kernel.split("<", 1)[1].split(",")[0].rstrip(">").strip() == typ
 
 
 def _csv(d, suffix):
@@ -53,13 +64,13 @@ def counters(d):
     return out
 
 
-def sweep_spans(trace_dir):
+def sweep_spans(trace_dir, typ=None):
     """Per sweep family (SWEEPS): number of sweeps and the mean span
     (us) from the first start to the last end of each run of that family's
     class launches, with the dispatches of the whole run in start order."""
     rows = _csv(trace_dir, "kernel_trace.csv")
     ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), family(short(r["Kernel_Name"])))
-                for r in rows)
+                for r in rows if of_type(short(r["Kernel_Name"]), typ))
     out = defaultdict(list)
     cur, lo, hi = None, 0, 0
     for st, en, base in ev + [(0, 0, None)]:
@@ -80,9 +91,15 @@ def source_hash() -> str:
 
 
 def main(argv):
-    only = None
-    if argv and argv[0].startswith("--only="):
-        only = set(argv[0][len("--only="):].split(","))
+    only, typ = None, None
+    while argv and argv[0].startswith("--"):
+        opt, _, val = argv[0].partition("=")
+        if opt == "--only":
+            only = set(val.split(","))
+        elif opt == "--type":
+            typ = val
+        else:
+            raise SystemExit(f"unknown option {argv[0]}")
         argv = argv[1:]
     trace, fetch, write, cfetch, cwrite, copy_bytes, out = argv[:7]
     cmds = argv[7:]
@@ -90,12 +107,15 @@ def main(argv):
     stats = _csv(trace, "kernel_stats.csv")
     if only is not None:
         stats = [r for r in stats if short(r["Name"]).split("<")[0] in only]
+    stats = [r for r in stats if of_type(short(r["Name"]), typ)]
     f, w = counters(fetch), counters(write)
     cf, cw = counters(cfetch), counters(cwrite)
     ckey = max(cf, key=lambda k: sum(cf[k]))
     f_scale = copy_bytes / (sum(cf[ckey]) / len(cf[ckey]) * 1024.0)
     w_scale = copy_bytes / (sum(cw[ckey]) / len(cw[ckey]) * 1024.0)
     title = "GNOR-FDTD step kernels" if only is None else "GNOR-FDTD kernels " + ", ".join(sorted(only))
+    if typ is not None:
+        title += f" ({typ})"
     lines = ["# rocprofv3 summary: " + title, "",
              f"library source hash (csrc/*): `{source_hash()}`", "", "Commands (repository root):", ""]
     lines += [f"    {c}" for c in cmds]
@@ -117,7 +137,7 @@ def main(argv):
             e[0] += avg / 1e3
             e[1] += fm
             e[2] += wm
-    spans = sweep_spans(trace)
+    spans = sweep_spans(trace, typ)
     lines += ["", "Sweeps (one launch per tile class, the classes of a sweep running concurrently).",
               "Span = first start to last end of a sweep's class launches, averaged over the sweeps;",
               "bytes = per-dispatch counters summed over the classes (each runs once per sweep)",
