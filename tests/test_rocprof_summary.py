@@ -1,0 +1,92 @@
+"""Host logic of the rocprofv3 summary (CPU only): sweep spans over concurrent
+class launches, kernels counted with the sweep they run inside, the
+element-type filter, and the counter scaling by a copy of known size.  The
+inputs are small CSV files in rocprofv3's column layout with values chosen
+so that every expected figure is worked out by hand below."""
+import csv
+import os
+
+from paper_2005_06997_amd import rocprof_summary as R
+
+
+def write_csv(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def trace(d, events):
+    write_csv(os.path.join(d, "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+              events)
+
+
+def counters(d, rows):
+    write_csv(os.path.join(d, "run_counter_collection.csv"), ["Kernel_Name", "Counter_Value"], rows)
+
+
+def test_family_and_type_filter():
+    assert R.family("k_aux_e_batch<float>") == "k_ej_batch"
+    assert R.family("k_h<float, 2, 0, true>") == "k_h"
+    assert R.of_type("k_h<double, 2, 0, true>", "double")
+    assert not R.of_type("k_h<float, 2, 0, true>", "double")
+    assert R.of_type("k_dft<double>", "double")
+    assert not R.of_type("k_flux_acc", "double")
+    assert R.of_type("k_flux_acc", None)
+
+
+def test_sweep_spans_group_concurrent_classes(tmp_path):
+    """Two batched H sweeps (classes overlapping in time), each followed by a
+    batched E/J sweep whose line kernel starts between its class launches;
+    an FP64 launch in between is dropped by the type filter.  Spans: H
+    (0..300) and (1000..1250) -> mean 275 ns = 0.275 us; E/J (400..900) and
+    (1300..1700) -> 0.45 us, the line kernel counted inside its sweep."""
+    d = str(tmp_path / "t")
+    ns = "void gnor::(anonymous namespace)::"
+    ev = [
+        (ns + "k_h_batch<float, 2, 0, true>(...)", 0, 200),
+        (ns + "k_h_batch<float, 2, 1, true>(...)", 50, 300),
+        (ns + "k_ej_batch<float, 2, 0, false, true>(...)", 400, 800),
+        (ns + "k_aux_e_batch<float>(...)", 410, 500),
+        (ns + "k_ej_batch<float, 2, 1, false, true>(...)", 420, 900),
+        (ns + "k_h<double, 2, 0, true>(...)", 950, 990),
+        (ns + "k_h_batch<float, 2, 0, true>(...)", 1000, 1250),
+        (ns + "k_ej_batch<float, 2, 0, false, true>(...)", 1300, 1700),
+    ]
+    trace(d, ev)
+    spans = R.sweep_spans(d, "float")
+    assert spans["k_h_batch"][0] == 2 and abs(spans["k_h_batch"][1] - 0.275) < 1e-12
+    assert spans["k_ej_batch"][0] == 2 and abs(spans["k_ej_batch"][1] - 0.45) < 1e-12
+    assert "k_aux_e_batch" not in spans and "k_h" not in spans
+    no_filter = R.sweep_spans(d)
+    assert no_filter["k_h"][0] == 1  # the FP64 launch forms a sweep of its own
+
+
+def test_summary_scales_counters_and_sums_classes(tmp_path):
+    """A copy of 2 GiB reads FETCH_SIZE 2 GiB / 2 and WRITE_SIZE 2 GiB in
+    KiB, so the scales are 2 and 1.  The H sweep's two classes read 100 and
+    50 KiB (scaled: 200 and 100 KiB = 0.2048 and 0.1024 MB) and write 10 and
+    5 KiB; its span is 1 us, so 0.3072 + 0.01536 MB in 1 us = 322.56 GB/s."""
+    base = str(tmp_path)
+    tr, fe, wr, cf, cw = (os.path.join(base, n) for n in ("trace", "fetch", "write", "cfetch", "cwrite"))
+    k0 = "void gnor::(anonymous namespace)::k_h<float, 2, 0, true>(...)"
+    k1 = "void gnor::(anonymous namespace)::k_h<float, 2, 1, true>(...)"
+    trace(tr, [(k0, 0, 800), (k1, 100, 1000)])
+    write_csv(os.path.join(tr, "run_kernel_stats.csv"), ["Name", "Calls", "AverageNs"],
+              [(k0, 1, 800), (k1, 1, 900)])
+    counters(fe, [(k0, 100.0), (k1, 50.0)])
+    counters(wr, [(k0, 10.0), (k1, 5.0)])
+    copy = "void at::native::copy_kernel(...)"
+    gib2 = 2.0 * 2 ** 30
+    counters(cf, [(copy, gib2 / 2 / 1024)])
+    counters(cw, [(copy, gib2 / 1024)])
+    out = os.path.join(base, "s.md")
+    R.main([tr, fe, wr, cf, cw, str(gib2), out, "cmd"])
+    text = open(out).read()
+    assert "FETCH_SIZE scale 2.0000, WRITE_SIZE scale 1.0000" in text
+    fetch_mb = (100 + 50) * 1024 * 2 / 1e6
+    write_mb = (10 + 5) * 1024 / 1e6
+    assert f"<!-- traffic k_h sweep {(fetch_mb + write_mb) * 1e6:.0f} -->" in text
+    assert "<!-- time k_h sweep 1.00 -->" in text
+    assert f"| {(fetch_mb + write_mb) * 1e6 / 1e-6 / 1e9:.0f} |" in text
