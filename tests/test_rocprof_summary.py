@@ -90,3 +90,19 @@ def test_summary_scales_counters_and_sums_classes(tmp_path):
     assert f"<!-- traffic k_h sweep {(fetch_mb + write_mb) * 1e6:.0f} -->" in text
     assert "<!-- time k_h sweep 1.00 -->" in text
     assert f"| {(fetch_mb + write_mb) * 1e6 / 1e-6 / 1e9:.0f} |" in text
+
+
+def test_bench_reads_traffic_only_for_the_current_sources(tmp_path):
+    """bench.py takes a sweep's measured bytes from a summary only while the
+    summary's source hash matches the kernel sources; otherwise, or without
+    a summary, the traffic is reported as null."""
+    import bench
+    f = tmp_path / "s.md"
+    f.write_text(f"library source hash (csrc/*): `{R.source_hash()}`\n"
+                 "<!-- traffic k_ej sweep 123456 -->\n<!-- traffic k_h sweep 654321 -->\n")
+    assert bench.measured_traffic("k_ej", str(f)) == 123456.0
+    assert bench.measured_traffic("k_h", str(f)) == 654321.0
+    assert bench.measured_traffic("k_ej_batch", str(f)) is None
+    f.write_text("library source hash (csrc/*): `0123456789abcdef`\n<!-- traffic k_ej sweep 123456 -->\n")
+    assert bench.measured_traffic("k_ej", str(f)) is None
+    assert bench.measured_traffic("k_ej", str(tmp_path / "missing.md")) is None
