@@ -14,6 +14,8 @@ too slow, properties that hold at any size and FP32-vs-FP64 agreement.
   FP32 vs FP64 spectra after a short early-pulse run.
 * 160^3 design problem: FP32 adjoint gradient vs central differences of the
   FP64 objective on random voxels.
+* 64-instance batch in the benchmark's launch configuration: sampled
+  instances equal their single runs bit for bit.
 """
 import numpy as np
 import pytest
@@ -195,3 +197,39 @@ def test_design160_fp32_gradient_vs_fd(B):
         errs.append(abs(fd - g[q]) / np.abs(g).max())
         print(f"  voxel {q}: adjoint(fp32) {g[q]:.6e} fd(fp64) {fd:.6e}", flush=True)
     assert max(errs) <= 2e-3
+
+
+def test_config4_batch_in_the_benchmark_launch(B):
+    """All 64 instances batched as the benchmark runs them (tiling (2, 5, 2),
+    graph chunks of 64, streaming stores chosen by the batch's total size),
+    with the pulse moved early so that it reaches every particle within the
+    run: the smallest and the largest instance, the first gap dimer and the
+    first single sphere equal their single runs bit for bit, and every
+    instance stays finite."""
+    fields = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "Jx", "Jy", "Jz")
+    ws = [W.early_pulse(w) for w in W.config4(seed=0, count=64)]
+    steps = 400
+    print(f"case config4 batch: {sum(w.cells for w in ws):.3e} cells, {steps} steps", flush=True)
+    sims = [B.Sim(w, precision="fp32") for w in ws]
+    bt = B.Batch(sims, tiling=(2, 5, 2))
+    bt.run(steps)
+    bt.synchronize()
+    assert all(s.check_finite() for s in sims)
+    q_small = min(range(len(ws)), key=lambda q: ws[q].cells)
+    q_large = max(range(len(ws)), key=lambda q: ws[q].cells)
+    q_dimer = next(q for q, w in enumerate(ws) if "dimer" in w.name)
+    q_sphere = next(q for q, w in enumerate(ws) if "sphere" in w.name)
+    for q in sorted({q_small, q_large, q_dimer, q_sphere}):
+        print(f"  instance {ws[q].name}", flush=True)
+        got = {f: sims[q].field(f) for f in fields}
+        spec = sims[q].spectra()
+        s = B.Sim(ws[q], precision="fp32")
+        s.set_tiling(2, 5, 2)
+        s.run(steps)
+        for f in fields:
+            assert np.array_equal(s.field(f), got[f]), (ws[q].name, f)
+        for k, v in s.spectra().items():
+            assert np.array_equal(v, spec[k]), (ws[q].name, k)
+        assert np.abs(got["Jx"]).max() > 0, ws[q].name
+        s.close()
+    bt.close()
