@@ -571,6 +571,8 @@ struct Sim {
       cE[m] = std::cos(omega[m] * tE); sE[m] = std::sin(omega[m] * tE);
     }
     const double e0d = eps0() * (c.eps_inf - c.eps_b);
+    // planes are independent (each plane's sum keeps its own fixed order)
+#pragma omp parallel for schedule(static) num_threads(c.threads > 0 ? c.threads : 1)
     for (int k = 0; k < nz; ++k) {
       // induced current J_x^{n+1/2} = (P^{n+1}-P^n)/dt, plus the bound parts
       // eps0 (eps_inf - eps_b) dE/dt and dP_CP,p/dt inside the metal, summed
@@ -650,6 +652,8 @@ struct Sim {
     const int nf = c.nfreq;
     const int nb = f.hib - f.lob, nc = f.hic - f.loc;
     // E_b at (p, j+1/2, k) and H_c averaged across the plane, same point
+    // (every sample point owns its accumulators: rows run in parallel)
+#pragma omp parallel for schedule(static) num_threads(c.threads > 0 ? c.threads : 1)
     for (int kk = 0; kk <= nc; ++kk)
       for (int jj = 0; jj < nb; ++jj) {
         const int jb = f.lob + jj, kc = f.loc + kk;
@@ -663,6 +667,7 @@ struct Sim {
         }
       }
     // E_c at (p, j, k+1/2) and H_b averaged across the plane
+#pragma omp parallel for schedule(static) num_threads(c.threads > 0 ? c.threads : 1)
     for (int kk = 0; kk < nc; ++kk)
       for (int jj = 0; jj <= nb; ++jj) {
         const int jb = f.lob + jj, kc = f.loc + kk;

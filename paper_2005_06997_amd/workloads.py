@@ -302,6 +302,13 @@ def config5_small(seed: int = 0) -> Workload:
                         precision="fp64")
 
 
+def design_direction(shape, seed: int) -> np.ndarray:
+    """A seeded direction in design-density space (standard normal entries,
+    shape (z, y, x)) along which a gradient is projected."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    return g.standard_normal(size=tuple(shape))
+
+
 def small_sphere(n: int = 32, dx: float = 0.25e-9, radius: float = 1.2e-9, npml: int = 4,
                  seed: int = 0, steps: int = 200, **kw) -> Workload:
     """Small test problem: one sphere near the grid centre (offset U(-0.5, 0.5) cell)."""
