@@ -8,12 +8,16 @@ gold-like sphere of radius 10 nm on a 320^3 grid at dx = 0.1 nm (12-cell
 CPML), FP32 fields and currents with FP64 spectral accumulators.
 
 Prints one JSON line:  value = Gcell-updates/s (nx ny nz steps / time) of the
-FP32 path; roofline = achieved algorithmic HBM bytes / s of the dominant
-kernel (the E/J sweep, one launch per tile class, timed as a whole) from HIP
-events on the library's stream; traffic = its measured HBM bytes per sweep
-from the committed rocprofv3 counter summary when that summary was taken on
-the current kernel sources (else null); cpu_baseline = the FP64 CPU oracle on
-the host cores on a short sample of the same grid.
+FP32 path over exactly --steps steps, the timed region holding every
+flux-box fold those steps owe (see run_gpu); roofline = achieved algorithmic
+HBM bytes / s of the dominant kernel (the E/J sweep, one launch per tile
+class, timed as a whole) from HIP events on the library's stream; traffic =
+its measured HBM bytes per sweep from the committed rocprofv3 counter summary
+when that summary was taken on the current kernel sources (else null); the
+FP32 path's spectral errors from fixed-length legs (against the FP64 path,
+and against the FP64 oracle on the coarsened copy); cpu_baseline = the FP64
+CPU oracle on the host cores (all of the GPU's share, and one) on short
+samples of the same grid.
 """
 from __future__ import annotations
 
@@ -69,6 +73,12 @@ def algorithmic_bytes(w, mask, word):
 
 
 def run_gpu(w, precision, steps, warmup, tiling=None, serial=False):
+    """Warm up, then time `steps` full steps.  The timed region holds every
+    flux-box fold its steps owe: the warm-up's staged samples are folded
+    before it starts, and it ends with the fold of the samples its own steps
+    staged since the last window fold (a partial window costs the whole
+    accumulator read-modify-write, so short runs are charged more per step
+    than long ones)."""
     import torch
     from paper_2005_06997_amd import binding
 
@@ -81,29 +91,91 @@ def run_gpu(w, precision, steps, warmup, tiling=None, serial=False):
         sim.set_tiling(*tiling)
         sim.tiling = dict(ty=tiling[0], kz=tiling[1], xcd=tiling[2], cached=False)
     sim.run(warmup)
+    sim.flush_spectra()
     sim.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.run(steps)
+    sim.flush_spectra()
     sim.synchronize()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return sim, dt
 
 
-def cpu_baseline(w, steps):
+def spectral_errors(a, b):
+    out = {}
+    for k in ("inc", "ext", "abs", "sca"):
+        den = np.linalg.norm(b[k])
+        out[k] = float(np.linalg.norm(a[k] - b[k]) / den) if den > 0 else None
+    return out
+
+
+def error_legs(tiling):
+    """Spectral errors of the FP32 path from runs of fixed length (independent
+    of --steps): FP32 vs FP64 on the 320^3 workload with the pulse moved early
+    (2400 steps: the pulse has crossed the particle), and FP32 vs the FP64
+    oracle's spectra of the 2x-coarsened copy over its full 10 000 steps
+    (stored in tests/golden by an oracle-only script)."""
+    import torch
+    from paper_2005_06997_amd import binding
+    from paper_2005_06997_amd import workloads as W
+
+    w = W.early_pulse(W.config2())
+    spec = {}
+    for prec in ("fp32", "fp64"):
+        s = binding.Sim(w, precision=prec)
+        s.set_tiling(*tiling)
+        s.run(2400)
+        spec[prec] = s.spectra()
+        s.close()
+        torch.cuda.empty_cache()
+    out = {"fp32_vs_fp64_spectra_rel_l2": spectral_errors(spec["fp32"], spec["fp64"]),
+           "fp32_vs_fp64_leg": "320^3 sphere, pulse peak at 1.2 tau, 2400 steps"}
+    path = os.path.join(ROOT, "tests", "golden", "config2_coarse_oracle_spectra.txt")
+    if os.path.exists(path):
+        rows = np.array([[float(v) for v in line.split()] for line in open(path)
+                         if line.strip() and not line.startswith("#")])
+        gold = dict(inc=rows[:, 1], ext=rows[:, 2], abs=rows[:, 3], sca=rows[:, 4])
+        wc = W.config2_coarse()
+        s = binding.Sim(wc, precision="fp32")
+        t0 = time.perf_counter()
+        s.run(wc.steps)
+        sp = s.spectra()
+        tc = time.perf_counter() - t0
+        s.close()
+        torch.cuda.empty_cache()
+        out["fp32_vs_oracle_coarse_spectra_rel_l2"] = spectral_errors(sp, gold)
+        out["fp32_vs_oracle_leg"] = ("160^3 coarsened copy (dx 0.2 nm, 10 000 steps) vs the FP64 "
+                                     f"oracle's spectra; GPU run {tc:.2f} s")
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, steps, threads):
+    """The FP64 oracle as it stands on `threads` host threads: Gcell-updates/s
+    over `steps` steps of the workload (after one untimed step that touches
+    every array)."""
     from oracle import oracle as orc
     from tests.helpers import oracle_mask, oracle_problem
 
-    threads = min(16, os.cpu_count() or 1)
     p = oracle_problem(w, threads=threads)
     s = orc.OracleSim(p, oracle_mask(w))
-    s.run(1)  # first-touch of the arrays
+    s.run(1)
     t0 = time.perf_counter()
     s.run(steps)
     dt = time.perf_counter() - t0
     s.close()
-    return w.cells * steps / dt / 1e9, threads, dt
+    return w.cells * steps / dt / 1e9, dt
 
 
 def main():
@@ -116,7 +188,10 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="oracle steps of the all-cores CPU sample (the 1-core sample takes 2)")
+    ap.add_argument("--no-error-legs", action="store_true",
+                    help="skip the fixed-length FP32 error legs")
     ap.add_argument("--adjoint-steps", type=int, default=6000,
                     help="steps of the design-gradient run (forward + adjoint; 0 = skip)")
     ap.add_argument("--cp-steps", type=int, default=512,
@@ -159,7 +234,6 @@ def main():
     sim, dt = run_gpu(w, "fp32", args.steps, args.warmup, tiling, args.serial_classes)
     value = w.cells * args.steps / dt / 1e9
     ms_step = dt / args.steps * 1e3
-    spec32 = sim.spectra()  # after warmup + steps, before profiling adds steps
     prof = sim.profile(args.profile_steps)  # each sweep timed as it runs (classes concurrent)
     classes = sim.tile_classes()
     sim.set_class_streams(False)
@@ -206,27 +280,21 @@ def main():
     del sim
     torch.cuda.empty_cache()
     if not args.no_fp64:
-        steps64 = max(2, args.steps // 2)
-        sim64, dt64 = run_gpu(w, "fp64", steps64, args.warmup, tiling, args.serial_classes)
-        v64 = w.cells * steps64 / dt64 / 1e9
+        # the same K steps in FP64 (same warm-up and fold accounting)
+        sim64, dt64 = run_gpu(w, "fp64", args.steps, args.warmup, tiling, args.serial_classes)
+        v64 = w.cells * args.steps / dt64 / 1e9
         prof64 = sim64.profile(max(2, args.profile_steps // 2))
         _, ejb64, _, _ = algorithmic_bytes(w, sim64.mask, 8)
-        out["fp64"] = {"value": round(v64, 3), "ms_per_step": round(dt64 / steps64 * 1e3, 5),
+        out["fp64"] = {"value": round(v64, 3), "ms_per_step": round(dt64 / args.steps * 1e3, 5),
                        "roofline_frac": round(ejb64 / (prof64["ej"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                        "traffic": measured_traffic("k_ej", PROFILE_SUMMARY_FP64),
                        "tiling": {k: sim64.tiling[k] for k in ("ty", "kz", "xcd")},
                        "fp32_speedup": round(value / v64, 3)}
-        # FP32 and FP64 runs of equal length, compared spectrum by spectrum
-        sim64.reset()
-        sim64.run(args.warmup + args.steps)
-        s64 = sim64.spectra()
-        err = {}
-        for k in ("ext", "abs", "sca"):
-            den = np.linalg.norm(s64[k])
-            err[k] = float(np.linalg.norm(spec32[k] - s64[k]) / den) if den > 0 else None
-        out["fp32_vs_fp64_spectra_rel_l2"] = err
         del sim64
         torch.cuda.empty_cache()
+    if not args.no_error_legs:
+        tl = out["tiling"]
+        out.update(error_legs((tl["ty"], tl["kz"], tl["xcd"])))
     if args.cp_steps > 0:
         # bound electrons: the same sphere with two critical points (f3); the
         # E/J sweep adds P_CP and its increment (read + write) per pole and
@@ -343,11 +411,17 @@ def main():
         sd.close()
         torch.cuda.empty_cache()
     if not args.no_cpu:
-        v, cores, secs = cpu_baseline(w, args.cpu_steps)
+        # all host threads of the GPU's share (at most 16), then one core
+        cores = min(16, os.cpu_count() or 1)
+        v, secs = cpu_baseline(w, args.cpu_steps, cores)
+        v1, secs1 = cpu_baseline(w, 2, 1)
         out["cpu_baseline"] = {"value": round(v, 5), "unit": "Gcell-updates/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"{args.cpu_steps} FP64 oracle steps of the same 320^3 problem "
-                                         f"({secs:.1f} s)"}
+                                         f"on {cores} threads ({secs:.1f} s)",
+                               "one_core": {"value": round(v1, 6), "unit": "Gcell-updates/s",
+                                            "sample": f"2 steps on 1 thread ({secs1:.1f} s)"},
+                               "cpu_model": cpu_model(), "nproc": os.cpu_count()}
     print(json.dumps(out), flush=True)
 
 

@@ -24,8 +24,11 @@
  *  - Ownership: the caller allocates ONE device buffer of
  *    gnor_required_bytes() bytes and a HIP stream and binds both with
  *    gnor_bind_memory(); the library carves all device state out of that
- *    buffer, never frees it, and enqueues all work on that stream.  Host
- *    inputs are copied before a call returns; outputs go to caller arrays.
+ *    buffer, never frees it, and enqueues all work on that stream.  The
+ *    gradient's workspace and a batch's parameter tables are further caller
+ *    buffers (gnor_gradient_required_bytes, gnor_batch_required_bytes): the
+ *    library allocates no device memory.  Host inputs are copied before a
+ *    call returns; outputs go to caller arrays.
  *  - Errors: every call returns a gnor_status; nothing is thrown across the
  *    ABI.  gnor_last_error() gives a message for the last failure on a sim.
  *  - Threads: one gnor_sim must not be used by two host threads at once.
@@ -161,9 +164,19 @@ gnor_status gnor_bind_memory(gnor_sim *sim, void *device_ptr, size_t bytes, void
 gnor_status gnor_reset(gnor_sim *sim);
 
 /* Enqueue nsteps leapfrog steps on the bound stream (asynchronous).  Steps
- * are replayed from captured HIP graphs in chunks (gnor_set_graph_chunk). */
+ * are replayed from captured HIP graphs in chunks (gnor_set_graph_chunk).
+ * Non-finite watchdog (on by default, gnor_set_watchdog): after every chunk
+ * of steps (the graph chunk; 64 steps when graphs are off; counted across
+ * calls) a scan of E^n for NaN / Inf sets a device flag that is part of the
+ * state (cleared by gnor_reset, restored by gnor_load_state).  While the
+ * next chunk runs, gnor_run waits for the previous chunk's scan only and
+ * returns GNOR_E_NONFINITE if it found one (the steps enqueued so far still
+ * run); gnor_synchronize reads the last scan's flag after the stream drains
+ * and returns GNOR_E_NONFINITE the same way. */
 gnor_status gnor_run(gnor_sim *sim, int64_t nsteps);
 gnor_status gnor_synchronize(gnor_sim *sim);
+/* on = 1 (default) or 0; INVALID_ARG otherwise. */
+gnor_status gnor_set_watchdog(gnor_sim *sim, int32_t on);
 int64_t gnor_step_index(const gnor_sim *sim);
 
 /* Steps per captured graph (even; 0 = launch every kernel directly). */
@@ -177,6 +190,14 @@ gnor_status gnor_set_graph_chunk(gnor_sim *sim, int32_t steps);
  * sca = +eta0 (outward flux through the scattering box) / inc.
  * Synchronises the stream. */
 gnor_status gnor_get_spectra(gnor_sim *sim, double *inc, double *ext, double *abs_, double *sca);
+
+/* Enqueue (asynchronously, on the bound stream) the fold of the flux-box
+ * samples staged since the last fold into the FP64 accumulators.  Steps
+ * stage their samples and fold them every 256 steps; gnor_get_spectra folds
+ * a partly filled window itself.  This call lets a caller put that fold
+ * where it wants it (for example inside a timed region).  A no-op without
+ * flux boxes or right after a fold. */
+gnor_status gnor_flush_spectra(gnor_sim *sim);
 
 /* Raw transforms (SI): A[k][m], B[k][m] as separate real/imag arrays of
  * nz * nfreq doubles each. */
@@ -208,8 +229,12 @@ gnor_status gnor_get_maps(gnor_sim *sim, double *fields, double *inc, size_t cou
 /* Copy one field to host as nx*ny*nz doubles in SI units:
  * 0-2 E^n (V/m), 3-5 H^{n-1/2} (A/m), 6-8 J^{n-1/2} = dP_f/dt (A/m^2),
  * 9 + 3p + c (p < ncp): component c of the critical-point polarisation
- * P_CP,p^n (C/m^2; zero outside the metal).
+ * P_CP,p^n (C/m^2; zero outside the metal),
+ * 21 (GNOR_FIELD_DENSITY): the free-electron density n - n0 = div P_f^n / e
+ * (m^-3, Eq. Nsol) at the nodes (i, j, k), with backward differences of the
+ * Yee-staggered P_f^n (zero away from the metal).
  * count must be nx*ny*nz.  Synchronises the stream. */
+#define GNOR_FIELD_DENSITY 21
 gnor_status gnor_get_field(gnor_sim *sim, int32_t which, double *host_dst, size_t count);
 
 /* Auxiliary line E_inc^n, H_inc^{n-1/2} (SI), n1 = nz + 50 doubles each. */
@@ -307,21 +332,35 @@ gnor_status gnor_voxelize_star(int32_t nx, int32_t ny, int32_t nz, double dx, co
  * [0, 1] scaling wp^2, beta^2 and D (gamma unchanged; rho = 0 leaves P = 0).
  * The region replaces any fixed metal inside it and must lie 2 cells inside
  * the TF box.  Call after gnor_set_material, before gnor_bind_memory;
- * rho holds prod(hi - lo) floats.  gnor_update_design replaces the
- * densities of a bound simulation (the state is not reset). */
-gnor_status gnor_set_design(gnor_sim *sim, const int32_t lo[3], const int32_t hi[3], const float *rho);
-gnor_status gnor_update_design(gnor_sim *sim, const float *rho);
+ * rho_init is a HOST array of prod(hi - lo) floats copied before return
+ * (NULL: density 1), uploaded by gnor_bind_memory.
+ * gnor_update_design replaces the densities of a bound simulation from a
+ * DEVICE array rho_device of prod(hi - lo) floats (x fastest, 4-byte
+ * aligned, read in stream order on the bound stream; the state is not
+ * reset).  It checks the values on the device and synchronises the stream:
+ * any value outside [0, 1] (or NaN) gives GNOR_E_INVALID_ARG and leaves the
+ * densities unchanged. */
+gnor_status gnor_set_design(gnor_sim *sim, const int32_t lo[3], const int32_t hi[3], const float *rho_init);
+gnor_status gnor_update_design(gnor_sim *sim, const float *rho_device);
 
 /* Objective sigma_ext(omega[m_target]) (as gnor_get_spectra) of nsteps steps
  * from rest, and its exact discrete-adjoint gradient with respect to the
- * design densities (grad: prod(hi - lo) doubles, x fastest).  Forward pass
- * with a full-state checkpoint every ckpt_every steps; backward pass segment
- * by segment with recomputation.  Needs dft_every = 1 and eps_inf =
- * eps_background.  Allocates its workspace with hipMalloc (checkpoints,
- * adjoint fields, per-segment design-region history) and frees it before
- * returning; the simulation state afterwards is unspecified (gnor_reset). */
+ * design densities.  Forward pass with a full-state checkpoint every
+ * ckpt_every steps; backward pass segment by segment with recomputation.
+ * Needs dft_every = 1 and eps_inf = eps_background.
+ * workspace: caller DEVICE buffer of at least
+ * gnor_gradient_required_bytes(sim, nsteps, ckpt_every) bytes, 256-byte
+ * aligned (checkpoints, adjoint fields, per-segment design-region history;
+ * the library writes it and never frees it); gnor_gradient_required_bytes
+ * returns 0 before gnor_bind_memory or without a design region.
+ * objective: HOST double (may be NULL); grad: DEVICE array of prod(hi - lo)
+ * doubles, x fastest, overwritten.  Synchronises the stream before return;
+ * the simulation state afterwards is unspecified (gnor_reset).  Errors:
+ * GNOR_E_BUFFER_TOO_SMALL for a short workspace, INVALID_ARG for an
+ * unaligned one or bad counts, STATE without a design region. */
+size_t gnor_gradient_required_bytes(const gnor_sim *sim, int64_t nsteps, int32_t ckpt_every);
 gnor_status gnor_gradient(gnor_sim *sim, int64_t nsteps, int32_t ckpt_every, int32_t m_target,
-                          double *objective, double *grad);
+                          void *workspace, size_t workspace_bytes, double *objective, double *grad);
 
 /* Batches: n independent simulations (bound, same precision, same step
  * index, same tile height) stepped in lockstep; every phase of a step is one
@@ -329,10 +368,16 @@ gnor_status gnor_gradient(gnor_sim *sim, int64_t nsteps, int32_t ckpt_every, int
  * advances every instance's incident line).  The batch enqueues on hip_stream
  * (NULL: a stream of its own); call gnor_batch_synchronize before reading an
  * instance.  Instances must not be stepped outside the batch while it is in
- * use (GNOR_E_STATE).  The library allocates the batch's small parameter
- * table (2 n records) with hipMalloc and frees it in gnor_batch_destroy.
- * Results equal those of the instances run one by one. */
-gnor_status gnor_batch_create(int32_t n, gnor_sim *const *sims, void *hip_stream, gnor_batch **out);
+ * use (GNOR_E_STATE).  table: caller DEVICE buffer of at least
+ * gnor_batch_required_bytes(n, sims) bytes, 256-byte aligned, that holds the
+ * batch's two per-instance parameter tables until gnor_batch_destroy (the
+ * library writes it at creation and never frees it); a short or unaligned
+ * buffer gives GNOR_E_BUFFER_TOO_SMALL.  The non-finite watchdog of gnor_run
+ * does not run inside batches.  Results equal those of the instances run
+ * one by one. */
+size_t gnor_batch_required_bytes(int32_t n, gnor_sim *const *sims);
+gnor_status gnor_batch_create(int32_t n, gnor_sim *const *sims, void *hip_stream, void *table,
+                              size_t table_bytes, gnor_batch **out);
 gnor_status gnor_batch_run(gnor_batch *batch, int64_t nsteps);
 gnor_status gnor_batch_synchronize(gnor_batch *batch);
 gnor_status gnor_batch_set_graph_chunk(gnor_batch *batch, int32_t steps);

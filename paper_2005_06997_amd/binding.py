@@ -21,7 +21,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "gnor_fdtd.h")
 GNOR_FP32, GNOR_FP64 = 0, 1
 STATUS = {0: "GNOR_OK", 1: "GNOR_E_INVALID_ARG", 2: "GNOR_E_UNSTABLE", 3: "GNOR_E_OUT_OF_MEMORY",
           4: "GNOR_E_DEVICE", 5: "GNOR_E_STATE", 6: "GNOR_E_BUFFER_TOO_SMALL", 7: "GNOR_E_NONFINITE"}
-FIELDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Hx": 3, "Hy": 4, "Hz": 5, "Jx": 6, "Jy": 7, "Jz": 8}
+FIELDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Hx": 3, "Hy": 4, "Hz": 5, "Jx": 6, "Jy": 7, "Jz": 8,
+          "n": 21}  # n: free-electron density n - n0 at the nodes (GNOR_FIELD_DENSITY)
 # critical-point polarisation P_CP,p^n: "PC<p><c>"
 FIELDS.update({f"PC{p}{c}": 9 + 3 * p + i for p in range(4) for i, c in enumerate("xyz")})
 
@@ -102,10 +103,12 @@ def load() -> C.CDLL:
         "gnor_bind_memory": (i32, [vp, vp, sz, vp]),
         "gnor_reset": (i32, [vp]),
         "gnor_run": (i32, [vp, i64]),
+        "gnor_set_watchdog": (i32, [vp, i32]),
         "gnor_synchronize": (i32, [vp]),
         "gnor_step_index": (i64, [vp]),
         "gnor_set_graph_chunk": (i32, [vp, i32]),
         "gnor_get_spectra": (i32, [vp, dp, dp, dp, dp]),
+        "gnor_flush_spectra": (i32, [vp]),
         "gnor_get_dft": (i32, [vp, dp, dp, dp, dp]),
         "gnor_get_field": (i32, [vp, i32, dp, sz]),
         "gnor_get_aux": (i32, [vp, dp, dp, sz]),
@@ -123,8 +126,10 @@ def load() -> C.CDLL:
         "gnor_voxelize_star": (i32, [i32, i32, i32, dbl, vp, i32, vp]),
         "gnor_set_design": (i32, [vp, C.POINTER(i32), C.POINTER(i32), vp]),
         "gnor_update_design": (i32, [vp, vp]),
-        "gnor_gradient": (i32, [vp, i64, i32, i32, dp, dp]),
-        "gnor_batch_create": (i32, [i32, vp, vp, C.POINTER(vp)]),
+        "gnor_gradient_required_bytes": (sz, [vp, i64, i32]),
+        "gnor_gradient": (i32, [vp, i64, i32, i32, vp, sz, dp, vp]),
+        "gnor_batch_required_bytes": (sz, [i32, vp]),
+        "gnor_batch_create": (i32, [i32, vp, vp, vp, sz, C.POINTER(vp)]),
         "gnor_batch_run": (i32, [vp, i64]),
         "gnor_batch_synchronize": (i32, [vp]),
         "gnor_batch_set_graph_chunk": (i32, [vp, i32]),
@@ -259,8 +264,16 @@ class Sim:
     def synchronize(self):
         self._check(self.L.gnor_synchronize(self.h))
 
+    def flush_spectra(self):
+        """Enqueue the fold of the flux samples staged since the last fold."""
+        self._check(self.L.gnor_flush_spectra(self.h))
+
     def reset(self):
         self._check(self.L.gnor_reset(self.h))
+
+    def set_watchdog(self, on: bool):
+        """Non-finite scan of E after every chunk of steps inside run()."""
+        self._check(self.L.gnor_set_watchdog(self.h, 1 if on else 0))
 
     def check_finite(self) -> bool:
         st = self.L.gnor_check_finite(self.h)
@@ -346,18 +359,38 @@ class Sim:
         return [int(v) for v in c]
 
     def update_design(self, rho):
-        """New design densities (z, y, x) in [0, 1]; the state is not reset."""
-        r = np.ascontiguousarray(rho, dtype=np.float32).reshape(self.design_shape)
-        self._check(self.L.gnor_update_design(self.h, r.ctypes.data))
+        """New design densities (z, y, x) in [0, 1] from a device tensor on this
+        simulation's GPU (float32, contiguous) or any array (copied to the
+        device first); the state is not reset."""
+        import torch
+        if isinstance(rho, torch.Tensor) and rho.device == self.device and rho.dtype == torch.float32:
+            r = rho.contiguous()
+        else:
+            r = torch.as_tensor(np.asarray(rho, dtype=np.float32)).to(self.device)
+        assert tuple(r.shape) == self.design_shape, (tuple(r.shape), self.design_shape)
+        # the library reads r in stream order on the simulation's stream; wait
+        # for that read, so that the caller may reuse rho at once
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(self.L.gnor_update_design(self.h, C.c_void_p(r.data_ptr())))
+        self.stream.synchronize()
 
-    def gradient(self, nsteps: int, ckpt_every: int, m_target: int):
+    def gradient(self, nsteps: int, ckpt_every: int, m_target: int, as_tensor: bool = False):
         """sigma_ext(omega[m_target]) of nsteps steps from rest and its exact
-        adjoint gradient w.r.t. the design densities, shape (z, y, x)."""
-        g = np.empty(self.design_shape, np.float64)
+        adjoint gradient w.r.t. the design densities, shape (z, y, x): a numpy
+        array, or with as_tensor a float64 device tensor."""
+        import torch
+        nbytes = int(self.L.gnor_gradient_required_bytes(self.h, int(nsteps), int(ckpt_every)))
+        if nbytes == 0:
+            raise GnorError(5, "no design region or memory not bound")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        g = torch.empty(self.design_shape, dtype=torch.float64, device=self.device)
         obj = C.c_double()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._check(self.L.gnor_gradient(self.h, int(nsteps), int(ckpt_every), int(m_target),
-                                         C.byref(obj), _dp(g)))
-        return obj.value, g
+                                         C.c_void_p(ws.data_ptr()), nbytes, C.byref(obj),
+                                         C.c_void_p(g.data_ptr())))
+        del ws  # the call synchronised its stream
+        return obj.value, (g if as_tensor else g.cpu().numpy())
 
     def set_tiling(self, ty: int, kz: int, xcd: int = 0):
         self._check(self.L.gnor_set_tiling(self.h, int(ty), int(kz), int(xcd)))
@@ -397,15 +430,18 @@ class Batch:
     launch over the tiles of every instance (see gnor_batch_create)."""
 
     def __init__(self, sims, tiling=(2, 5, 2), graph_chunk: int = 64):
+        import torch
         L = load()
         self.L = L
         self.sims = list(sims)
         for s in self.sims:
             s.set_tiling(*tiling)
         arr = (C.c_void_p * len(self.sims))(*[s.h.value for s in self.sims])
+        nbytes = int(L.gnor_batch_required_bytes(len(self.sims), arr))
+        self.table = torch.empty(nbytes, dtype=torch.uint8, device=self.sims[0].device)
         h = C.c_void_p()
         st = L.gnor_batch_create(len(self.sims), arr, C.c_void_p(self.sims[0].stream.cuda_stream),
-                                 C.byref(h))
+                                 C.c_void_p(self.table.data_ptr()), nbytes, C.byref(h))
         if st:
             raise GnorError(st, "gnor_batch_create rejected the instances")
         self.h = h
@@ -440,11 +476,20 @@ def extinction_objective():
     import torch
 
     class ExtinctionObjective(torch.autograd.Function):
+        """rho stays on the simulation's device; the adjoint runs in forward
+        only when rho requires a gradient (otherwise only the objective's
+        forward run)."""
+
         @staticmethod
         def forward(ctx, rho, sim, nsteps, ckpt_every, m_target):
-            sim.update_design(rho.detach().to("cpu", torch.float32).numpy())
-            obj, grad = sim.gradient(nsteps, ckpt_every, m_target)
-            ctx.save_for_backward(torch.from_numpy(grad).to(device=rho.device, dtype=rho.dtype))
+            sim.update_design(rho.detach().to(device=sim.device, dtype=torch.float32))
+            if ctx.needs_input_grad[0]:
+                obj, grad = sim.gradient(nsteps, ckpt_every, m_target, as_tensor=True)
+                ctx.save_for_backward(grad.to(device=rho.device, dtype=rho.dtype))
+            else:
+                sim.reset()
+                sim.run(nsteps)
+                obj = float(sim.spectra()["ext"][m_target])
             return rho.new_tensor(obj)
 
         @staticmethod

@@ -23,6 +23,7 @@ SOURCES = [
     # registers the loop-carried sums were copied out and back every step
     ("gnor_spectra.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
     ("gnor_adjoint.hip", []),
+    ("gnor_util.hip", []),
     # the voxelisers' floating-point tests must not be contracted into FMAs
     ("gnor_runtime.cpp", ["-ffp-contract=off"]),
 ]

@@ -326,6 +326,22 @@ void launch_flux_reduce(const double* acc_re, const double* acc_im, const double
                         int npairs_box0, int nf, double* out, hipStream_t s);
 template <class T>
 void launch_nonfinite(const T* a, size_t n, int* flag, hipStream_t s);
+
+// Design box inside the metal sub-grid: dn cells per axis, starting at
+// sub-grid cell off; the sub-grid has mn cells per axis.
+struct DesignMap {
+  int dn[3], off[3], mn[3];
+};
+// any rho outside [0, 1] (or NaN) sets *flag
+void launch_design_check(const float* rho, size_t n, int* flag, hipStream_t s);
+// rho[z][y][x] of the design box -> the sub-grid weight array
+void launch_design_scatter(const float* rho, const DesignMap& d, float* weight, hipStream_t s);
+// n - n0 (m^-3) at the sub-grid nodes from Phi~_P^{n-1} and J~^{n-1/2}
+template <class T>
+void launch_density(const T* pp, const T* jx, const T* jy, const T* jz, const int mn[3], double scale,
+                    double* out, hipStream_t s);
+// zero `bytes` (a multiple of 4) with a kernel (graph-safe clear)
+void launch_fill_zero(void* a, size_t bytes, hipStream_t s);
 Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
 // Classify the tiles (metal: a metal point within two cells, by the per-row
 // x extents rowx of the metal points, null = no metal; CPML: slabs of np

@@ -24,6 +24,8 @@ namespace {
 
 constexpr double kC0 = 299792458.0;
 constexpr double kMu0 = 1.25663706212e-6;
+constexpr double kElementaryCharge = 1.602176634e-19;  // C
+constexpr int kFieldDensity = 21;  // gnor_get_field index of n - n0
 double eps0() { return 1.0 / (kMu0 * kC0 * kC0); }
 double eta0() { return std::sqrt(kMu0 / eps0()); }
 
@@ -53,6 +55,9 @@ struct Layout {
   // static region
   size_t mask = 0, rho = 0, cpml[3] = {0, 0, 0}, aux_prof = 0, omega = 0, fpw = 0, tiles = 0,
          colz = 0, map_om = 0;
+  // scratch outside the state: density read-out (M doubles), the flags of
+  // gnor_check_finite and of the design-density check
+  size_t dens = 0, chk = 0, dflag = 0;
   size_t static_end = 0;
   // state region
   size_t state_begin = 0;
@@ -111,6 +116,15 @@ struct gnor_sim {
   int graph_chunk = 64;
   hipGraphExec_t graph = nullptr;
   int graph_steps = 0;
+  // non-finite watchdog of gnor_run: E is scanned after every chunk of steps
+  // (flag in the state region, sticky until reset or load); the host reads
+  // a chunk's flag while the next chunk runs, on a stream of its own
+  bool watchdog = true;
+  hipStream_t wstream = nullptr;
+  hipEvent_t wev[2] = {nullptr, nullptr};
+  int wslot = 0;
+  bool wpending = false;  // the last scanned chunk's flag has not been read yet
+  int64_t wsince = 0;     // steps enqueued since the last scan
   std::string last_error;
 };
 
@@ -229,6 +243,9 @@ void plan_layout(gnor_sim* s) {
   // tile lists: room for the finest tiling (ty = 2, kz = 1)
   L.tiles = P.take((size_t)s->nbx * ((s->g.ny + 1) / 2) * s->g.nz * 4 + 4);
   L.map_om = P.take((size_t)std::max(1, s->maps.nmap) * 8);
+  L.dens = P.take(M * 8);
+  L.chk = P.take(4);
+  L.dflag = P.take(4);
   L.static_end = P.off;
   L.state_begin = P.off;
   for (int pp = 0; pp < 2; ++pp)
@@ -445,7 +462,7 @@ gnor::MapParams<T> make_maps(gnor_sim* s, int parity) {
   m.acc = ptr<double>(s, s->L.maps);
   m.inc = ptr<double>(s, s->L.map_inc);
   m.dt = s->dt;
-  m.nscale = eps0() / (s->g.dx * 1.602176634e-19);  // Phi~_P = dx div P / eps0; n - n0 = div P / e
+  m.nscale = eps0() / (s->g.dx * kElementaryCharge);  // Phi~_P = dx div P / eps0; n - n0 = div P / e
   for (int d = 0; d < 3; ++d) { m.mlo[d] = s->mlo[d]; m.mn[d] = s->mn[d]; }
   const int b = (parity & 1) ^ 1;
   for (int c = 0; c < 3; ++c) m.E[c] = ptr<T>(s, s->L.E[b][c]);
@@ -797,6 +814,9 @@ void gnor_destroy(gnor_sim* s) {
     if (s->ev_join[q]) (void)hipEventDestroy(s->ev_join[q]);
   }
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->wstream) (void)hipStreamDestroy(s->wstream);
+  for (int q = 0; q < 2; ++q)
+    if (s->wev[q]) (void)hipEventDestroy(s->wev[q]);
   delete s;
 }
 
@@ -855,7 +875,7 @@ gnor_status gnor_set_material(gnor_sim* s, const uint8_t* mask, const gnor_mater
 }
 
 gnor_status gnor_set_design(gnor_sim* s, const int32_t* lo, const int32_t* hi, const float* rho) {
-  if (!s || !lo || !hi || !rho) return GNOR_E_INVALID_ARG;
+  if (!s || !lo || !hi) return GNOR_E_INVALID_ARG;
   if (!s->have_material) return fail(s, GNOR_E_STATE, "gnor_set_material must come first");
   if (s->bound) return fail(s, GNOR_E_STATE, "the design region must be set before gnor_bind_memory");
   if (s->g.eps_substrate > 0.0) return fail(s, GNOR_E_INVALID_ARG, "design regions do not cover a substrate");
@@ -867,8 +887,9 @@ gnor_status gnor_set_design(gnor_sim* s, const int32_t* lo, const int32_t* hi, c
                   "design region must be non-empty and lie 2 cells inside the TF box");
     nd *= (size_t)(hi[d] - lo[d]);
   }
-  for (size_t q = 0; q < nd; ++q)
-    if (!(rho[q] >= 0.0f && rho[q] <= 1.0f)) return fail(s, GNOR_E_INVALID_ARG, "rho must lie in [0, 1]");
+  if (rho)
+    for (size_t q = 0; q < nd; ++q)
+      if (!(rho[q] >= 0.0f && rho[q] <= 1.0f)) return fail(s, GNOR_E_INVALID_ARG, "rho must lie in [0, 1]");
   int mlo[3], mhi[3];
   for (int d = 0; d < 3; ++d) {
     mlo[d] = s->any_metal ? std::min(s->mlo[d] + 1, lo[d]) : lo[d];
@@ -885,20 +906,34 @@ gnor_status gnor_set_design(gnor_sim* s, const int32_t* lo, const int32_t* hi, c
     s->dlo[d] = lo[d];
     s->dhi[d] = hi[d];
   }
-  s->rho.assign(rho, rho + nd);
+  if (rho) s->rho.assign(rho, rho + nd);
+  else s->rho.assign(nd, 1.0f);
   s->design = true;
   return GNOR_OK;
 }
 
-gnor_status gnor_update_design(gnor_sim* s, const float* rho) {
+gnor_status gnor_update_design(gnor_sim* s, const float* rho_dev) {
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
-  if (!s->design || !rho) return fail(s, GNOR_E_STATE, "no design region");
-  for (size_t q = 0; q < s->rho.size(); ++q)
-    if (!(rho[q] >= 0.0f && rho[q] <= 1.0f)) return fail(s, GNOR_E_INVALID_ARG, "rho must lie in [0, 1]");
+  if (!s->design) return fail(s, GNOR_E_STATE, "no design region");
+  if (!rho_dev) return fail(s, GNOR_E_INVALID_ARG, "null density pointer");
+  // check on the device (stream-ordered after the queued steps), then scatter
+  int* flag = ptr<int>(s, s->L.dflag);
+  gnor::launch_fill_zero(flag, 4, s->stream);
+  gnor::launch_design_check(rho_dev, s->rho.size(), flag, s->stream);
+  int bad = 0;
+  HIPCHECK(s, hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, s->stream));
   HIPCHECK(s, hipStreamSynchronize(s->stream));
-  std::copy(rho, rho + s->rho.size(), s->rho.begin());
-  return upload_rho(s);
+  if (bad) return fail(s, GNOR_E_INVALID_ARG, "rho must lie in [0, 1]");
+  gnor::DesignMap d{};
+  for (int a = 0; a < 3; ++a) {
+    d.dn[a] = s->dhi[a] - s->dlo[a];
+    d.off[a] = s->dlo[a] - s->mlo[a];
+    d.mn[a] = s->mn[a];
+  }
+  gnor::launch_design_scatter(rho_dev, d, ptr<float>(s, s->L.rho), s->stream);
+  HIPCHECK(s, hipGetLastError());
+  return GNOR_OK;
 }
 
 gnor_status gnor_set_source(gnor_sim* s, const gnor_source_desc* src) {
@@ -978,6 +1013,8 @@ gnor_status gnor_reset(gnor_sim* s) {
   HIPCHECK(s, hipMemsetAsync(s->dev + s->L.state_begin, 0, s->L.state_end - s->L.state_begin, s->stream));
   HIPCHECK(s, hipStreamSynchronize(s->stream));
   s->step = 0;
+  s->wpending = false;
+  s->wsince = 0;
   return GNOR_OK;
 }
 
@@ -1007,6 +1044,11 @@ gnor_status gnor_bind_memory(gnor_sim* s, void* dptr, size_t bytes, void* stream
     }
     HIPCHECK(s, hipEventCreateWithFlags(&s->ev_fork, kJoinEventFlags));
   }
+  if (!s->wstream) {
+    HIPCHECK(s, hipStreamCreateWithFlags(&s->wstream, hipStreamNonBlocking));
+    for (int q = 0; q < 2; ++q) HIPCHECK(s, hipEventCreateWithFlags(&s->wev[q], kJoinEventFlags));
+  }
+  s->wpending = false;
   s->dev = reinterpret_cast<char*>(dptr);
   s->dev_bytes = bytes;
   s->bound = true;
@@ -1043,36 +1085,97 @@ gnor_status gnor_set_graph_chunk(gnor_sim* s, int32_t steps) {
   return GNOR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Watchdog: scan E^n (the state after the last enqueued step) for NaN / Inf
+// into the sticky flag and mark the scan with an event.
+void watch_scan(gnor_sim* s) {
+  int* flag = ptr<int>(s, s->L.flag);
+  const int parity = (int)(s->step & 1);
+  for (int c = 0; c < 3; ++c) {
+    if (s->g.precision == GNOR_FP32)
+      gnor::launch_nonfinite<float>(ptr<float>(s, s->L.E[parity][c]), s->N, flag, s->stream);
+    else
+      gnor::launch_nonfinite<double>(ptr<double>(s, s->L.E[parity][c]), s->N, flag, s->stream);
+  }
+  s->wslot ^= 1;
+  (void)hipEventRecord(s->wev[s->wslot], s->stream);
+  s->wpending = true;
+}
+
+// Read the flag of the scan marked by event slot `slot` (waits for that scan
+// only, not for work queued after it).
+gnor_status watch_read(gnor_sim* s, int slot) {
+  int h = 0;
+  HIPCHECK(s, hipStreamWaitEvent(s->wstream, s->wev[slot], 0));
+  HIPCHECK(s, hipMemcpyAsync(&h, ptr<int>(s, s->L.flag), 4, hipMemcpyDeviceToHost, s->wstream));
+  HIPCHECK(s, hipStreamSynchronize(s->wstream));
+  return h ? fail(s, GNOR_E_NONFINITE, "non-finite value in E (watchdog)") : GNOR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gnor_status gnor_set_watchdog(gnor_sim* s, int32_t on) {
+  if (!s || (on != 0 && on != 1)) return GNOR_E_INVALID_ARG;
+  s->watchdog = on != 0;
+  return GNOR_OK;
+}
+
 gnor_status gnor_run(gnor_sim* s, int64_t nsteps) {
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
   if (nsteps < 0) return fail(s, GNOR_E_INVALID_ARG, "nsteps < 0");
+  // a finished scan of an earlier call already flagged the state
+  if (s->watchdog && s->wpending && hipEventQuery(s->wev[s->wslot]) == hipSuccess) {
+    s->wpending = false;
+    st = watch_read(s, s->wslot);
+    if (st != GNOR_OK) return st;
+  }
   int64_t left = nsteps;
   const int align = chunk_alignment(s);
   int chunk = s->graph_chunk;
   if (chunk > 0) chunk = std::max(align, chunk / align * align);
+  // steps between watchdog scans: the graph chunk (eager runs: 64), counted
+  // across calls (a caller stepping one step at a time scans as rarely)
+  const int64_t period = chunk > 0 ? chunk : 64;
   while (left > 0) {
+    int64_t n;
     if (chunk > 0 && (s->step % align) == 0 && left >= chunk) {
       if (!s->graph || s->graph_steps != chunk) {
         st = build_graph(s, chunk);
         if (st != GNOR_OK) return st;
       }
       HIPCHECK(s, hipGraphLaunch(s->graph, s->stream));
-      s->step += chunk;
-      left -= chunk;
-      continue;
+      n = chunk;
+    } else {
+      // eager steps until the next aligned chunk start (or the end)
+      n = std::min(left, period);
+      if (chunk > 0) {
+        const int64_t to_align = (align - (s->step % align)) % align;
+        n = to_align > 0 ? std::min(left, to_align) : std::min(left, (int64_t)chunk);
+        if (to_align == 0 && left < chunk) n = left;
+      }
+      enqueue_steps_eager(s, s->step, n, s->stream, s->mode);
+      HIPCHECK(s, hipGetLastError());
     }
-    // eager steps until the next aligned chunk start (or the end)
-    int64_t n = left;
-    if (chunk > 0) {
-      const int64_t to_align = (align - (s->step % align)) % align;
-      n = to_align > 0 ? std::min(left, to_align) : std::min(left, (int64_t)chunk);
-      if (to_align == 0 && left < chunk) n = left;
-    }
-    enqueue_steps_eager(s, s->step, n, s->stream, s->mode);
-    HIPCHECK(s, hipGetLastError());
     s->step += n;
     left -= n;
+    s->wsince += n;
+    if (s->watchdog && s->wsince >= period) {
+      s->wsince = 0;
+      // the previous scan's flag is read while this chunk runs
+      const bool had = s->wpending;
+      watch_scan(s);
+      HIPCHECK(s, hipGetLastError());
+      if (had) {
+        st = watch_read(s, s->wslot ^ 1);
+        if (st != GNOR_OK) return st;
+      }
+    }
   }
   return GNOR_OK;
 }
@@ -1081,6 +1184,10 @@ gnor_status gnor_synchronize(gnor_sim* s) {
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
   HIPCHECK(s, hipStreamSynchronize(s->stream));
+  if (s->watchdog && s->wpending) {
+    s->wpending = false;
+    return watch_read(s, s->wslot);
+  }
   return GNOR_OK;
 }
 
@@ -1108,6 +1215,18 @@ gnor_status gnor_get_dft(gnor_sim* s, double* are, double* aim, double* bre, dou
 
 extern "C" {
 
+gnor_status gnor_flush_spectra(gnor_sim* s) {
+  gnor_status st = check_ready(s);
+  if (st != GNOR_OK) return st;
+  // fold the staged flux samples of the current window (a no-op right after
+  // a fold); the next window fold takes only the slots staged after this
+  if (s->nsamp > 0 && s->step > 0 && (s->step % s->slots) != 0) {
+    enqueue_flux_acc(s, -1, s->stream);  // last staged step = counter - 1
+    HIPCHECK(s, hipGetLastError());
+  }
+  return GNOR_OK;
+}
+
 gnor_status gnor_get_spectra(gnor_sim* s, double* inc, double* ext, double* absn, double* sca) {
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
@@ -1116,9 +1235,8 @@ gnor_status gnor_get_spectra(gnor_sim* s, double* inc, double* ext, double* absn
   std::vector<double> fs(2 * (size_t)nf, 0.0);
   if (s->nsamp > 0) {
     // fold the partially filled staging window into the accumulators
-    if (s->step > 0 && (s->step % s->slots) != 0) {
-      enqueue_flux_acc(s, -1, s->stream);  // last staged step = counter - 1
-    }
+    st = gnor_flush_spectra(s);
+    if (st != GNOR_OK) return st;
     gnor::launch_flux_reduce(ptr<double>(s, s->L.facc), ptr<double>(s, s->L.facc) + (size_t)nf * s->nsamp,
                        ptr<double>(s, s->L.fpw), s->npairs, s->npairs_box0, nf,
                        ptr<double>(s, s->L.fsum), s->stream);
@@ -1153,9 +1271,38 @@ gnor_status gnor_get_field(gnor_sim* s, int32_t which, double* dst, size_t count
   if (st != GNOR_OK) return st;
   if (!dst) return GNOR_E_INVALID_ARG;
   if (count != s->N) return fail(s, GNOR_E_BUFFER_TOO_SMALL, "count must be nx*ny*nz");
-  if (which < 0 || which >= 9 + 3 * s->mat.ncp) return fail(s, GNOR_E_INVALID_ARG, "field index out of range");
-  HIPCHECK(s, hipStreamSynchronize(s->stream));
+  const bool density = which == kFieldDensity;
+  if (!density && (which < 0 || which >= 9 + 3 * s->mat.ncp))
+    return fail(s, GNOR_E_INVALID_ARG, "field index out of range");
   const int parity = (int)(s->step & 1);
+  if (density) {
+    std::memset(dst, 0, s->N * 8);
+    if (!s->any_metal) return GNOR_OK;
+    // div P_f^n at the nodes: Phi~_P^{n-1} (left by the last H sweep in the
+    // buffer of this parity) plus the node divergence of J~^{n-1/2}
+    const double scale = eps0() / (s->g.dx * kElementaryCharge);
+    double* out = ptr<double>(s, s->L.dens);
+    if (s->g.precision == GNOR_FP32)
+      gnor::launch_density<float>(ptr<float>(s, s->L.PP[parity]), ptr<float>(s, s->L.J[parity][0]),
+                                  ptr<float>(s, s->L.J[parity][1]), ptr<float>(s, s->L.J[parity][2]),
+                                  s->mn, scale, out, s->stream);
+    else
+      gnor::launch_density<double>(ptr<double>(s, s->L.PP[parity]), ptr<double>(s, s->L.J[parity][0]),
+                                   ptr<double>(s, s->L.J[parity][1]), ptr<double>(s, s->L.J[parity][2]),
+                                   s->mn, scale, out, s->stream);
+    HIPCHECK(s, hipGetLastError());
+    std::vector<double> v(s->M);
+    HIPCHECK(s, hipMemcpyAsync(v.data(), out, s->M * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(s, hipStreamSynchronize(s->stream));
+    const gnor_grid_desc& g = s->g;
+    for (int z = 0; z < s->mn[2]; ++z)
+      for (int y = 0; y < s->mn[1]; ++y)
+        for (int x = 0; x < s->mn[0]; ++x)
+          dst[((size_t)(z + s->mlo[2]) * g.ny + (y + s->mlo[1])) * g.nx + (x + s->mlo[0])] =
+              v[((size_t)z * s->mn[1] + y) * s->mn[0] + x];
+    return GNOR_OK;
+  }
+  HIPCHECK(s, hipStreamSynchronize(s->stream));
   const int c = which % 3;
   const bool fp32 = s->g.precision == GNOR_FP32;
   auto fetch = [&](size_t off, size_t n, std::vector<double>& out) -> gnor_status {
@@ -1237,13 +1384,14 @@ gnor_status gnor_load_state(gnor_sim* s, const void* src, size_t bytes) {
   HIPCHECK(s, hipStreamSynchronize(s->stream));
   std::memcpy(&s->step, src, 8);
   HIPCHECK(s, hipMemcpy(s->dev + s->L.state_begin, static_cast<const char*>(src) + 8, n, hipMemcpyHostToDevice));
+  s->wpending = false;
   return GNOR_OK;
 }
 
 gnor_status gnor_check_finite(gnor_sim* s) {
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
-  int* flag = ptr<int>(s, s->L.flag);
+  int* flag = ptr<int>(s, s->L.chk);
   HIPCHECK(s, hipMemsetAsync(flag, 0, 4, s->stream));
   const int parity = (int)(s->step & 1);
   for (int c = 0; c < 3; ++c) {
@@ -1571,7 +1719,7 @@ struct gnor_batch {
   int n = 0;
   bool fp32 = true;
   int ty = 2;
-  char* tab = nullptr;       // two tables of n entries (parity 0, parity 1)
+  char* tab = nullptr;       // two tables of n entries (parity 0, parity 1), caller memory
   size_t entry_bytes = 0;
   int hblocks[gnor::kClasses] = {0, 0, 0, 0}, dblocks = 0;
   // concurrent class launches, as for a single simulation
@@ -1636,9 +1784,14 @@ gnor_status batch_tables(gnor_batch* b) {
     b->dblocks = d0;
   }
   b->entry_bytes = sizeof(gnor::BatchEntry<T>);
-  BHIPCHECK(b, hipMalloc(&b->tab, tab.size() * b->entry_bytes));
   BHIPCHECK(b, hipMemcpy(b->tab, tab.data(), tab.size() * b->entry_bytes, hipMemcpyHostToDevice));
   return GNOR_OK;
+}
+
+// device bytes of the two parameter tables of a batch of n instances
+size_t batch_table_bytes(int n, bool fp32) {
+  const size_t e = fp32 ? sizeof(gnor::BatchEntry<float>) : sizeof(gnor::BatchEntry<double>);
+  return 2 * (size_t)n * e;
 }
 
 template <class T>
@@ -1685,9 +1838,18 @@ void batch_enqueue_any(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st)
 
 extern "C" {
 
-gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, gnor_batch** out) {
-  if (!out || n < 1 || !sims) return GNOR_E_INVALID_ARG;
+size_t gnor_batch_required_bytes(int32_t n, gnor_sim* const* sims) {
+  if (n < 1 || !sims || !sims[0]) return 0;
+  return batch_table_bytes(n, sims[0]->g.precision == GNOR_FP32);
+}
+
+gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, void* table,
+                              size_t table_bytes, gnor_batch** out) {
+  if (!out || n < 1 || !sims || !table) return GNOR_E_INVALID_ARG;
   *out = nullptr;
+  if (!sims[0] || table_bytes < batch_table_bytes(n, sims[0]->g.precision == GNOR_FP32) ||
+      (((uintptr_t)table) & 255u))
+    return GNOR_E_BUFFER_TOO_SMALL;
   gnor_batch* b = new (std::nothrow) gnor_batch();
   if (!b) return GNOR_E_OUT_OF_MEMORY;
   b->n = n;
@@ -1708,6 +1870,7 @@ gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, gn
     b->any_cp = b->any_cp || s->mat.ncp > 0;
   }
   b->fp32 = sims[0]->g.precision == GNOR_FP32;
+  b->tab = static_cast<char*>(table);
   b->ty = sims[0]->tile_ty;
   b->step = sims[0]->step;
   b->stream = reinterpret_cast<hipStream_t>(stream);
@@ -1738,7 +1901,6 @@ gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, gn
 void gnor_batch_destroy(gnor_batch* b) {
   if (!b) return;
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
-  if (b->tab) (void)hipFree(b->tab);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   for (int q = 0; q < 2; ++q) {
     if (b->side[q]) (void)hipStreamDestroy(b->side[q]);
@@ -1825,48 +1987,60 @@ const char* gnor_batch_last_error(const gnor_batch* b) { return b ? b->last_erro
 // segment's steps in reverse order (gnor_adjoint.hip).
 namespace {
 
-template <class T>
-gnor_status gradient_impl(gnor_sim* s, int64_t nsteps, int C, int m, double* objective,
-                          double* grad_out) {
-  const size_t N = s->N, M = s->M;
+int nz_of(const gnor_sim* s) { return s->g.nz; }
+
+// Workspace of a gradient, carved from the caller's buffer: checkpoints,
+// then (zeroed) the adjoint fields and CPML memory, the gradient's incident
+// transform and the design region's stored forward values.
+struct GradPlan {
+  size_t ck = 0, zero = 0, Eb[3] = {}, Hb[3] = {}, D[6] = {}, Ob[3] = {}, Jb[3] = {}, dQb[3] = {};
+  size_t PPb = 0, PJb = 0, phi = 0, psiE[3][2] = {}, psiH[3][2] = {}, B = 0, fE = 0, fdQ = 0;
+  size_t total = 0;
+};
+
+GradPlan plan_gradient(const gnor_sim* s, int64_t nsteps, int C) {
+  GradPlan G;
+  const size_t N = s->N, M = s->M, w = s->elem;
   const gnor_grid_desc& g = s->g;
   const int np = g.npml;
+  const size_t nd = (size_t)(s->dhi[0] - s->dlo[0]) * (s->dhi[1] - s->dlo[1]) * (s->dhi[2] - s->dlo[2]);
+  const size_t sbytes = s->L.state_end - s->L.state_begin;
+  const size_t nseg = (size_t)((nsteps + C - 1) / C);
+  Planner P;
+  G.ck = P.take(sbytes * nseg);
+  G.zero = P.off;  // everything from here on is zeroed
+  for (int c = 0; c < 3; ++c) { G.Eb[c] = P.take(N * w); G.Hb[c] = P.take(N * w); }
+  for (int q = 0; q < 6; ++q) G.D[q] = P.take(N * w);
+  for (int c = 0; c < 3; ++c) { G.Ob[c] = P.take(M * w); G.Jb[c] = P.take(M * w); G.dQb[c] = P.take(M * w); }
+  G.PPb = P.take(M * w); G.PJb = P.take(M * w); G.phi = P.take(M * w);
+  const size_t nxs = g.nx, nys = g.ny, nzs = g.nz;
+  const size_t slab[3] = {nzs * nys * 2 * np, nzs * 2 * np * nxs, 2 * np * nys * nxs};
+  for (int a = 0; a < 3; ++a)
+    for (int t = 0; t < 2; ++t) {
+      G.psiE[a][t] = P.take(slab[a] * w + 8);
+      G.psiH[a][t] = P.take(slab[a] * w + 8);
+    }
+  G.B = P.take((size_t)2 * nz_of(s) * 8);
+  G.fE = P.take((size_t)(C + 2) * 3 * nd * w);
+  G.fdQ = P.take((size_t)C * 3 * nd * w);
+  G.total = P.off;
+  return G;
+}
+
+template <class T>
+gnor_status gradient_impl(gnor_sim* s, int64_t nsteps, int C, int m, char* ws, double* objective,
+                          double* grad_dev) {
+  const gnor_grid_desc& g = s->g;
   const int nz = g.nz, nf = s->mon.nfreq;
   const int dn[3] = {s->dhi[0] - s->dlo[0], s->dhi[1] - s->dlo[1], s->dhi[2] - s->dlo[2]};
   const size_t nd = (size_t)dn[0] * dn[1] * dn[2];
   const size_t sbytes = s->L.state_end - s->L.state_begin;
   const int nseg = (int)((nsteps + C - 1) / C);
   const hipStream_t st = s->stream;
-  // workspace (library-allocated, freed before return)
-  Planner P;
-  const size_t o_ck = P.take(sbytes * (size_t)nseg);
-  const size_t o_zero = P.off;  // everything below is zeroed
-  size_t o_Eb[3], o_Hb[3], o_D[6], o_Ob[3], o_Jb[3], o_dQb[3], o_psiE[3][2], o_psiH[3][2];
-  for (int c = 0; c < 3; ++c) { o_Eb[c] = P.take(N * sizeof(T)); o_Hb[c] = P.take(N * sizeof(T)); }
-  for (int q = 0; q < 6; ++q) o_D[q] = P.take(N * sizeof(T));
-  for (int c = 0; c < 3; ++c) {
-    o_Ob[c] = P.take(M * sizeof(T)); o_Jb[c] = P.take(M * sizeof(T)); o_dQb[c] = P.take(M * sizeof(T));
-  }
-  const size_t o_PPb = P.take(M * sizeof(T)), o_PJb = P.take(M * sizeof(T)), o_phi = P.take(M * sizeof(T));
-  const size_t nxs = g.nx, nys = g.ny, nzs = g.nz;
-  const size_t slab[3] = {nzs * nys * 2 * np, nzs * 2 * np * nxs, 2 * np * nys * nxs};
-  for (int a = 0; a < 3; ++a)
-    for (int t = 0; t < 2; ++t) {
-      o_psiE[a][t] = P.take(slab[a] * sizeof(T) + 8);
-      o_psiH[a][t] = P.take(slab[a] * sizeof(T) + 8);
-    }
-  const size_t o_grad = P.take(nd * 8);
-  const size_t o_B = P.take((size_t)2 * nz * 8);
-  const size_t o_fE = P.take((size_t)(C + 2) * 3 * nd * sizeof(T));
-  const size_t o_fdQ = P.take((size_t)C * 3 * nd * sizeof(T));
-  const size_t total = P.off;
-  char* ws = nullptr;
-  HIPCHECK(s, hipMalloc(&ws, total));
-  struct Free {
-    char* p;
-    ~Free() { if (p) (void)hipFree(p); }
-  } guard{ws};
+  const GradPlan G = plan_gradient(s, nsteps, C);
+  const size_t o_ck = G.ck, o_zero = G.zero, total = G.total;
   HIPCHECK(s, hipMemsetAsync(ws + o_zero, 0, total - o_zero, st));
+  HIPCHECK(s, hipMemsetAsync(grad_dev, 0, nd * 8, st));
 
   // ---- forward pass with checkpoints
   gnor_status rc = gnor_reset(s);
@@ -1891,36 +2065,36 @@ gnor_status gradient_impl(gnor_sim* s, int64_t nsteps, int C, int m, double* obj
     B[nz + k] = bim[(size_t)k * nf + m];
   }
   const double b2 = B[s->mon.norm_k] * B[s->mon.norm_k] + B[nz + s->mon.norm_k] * B[nz + s->mon.norm_k];
-  HIPCHECK(s, hipMemcpy(ws + o_B, B.data(), B.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(s, hipMemcpy(ws + G.B, B.data(), B.size() * 8, hipMemcpyHostToDevice));
 
   // ---- adjoint
   gnor::AdjParams<T> A{};
   A.p = make_params<T>(s, 0);
   for (int c = 0; c < 3; ++c) {
-    A.Eb[c] = reinterpret_cast<T*>(ws + o_Eb[c]);
-    A.Hb[c] = reinterpret_cast<T*>(ws + o_Hb[c]);
-    A.Ob[c] = reinterpret_cast<T*>(ws + o_Ob[c]);
-    A.Jb[c] = reinterpret_cast<T*>(ws + o_Jb[c]);
-    A.dQb[c] = reinterpret_cast<T*>(ws + o_dQb[c]);
+    A.Eb[c] = reinterpret_cast<T*>(ws + G.Eb[c]);
+    A.Hb[c] = reinterpret_cast<T*>(ws + G.Hb[c]);
+    A.Ob[c] = reinterpret_cast<T*>(ws + G.Ob[c]);
+    A.Jb[c] = reinterpret_cast<T*>(ws + G.Jb[c]);
+    A.dQb[c] = reinterpret_cast<T*>(ws + G.dQb[c]);
   }
-  for (int q = 0; q < 6; ++q) A.D[q] = reinterpret_cast<T*>(ws + o_D[q]);
-  A.PPb = reinterpret_cast<T*>(ws + o_PPb);
-  A.PJb = reinterpret_cast<T*>(ws + o_PJb);
-  A.phiJb = reinterpret_cast<T*>(ws + o_phi);
+  for (int q = 0; q < 6; ++q) A.D[q] = reinterpret_cast<T*>(ws + G.D[q]);
+  A.PPb = reinterpret_cast<T*>(ws + G.PPb);
+  A.PJb = reinterpret_cast<T*>(ws + G.PJb);
+  A.phiJb = reinterpret_cast<T*>(ws + G.phi);
   for (int a = 0; a < 3; ++a)
     for (int t = 0; t < 2; ++t) {
-      A.psiEb[a][t] = reinterpret_cast<T*>(ws + o_psiE[a][t]);
-      A.psiHb[a][t] = reinterpret_cast<T*>(ws + o_psiH[a][t]);
+      A.psiEb[a][t] = reinterpret_cast<T*>(ws + G.psiE[a][t]);
+      A.psiHb[a][t] = reinterpret_cast<T*>(ws + G.psiH[a][t]);
     }
   for (int d = 0; d < 3; ++d) { A.dlo[d] = s->dlo[d]; A.dn[d] = dn[d]; }
-  A.fE = reinterpret_cast<const T*>(ws + o_fE);
-  A.fdQ = reinterpret_cast<const T*>(ws + o_fdQ);
-  A.grad = reinterpret_cast<double*>(ws + o_grad);
+  A.fE = reinterpret_cast<const T*>(ws + G.fE);
+  A.fdQ = reinterpret_cast<const T*>(ws + G.fdQ);
+  A.grad = grad_dev;
   A.dt = s->dt;
   A.omega = s->omega[m];
   // sigma_ext = eta0 dx^3 sum_k Re(A conj B) / |B(norm_k)|^2 with A = (eps0/dt) sum_n dt e^{i w t} J~-sums
   A.CL = eta0() * g.dx * g.dx * g.dx * s->dt * (eps0() / s->dt) / b2;
-  A.Bre = reinterpret_cast<const double*>(ws + o_B);
+  A.Bre = reinterpret_cast<const double*>(ws + G.B);
   A.Bim = A.Bre + nz;
   gnor::launch_adjoint_source<T>(A, nsteps - 1, st);
   for (int seg = nseg - 1; seg >= 0; --seg) {
@@ -1950,18 +2124,27 @@ gnor_status gradient_impl(gnor_sim* s, int64_t nsteps, int C, int m, double* obj
     HIPCHECK(s, hipGetLastError());
   }
   HIPCHECK(s, hipStreamSynchronize(st));
-  HIPCHECK(s, hipMemcpy(grad_out, ws + o_grad, nd * 8, hipMemcpyDeviceToHost));
   return GNOR_OK;
 }
 
 }  // namespace
 
+extern "C" size_t gnor_gradient_required_bytes(const gnor_sim* s, int64_t nsteps, int32_t ckpt_every) {
+  if (!s || !s->bound || !s->design || nsteps < 1 || ckpt_every < 1) return 0;
+  return plan_gradient(s, nsteps, ckpt_every).total + 256;
+}
+
 extern "C" gnor_status gnor_gradient(gnor_sim* s, int64_t nsteps, int32_t ckpt_every, int32_t m_target,
-                                     double* objective, double* grad) {
+                                     void* workspace, size_t workspace_bytes, double* objective,
+                                     double* grad) {
   gnor_status st = check_ready(s);
   if (st != GNOR_OK) return st;
   if (!s->design) return fail(s, GNOR_E_STATE, "no design region (gnor_set_design)");
   if (!grad || nsteps < 1 || ckpt_every < 1) return fail(s, GNOR_E_INVALID_ARG, "bad gradient arguments");
+  if (!workspace || (((uintptr_t)workspace) & 255u))
+    return fail(s, GNOR_E_INVALID_ARG, "workspace must be a 256-byte aligned device buffer");
+  if (workspace_bytes < plan_gradient(s, nsteps, ckpt_every).total)
+    return fail(s, GNOR_E_BUFFER_TOO_SMALL, "workspace smaller than gnor_gradient_required_bytes");
   if (m_target < 0 || m_target >= s->mon.nfreq) return fail(s, GNOR_E_INVALID_ARG, "m_target outside the frequency list");
   if (s->mon.dft_every > 1) return fail(s, GNOR_E_INVALID_ARG, "gradients need dft_every = 1");
   if (s->mat.ncp > 0) return fail(s, GNOR_E_INVALID_ARG, "gradients do not cover critical points");
@@ -1974,8 +2157,9 @@ extern "C" gnor_status gnor_gradient(gnor_sim* s, int64_t nsteps, int32_t ckpt_e
   const int mode = s->mode;
   st = set_mode(s, 0);
   if (st != GNOR_OK) return st;
-  st = s->g.precision == GNOR_FP32 ? gradient_impl<float>(s, nsteps, ckpt_every, m_target, objective, grad)
-                                   : gradient_impl<double>(s, nsteps, ckpt_every, m_target, objective, grad);
+  char* ws = static_cast<char*>(workspace);
+  st = s->g.precision == GNOR_FP32 ? gradient_impl<float>(s, nsteps, ckpt_every, m_target, ws, objective, grad)
+                                   : gradient_impl<double>(s, nsteps, ckpt_every, m_target, ws, objective, grad);
   const gnor_status st2 = set_mode(s, mode);
   return st != GNOR_OK ? st : st2;
 }

@@ -158,3 +158,21 @@ def test_material_rejects_bad_critical_points(lib):
     assert lib.gnor_set_material(h, mp, C.byref(m)) == 0
     assert lib.gnor_set_fused(h, 1) == 1
     lib.gnor_destroy(h)
+
+
+def test_new_entry_points_validate_on_the_host(lib):
+    """Host-side checks of the caller-buffer and watchdog entry points (no
+    device work: each returns before any HIP call)."""
+    w = W.config1(0)
+    st, h = _create(lib, _grid(w))
+    assert st == 0
+    assert lib.gnor_set_watchdog(h, 2) == 1
+    assert lib.gnor_set_watchdog(h, 0) == 0
+    assert lib.gnor_gradient_required_bytes(h, 100, 10) == 0  # not bound, no design region
+    assert lib.gnor_batch_required_bytes(0, None) == 0
+    arr = (C.c_void_p * 1)(h.value)
+    out = C.c_void_p()
+    assert lib.gnor_batch_create(1, arr, None, None, 0, C.byref(out)) == 1  # no table
+    assert lib.gnor_update_design(h, None) == 5  # not bound
+    assert lib.gnor_flush_spectra(h) == 5
+    lib.gnor_destroy(h)

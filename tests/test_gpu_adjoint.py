@@ -99,3 +99,37 @@ def test_gradient_fp32_close_to_fp64_and_autograd(B):
     L = F.apply(rho, s64, w.steps, 100, m)
     L.backward()
     assert np.allclose(rho.grad.numpy(), g64, rtol=1e-12, atol=0)
+
+
+def read_golden_directional():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "config5_small_oracle_directional.txt")
+    rows = []
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            seed, val, der = line.split()
+            rows.append((int(seed), float(val), float(der)))
+    return rows
+
+
+def test_config5_copy_gradient_vs_oracle_golden(B):
+    """The adjoint workload's 48^3 copy over its full 6000 steps: the GPU
+    gradient projected on the three seeded directions against the oracle's
+    exact dual-number derivatives (tests/golden, written by an oracle-only
+    script), FP64 to 1e-8 and FP32 to 2e-3; the objectives too."""
+    from tests.golden.make_config5_small import M_TARGET, workload
+    w = workload()
+    rows = read_golden_directional()
+    assert len(rows) == 3
+    for prec, dtol, vtol in (("fp64", 1e-8, 1e-10), ("fp32", 2e-3, 1e-4)):
+        print(f"case config5 48^3 copy, {w.steps} steps, {prec} adjoint vs oracle golden", flush=True)
+        s = B.Sim(w, precision=prec)
+        obj, g = s.gradient(w.steps, 500, M_TARGET)
+        for seed, val, der in rows:
+            v = W.design_direction(g.shape, seed)
+            gd = float(np.sum(g * v))
+            print(f"  seed {seed}: L {obj:.12e} / {val:.12e}, dL {gd:.12e} / {der:.12e} "
+                  f"(rel {abs(gd - der) / abs(der):.2e})", flush=True)
+            assert abs(obj - val) <= vtol * abs(val)
+            assert abs(gd - der) <= dtol * abs(der)
+        s.close()

@@ -101,19 +101,46 @@ def test_batch_with_streamed_stores_bitwise(B):
 
 
 def test_batch_instance_vs_oracle(B):
+    """Every instance of an FP64 batch (a 128^3 sphere, a 192^3 gap dimer with
+    flux boxes, a 104^3 sphere) against the oracle after 320 steps: the
+    incident front, which starts with the pulse at t = 0, crosses the last
+    metal plane of the largest instance (plane 129) after about 2 (129 + 3) =
+    264 steps, so every particle has responded.  All nine fields and the four
+    spectra; and in every instance the metal's current reaches a stated
+    fraction of eps0 wp e0 (the current a unit field drives at the plasma
+    frequency)."""
     ws = instances(count=3, seed=1)
-    print("case batch fp64 vs oracle", flush=True)
+    steps = 320
+    print(f"case batch fp64 vs oracle, {steps} steps: {[w.name for w in ws]}", flush=True)
     sims = [B.Sim(w, precision="fp64") for w in ws]
     bt = B.Batch(sims)  # the default batch tiling (XCD-aware order, rotated starts)
-    bt.run(120)
+    bt.run(steps)
     bt.synchronize()
+    eps0 = 8.8541878128e-12
     for w, s in zip(ws, sims):  # every instance, the gap dimer included
         print(f"  instance {w.name}", flush=True)
-        o = orc.OracleSim(oracle_problem(w, threads=8), oracle_mask(w))
-        o.run(120)
-        for f in ("Ex", "Hy", "Jx", "Jz"):
-            assert rel_l2(s.field(f), o.get(f)) <= 1e-10, (w.name, f)
-        assert rel_l2(s.spectra()["ext"], o.spectra()["ext"]) <= 1e-10, w.name
+        m = oracle_mask(w)
+        top = int(np.nonzero(m.any(axis=(1, 2)))[0].max())
+        assert steps >= 2 * (top + 3) + 40, (w.name, top)
+        o = orc.OracleSim(oracle_problem(w, threads=8), m)
+        o.run(steps)
+        ref = {f: o.get(f) for f in FIELDS}
+        for f in FIELDS:
+            a, b = s.field(f), ref[f]
+            # components that are rounding noise on both sides are measured
+            # against 1e-3 of the largest component of the same field
+            floor = 1e-3 * max(np.linalg.norm(ref[g]) for g in FIELDS if g[0] == f[0])
+            e = np.linalg.norm(a - b) / max(np.linalg.norm(b), floor)
+            assert e <= 1e-10, (w.name, f, e)
+        sg, so = s.spectra(), o.spectra()
+        for k in ("inc", "ext", "abs", "sca"):
+            assert rel_l2(sg[k], so[k]) <= 1e-10, (w.name, k)
+        if w.flux:
+            assert np.abs(so["abs"]).max() > 0 and np.abs(so["sca"]).max() > 0, w.name
+        jmax = float(np.abs(ref["Jx"][m & 1 != 0]).max())
+        print(f"    max|Jx| in the metal {jmax:.3e} A/m^2 = {jmax / (eps0 * w.wp * w.e0):.3f} eps0 wp e0",
+              flush=True)
+        assert jmax >= 0.05 * eps0 * w.wp * w.e0, w.name
         o.close()
 
 

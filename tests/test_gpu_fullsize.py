@@ -10,10 +10,14 @@ too slow, properties that hold at any size and FP32-vs-FP64 agreement.
   FP32 spectra within 1e-4 of the FP64 GPU path after 2400 steps and after
   the full 20 000; div H invariant in the FP64 run away from the TF surface
   and the CPML.
+* The sphere workload's 2x-coarsened copy (160^3 at dx = 0.2 nm, 10 000
+  steps): FP64 and FP32 spectra against the oracle's spectra of the same
+  copy, stored by an oracle-only script.
 * 640^3 star: the library's and the oracle's voxelisers agree bit for bit;
-  FP32 vs FP64 spectra after a short early-pulse run.
-* 160^3 design problem: FP32 adjoint gradient vs central differences of the
-  FP64 objective on random voxels.
+  FP32 vs FP64 spectra (all four) after a short early-pulse run.
+* 160^3 design problem over its full 6000 steps: the FP64 adjoint gradient
+  against central differences on 32 random voxels (each error against its
+  own difference), the FP32 adjoint against the FP64 one.
 * 64-instance batch in the benchmark's launch configuration: sampled
   instances equal their single runs bit for bit.
 """
@@ -144,6 +148,38 @@ def test_sphere320_full_length_fp32_vs_fp64(B):
     assert np.all(np.isfinite(ext)) and ext.max() > 0
 
 
+def read_golden_spectra(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = np.array([[float(v) for v in line.split()] for line in open(path)
+                     if line.strip() and not line.startswith("#")])
+    return dict(omega=rows[:, 0], inc=rows[:, 1], ext=rows[:, 2], abs=rows[:, 3], sca=rows[:, 4])
+
+
+def test_sphere_coarse_copy_vs_oracle_golden(B):
+    """The 320^3 sphere workload's 2x-coarsened copy (160^3 at dx = 0.2 nm,
+    8-cell CPML, the same particle, 10 000 steps = the same 3.3 fs) against
+    the FP64 oracle's spectra of the same copy (tests/golden, written by an
+    oracle-only script): FP64 to 1e-10, FP32 to 1e-4 on inc, ext, abs and
+    sca."""
+    import torch
+    gold = read_golden_spectra("config2_coarse_oracle_spectra.txt")
+    w = W.config2_coarse()
+    assert w.steps == 10000 and np.allclose(gold["omega"], w.omega, rtol=1e-15)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        print(f"case 160^3 coarsened sphere, {w.steps} steps, {prec} vs oracle golden", flush=True)
+        s = B.Sim(w, precision=prec)
+        s.run(w.steps)
+        sp = s.spectra()
+        s.close()
+        torch.cuda.empty_cache()
+        for k in ("inc", "ext", "abs", "sca"):
+            e = rel_l2(sp[k], gold[k])
+            print(f"  {k}: rel-L2 {e:.3e}", flush=True)
+            assert e <= tol, (prec, k, e)
+    assert gold["ext"].max() > 0 and gold["sca"].max() > 0
+
+
 def test_star640_masks_and_fp32_vs_fp64(B):
     import torch
     w = W.early_pulse(W.config3(seed=0))
@@ -153,7 +189,10 @@ def test_star640_masks_and_fp32_vs_fp64(B):
     m_orc = oracle_mask(w)
     assert np.array_equal(m_lib, m_orc)
     del m_orc
-    steps = 600
+    # 1000 steps: the scattered flux is then far above the FP32 rounding of
+    # the total-minus-incident cancellation at the TF surface (after 600
+    # steps sigma_sca differed by 9.9e-5 between FP32 and FP64)
+    steps = 1000
     out = {}
     for prec in ("fp32", "fp64"):
         s = B.Sim(w, precision=prec, mask=m_lib)
@@ -162,41 +201,72 @@ def test_star640_masks_and_fp32_vs_fp64(B):
         s.close()
         torch.cuda.empty_cache()
     assert out["fp32"][1] and out["fp64"][1]
-    for k in ("inc", "ext"):
+    for k in ("inc", "ext", "abs", "sca"):
         e = rel_l2(out["fp32"][0][k], out["fp64"][0][k])
         print(f"  {k}: fp32 vs fp64 rel-L2 {e:.3e}", flush=True)
         assert e <= 1e-4
+    assert np.abs(out["fp64"][0]["sca"]).max() > 0
 
 
-def test_design160_fp32_gradient_vs_fd(B):
-    w = W.early_pulse(W.config5(0))
+def test_design160_gradient_vs_fd_on_32_voxels(B):
+    """The adjoint workload as stated: 160^3, 60^3 design region, objective
+    sigma_ext at 2.5 eV, 6000 steps, checkpoints every 500.  The FP64 adjoint
+    against FP64 central differences (Richardson-extrapolated from steps h
+    and h/2) on 32 seeded random voxels, each error measured against that
+    voxel's own difference (floor: the objective's FP64 rounding over the
+    run divided by the step); the FP32 adjoint against the FP64 adjoint over
+    the whole region and voxel by voxel."""
+    import torch
+    w = W.config5(0)
     w.omega = W.spectrum_omegas(9, 2.0, 3.0)  # 2.5 eV is index 4
     m = 4
-    steps = 3000
-    print(f"case 160^3 design gradient fp32 ({steps} steps, checkpoints every 500) vs fd(fp64)",
-          flush=True)
-    s32 = B.Sim(w, precision="fp32")
-    obj, g = s32.gradient(steps, 500, m)
+    steps = w.steps
+    assert steps == 6000
+    print(f"case 160^3 design gradient ({steps} steps, checkpoints every 500): fp64 adjoint vs fd "
+          "on 32 voxels, fp32 adjoint vs fp64", flush=True)
     s64 = B.Sim(w, precision="fp64")
+    obj64, g64 = s64.gradient(steps, 500, m)
+    s32 = B.Sim(w, precision="fp32")
+    obj32, g32 = s32.gradient(steps, 500, m)
+    s32.close()
+    torch.cuda.empty_cache()
+    e32 = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    gmax = float(np.abs(g64).max())
+    print(f"  objective fp64 {obj64:.6e} fp32 {obj32:.6e}; gradient fp32 vs fp64 rel-L2 {e32:.2e}",
+          flush=True)
+    assert abs(obj32 - obj64) <= 1e-4 * abs(obj64)
+    assert e32 <= 5e-3
+    assert np.all(np.abs(g32 - g64) <= 0.05 * np.abs(g64) + 5e-3 * gmax)
     rho0 = np.array(w.rho, dtype=np.float32)
     rng = np.random.default_rng(11)
-    errs = []
-    for _ in range(6):
-        q = tuple(int(rng.integers(0, n)) for n in g.shape)
-        h = min(1.0 / 64.0, float(rho0[q]) / 2, (1.0 - float(rho0[q])) / 2)
+
+    def central(q, h):
         vals, pts = [], []
         for sgn in (+1, -1):
             r = rho0.copy()
             r[q] = np.float32(rho0[q] + sgn * h)
-            pts.append(float(r[q]))
+            pts.append(float(r[q]))  # the step actually taken in FP32
             s64.update_design(r)
             s64.reset()
             s64.run(steps)
             vals.append(s64.spectra()["ext"][m])
-        fd = (vals[0] - vals[1]) / (pts[0] - pts[1])
-        errs.append(abs(fd - g[q]) / np.abs(g).max())
-        print(f"  voxel {q}: adjoint(fp32) {g[q]:.6e} fd(fp64) {fd:.6e}", flush=True)
-    assert max(errs) <= 2e-3
+        return (vals[0] - vals[1]) / (pts[0] - pts[1])
+
+    # Richardson extrapolation of central differences at h and h/2 removes
+    # their O(h^2) truncation (3e-4 of the derivative at h = 1/256 on some
+    # voxels); the floor is the objective's FP64 rounding over the run
+    # divided by the smaller step
+    h0 = 1.0 / 512.0
+    for t in range(32):
+        q = tuple(int(rng.integers(0, n)) for n in g64.shape)
+        h = min(h0, float(rho0[q]) / 2, (1.0 - float(rho0[q])) / 2)
+        fd = (4.0 * central(q, h / 2) - central(q, h)) / 3.0
+        floor = 1e-13 * abs(obj64) / (h / 2)
+        err = abs(fd - g64[q]) / max(abs(fd), floor)
+        print(f"  voxel {q}: adjoint(fp64) {g64[q]:.8e} fd {fd:.8e} rel {err:.1e}; "
+              f"adjoint(fp32) {g32[q]:.6e}", flush=True)
+        assert err <= 1e-4, (q, g64[q], fd)
+        assert np.sign(g32[q]) == np.sign(g64[q]) or abs(g64[q]) <= 5e-3 * gmax
 
 
 def test_config4_batch_in_the_benchmark_launch(B):
