@@ -56,8 +56,8 @@ def main():
                  "# (oracle only).  Columns: omega [rad/s], inc [(V s/m)^2], ext, abs,\n"
                  "# sca [m^2].\n")
         for m in range(len(w.omega)):
-            fh.write(f"{w.omega[m]!r} {sp['inc'][m]!r} {sp['ext'][m]!r} {sp['abs'][m]!r} "
-                     f"{sp['sca'][m]!r}\n")
+            row = (w.omega[m], sp["inc"][m], sp["ext"][m], sp["abs"][m], sp["sca"][m])
+            fh.write(" ".join(repr(float(v)) for v in row) + "\n")
     os.replace(OUT + ".tmp", OUT)
     print(f"wrote {OUT} ({time.time() - t0:.0f} s)")
     assert np.all(np.isfinite(sp["ext"]))

@@ -70,7 +70,7 @@ def main():
                  "# make_config5_small.py (oracle only).\n"
                  "# Columns: direction seed, objective [m^2], derivative along v [m^2].\n")
         for seed, val, der in rows:
-            fh.write(f"{seed} {val!r} {der!r}\n")
+            fh.write(f"{seed} {float(val)!r} {float(der)!r}\n")
     os.replace(OUT + ".tmp", OUT)
     print(f"wrote {OUT} ({time.time() - t0:.0f} s)")
 
