@@ -271,8 +271,12 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * fused pass for the tiles that meet no CPML slab (classes 0 and 2; class 2
  * stays two-sweep with critical points), then the auxiliary line, then the
  * E/J sweep of the CPML classes, whose H sweep ran alongside the fused
- * tiles.  All forms give the same fields up to rounding; batches and
- * gnor_gradient always use the two-sweep form.
+ * tiles; gnor_set_fused(sim, 3) the same order with only class 0 (here
+ * without x-slab tiles) in one pass, by a lighter kernel whose wavefronts
+ * recompute their halo H instead of sharing it (no barriers), and the metal
+ * and CPML classes in two sweeps (critical points and a substrate allowed).
+ * All forms give the same fields up to rounding; batches and gnor_gradient
+ * always use the two-sweep form.
  * gnor_profile_kernels times each sweep as it runs: with concurrent class
  * launches (the default, see gnor_set_class_streams) a sweep is timed from its
  * fork to its join; with serial class launches, count >= 14 also returns
@@ -283,8 +287,8 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * tiles and H sweeps) and ms[1] the second (auxiliary line and E/J sweeps).
  * gnor_tile_classes writes the number of tiles of each class of the current
  * tiling to counts[0..3] (valid once the memory is bound).
- * gnor_set_fused: on must be 0, 1 or 2 (INVALID_ARG otherwise; 1 also with
- * critical points). */
+ * gnor_set_fused: on must be 0, 1, 2 or 3 (INVALID_ARG otherwise; 1 also
+ * with critical points, 1 and 2 also with a substrate). */
 gnor_status gnor_set_fused(gnor_sim *sim, int32_t on);
 
 /* The four tile-class launches of a sweep run concurrently (on = 1, the

@@ -19,6 +19,7 @@ COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
 SOURCES = [
     ("gnor_sweeps.hip", []),
     ("gnor_fused.hip", []),
+    ("gnor_fplain.hip", []),
     # matrix-core accumulators in ordinary VGPRs: with the accumulation
     # registers the loop-carried sums were copied out and back every step
     ("gnor_spectra.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]),

@@ -308,6 +308,10 @@ void launch_ej_class(const Params<T>& p, const AuxParams& a, int sub, int c, hip
 template <class T>
 void launch_step_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s);
 void launch_aux(const AuxParams& a, int sub, hipStream_t s);
+// one-pass step of the plain tiles (class 0 without CPML; gnor_fplain.hip),
+// before the auxiliary line's step
+template <class T>
+void launch_fplain(const Params<T>& p, const AuxParams& a, hipStream_t s);
 template <class T>
 void launch_step(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s);
 template <class T>

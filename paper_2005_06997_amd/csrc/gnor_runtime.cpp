@@ -99,7 +99,9 @@ struct gnor_sim {
   gnor::Tiling tl{};                              // that tiling with its tile classes
   std::vector<int> tile_list;                     // the classes' tile lists (host copy)
   std::vector<int> rowx;                          // x extent of the metal points per (y, z) row
-  int mode = 0;  // step form: 0 H and E/J sweeps, 1 one-pass fused step, 2 hybrid (see hybrid_fused)
+  // step form: 0 H and E/J sweeps, 1 one-pass fused step, 2 hybrid, 3 fused
+  // plain tiles (see hybrid_fused)
+  int mode = 0;
   gnor_map_desc maps{};                           // near-field / density maps (nmap = 0: off)
   std::vector<double> map_omega;
   Layout L;
@@ -511,7 +513,12 @@ void enqueue_classes(gnor_sim* s, hipStream_t st, F launch) {
 //   2. the auxiliary line (after every reader of E_inc^n);
 //   3. E/J sweeps of the two-sweep classes (they read H^{n+1/2} of fused
 //      neighbours and H_inc^{n+1/2}).
-bool hybrid_fused(const gnor_sim* s, int c) { return c == 0 || (c == 2 && s->mat.ncp == 0); }
+// Form 3: only the plain tiles (no metal, no CPML slab within one cell) take
+// the one-pass kernel of gnor_fplain.hip, metal and CPML tiles the two sweeps.
+bool hybrid_fused(const gnor_sim* s, int c) {
+  if (s->mode == 3) return c == 0;
+  return c == 0 || (c == 2 && s->mat.ncp == 0);
+}
 
 // First half of a step: the H sweep (mode 0), the fused step (mode 1), or
 // phase 1 of the hybrid form.
@@ -520,10 +527,11 @@ void enqueue_first(gnor_sim* s, const gnor::Params<T>& p, const gnor::AuxParams&
                    hipStream_t st) {
   if (mode == 1) {
     enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_step_class<T>(p, a, c, q); });
-  } else if (mode == 2) {
+  } else if (mode == 2 || mode == 3) {
     enqueue_classes(s, st, [&](int c, hipStream_t q) {
-      if (hybrid_fused(s, c)) gnor::launch_step_class<T>(p, a, c, q);
-      else gnor::launch_h_class<T>(p, a, c, q);
+      if (!hybrid_fused(s, c)) gnor::launch_h_class<T>(p, a, c, q);
+      else if (mode == 3) gnor::launch_fplain<T>(p, a, q);
+      else gnor::launch_step_class<T>(p, a, c, q);
     });
   } else {
     enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_h_class<T>(p, a, c, q); });
@@ -536,7 +544,7 @@ void enqueue_second(gnor_sim* s, const gnor::Params<T>& p, const gnor::AuxParams
                     hipStream_t st) {
   if (mode == 1) {
     gnor::launch_aux(a, sub, st);
-  } else if (mode == 2) {
+  } else if (mode == 2 || mode == 3) {
     gnor::launch_aux(a, sub, st);
     enqueue_classes(s, st, [&](int c, hipStream_t q) {
       if (!hybrid_fused(s, c)) gnor::launch_ej_class<T>(p, a, sub, c, q);
@@ -623,6 +631,11 @@ gnor_status upload_rho(gnor_sim* s) {
   return GNOR_OK;
 }
 
+// Do the tiles that meet only an x slab join class 0?  Yes for the step forms
+// whose class-0 kernels carry the x-slab CPML (the two-sweep plain kernels and
+// the one-pass plain kernel of form 3), no for the fused kernel of forms 1, 2.
+bool merge_x_slabs(int mode) { return mode == 0 || mode == 3; }
+
 // Tile classes of the current tiling and step form; uploaded when the memory
 // is bound (after the stream's queued steps, which read the old lists).
 gnor_status plan_tiles(gnor_sim* s) {
@@ -646,7 +659,7 @@ gnor_status plan_tiles(gnor_sim* s) {
   // x-slab tiles join the plain class only in the two-sweep form: the fused
   // and hybrid forms run class 0 on the fused kernel, which has no CPML
   gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->any_metal ? s->rowx.data() : nullptr,
-                       s->tile_list, s->mode == 0);
+                       s->tile_list, merge_x_slabs(s->mode));
   if (s->bound && !s->tile_list.empty()) {
     HIPCHECK(s, hipStreamSynchronize(s->stream));
     HIPCHECK(s, hipMemcpy(s->dev + s->L.tiles, s->tile_list.data(), s->tile_list.size() * 4,
@@ -658,7 +671,7 @@ gnor_status plan_tiles(gnor_sim* s) {
 // Change the step form; the class lists depend on it (see plan_tiles).
 gnor_status set_mode(gnor_sim* s, int mode) {
   if (mode == s->mode) return GNOR_OK;
-  const bool replan = (mode == 0) != (s->mode == 0);
+  const bool replan = merge_x_slabs(mode) != merge_x_slabs(s->mode);
   s->mode = mode;
   drop_graph(s);
   return replan ? plan_tiles(s) : GNOR_OK;
@@ -1069,10 +1082,10 @@ gnor_status gnor_set_class_streams(gnor_sim* s, int32_t on) {
 }
 
 gnor_status gnor_set_fused(gnor_sim* s, int32_t on) {
-  if (!s || on < 0 || on > 2) return GNOR_E_INVALID_ARG;
+  if (!s || on < 0 || on > 3) return GNOR_E_INVALID_ARG;
   if (on == 1 && s->have_material && s->mat.ncp > 0)
     return fail(s, GNOR_E_INVALID_ARG, "the fused step has no critical-point terms");
-  if (on != 0 && s->g.eps_substrate > 0.0)
+  if ((on == 1 || on == 2) && s->g.eps_substrate > 0.0)
     return fail(s, GNOR_E_INVALID_ARG, "the fused and hybrid step forms have no substrate");
   return set_mode(s, on);
 }
@@ -1438,7 +1451,7 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   const bool fp32 = s->g.precision == GNOR_FP32;
   const int mode = s->mode;
   const bool fused = mode == 1;
-  const bool whole = s->concurrent || mode == 2;  // each half timed as a whole
+  const bool whole = s->concurrent || mode >= 2;  // each half timed as a whole
   for (int64_t q = 0; q < nsteps; ++q) {
     const int64_t n = s->step;
     const int parity = (int)(n & 1);

@@ -84,7 +84,7 @@ def test_fp32_critical_points_vs_oracle(B):
     compare(g, o, w, 1e-3, 1e-4)
 
 
-@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("mode", [0, 2, 3])
 def test_critical_points_in_metal_cpml_class(B, mode):
     """A sphere across x tiles 0 and 1 of a 160-wide grid: tile 0 holds the
     low x slab (metal + CPML class), tile 1 no slab (metal class), so both

@@ -149,13 +149,14 @@ def test_fused_and_two_sweep_forms_agree(B, prec):
     assert runs[0].profile(2)["fused"] and not runs[1].profile(2)["fused"]
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_metal_across_x_tiles_vs_oracle(B, mode):
     """A sphere straddling the boundary between x tiles 0 and 1 of a 160-wide
     grid: tile 0 holds the low x slab (class metal + CPML), tile 1 no slab
     (class metal).  Step forms: two sweeps, fused, hybrid (the metal tile
     fused, its metal + CPML neighbour two-sweep: each reads the other's H and
-    node scalars)."""
+    node scalars), fused plain tiles (plain tiles in one pass beside
+    two-sweep metal and CPML tiles)."""
     n, dx, r = 160, 0.25e-9, 2.0e-9
     c = np.array([62.3, 23.5, 23.2])
     w = W.sphere_problem("wrap", n, dx, 8, c, r, steps=300)
@@ -173,12 +174,12 @@ def test_metal_across_x_tiles_vs_oracle(B, mode):
     compare(g, o, 1e-10, 1e-10)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_hybrid_and_two_sweep_forms_agree(B, prec):
+@pytest.mark.parametrize("prec,mode", [("fp32", 2), ("fp64", 2), ("fp32", 3), ("fp64", 3)])
+def test_hybrid_and_two_sweep_forms_agree(B, prec, mode):
     """A 192 x 96 x 80 grid with a sphere across x tiles 0 and 1: every tile
-    class occurs; the hybrid form (fused where no CPML slab is met) and the
-    two-sweep form give the same fields and spectra up to rounding, through
-    graph chunks and eager steps."""
+    class occurs; the hybrid form (fused where no CPML slab is met), the form
+    with fused plain tiles and the two-sweep form give the same fields and
+    spectra up to rounding, through graph chunks and eager steps."""
     n, dx, r = 192, 0.25e-9, 3.0e-9
     c = np.array([66.3, 47.6, 39.2])
     w = W.sphere_problem("hybrid", n, dx, 8, c, r, steps=260)
@@ -186,11 +187,11 @@ def test_hybrid_and_two_sweep_forms_agree(B, prec):
     w = W._boxes(w, c * dx - r, c * dx + r)
     w = W.early_pulse(w)
     w.omega = W.spectrum_omegas(16)
-    say(f"case hybrid vs two-sweep 192x96x80, {prec}")
+    say(f"case step form {mode} vs two-sweep 192x96x80, {prec}")
     runs = []
-    for mode in (0, 2):
+    for m in (0, mode):
         g = B.Sim(w, precision=prec)
-        g.set_mode(mode)
+        g.set_mode(m)
         g.run(w.steps)
         runs.append(g)
     assert min(runs[1].tile_classes()) > 0
@@ -200,11 +201,33 @@ def test_hybrid_and_two_sweep_forms_agree(B, prec):
     for f in FIELDS:
         scale = max(np.linalg.norm(fa[g]) for g in FIELDS if g[0] == f[0])
         d = np.linalg.norm(fa[f] - fb[f]) / scale
-        say(f"  {f}: hybrid vs two-sweep {d:.2e}")
+        say(f"  {f}: form {mode} vs two-sweep {d:.2e}")
         assert d <= agree, f
     sa, sb = runs[0].spectra(), runs[1].spectra()
     for k in ("inc", "ext", "abs", "sca"):
         assert rel_l2(sb[k], sa[k]) <= agree, k
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", (1e-10, 1e-10)), ("fp32", (1e-3, 1e-4))])
+def test_fused_plain_tiles_at_the_grid_walls_vs_oracle(B, prec, tol):
+    """No CPML (a PEC box): the plain tiles of the one-pass kernel touch the
+    walls on every face, and the grid is ragged in x (72 = 64 + 8) and y, so
+    the kernel's range guards and clamped halo loads all act; against the
+    oracle, with a sphere inside the TF box."""
+    c = np.array([35.3, 20.2, 21.6])
+    w = W.sphere_problem("walls", 72, 0.25e-9, 0, c, 1.6e-9, steps=240)
+    w.ny, w.nz = 41, 44
+    w = W._boxes(w, c * 0.25e-9 - 1.6e-9, c * 0.25e-9 + 1.6e-9)
+    w = W.early_pulse(w)
+    w.omega = W.spectrum_omegas(16)
+    say(f"case fused plain tiles at the walls 72x41x44, {prec}")
+    g = B.Sim(w, precision=prec)
+    g.set_mode(3)
+    g.set_tiling(2, 4, 0)
+    assert g.tile_classes()[0] > 0
+    g.run(w.steps)
+    o = oracle_run(w, w.steps)
+    compare(g, o, *tol)
 
 
 def test_fp64_vacuum_no_metal(B):

@@ -55,11 +55,15 @@ def compare(g, o, ftol, stol):
         assert worst[k] <= stol, (k, worst[k])
 
 
-@pytest.mark.parametrize("prec,seed", [("fp64", 0), ("fp64", 3), ("fp32", 1)])
-def test_sphere_on_substrate_vs_oracle(B, prec, seed):
+@pytest.mark.parametrize("prec,seed,mode", [("fp64", 0, 0), ("fp64", 3, 0), ("fp32", 1, 0),
+                                            ("fp64", 0, 3)])
+def test_sphere_on_substrate_vs_oracle(B, prec, seed, mode):
+    """Step form 3 (plain tiles in one pass) takes the substrate's per-plane
+    coefficients in its own kernel."""
     w = on_substrate(seed)
-    say(f"case {prec} sphere on substrate, seed {seed}, plane {w.sub_k}")
+    say(f"case {prec} sphere on substrate, seed {seed}, plane {w.sub_k}, step form {mode}")
     g = B.Sim(w, precision=prec)
+    g.set_mode(mode)
     g.run(w.steps)
     o = orc.OracleSim(oracle_problem(w, threads=8), oracle_mask(w))
     o.run(w.steps)
