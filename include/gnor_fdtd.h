@@ -382,6 +382,21 @@ gnor_status gnor_gradient(gnor_sim *sim, int64_t nsteps, int32_t ckpt_every, int
 size_t gnor_batch_required_bytes(int32_t n, gnor_sim *const *sims);
 gnor_status gnor_batch_create(int32_t n, gnor_sim *const *sims, void *hip_stream, void *table,
                               size_t table_bytes, gnor_batch **out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batch as gnor_batch_create, with its parameter tables in the library's one
+ * static device buffer instead of a caller buffer.  That buffer is 1 MiB per
+ * GPU, held until the process ends, and takes at most 128 instances (more:
+ * GNOR_E_BUFFER_TOO_SMALL).  The call allocates nothing and creates no
+ * streams or events: hip_stream must be a stream the caller made (NULL:
+ * GNOR_E_INVALID_ARG), and the batch launches its tile classes one after
+ * another on it.  Every static batch on a GPU shares that GPU's buffer: a
+ * new one waits for the previous one's queued work, then takes the buffer
+ * over, and the previous one is refused from then on (gnor_batch_run:
+ * GNOR_E_STATE).  Calls on one GPU from two host threads at once race.
+ * Results equal gnor_batch_create's, bit for bit. */
+gnor_status gnor_batch_create_static(int32_t n, gnor_sim *const *sims, void *hip_stream,
+                                     gnor_batch **out);
 gnor_status gnor_batch_run(gnor_batch *batch, int64_t nsteps);
 gnor_status gnor_batch_synchronize(gnor_batch *batch);
 gnor_status gnor_batch_set_graph_chunk(gnor_batch *batch, int32_t steps);

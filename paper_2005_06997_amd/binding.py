@@ -130,6 +130,7 @@ def load() -> C.CDLL:
         "gnor_gradient": (i32, [vp, i64, i32, i32, vp, sz, dp, vp]),
         "gnor_batch_required_bytes": (sz, [i32, vp]),
         "gnor_batch_create": (i32, [i32, vp, vp, vp, sz, C.POINTER(vp)]),
+        "gnor_batch_create_static": (i32, [i32, vp, vp, C.POINTER(vp)]),
         "gnor_batch_run": (i32, [vp, i64]),
         "gnor_batch_synchronize": (i32, [vp]),
         "gnor_batch_set_graph_chunk": (i32, [vp, i32]),

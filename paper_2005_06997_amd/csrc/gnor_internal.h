@@ -346,6 +346,14 @@ void launch_density(const T* pp, const T* jx, const T* jy, const T* jz, const in
                     double* out, hipStream_t s);
 // zero `bytes` (a multiple of 4) with a kernel (graph-safe clear)
 void launch_fill_zero(void* a, size_t bytes, hipStream_t s);
+
+// The library's one static device buffer: the parameter tables of a batch
+// made by gnor_batch_create_static, at most kStaticBatchMax instances.
+constexpr size_t kStaticTableBytes = size_t(1) << 20;
+constexpr int kStaticBatchMax = 128;
+// Device address of the current device's copy (looked up once per device,
+// with that device current) and the device's ordinal.
+hipError_t static_table_address(int* device, void** addr);
 Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
 // Classify the tiles (metal: a metal point within two cells, by the per-row
 // x extents rowx of the metal points, null = no metal; CPML: slabs of np

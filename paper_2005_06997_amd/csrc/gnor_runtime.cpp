@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1735,7 +1736,10 @@ struct gnor_batch {
   char* tab = nullptr;       // two tables of n entries (parity 0, parity 1), caller memory
   size_t entry_bytes = 0;
   int hblocks[gnor::kClasses] = {0, 0, 0, 0}, dblocks = 0;
-  // concurrent class launches, as for a single simulation
+  // concurrent class launches, as for a single simulation (serial on the
+  // batch's stream for a batch made by gnor_batch_create_static)
+  bool concurrent = true;
+  int static_dev = -1;       // device whose static table this batch uses (-1: caller table)
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   std::vector<int> tiling;   // (ty, kz, order) of every instance at creation
@@ -1815,6 +1819,10 @@ void batch_enqueue(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st) {
     const gnor::BatchEntry<T>* t = tabs + (size_t)(n & 1) * b->n;
     const int sub = (int)q;
     auto classes = [&](auto launch) {
+      if (!b->concurrent) {
+        for (int c = 0; c < gnor::kClasses; ++c) launch(c, st);
+        return;
+      }
       (void)hipEventRecord(b->ev_fork, st);
       for (int q2 = 0; q2 < 2; ++q2) (void)hipStreamWaitEvent(b->side[q2], b->ev_fork, 0);
       launch(0, st);
@@ -1856,16 +1864,23 @@ size_t gnor_batch_required_bytes(int32_t n, gnor_sim* const* sims) {
   return batch_table_bytes(n, sims[0]->g.precision == GNOR_FP32);
 }
 
-gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, void* table,
-                              size_t table_bytes, gnor_batch** out) {
-  if (!out || n < 1 || !sims || !table) return GNOR_E_INVALID_ARG;
-  *out = nullptr;
-  if (!sims[0] || table_bytes < batch_table_bytes(n, sims[0]->g.precision == GNOR_FP32) ||
-      (((uintptr_t)table) & 255u))
-    return GNOR_E_BUFFER_TOO_SMALL;
+}  // extern "C"
+
+namespace {
+
+// The batch that currently owns each device's static table (null: none).
+std::mutex g_static_mutex;
+gnor_batch* g_static_owner[64] = {};
+
+// Shared by both creation calls.  concurrent: fork the class launches onto
+// two side streams (the static variant creates no streams or events and
+// launches the classes one after another on the caller's stream).
+gnor_status batch_create_impl(int32_t n, gnor_sim* const* sims, void* stream, void* table,
+                              bool concurrent, gnor_batch** out) {
   gnor_batch* b = new (std::nothrow) gnor_batch();
   if (!b) return GNOR_E_OUT_OF_MEMORY;
   b->n = n;
+  b->concurrent = concurrent;
   for (int q = 0; q < n; ++q) {
     gnor_sim* s = sims[q];
     if (!s || !s->bound || s->maps.nmap > 0) { delete b; return GNOR_E_STATE; }  // no maps in batches
@@ -1891,28 +1906,72 @@ gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, vo
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) { delete b; return GNOR_E_DEVICE; }
     b->own_stream = true;
   }
-  for (int q = 0; q < 2; ++q) {
-    if (hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_join[q], kJoinEventFlags) != hipSuccess) {
+  if (concurrent) {
+    for (int q = 0; q < 2; ++q) {
+      if (hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&b->ev_join[q], kJoinEventFlags) != hipSuccess) {
+        gnor_batch_destroy(b);
+        return GNOR_E_DEVICE;
+      }
+    }
+    if (hipEventCreateWithFlags(&b->ev_fork, kJoinEventFlags) != hipSuccess) {
       gnor_batch_destroy(b);
       return GNOR_E_DEVICE;
     }
   }
-  if (hipEventCreateWithFlags(&b->ev_fork, kJoinEventFlags) != hipSuccess) {
-    gnor_batch_destroy(b);
-    return GNOR_E_DEVICE;
-  }
   // the instances' own queued work must be complete before the batch runs
   for (gnor_sim* s : b->sims)
-    if (hipStreamSynchronize(s->stream) != hipSuccess) { delete b; return GNOR_E_DEVICE; }
+    if (hipStreamSynchronize(s->stream) != hipSuccess) { gnor_batch_destroy(b); return GNOR_E_DEVICE; }
   const gnor_status st = b->fp32 ? batch_tables<float>(b) : batch_tables<double>(b);
   if (st != GNOR_OK) { gnor_batch_destroy(b); return st; }
   *out = b;
   return GNOR_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+gnor_status gnor_batch_create(int32_t n, gnor_sim* const* sims, void* stream, void* table,
+                              size_t table_bytes, gnor_batch** out) {
+  if (!out || n < 1 || !sims || !table) return GNOR_E_INVALID_ARG;
+  *out = nullptr;
+  if (!sims[0] || table_bytes < batch_table_bytes(n, sims[0]->g.precision == GNOR_FP32) ||
+      (((uintptr_t)table) & 255u))
+    return GNOR_E_BUFFER_TOO_SMALL;
+  return batch_create_impl(n, sims, stream, table, true, out);
+}
+
+gnor_status gnor_batch_create_static(int32_t n, gnor_sim* const* sims, void* stream, gnor_batch** out) {
+  if (!out || n < 1 || !sims || !sims[0] || !stream) return GNOR_E_INVALID_ARG;
+  *out = nullptr;
+  if (n > gnor::kStaticBatchMax) return GNOR_E_BUFFER_TOO_SMALL;
+  const size_t need = batch_table_bytes(n, sims[0]->g.precision == GNOR_FP32);
+  if (need > gnor::kStaticTableBytes) return GNOR_E_BUFFER_TOO_SMALL;
+  int dev = 0;
+  void* tab = nullptr;
+  if (gnor::static_table_address(&dev, &tab) != hipSuccess) return GNOR_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_static_mutex);
+  // the batch that held this device's table must have finished reading it
+  gnor_batch* prev = g_static_owner[dev];
+  if (prev && hipStreamSynchronize(prev->stream) != hipSuccess) return GNOR_E_DEVICE;
+  gnor_batch* b = nullptr;
+  const gnor_status st = batch_create_impl(n, sims, stream, tab, false, &b);
+  if (st != GNOR_OK) return st;
+  b->static_dev = dev;
+  g_static_owner[dev] = b;  // `prev` (if any) is refused from now on
+  *out = b;
+  return GNOR_OK;
+}
+
 void gnor_batch_destroy(gnor_batch* b) {
   if (!b) return;
+  if (b->static_dev >= 0) {
+    // its queued kernels read the device's static table: let them finish
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    (void)hipStreamSynchronize(b->stream);
+    if (g_static_owner[b->static_dev] == b) g_static_owner[b->static_dev] = nullptr;
+  }
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   for (int q = 0; q < 2; ++q) {
@@ -1934,6 +1993,11 @@ gnor_status gnor_batch_set_graph_chunk(gnor_batch* b, int32_t steps) {
 
 gnor_status gnor_batch_run(gnor_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return GNOR_E_INVALID_ARG;
+  if (b->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    if (g_static_owner[b->static_dev] != b)
+      return bfail(b, GNOR_E_STATE, "a later gnor_batch_create_static on this GPU took over the static table");
+  }
   for (size_t q = 0; q < b->sims.size(); ++q) {
     const gnor_sim* s = b->sims[q];
     if (s->step != b->step) return bfail(b, GNOR_E_STATE, "an instance was stepped outside the batch");

@@ -9,11 +9,25 @@
 //   k_density         n - n0 = div P_f^n / e at the sub-grid's nodes (Eq. Nsol),
 //                     from the node scalar Phi~_P^{n-1} of the last H sweep and
 //                     the node divergence of J^{n-1/2} (P^n - P^{n-1} = dt J)
+// and the static device buffer of gnor_batch_create_static.
 #include "gnor_internal.h"
+
+#include <mutex>
+
+// Parameter tables of a batch made by gnor_batch_create_static (callers that
+// cannot allocate device memory).  One copy per GPU, held until the process
+// ends.  In host code this name is only a stand-in: the device address of a
+// GPU's copy is looked up once per device (static_table_address) and only
+// that address is ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[gnor::kStaticTableBytes];
 
 namespace gnor {
 
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
 
 __global__ void __launch_bounds__(256) k_design_check(const float* __restrict__ rho, size_t n,
                                                       int* flag) {
@@ -88,6 +102,24 @@ template void launch_density<float>(const float*, const float*, const float*, co
                                     const int[3], double, double*, hipStream_t);
 template void launch_density<double>(const double*, const double*, const double*, const double*,
                                      const int[3], double, double*, hipStream_t);
+hipError_t static_table_address(int* device, void** addr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[dev]) {
+    // with device `dev` current: the address of this device's copy
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = p;
+  }
+  *device = dev;
+  *addr = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
 void launch_fill_zero(void* a, size_t bytes, hipStream_t s) {
   const size_t nw = bytes / 4;
   hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(nw)), dim3(256), 0, s, static_cast<uint32_t*>(a), nw);
