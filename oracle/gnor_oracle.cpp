@@ -43,6 +43,11 @@
 //     incident field, and of tangential E and H on two flux boxes
 //     (absorption: total field inside the TF box; scattering: scattered
 //     field outside it).
+//   * Total-field operation, for metal that reaches the boundary (a plasmonic
+//     substrate) where TF/SF cannot hold it: a soft plane source on E_x of
+//     one node plane, and the remedy the end of Sec. III gives -- metal
+//     inside the absorbing layers follows the local (LRA) Drude model, the
+//     nonlocal model holds everywhere else.
 //   * Near-field and free-electron density maps on one grid plane (the field
 //     and density distributions of Sec. V): running transforms of E_x, E_y,
 //     E_z at their Yee points of the plane (stamped (n+1) dt) and of the
@@ -136,6 +141,14 @@ typedef struct {
   // permittivity eps_sub when eps_sub > 0 (0: uniform background eps_b)
   double eps_sub;
   int32_t sub_k;
+  // total-field operation (no TF/SF; metal may reach into the absorbing
+  // layers, where it follows the local Drude model): a soft plane source on
+  // E_x of node plane source_k, with the pulse the 1D line also takes at
+  // that plane (the line then only gives the incident reference transform)
+  int32_t total_field, source_k;
+  // periodic in x and y (CPML only on the z faces): a laterally infinite
+  // layered problem on a grid a few cells wide (test mode)
+  int32_t periodic_xy;
 } or_config;
 
 }  // extern "C"
@@ -182,9 +195,11 @@ struct Sim {
   std::vector<double> map_inc;      // [m][re, im] incident transform at norm_k
 
   size_t id(int i, int j, int k) const { return ((size_t)k * ny + j) * nx + i; }
-  int wrap(int i, int n) const { return c.periodic ? ((i % n) + n) % n : i; }
+  // is axis `a` periodic (all three in periodic mode; x and y with periodic_xy)
+  bool per(int a) const { return c.periodic || (c.periodic_xy && a < 2); }
+  int wrap(int i, int n, int a) const { return per(a) ? ((i % n) + n) % n : i; }
   R at(const std::vector<R>& a, int i, int j, int k) const {
-    i = wrap(i, nx); j = wrap(j, ny); k = wrap(k, nz);
+    i = wrap(i, nx, 0); j = wrap(j, ny, 1); k = wrap(k, nz, 2);
     if (i < 0 || j < 0 || k < 0 || i >= nx || j >= ny || k >= nz) {
       std::fprintf(stderr, "oracle: index (%d,%d,%d) out of range\n", i, j, k);
       std::abort();
@@ -277,10 +292,10 @@ struct Sim {
       for (int e = 0; e < 3; ++e) { psiE[d][e].assign(N, R(0.0)); psiH[d][e].assign(N, R(0.0)); }
       for (int q = 0; q < ncp; ++q) { PC[q][d].assign(N, R(0.0)); PCm[q][d].assign(N, R(0.0)); }
     }
-    const int L = c.periodic ? 0 : c.npml;
     const int ns[3] = {nx, ny, nz};
     for (int d = 0; d < 3; ++d) {
       const int n = ns[d];
+      const int L = per(d) ? 0 : c.npml;
       be[d].resize(n); ae[d].resize(n); ke[d].resize(n);
       bh[d].resize(n); ah[d].resize(n); kh[d].resize(n);
       for (int i = 0; i < n; ++i) {
@@ -337,12 +352,12 @@ struct Sim {
   // half a cell beyond the last node plane does not exist.
   void erange(int comp, int axis, int& lo, int& hi) const {
     const int n = axis == 0 ? nx : axis == 1 ? ny : nz;
-    if (c.periodic) { lo = 0; hi = n - 1; return; }
+    if (per(axis)) { lo = 0; hi = n - 1; return; }
     if (axis == comp) { lo = 0; hi = n - 2; } else { lo = 1; hi = n - 2; }
   }
   void hrange(int comp, int axis, int& lo, int& hi) const {
     const int n = axis == 0 ? nx : axis == 1 ? ny : nz;
-    if (c.periodic) { lo = 0; hi = n - 1; return; }
+    if (per(axis)) { lo = 0; hi = n - 1; return; }
     if (axis == comp) { lo = 1; hi = n - 2; } else { lo = 0; hi = n - 2; }
   }
 
@@ -418,8 +433,35 @@ struct Sim {
       pe1[q] = be1[q] * pe1[q] + ae1[q] * d;
       e1[q] -= ce * (ke1[q] * d + pe1[q]);
     }
-    e1[kAuxSrc] += source(t_next);
+    e1[c.total_field ? c.source_k + kAuxOff : kAuxSrc] += source(t_next);
   }
+
+  // Total-field source: E_x^{n+1} += f(t_{n+1}) on node plane source_k (at
+  // every E_x point the update reaches), after the E and P_f updates.
+  void plane_source(double t_next) {
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) erange(0, d, lo[d], hi[d]);
+    const int k = c.source_k;
+    if (k < lo[2] || k > hi[2]) return;
+    const double f = source(t_next);
+    for (int j = lo[1]; j <= hi[1]; ++j)
+      for (int i = lo[0]; i <= hi[0]; ++i) E[0][id(i, j, k)] += f;
+  }
+
+  // Inside the absorbing layers (cell (i, j, k) within npml cells of a
+  // non-periodic face)?  In total-field operation metal there follows the
+  // local Drude model (the remedy of the end of Sec. III for nonlocal
+  // material that reaches the boundary).
+  bool in_pml(int i, int j, int k) const {
+    const int L = c.npml;
+    if (L <= 0) return false;
+    const int ii[3] = {i, j, k}, ns[3] = {nx, ny, nz};
+    for (int d = 0; d < 3; ++d)
+      if (!per(d) && (ii[d] < L || ii[d] > ns[d] - 1 - L)) return true;
+    return false;
+  }
+  // weight of the nonlocal (beta^2, D) terms at cell (i, j, k)
+  double nonlocal_on(int i, int j, int k) const { return (c.total_field && in_pml(i, j, k)) ? 0.0 : 1.0; }
 
   // ------------------------------------------------- Eq. (GradDiv), term by term
   R grad_div(int comp, int i, int j, int k, const std::vector<R>* Pa) const {
@@ -482,10 +524,10 @@ struct Sim {
               Enew[comp][p] = E[comp][p] + dt / (eps0() * eps_at(comp, k)) * curl;
             } else {
               const R d3 = w[p] * D3;
-              const R rhs_gd = (c.model == 1)
+              const R rhs_gd = nonlocal_on(i, j, k) * ((c.model == 1)
                   ? (w[p] * DNL) * GD[comp][p]
                   : (w[p] * DG1) * GD[comp][p] +
-                    (w[p] * DG2) * (3.0 * GD[comp][p] - 4.0 * GD1[comp][p] + GD2[comp][p]);
+                    (w[p] * DG2) * (3.0 * GD[comp][p] - 4.0 * GD1[comp][p] + GD2[comp][p]));
               R num = dt * curl + (e0ei - 2.0 * d3) * E[comp][p] - d3 * Em[comp][p] -
                       (D1 - 1.0) * P[comp][p] - D2 * Pm[comp][p] - rhs_gd;
               R den = e0ei + d3;
@@ -525,10 +567,10 @@ struct Sim {
             const size_t p = id(i, j, k);
             if (!active(comp, p)) continue;
             const R d3 = w[p] * D3;
-            const R gd = (c.model == 1)
+            const R gd = nonlocal_on(i, j, k) * ((c.model == 1)
                 ? (w[p] * DNL) * GD[comp][p]
                 : (w[p] * DG1) * GD[comp][p] +
-                  (w[p] * DG2) * (3.0 * GD[comp][p] - 4.0 * GD1[comp][p] + GD2[comp][p]);
+                  (w[p] * DG2) * (3.0 * GD[comp][p] - 4.0 * GD1[comp][p] + GD2[comp][p]));
             Pnew[comp][p] = D1 * P[comp][p] + D2 * Pm[comp][p] +
                             d3 * (Em[comp][p] + 2.0 * E[comp][p] + Enew[comp][p]) + gd;
           }
@@ -741,8 +783,9 @@ struct Sim {
     for (long s = 0; s < nsteps; ++s) {
       const long n = step;
       update_h();                    // H^{n+1/2}, uses E_inc^n
-      if (c.tfsf) update_h1();       // H_inc^{n+1/2}
+      if (c.tfsf || c.total_field) update_h1();  // H_inc^{n+1/2}
       update_e_p();                  // E^{n+1}, P^{n+1}; uses H_inc^{n+1/2}
+      if (c.total_field) plane_source((n + 1) * dt);
       if (c.tfsf || c.src_kind) update_e1((n + 1) * dt);  // E_inc^{n+1}
       accumulate(n);
       accumulate_maps(n);

@@ -105,6 +105,8 @@ class OrConfig(C.Structure):
         ("map_axis", C.c_int32), ("map_index", C.c_int32), ("nmap", C.c_int32),
         ("map_every", C.c_int32), ("map_omega", C.c_double * 8),
         ("eps_sub", C.c_double), ("sub_k", C.c_int32),
+        ("total_field", C.c_int32), ("source_k", C.c_int32),
+        ("periodic_xy", C.c_int32),
     ]
 
 
@@ -158,6 +160,13 @@ class Problem:
     # (0: none)
     eps_sub: float = 0.0
     sub_k: int = 0
+    # total-field operation: no TF/SF, a soft plane source on E_x of node
+    # plane source_k; metal inside the absorbing layers follows the local
+    # Drude model there
+    total_field: bool = False
+    source_k: int = 0
+    # periodic in x and y, CPML on the z faces only (test mode)
+    periodic_xy: bool = False
 
     def to_c(self) -> OrConfig:
         c = OrConfig()

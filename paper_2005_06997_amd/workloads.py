@@ -65,6 +65,11 @@ class Workload:
     # permittivity eps_sub (0: none)
     eps_sub: float = 0.0
     sub_k: int = 0
+    # total-field operation: no TF/SF box; a soft plane source on E_x of node
+    # plane source_k; metal may reach into the absorbing layers (local Drude
+    # there)
+    total_field: bool = False
+    source_k: int = 0
     tf_lo: Tuple[int, int, int] = (0, 0, 0)
     tf_hi: Tuple[int, int, int] = (0, 0, 0)
     # material

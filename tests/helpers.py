@@ -17,7 +17,10 @@ def oracle_problem(w, **over) -> "orc.Problem":
         omega=np.asarray(w.omega, dtype=np.float64), dft_every=w.dft_every, norm_k=w.norm_k,
         flux=bool(w.flux), abs_lo=w.abs_lo, abs_hi=w.abs_hi, sca_lo=w.sca_lo, sca_hi=w.sca_hi,
         cp=tuple(w.cp), map_axis=w.map_axis, map_index=w.map_index, map_every=w.map_every,
-        map_omega=np.asarray(w.map_omega, dtype=np.float64), eps_sub=w.eps_sub, sub_k=w.sub_k)
+        map_omega=np.asarray(w.map_omega, dtype=np.float64), eps_sub=w.eps_sub, sub_k=w.sub_k,
+        total_field=bool(w.total_field), source_k=w.source_k)
+    if w.total_field:
+        p.tfsf = False
     for k, v in over.items():
         setattr(p, k, v)
     return p
