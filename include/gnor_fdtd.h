@@ -89,6 +89,20 @@ typedef struct {
    * eps_background grading on both sides. */
   double eps_substrate;
   int32_t substrate_k;
+  /* Total-field operation (end of Sec. III: geometries that TF/SF cannot
+   * hold, such as a plasmonic substrate).  total_field = 1: no TF/SF box
+   * (tf_lo/tf_hi are ignored); the source is soft on node plane source_k,
+   * E_x^{n+1} += f(t_{n+1}) at every E_x point of the plane, added after the
+   * E and current updates of the step; metal may reach into the CPML (any
+   * node index in [1, n - 2] per axis), and there it follows the local Drude
+   * model: the beta^2 and D terms are dropped at metal points in cells
+   * within npml of a face.  The 1D line carries the same soft source at line
+   * cell source_k + 25, so the spectra normalise by its wave.  source_k must
+   * lie in [npml + 1, nz - 2 - npml].  Not available with a substrate, flux
+   * boxes, a design region or gradient, batches, or the fused step form 1
+   * (GNOR_E_INVALID_ARG).  0 = TF/SF as above. */
+  int32_t total_field;
+  int32_t source_k;
 } gnor_grid_desc;
 
 /* Free-electron metal (Sec. II): wp (rad/s), gamma (rad/s), beta (m/s; the

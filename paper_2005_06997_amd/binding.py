@@ -40,7 +40,8 @@ class GridDesc(C.Structure):
                 ("pml_kappa_max", C.c_double), ("pml_alpha_max", C.c_double),
                 ("eps_background", C.c_double),
                 ("tf_lo", C.c_int32 * 3), ("tf_hi", C.c_int32 * 3), ("precision", C.c_int32),
-                ("eps_substrate", C.c_double), ("substrate_k", C.c_int32)]
+                ("eps_substrate", C.c_double), ("substrate_k", C.c_int32),
+                ("total_field", C.c_int32), ("source_k", C.c_int32)]
 
 
 MAX_CP = 4
@@ -185,7 +186,9 @@ class Sim:
                      pml_order=w.pml_order, pml_sigma_scale=w.pml_sigma_scale,
                      pml_kappa_max=w.pml_kappa_max, pml_alpha_max=w.pml_alpha_max,
                      eps_background=w.eps_b, precision=GNOR_FP32 if prec == "fp32" else GNOR_FP64,
-                     eps_substrate=getattr(w, "eps_sub", 0.0), substrate_k=getattr(w, "sub_k", 0))
+                     eps_substrate=getattr(w, "eps_sub", 0.0), substrate_k=getattr(w, "sub_k", 0),
+                     total_field=int(bool(getattr(w, "total_field", False))),
+                     source_k=int(getattr(w, "source_k", 0)))
         g.tf_lo[:] = list(w.tf_lo)
         g.tf_hi[:] = list(w.tf_hi)
         h = C.c_void_p()
@@ -350,7 +353,8 @@ class Sim:
 
     def set_mode(self, mode: int):
         """Step form: 0 two sweeps, 1 fused one-pass step, 2 hybrid (fused
-        where no CPML slab is met, two sweeps elsewhere)."""
+        where no CPML slab is met, two sweeps elsewhere), 3 one-pass kernel
+        for the plain tiles only."""
         self._check(self.L.gnor_set_fused(self.h, int(mode)))
 
     def tile_classes(self):

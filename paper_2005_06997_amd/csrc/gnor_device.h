@@ -99,7 +99,7 @@ __device__ void aux_e_block(const AuxParams& a, int sub, int tid, int nthr) {
     a.phase[3 * a.nf + m] = s;
   }
   __syncthreads();
-  if (tid == 0) a.e1[kAuxSrc] += source_value(a, (double)(n + 1) * a.dt);
+  if (tid == 0) a.e1[a.src_cell] += source_value(a, (double)(n + 1) * a.dt);
 }
 
 // [lo, hi) meets [0, np) or [n - 1 - np, n)  (the E and H slabs of an axis)

@@ -98,6 +98,7 @@ struct AuxParams {
   const double* ah;
   const double* kh;
   int src_kind;
+  int src_cell;   // line cell of the soft source (kAuxSrc, or the source plane + kAuxOff)
   double e0, omega_c, tau, t0, omega_max, dt;
   // phase table of the step for the spectra: [cos tJ, sin tJ, cos tE, sin tE][nf]
   int nf;
@@ -153,6 +154,9 @@ struct Params {
   const T* psiHi[3][2];
   T* psiH[3][2];
   CpmlAxis<T> cp[3];
+  // total-field operation: metal points in cells within np of a face follow
+  // the local Drude model (G = 0 there; tiles of class 3 only)
+  int lra_pml;
   // TF/SF
   int tfsf;
   int tf_lo[3], tf_hi[3];
@@ -314,6 +318,10 @@ template <class T>
 void launch_fplain(const Params<T>& p, const AuxParams& a, hipStream_t s);
 template <class T>
 void launch_step(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s);
+// soft plane source of total-field operation: E_x^{n+1} += f(t_{n+1}) on node
+// plane k (after every E/J sweep of the step)
+template <class T>
+void launch_plane_source(const Params<T>& p, const AuxParams& a, int k, int sub, hipStream_t s);
 template <class T>
 void launch_h(const Params<T>& p, const AuxParams& a, hipStream_t s);
 template <class T>

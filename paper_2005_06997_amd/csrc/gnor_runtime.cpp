@@ -382,7 +382,8 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
     c.be = base; c.ae = base + 2 * np; c.ke = base + 4 * np;
     c.bh = base + 6 * np; c.ah = base + 8 * np; c.kh = base + 10 * np;
   }
-  p.tfsf = 1;
+  p.tfsf = g.total_field ? 0 : 1;
+  p.lra_pml = g.total_field ? 1 : 0;
   for (int d = 0; d < 3; ++d) { p.tf_lo[d] = g.tf_lo[d]; p.tf_hi[d] = g.tf_hi[d]; }
   double* aux = ptr<double>(s, s->L.aux);
   p.e1 = aux; p.h1 = aux + s->n1;
@@ -408,6 +409,7 @@ gnor::AuxParams make_aux(gnor_sim* s) {
   a.be = pr; a.ae = pr + s->n1; a.ke = pr + 2 * s->n1;
   a.bh = pr + 3 * s->n1; a.ah = pr + 4 * s->n1; a.kh = pr + 5 * s->n1;
   a.src_kind = s->have_source ? s->src.kind : 0;
+  a.src_cell = s->g.total_field ? s->g.source_k + gnor::kAuxOff : gnor::kAuxSrc;
   a.e0 = s->src.e0; a.omega_c = s->src.omega_c; a.tau = s->src.tau; a.t0 = s->src.t0;
   a.omega_max = s->src.omega_max; a.dt = s->dt;
   a.nf = s->mon.nfreq;
@@ -561,6 +563,7 @@ void enqueue_step(gnor_sim* s, int parity, int sub, int mode, hipStream_t st) {
   const gnor::AuxParams a = make_aux(s);
   enqueue_first<T>(s, p, a, mode, st);
   enqueue_second<T>(s, p, a, sub, mode, st);
+  if (s->g.total_field) gnor::launch_plane_source<T>(p, a, s->g.source_k, sub, st);
   if (s->mon.nfreq > 0) gnor::launch_dft_stage<T>(make_dft(s), make_flux(s), p, sub, st);
   if (s->maps.nmap > 0) gnor::launch_maps<T>(make_maps<T>(s, parity), sub, st);
 }
@@ -808,9 +811,15 @@ gnor_status gnor_create(const gnor_grid_desc* g, gnor_sim** out) {
   if (!(g->courant > 0.0) || g->courant >= 1.0 / std::sqrt(3.0)) return GNOR_E_UNSTABLE;
   if (g->npml < 0 || 2 * g->npml + 4 > std::min(g->nx, std::min(g->ny, g->nz))) return GNOR_E_INVALID_ARG;
   const int n[3] = {g->nx, g->ny, g->nz};
-  for (int d = 0; d < 3; ++d)
-    if (g->tf_lo[d] < g->npml + 1 || g->tf_hi[d] > n[d] - 2 - g->npml || g->tf_hi[d] - g->tf_lo[d] < 4)
-      return GNOR_E_INVALID_ARG;
+  if (g->total_field != 0 && g->total_field != 1) return GNOR_E_INVALID_ARG;
+  if (g->total_field) {
+    if (g->eps_substrate > 0.0) return GNOR_E_INVALID_ARG;
+    if (g->source_k < g->npml + 1 || g->source_k > g->nz - 2 - g->npml) return GNOR_E_INVALID_ARG;
+  } else {
+    for (int d = 0; d < 3; ++d)
+      if (g->tf_lo[d] < g->npml + 1 || g->tf_hi[d] > n[d] - 2 - g->npml || g->tf_hi[d] - g->tf_lo[d] < 4)
+        return GNOR_E_INVALID_ARG;
+  }
   gnor_sim* s = new (std::nothrow) gnor_sim();
   if (!s) return GNOR_E_OUT_OF_MEMORY;
   s->g = *g;
@@ -852,6 +861,7 @@ gnor_status gnor_set_material(gnor_sim* s, const uint8_t* mask, const gnor_mater
   s->mask.assign(N, 0);
   s->rowx.clear();
   int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+  const int nn[3] = {g.nx, g.ny, g.nz};
   bool any = false;
   if (mask) {
     for (int k = 0; k < g.nz; ++k)
@@ -865,7 +875,10 @@ gnor_status gnor_set_material(gnor_sim* s, const uint8_t* mask, const gnor_mater
           if (g.eps_substrate > 0.0 && k >= g.substrate_k)
             return fail(s, GNOR_E_INVALID_ARG, "metal must lie below the substrate plane");
           for (int d = 0; d < 3; ++d) {
-            if (ii[d] < g.tf_lo[d] + 2 || ii[d] > g.tf_hi[d] - 2) {
+            if (g.total_field) {
+              if (ii[d] < 1 || ii[d] > nn[d] - 2)
+                return fail(s, GNOR_E_INVALID_ARG, "metal must lie off the outer node planes");
+            } else if (ii[d] < g.tf_lo[d] + 2 || ii[d] > g.tf_hi[d] - 2) {
               char buf[160];
               std::snprintf(buf, sizeof buf,
                             "metal at (%d,%d,%d) is not 2 cells inside the TF box: nonlocal material "
@@ -893,6 +906,7 @@ gnor_status gnor_set_design(gnor_sim* s, const int32_t* lo, const int32_t* hi, c
   if (!s->have_material) return fail(s, GNOR_E_STATE, "gnor_set_material must come first");
   if (s->bound) return fail(s, GNOR_E_STATE, "the design region must be set before gnor_bind_memory");
   if (s->g.eps_substrate > 0.0) return fail(s, GNOR_E_INVALID_ARG, "design regions do not cover a substrate");
+  if (s->g.total_field) return fail(s, GNOR_E_INVALID_ARG, "design regions need the TF/SF source");
   const gnor_grid_desc& g = s->g;
   size_t nd = 1;
   for (int d = 0; d < 3; ++d) {
@@ -968,6 +982,7 @@ gnor_status gnor_set_monitors(gnor_sim* s, const gnor_monitor_desc* m) {
   if (m->norm_k < 0 || m->norm_k >= s->g.nz) return fail(s, GNOR_E_INVALID_ARG, "norm_k outside the grid");
   if (m->dft_every < 0) return fail(s, GNOR_E_INVALID_ARG, "dft_every must be >= 0");
   if (m->flux_enabled) {
+    if (s->g.total_field) return fail(s, GNOR_E_INVALID_ARG, "flux boxes need the TF/SF source");
     if (m->dft_every > 1) return fail(s, GNOR_E_INVALID_ARG, "flux boxes require dft_every = 1");
     const gnor_grid_desc& g = s->g;
     const int n[3] = {g.nx, g.ny, g.nz};
@@ -1088,6 +1103,8 @@ gnor_status gnor_set_fused(gnor_sim* s, int32_t on) {
     return fail(s, GNOR_E_INVALID_ARG, "the fused step has no critical-point terms");
   if ((on == 1 || on == 2) && s->g.eps_substrate > 0.0)
     return fail(s, GNOR_E_INVALID_ARG, "the fused and hybrid step forms have no substrate");
+  if (on == 1 && s->g.total_field)
+    return fail(s, GNOR_E_INVALID_ARG, "the fused step has no local-Drude absorbing layers");
   return set_mode(s, on);
 }
 
@@ -1489,6 +1506,10 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       }
       (void)hipEventRecord(ev[1 + NC + c], str);
     }
+    if (s->g.total_field) {  // timed with the spectra
+      if (fp32) gnor::launch_plane_source<float>(make_params<float>(s, parity), a, s->g.source_k, 0, str);
+      else gnor::launch_plane_source<double>(make_params<double>(s, parity), a, s->g.source_k, 0, str);
+    }
     if (s->mon.nfreq > 0) {
       if (fp32) gnor::launch_dft_stage<float>(make_dft(s), make_flux(s), make_params<float>(s, parity), 0, str);
       else gnor::launch_dft_stage<double>(make_dft(s), make_flux(s), make_params<double>(s, parity), 0, str);
@@ -1884,6 +1905,7 @@ gnor_status batch_create_impl(int32_t n, gnor_sim* const* sims, void* stream, vo
   for (int q = 0; q < n; ++q) {
     gnor_sim* s = sims[q];
     if (!s || !s->bound || s->maps.nmap > 0) { delete b; return GNOR_E_STATE; }  // no maps in batches
+    if (s->g.total_field) { delete b; return GNOR_E_INVALID_ARG; }  // no plane source in batches
     if (q > 0 && (s->g.precision != sims[0]->g.precision || s->step != sims[0]->step ||
                   s->tile_ty != sims[0]->tile_ty)) {
       delete b;

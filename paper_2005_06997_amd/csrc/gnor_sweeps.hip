@@ -391,6 +391,9 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
     if (METAL) {
       const int lz = k - p.mlo[2];
       const bool zsub = lz >= 0 && lz < p.mn[2];
+      // total-field operation: the cell lies in an absorbing layer, so its
+      // metal follows the local Drude model (no nonlocal force G)
+      const bool local = PYZ && p.lra_pml && (sxe >= 0 || sye >= 0 || slab_e(k, nz, np) >= 0);
       const size_t l = (col_sub && zsub) ? (size_t)lz * m2 + lcol : 0;
       const uint32_t mb = (col_sub && zsub) ? p.mask[l] : 0u;
       double jsum = 0.0;
@@ -413,7 +416,7 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
         const T ag = p.agam;
         CpState<T> cps;
         if (b0) {
-          const T G = r * (qx - q);
+          const T G = local ? T(0) : r * (qx - q);
           const T rs = CP ? cp_known(p, 0, l, r, ex, emx, cps) : T(0);
           const T en = ex + (cS * cxv - c3 * ex - c1 * emx + cJ * jx - cG * (CP ? G + rs : G));
           const T jn = jx + (d3 * (emx + T(2) * ex + en) - ag * jx + G);
@@ -423,7 +426,7 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
           nx_ = en;
         }
         if (b1) {
-          const T G = r * (qy - q);
+          const T G = local ? T(0) : r * (qy - q);
           const T rs = CP ? cp_known(p, 1, l, r, ey, emy, cps) : T(0);
           const T en = ey + (cS * cyv - c3 * ey - c1 * emy + cJ * jy - cG * (CP ? G + rs : G));
           p.Jo[1][l] = jy + (d3 * (emy + T(2) * ey + en) - ag * jy + G);
@@ -431,7 +434,7 @@ __device__ __forceinline__ void ej_tile(const Params<T>& p, const Tile tile, boo
           ny_ = en;
         }
         if (b2) {
-          const T G = r * (qz - q);
+          const T G = local ? T(0) : r * (qz - q);
           const T rs = CP ? cp_known(p, 2, l, r, ez, emz, cps) : T(0);
           const T en = ez + (cS * czv - c3 * ez - c1 * emz + cJ * jz - cG * (CP ? G + rs : G));
           p.Jo[2][l] = jz + (d3 * (emz + T(2) * ez + en) - ag * jz + G);
@@ -547,6 +550,22 @@ __global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __res
 template <class T>
 __global__ void __launch_bounds__(kAuxThreads) k_aux_e_batch(const BatchEntry<T>* __restrict__ e, int sub) {
   aux_e_block(e[blockIdx.x].a, sub, threadIdx.x, kAuxThreads);
+}
+
+// Soft plane source of total-field operation: E_x^{n+1} += f(t_{n+1}) at
+// the E_x points (i + 1/2, j, k) the update reaches (0 <= i <= nx - 2,
+// 1 <= j <= ny - 2) of node plane k.  Every thread evaluates f itself (one
+// plane: a few hundred FP64 exponentials per block).
+template <class T>
+__global__ void __launch_bounds__(256) k_plane_source(T* __restrict__ ex, int nx, int ny, int k,
+                                                      AuxParams a, int sub) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = 1 + blockIdx.y * 4 + threadIdx.y;
+  if (i > nx - 2 || j > ny - 2) return;
+  const int64_t n = a.step_base[0] + sub;
+  const double f = source_value(a, (double)(n + 1) * a.dt);
+  T* q = ex + ((size_t)k * ny + j) * nx + i;
+  *q = *q + (T)f;
 }
 
 }  // namespace
@@ -726,6 +745,13 @@ template void launch_ej_batch_class<double>(const BatchEntry<double>*, int, int,
                                             hipStream_t);
 template void launch_aux_e_batch<float>(const BatchEntry<float>*, int, int, hipStream_t);
 template void launch_aux_e_batch<double>(const BatchEntry<double>*, int, int, hipStream_t);
+template <class T>
+void launch_plane_source(const Params<T>& p, const AuxParams& a, int k, int sub, hipStream_t s) {
+  const dim3 grid((p.nx - 1 + 63) / 64, (p.ny - 2 + 3) / 4);
+  k_plane_source<T><<<grid, dim3(64, 4), 0, s>>>(p.O[0], p.nx, p.ny, k, a, sub);
+}
+template void launch_plane_source<float>(const Params<float>&, const AuxParams&, int, int, hipStream_t);
+template void launch_plane_source<double>(const Params<double>&, const AuxParams&, int, int, hipStream_t);
 template void launch_h<float>(const Params<float>&, const AuxParams&, hipStream_t);
 template void launch_h<double>(const Params<double>&, const AuxParams&, hipStream_t);
 template void launch_ej<float>(const Params<float>&, const AuxParams&, int, hipStream_t);

@@ -176,3 +176,44 @@ def test_new_entry_points_validate_on_the_host(lib):
     assert lib.gnor_update_design(h, None) == 5  # not bound
     assert lib.gnor_flush_spectra(h) == 5
     lib.gnor_destroy(h)
+
+
+def test_total_field_operation_validates_on_the_host(lib):
+    """Total-field grids: the source plane must lie between the absorbing
+    layers; no substrate, flux boxes, design region or fused form 1; metal may
+    reach into the layers but not onto the outer node planes."""
+    w = W.config1(0)
+    n, L = w.nz, w.npml
+    for k, ok in ((L, False), (L + 1, True), (n - 2 - L, True), (n - 1 - L, False)):
+        st, h = _create(lib, _grid(w, total_field=1, source_k=k, tf_lo=(0, 0, 0), tf_hi=(0, 0, 0)))
+        assert (st == 0) == ok, k
+        if st == 0:
+            lib.gnor_destroy(h)
+    st, h = _create(lib, _grid(w, total_field=2, source_k=L + 1))
+    assert st == 1
+    st, h = _create(lib, _grid(w, total_field=1, source_k=L + 1, eps_substrate=2.25, substrate_k=n // 2))
+    assert st == 1
+    st, h = _create(lib, _grid(w, total_field=1, source_k=L + 1))
+    assert st == 0
+    mat = B.MaterialDesc(wp=w.wp, gamma=w.gamma, beta=w.beta, diffusion=w.diff, eps_inf=1.0)
+    m = np.zeros((w.nz, w.ny, w.nx), np.uint8)
+    m[n // 2:n // 2 + 4, 1:w.ny - 1, 1:w.nx - 1] = 7  # through the x and y layers
+    assert lib.gnor_set_material(h, m.ctypes.data_as(C.c_void_p), C.byref(mat)) == 0
+    m[n // 2, 0, 5] = 7  # on an outer node plane
+    assert lib.gnor_set_material(h, m.ctypes.data_as(C.c_void_p), C.byref(mat)) == 1
+    m[n // 2, 0, 5] = 0
+    assert lib.gnor_set_material(h, m.ctypes.data_as(C.c_void_p), C.byref(mat)) == 0
+    assert lib.gnor_set_fused(h, 1) == 1
+    for form in (0, 2, 3):
+        assert lib.gnor_set_fused(h, form) == 0
+    lo = (C.c_int32 * 3)(10, 10, 10)
+    hi = (C.c_int32 * 3)(12, 12, 12)
+    rho = np.full(8, 0.5, np.float32)
+    assert lib.gnor_set_design(h, lo, hi, rho.ctypes.data_as(C.c_void_p)) == 1
+    om = np.array([4e15])
+    mon = B.MonitorDesc(nfreq=1, omega=om.ctypes.data_as(C.POINTER(C.c_double)), norm_k=L + 1,
+                        dft_every=1, flux_enabled=1)
+    assert lib.gnor_set_monitors(h, C.byref(mon)) == 1
+    mon.flux_enabled = 0
+    assert lib.gnor_set_monitors(h, C.byref(mon)) == 0
+    lib.gnor_destroy(h)
