@@ -72,24 +72,55 @@ def algorithmic_bytes(w, mask, word):
     return h, ej, nm, cd
 
 
-def run_gpu(w, precision, steps, warmup, tiling=None, serial=False):
-    """Warm up, then time `steps` full steps.  The timed region holds every
-    flux-box fold its steps owe: the warm-up's staged samples are folded
-    before it starts, and it ends with the fold of the samples its own steps
-    staged since the last window fold (a partial window costs the whole
-    accumulator read-modify-write, so short runs are charged more per step
-    than long ones)."""
+def dominant(form, word, cells, slab_dirs, ejb, prof, prof_serial):
+    """The dominant kernel of a step form: its name, algorithmic bytes per
+    launch, average launch time (ms) and kernel family.  Form 3: the one-pass
+    launch of the plain tiles (class 0, x-slab tiles included, with its TF/SF
+    launch), timed alone (serial classes), at 18 field words per cell and 8
+    psi words per (cell, axis) in a slab, the per-unit figures of the step.
+    Form 0: the E/J sweep, its classes timed together."""
+    if form == 3:
+        return ("k_fplain (class 0 in one pass: plain and x-slab launches + k_tfsf_fix, timed alone)",
+                word * (18 * cells[0] + 8 * slab_dirs[0]), prof_serial["h_cls"][0], "k_fplain")
+    return ("k_ej (E/J sweep = one launch per tile class, timed together)", ejb, prof["ej"], "k_ej")
+
+
+def run_gpu(w, precision, steps, warmup, tiling=None, serial=False, forms=(0, 3)):
+    """Pick the step form (two sweeps, or the plain tiles in one pass) and
+    the sweep tiling, warm up, then time `steps` full steps.  The timed
+    region holds every flux-box fold its steps owe: the warm-up's staged
+    samples are folded before it starts, and it ends with the fold of the
+    samples its own steps staged since the last window fold (a partial window
+    costs the whole accumulator read-modify-write, so short runs are charged
+    more per step than long ones)."""
     import torch
     from paper_2005_06997_amd import binding
 
     sim = binding.Sim(w, precision=precision)
     if serial:
         sim.set_class_streams(False)
-    if tiling is None:
-        sim.tiling = sim.autotune(trial_steps=10)  # timed search over sweep tilings (state reset after)
-    else:
-        sim.set_tiling(*tiling)
-        sim.tiling = dict(ty=tiling[0], kz=tiling[1], xcd=tiling[2], cached=False)
+    best = None
+    for form in forms:
+        sim.set_mode(form)
+        if tiling is None:
+            tl = sim.autotune(trial_steps=10)  # timed search over sweep tilings (state reset after)
+        else:
+            sim.set_tiling(*tiling)
+            sim.reset()
+            sim.run(8)
+            sim.synchronize()
+            t0 = time.perf_counter()
+            sim.run(64)
+            sim.synchronize()
+            tl = dict(ty=tiling[0], kz=tiling[1], xcd=tiling[2], ms=(time.perf_counter() - t0) / 64 * 1e3,
+                      cached=False)
+            sim.reset()
+        if best is None or tl["ms"] < best[1]["ms"]:
+            best = (form, tl)
+    sim.set_mode(best[0])
+    sim.set_tiling(best[1]["ty"], best[1]["kz"], best[1]["xcd"])
+    sim.tiling = best[1]
+    sim.form = best[0]
     sim.run(warmup)
     sim.flush_spectra()
     sim.synchronize()
@@ -111,7 +142,7 @@ def spectral_errors(a, b):
     return out
 
 
-def error_legs(tiling):
+def error_legs(tiling, form):
     """Spectral errors of the FP32 path from runs of fixed length (independent
     of --steps): FP32 vs FP64 on the 320^3 workload with the pulse moved early
     (2400 steps: the pulse has crossed the particle), and FP32 vs the FP64
@@ -125,6 +156,7 @@ def error_legs(tiling):
     spec = {}
     for prec in ("fp32", "fp64"):
         s = binding.Sim(w, precision=prec)
+        s.set_mode(form)
         s.set_tiling(*tiling)
         s.run(2400)
         spec[prec] = s.spectra()
@@ -139,6 +171,7 @@ def error_legs(tiling):
         gold = dict(inc=rows[:, 1], ext=rows[:, 2], abs=rows[:, 3], sca=rows[:, 4])
         wc = W.config2_coarse()
         s = binding.Sim(wc, precision="fp32")
+        s.set_mode(form)
         t0 = time.perf_counter()
         s.run(wc.steps)
         sp = s.spectra()
@@ -207,6 +240,9 @@ def main():
                     help="steps of the 64-instance batched sweep (0 = skip)")
     ap.add_argument("--tiling", type=str, default=None,
                     help="ty,kz,order: fixed sweep tiling instead of the autotuner (profiling runs)")
+    ap.add_argument("--form", type=int, default=None, choices=(0, 3),
+                    help="step form (0 two sweeps, 3 plain tiles in one pass) instead of the "
+                         "faster of the two")
     ap.add_argument("--serial-classes", action="store_true",
                     help="tile-class launches one after another (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -231,19 +267,24 @@ def main():
 
     w = W.config2("fp32")
     tiling = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
-    sim, dt = run_gpu(w, "fp32", args.steps, args.warmup, tiling, args.serial_classes)
+    forms = (0, 3) if args.form is None else (args.form,)
+    sim, dt = run_gpu(w, "fp32", args.steps, args.warmup, tiling, args.serial_classes, forms)
     value = w.cells * args.steps / dt / 1e9
     ms_step = dt / args.steps * 1e3
     prof = sim.profile(args.profile_steps)  # each sweep timed as it runs (classes concurrent)
     classes = sim.tile_classes()
+    cells, slab_dirs = sim.tile_class_cells()
     sim.set_class_streams(False)
     prof_serial = sim.profile(max(2, args.profile_steps // 4))  # per-class breakdown
     sim.set_class_streams(not args.serial_classes)
+    form = sim.form
     sim.set_fused(True)
     prof_fused = sim.profile(max(2, args.profile_steps // 4))
-    sim.set_fused(False)
+    sim.set_mode(form)
     hb, ejb, nmetal, ncd = algorithmic_bytes(w, sim.mask, 4)
-    ach = ejb / (prof["ej"] * 1e-3) / 1e9
+    dom, dom_bytes, dom_ms, dom_kernel = dominant(form, 4, cells, slab_dirs, ejb, prof, prof_serial)
+    dom_traffic = measured_traffic(dom_kernel)
+    ach = dom_bytes / (dom_ms * 1e-3) / 1e9
     out = {
         "metric": "Gcell-updates/s and % HBM roofline, FP32 vs FP64 GNOR-FDTD at stated error",
         "value": round(value, 3),
@@ -260,58 +301,72 @@ def main():
         "config": {"workload": "sphere_r10nm_320^3_dx0.1nm_gnor_fp32_fields_fp64_spectra",
                    "grid": [w.nx, w.ny, w.nz], "npml": w.npml, "metal_cells": nmetal,
                    "nfreq": int(len(w.omega)), "flux_boxes": bool(w.flux)},
-        "roofline": {"bound": "hbm",
-                     "kernel": "k_ej (E/J sweep = one launch per tile class, timed together)",
+        "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_ej"),
-                     "bytes_per_launch": ejb, "avg_launch_ms": round(prof["ej"], 5)},
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": dom_traffic,
+                     "bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 5)},
+        "step_form": form,
+        "class_cells": cells, "class_slab_dirs": slab_dirs,
         "kernels_ms": {k: round(prof[k], 5) for k in ("h", "ej", "dft", "flux_acc")},
         "class_ms_serial": {"h": [round(v, 5) for v in prof_serial["h_cls"]],
                             "ej": [round(v, 5) for v in prof_serial["ej_cls"]]},
         "tile_classes": {"plain": classes[0], "cpml": classes[1], "metal": classes[2],
                          "metal_cpml": classes[3]},
         "tiling": {k: sim.tiling[k] for k in ("ty", "kz", "xcd")},
-        "h_roofline_frac": round(hb / (prof["h"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # (form 3: "h" is the first phase, one-pass class 0 beside the H sweep of the rest)
+        "h_roofline_frac": round(hb / (prof["h"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if form == 0 else None,
         "step_roofline_frac": round((hb + ejb) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "fused_step": {"note": "one-pass H+E/J variant (12 instead of 18 field words per cell), "
-                               "not the default: slower here, see DESIGN.md",
+        "fused_step": {"note": "one-pass H+E/J variant for every class (12 instead of 18 field words "
+                               "per cell): slower here, see DESIGN.md",
                        "step_ms": round(prof_fused["step"], 5)},
     }
     del sim
     torch.cuda.empty_cache()
     if not args.no_fp64:
         # the same K steps in FP64 (same warm-up and fold accounting)
-        sim64, dt64 = run_gpu(w, "fp64", args.steps, args.warmup, tiling, args.serial_classes)
+        sim64, dt64 = run_gpu(w, "fp64", args.steps, args.warmup, tiling, args.serial_classes, forms)
         v64 = w.cells * args.steps / dt64 / 1e9
         prof64 = sim64.profile(max(2, args.profile_steps // 2))
+        sim64.set_class_streams(False)
+        prof64s = sim64.profile(max(2, args.profile_steps // 4))
+        sim64.set_class_streams(not args.serial_classes)
         _, ejb64, _, _ = algorithmic_bytes(w, sim64.mask, 8)
+        c64, d64 = sim64.tile_class_cells()
+        name64, b64, ms64, k64 = dominant(sim64.form, 8, c64, d64, ejb64, prof64, prof64s)
         out["fp64"] = {"value": round(v64, 3), "ms_per_step": round(dt64 / args.steps * 1e3, 5),
-                       "roofline_frac": round(ejb64 / (prof64["ej"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                       "traffic": measured_traffic("k_ej", PROFILE_SUMMARY_FP64),
+                       "step_form": sim64.form, "roofline_kernel": name64,
+                       "roofline_frac": round(b64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "traffic": measured_traffic(k64, PROFILE_SUMMARY_FP64),
                        "tiling": {k: sim64.tiling[k] for k in ("ty", "kz", "xcd")},
                        "fp32_speedup": round(value / v64, 3)}
         del sim64
         torch.cuda.empty_cache()
     if not args.no_error_legs:
         tl = out["tiling"]
-        out.update(error_legs((tl["ty"], tl["kz"], tl["xcd"])))
+        out.update(error_legs((tl["ty"], tl["kz"], tl["xcd"]), out["step_form"]))
     if args.cp_steps > 0:
         # bound electrons: the same sphere with two critical points (f3); the
         # E/J sweep adds P_CP and its increment (read + write) per pole and
         # component at the metal points
         wc = W.with_critical_points(w)
         tl = out["tiling"]
-        simc, dtc = run_gpu(wc, "fp32", args.cp_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]))
-        profc = simc.profile(max(2, args.profile_steps))
-        hbc, ejbc, nmc, _ = algorithmic_bytes(wc, simc.mask, 4)
-        ejbc += 4 * 12 * nmc * len(wc.cp)
+        simc, dtc = run_gpu(wc, "fp32", args.cp_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]), forms=(out["step_form"],))
+        # the poles live in the E/J launches of the metal classes (2, 3),
+        # timed alone: 9 field words per cell of their tiles, 13 per metal
+        # cell, 12 per metal cell and pole, 4 per (cell, axis) in a slab
+        simc.set_class_streams(False)
+        profc = simc.profile(max(2, args.profile_steps // 4))
+        cc, dc = simc.tile_class_cells()
+        nmc = int(np.count_nonzero(simc.mask))
+        mbytes = 4 * (9 * (cc[2] + cc[3]) + 13 * nmc + 12 * nmc * len(wc.cp) + 4 * dc[3])
+        mms = profc["ej_cls"][2] + profc["ej_cls"][3]
         out["critical_points"] = {
             "workload": "the same sphere with 2 synthetic critical points, eps_inf 1.1, FP32",
             "poles": len(wc.cp), "steps": args.cp_steps,
             "value": round(wc.cells * args.cp_steps / dtc / 1e9, 3), "unit": "Gcell-updates/s",
             "ms_per_step": round(dtc / args.cp_steps * 1e3, 5),
-            "ej_ms": round(profc["ej"], 5),
-            "ej_roofline_frac": round(ejbc / (profc["ej"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "metal_ej_ms": round(mms, 5),
+            "metal_ej_roofline_frac": round(mbytes / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del simc
         torch.cuda.empty_cache()
     if args.maps_steps > 0:
@@ -319,7 +374,7 @@ def main():
         # the sphere, every step (8 FP64 accumulators per point and frequency)
         wm = W.with_maps(w, W.spectrum_omegas(4, 2.5, 4.0), every=1, axis=1)
         tl = out["tiling"]
-        simm, dtm = run_gpu(wm, "fp32", args.maps_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]))
+        simm, dtm = run_gpu(wm, "fp32", args.maps_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]), forms=(out["step_form"],))
         mp = simm.maps()
         out["maps"] = {
             "workload": "the same sphere with maps at 4 frequencies on the 320x320 xz plane, every step",
@@ -336,7 +391,7 @@ def main():
         ws_ = replace(w, eps_b=1.69, eps_sub=2.25,
                       sub_k=int(round((w.spheres[0, 2] + w.spheres[0, 3]) / w.dx)) + 1)
         tl = out["tiling"]
-        sims_, dts = run_gpu(ws_, "fp32", args.substrate_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]))
+        sims_, dts = run_gpu(ws_, "fp32", args.substrate_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]), forms=(out["step_form"],))
         out["substrate"] = {
             "workload": "the same sphere in an n = 1.3 background on an eps 2.25 substrate (plane "
                         f"{ws_.sub_k}), FP32",
@@ -350,7 +405,7 @@ def main():
         # 0.2 nm, 12-cell CPML (run at the sphere's tiling)
         wst = W.config3(seed=0)
         tl = out["tiling"]
-        simst, dtst = run_gpu(wst, "fp32", args.star_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]))
+        simst, dtst = run_gpu(wst, "fp32", args.star_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]), forms=(out["step_form"],))
         out["star"] = {
             "workload": "640^3 star particle (sphere R 15 nm + 6 cones), dx 0.2 nm, 12-cell CPML, "
                         "100 frequencies with flux boxes, FP32",

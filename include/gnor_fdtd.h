@@ -285,12 +285,13 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * fused pass for the tiles that meet no CPML slab (classes 0 and 2; class 2
  * stays two-sweep with critical points), then the auxiliary line, then the
  * E/J sweep of the CPML classes, whose H sweep ran alongside the fused
- * tiles; gnor_set_fused(sim, 3) the same order with only class 0 (here
- * without x-slab tiles) in one pass, by a lighter kernel whose wavefronts
- * recompute their halo H instead of sharing it (no barriers), and the metal
- * and CPML classes in two sweeps (critical points and a substrate allowed).
- * All forms give the same fields up to rounding; batches and gnor_gradient
- * always use the two-sweep form.
+ * tiles; gnor_set_fused(sim, 3) the same order with only class 0 (x-slab
+ * tiles included) in one pass, by a lighter kernel whose wavefronts share
+ * halo H through lane shuffles and LDS, followed by a small launch that adds
+ * the TF/SF terms on the faces of the TF box at class-0 points, and the
+ * metal and CPML classes in two sweeps (critical points, a substrate and
+ * total-field operation allowed).  All forms give the same fields up to
+ * rounding; batches and gnor_gradient always use the two-sweep form.
  * gnor_profile_kernels times each sweep as it runs: with concurrent class
  * launches (the default, see gnor_set_class_streams) a sweep is timed from its
  * fork to its join; with serial class launches, count >= 14 also returns
@@ -298,9 +299,15 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * sweep's class c (0 otherwise); ms[13] is the auxiliary-line launch of the
  * fused form.  In fused form ms[0] = ms[1] = 0 and ms[3] holds the fused step
  * (classes + auxiliary line); in hybrid form ms[0] is the first phase (fused
- * tiles and H sweeps) and ms[1] the second (auxiliary line and E/J sweeps).
+ * tiles and H sweeps) and ms[1] the second (auxiliary line and E/J sweeps);
+ * in form 3 with serial class launches ms[5] is the one-pass class 0 (with
+ * its TF/SF launch) and ms[9] the auxiliary line.
  * gnor_tile_classes writes the number of tiles of each class of the current
  * tiling to counts[0..3] (valid once the memory is bound).
+ * gnor_tile_class_cells writes, per class c, the grid cells its tiles cover
+ * (tiles clipped to the grid) to cells[c] and the (cell, axis) pairs among
+ * them that lie in that axis's CPML slab to slab_dirs[c] (valid once the
+ * memory is bound). 
  * gnor_set_fused: on must be 0, 1, 2 or 3 (INVALID_ARG otherwise; 1 also
  * with critical points, 1 and 2 also with a substrate). */
 gnor_status gnor_set_fused(gnor_sim *sim, int32_t on);
@@ -312,6 +319,7 @@ gnor_status gnor_set_fused(gnor_sim *sim, int32_t on);
  * launch).  INVALID_ARG unless on is 0 or 1. */
 gnor_status gnor_set_class_streams(gnor_sim *sim, int32_t on);
 gnor_status gnor_tile_classes(const gnor_sim *sim, int32_t *counts);
+gnor_status gnor_tile_class_cells(const gnor_sim *sim, int64_t *cells, int64_t *slab_dirs);
 
 /* Sweep tiling: each block owns 64 (x) x ty (y) columns over kz planes;
  * ty in {2, 4, 8}, 1 <= kz <= nz.  Blocks are dealt to the 8 XCDs

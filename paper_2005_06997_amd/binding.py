@@ -119,6 +119,7 @@ def load() -> C.CDLL:
         "gnor_check_finite": (i32, [vp]),
         "gnor_profile_kernels": (i32, [vp, i64, dp, i32]),
         "gnor_tile_classes": (i32, [vp, C.POINTER(C.c_int32)]),
+        "gnor_tile_class_cells": (i32, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
         "gnor_set_fused": (i32, [vp, i32]),
         "gnor_set_class_streams": (i32, [vp, i32]),
         "gnor_set_tiling": (i32, [vp, i32, i32, i32]),
@@ -196,6 +197,7 @@ class Sim:
         if st:
             raise GnorError(st, "gnor_create rejected the grid")
         self.h = h
+        self.mode = 0
         self.mask = voxelize(w) if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         mat = MaterialDesc(wp=w.wp, gamma=w.gamma, beta=w.beta, diffusion=w.diff, eps_inf=w.eps_inf)
         cp = tuple(getattr(w, "cp", ()))
@@ -349,19 +351,28 @@ class Sim:
 
     def set_fused(self, on: bool):
         """One-pass fused step, or the two-sweep form."""
-        self._check(self.L.gnor_set_fused(self.h, 1 if on else 0))
+        self.set_mode(1 if on else 0)
 
     def set_mode(self, mode: int):
         """Step form: 0 two sweeps, 1 fused one-pass step, 2 hybrid (fused
         where no CPML slab is met, two sweeps elsewhere), 3 one-pass kernel
         for the plain tiles only."""
         self._check(self.L.gnor_set_fused(self.h, int(mode)))
+        self.mode = int(mode)
 
     def tile_classes(self):
         """Tiles per class (plain Yee, CPML, metal, metal + CPML) of the current tiling."""
         c = (C.c_int32 * 4)()
         self._check(self.L.gnor_tile_classes(self.h, c))
         return [int(v) for v in c]
+
+    def tile_class_cells(self):
+        """Per class: grid cells its tiles cover, and (cell, axis) pairs among
+        them inside that axis's CPML slab."""
+        c = (C.c_int64 * 4)()
+        d = (C.c_int64 * 4)()
+        self._check(self.L.gnor_tile_class_cells(self.h, c, d))
+        return [int(v) for v in c], [int(v) for v in d]
 
     def update_design(self, rho):
         """New design densities (z, y, x) in [0, 1] from a device tensor on this
@@ -401,12 +412,14 @@ class Sim:
         self._check(self.L.gnor_set_tiling(self.h, int(ty), int(kz), int(xcd)))
 
     def autotune(self, trial_steps: int = 20, cache: Optional[str] = None):
-        """Pick the sweep tiling by timing every candidate (library autotuner);
-        results are cached in a JSON file keyed by grid shape, precision and
-        metal-cell count (default ~/.cache/gnorfdtd/tiling.json)."""
+        """Pick the sweep tiling of the current step form by timing every
+        candidate (library autotuner); results are cached in a JSON file keyed
+        by grid shape, precision, metal-cell count and step form (default
+        ~/.cache/gnorfdtd/tiling.json)."""
         import json
         path = cache or os.path.join(os.path.expanduser("~"), ".cache", "gnorfdtd", "tiling.json")
-        key = f"{self.w.nx}x{self.w.ny}x{self.w.nz}:{self.precision}:{int(np.count_nonzero(self.mask))}"
+        key = (f"{self.w.nx}x{self.w.ny}x{self.w.nz}:{self.precision}:{int(np.count_nonzero(self.mask))}"
+               f":form{self.mode}")
         table = {}
         if os.path.exists(path):
             try:

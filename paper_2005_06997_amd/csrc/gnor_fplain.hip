@@ -1,23 +1,30 @@
 // One-pass step of the plain tiles (gfx950): f1 and f2 of Sec. III fused for
-// tiles that meet neither metal nor a CPML slab.  The two-sweep form reads
-// E^n twice and writes, then re-reads, H^{n+1/2}: 18 field words per cell.
-// Here a tile computes H^{n+1/2} and, at once, E^{n+1} from it: 12 words
-// (read E^n and H^{n-1/2}, write H^{n+1/2} and E^{n+1}).
+// tiles that meet no metal and at most an x slab of the CPML.  The two-sweep
+// form reads E^n twice and writes, then re-reads, H^{n+1/2}: 18 field words
+// per cell.  Here a tile computes H^{n+1/2} and, at once, E^{n+1} from it:
+// 12 words (read E^n and H^{n-1/2}, write H^{n+1/2} and E^{n+1}).
 //
 // Each wavefront owns one row (64 cells along x) of the tile and marches it
-// up the tile's planes, independent of every other wavefront: no LDS, no
-// barrier.  The E update at (i, j, k) needs H^{n+1/2} at (i-1, j, k),
-// (i, j-1, k) and (i, j, k-1).  The plane below is carried in registers; the
-// row below (H_x, H_z) and the column to the left (H_y, H_z) are recomputed
-// from E^n and H^{n-1/2}, whose values the neighbouring wavefronts load too
-// (cache hits).  Only a cell's own H is stored, so no wavefront sees another
-// one's new values, and H is read from the step's input buffer and written
-// to its output buffer.
+// up the tile's planes.  The E update at (i, j, k) needs H^{n+1/2} at
+// (i-1, j, k), (i, j-1, k) and (i, j, k-1).  The plane below is carried in
+// registers; the column to the left (H_y, H_z) is the left lane's (a lane
+// shuffle), the row below (H_x, H_z) the wavefront below's, through LDS, one
+// barrier per plane.  Only the tile's edges recompute halo H from E^n and
+// H^{n-1/2}: the first lane of a row that of column x-1, the block's first
+// row that of row y-1.  Likewise E at column x+1 is the right lane's, the
+// last lane loading the next tile's.  Per cell and plane that is 8 loads,
+// against 22 when every wavefront recomputed its halo itself (which ran no
+// faster than the two sweeps: the loads, not the bytes, set its pace).  Only
+// a cell's own H is stored, and H is read from the step's input buffer and
+// written to its output buffer.
 //
-// TF/SF corrections: the H update takes E_inc^n from the auxiliary line; the
-// E update takes H_inc^{n+1/2}, evaluated from the line's state with the
-// line's own update (the line itself advances after this launch).  The
-// background coefficients follow the planes (a substrate beyond sub_k).
+// TF/SF: the one-pass kernels leave the corrections out.  They are linear
+// and sit on the faces of the TF box, so k_tfsf_fix adds them afterwards, at
+// the points of one-pass tiles only: to H^{n+1/2} on the faces the E_inc^n
+// terms, and to E^{n+1} the E update's share of those terms plus its own
+// H_inc^{n+1/2} terms (evaluated from the line's state with the line's own H
+// update; the line advances after the fix).  The background coefficients
+// follow the planes (a substrate beyond sub_k).
 #include "gnor_device.h"
 
 namespace gnor {
@@ -28,29 +35,6 @@ template <bool NT, class T>
 __device__ __forceinline__ void put(T* a, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, a);
   else *a = v;
-}
-
-// H_inc^{n+1/2} at line cell q from E_inc^n, H_inc^{n-1/2} (the line's H update)
-__device__ __forceinline__ double fp_h_inc(const AuxParams& a, int q) {
-  const double d = a.e1[q + 1] - a.e1[q];
-  const double ps = a.bh[q] * a.ph[q] + a.ah[q] * d;
-  return a.h1[q] - a.S * (a.kh[q] * d + ps);
-}
-
-// TF/SF terms of the H update at (i, j, k) (index units, before the factor
-// -S): the H_y term of the plane faces and the H_z term of the y faces.
-template <class T>
-__device__ __forceinline__ void tf_h(const Params<T>& p, int i, int j, int k, T& ty_, T& tz_) {
-  ty_ = tz_ = T(0);
-  if (!p.tfsf || i < p.tf_lo[0] || i > p.tf_hi[0] - 1) return;
-  if (j >= p.tf_lo[1] && j <= p.tf_hi[1]) {
-    if (k == p.tf_lo[2] - 1) ty_ = -(T)p.e1[p.tf_lo[2] + kAuxOff];
-    if (k == p.tf_hi[2]) ty_ = (T)p.e1[p.tf_hi[2] + kAuxOff];
-  }
-  if ((j == p.tf_lo[1] - 1 || j == p.tf_hi[1]) && k >= p.tf_lo[2] && k <= p.tf_hi[2]) {
-    const T inc = (T)p.e1[k + kAuxOff];
-    tz_ = (j == p.tf_lo[1] - 1) ? inc : -inc;
-  }
 }
 
 // H update ranges (PEC walls on the outer node planes): the H point exists and
@@ -69,42 +53,12 @@ __device__ __forceinline__ bool upd_hz(int i, int j, int k, int nx, int ny, int 
 // round trip per plane).
 __device__ __forceinline__ void load_fence() { __asm__ volatile("" ::: "memory"); }
 
-// The loads of one plane k of a column: E^n around the cell and the H^{n-1/2}
-// and E^n the halo H values need (row y-1: H_x, H_z; column x-1: H_y, H_z),
-// and, in x-slab tiles, the H-slab CPML memory of those H values.
+// Neighbour lanes of the wavefront (one row of 64 cells along x): the value
+// of lane + 1 and of lane - 1 (a lane without such a neighbour gets its own).
 template <class T>
-struct PlaneLoads {
-  T ez, ex1, ey1, ezx, eyx, ezy, exy, hx, hy, hz;  // own cell
-  T ezd, eyd1, eydx, exd, hxd, hzd;                // row y-1
-  T ezl, eyl, exl1, exly, hyl, hzl;                // column x-1
-  T sy_, sz_, szd, syl, szl;                       // psi_H^{n-1/2}: own H_y, H_z; H_z(y-1); H_y, H_z(x-1)
-};
-
-template <class T, bool XS>
-__device__ __forceinline__ void load_plane(const Params<T>& p, uint32_t id, uint32_t dzp, uint32_t dxp,
-                                           uint32_t dyp, uint32_t dxm, uint32_t dym, uint32_t qs,
-                                           uint32_t qsl, uint32_t sq, PlaneLoads<T>& v) {
-  const T* __restrict__ Ex = p.E[0];
-  const T* __restrict__ Ey = p.E[1];
-  const T* __restrict__ Ez = p.E[2];
-  v.ez = Ez[id];
-  v.ex1 = Ex[id + dzp]; v.ey1 = Ey[id + dzp];
-  v.ezx = Ez[id + dxp]; v.eyx = Ey[id + dxp];
-  v.ezy = Ez[id + dyp]; v.exy = Ex[id + dyp];
-  v.hx = p.Hi[0][id]; v.hy = p.Hi[1][id]; v.hz = p.Hi[2][id];
-  const uint32_t qd = id - dym, ql = id - dxm;
-  v.ezd = Ez[qd]; v.eyd1 = Ey[qd + dzp]; v.eydx = Ey[qd + dxp]; v.exd = Ex[qd];
-  v.hxd = p.Hi[0][qd]; v.hzd = p.Hi[2][qd];
-  v.ezl = Ez[ql]; v.eyl = Ey[ql]; v.exl1 = Ex[ql + dzp]; v.exly = Ex[ql + dyp];
-  v.hyl = p.Hi[1][ql]; v.hzl = p.Hi[2][ql];
-  if (XS) {
-    // x-slab memory at (slab column, j, k): own and row y-1 (column qs),
-    // column x-1 (column qsl); sq steps one row
-    v.sy_ = p.psiHi[0][1][qs]; v.sz_ = p.psiHi[0][0][qs];
-    v.szd = p.psiHi[0][0][qs - (dym ? sq : 0)];
-    v.syl = p.psiHi[0][1][qsl]; v.szl = p.psiHi[0][0][qsl];
-  }
-}
+__device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, kBX); }
+template <class T>
+__device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, kBX); }
 
 // x-slab coefficients at one position (b = 1, a = 0, k = 1 outside the slab)
 template <class T>
@@ -124,12 +78,69 @@ __device__ __forceinline__ T xstretch(const XCoef<T>& c, T d, T psi_old, T& psi_
   return c.k * d + psi_new;
 }
 
+// The loads of one plane of a column: E^n around the cell, H^{n-1/2} and
+// x-slab memory; E at column x+1 (last lane, from the next tile); what the
+// recomputed halos need (first lane: column x-1; first row: row y-1).
+template <class T>
+struct PlaneIn {
+  T ez = T(0), ex1 = T(0), ey1 = T(0), ezy = T(0), exy = T(0), hx = T(0), hy = T(0), hz = T(0);
+  T sy_ = T(0), sz_ = T(0);
+  T ezr = T(0), eyr = T(0);
+  T ezl = T(0), eyl = T(0), exl1 = T(0), exly = T(0), hyo = T(0), hzo = T(0), syl = T(0), szl = T(0);
+  T eyd1 = T(0), ezd = T(0), exd = T(0), hxo = T(0), hzd_o = T(0), szd = T(0), eydr = T(0);
+};
+
+template <class T, bool XS>
+__device__ __forceinline__ void load_plane(const Params<T>& p, PlaneIn<T>& v, uint32_t id, uint32_t dzp,
+                                           uint32_t dyp, uint32_t sy, uint32_t qs, uint32_t qsl,
+                                           uint32_t sq, bool act, bool first, bool last, bool rd) {
+  const T* __restrict__ Ex = p.E[0];
+  const T* __restrict__ Ey = p.E[1];
+  const T* __restrict__ Ez = p.E[2];
+  if (act) {
+    v.ez = Ez[id];
+    v.ex1 = Ex[id + dzp]; v.ey1 = Ey[id + dzp];
+    v.ezy = Ez[id + dyp]; v.exy = Ex[id + dyp];
+    v.hx = p.Hi[0][id]; v.hy = p.Hi[1][id]; v.hz = p.Hi[2][id];
+    if (XS) { v.sy_ = p.psiHi[0][1][qs]; v.sz_ = p.psiHi[0][0][qs]; }
+  }
+  if (last) { v.ezr = Ez[id + 1]; v.eyr = Ey[id + 1]; }
+  if (first) {
+    const uint32_t ql = id - 1;
+    v.ezl = Ez[ql]; v.eyl = Ey[ql]; v.exl1 = Ex[ql + dzp]; v.exly = Ex[ql + dyp];
+    v.hyo = p.Hi[1][ql]; v.hzo = p.Hi[2][ql];
+    if (XS) { v.syl = p.psiHi[0][1][qsl]; v.szl = p.psiHi[0][0][qsl]; }
+  }
+  if (rd) {
+    const uint32_t qd = id - sy;
+    v.ezd = Ez[qd]; v.eyd1 = Ey[qd + dzp]; v.exd = Ex[qd];
+    v.hxo = p.Hi[0][qd]; v.hzd_o = p.Hi[2][qd];
+    if (XS) v.szd = p.psiHi[0][0][qs - sq];
+    if (last) v.eydr = Ey[qd + 1];
+  }
+}
+
+// Rows of H_x^{n+1/2} and H_z^{n+1/2} of one plane, shared by the wavefronts
+// of a block; two planes deep, so that one barrier per plane suffices (a
+// wavefront overwrites a plane's rows only after the barrier of the next
+// plane, which every reader of that plane has passed).
+template <class T, int TY>
+struct HRows {
+  T h[2][2][TY][kBX];  // [plane & 1][0: H_x, 1: H_z][row][lane]
+};
+
+// XS: the tile meets an x slab (those tiles get a kernel of their own, so
+// that the others run code free of the CPML terms)
 template <class T, int TY, bool NT, bool XS>
-__device__ __forceinline__ void fplain_tile(const Params<T>& p, const AuxParams& a, const Tile tile) {
+__device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
+                                            HRows<T, TY>& sh) {
   const int nx = p.nx, ny = p.ny, nz = p.nz;
-  const int i = tile.bx * kBX + threadIdx.x;
-  const int j = tile.by * TY + threadIdx.y;
-  if (i >= nx || j >= ny) return;
+  const int lane = threadIdx.x, ty = threadIdx.y;
+  const int i = tile.bx * kBX + lane;
+  const int j = tile.by * TY + ty;
+  // lanes and rows outside the grid load and store nothing but take part in
+  // the shuffles and barriers
+  const bool act = i < nx && j < ny;
   const int k0 = tile.bz * p.tl.kz;
   const int k1 = min(nz, k0 + p.tl.kz);
   // 32-bit cell indices (at most 4e9 cells): one offset register serves the
@@ -147,22 +158,25 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const AuxParams&
   const T S = p.S;
   // neighbours that exist: x+1, y+1 (inside the grid), x-1, y-1
   const bool xp = i <= nx - 2, yp = j <= ny - 2, xm = i >= 1, ym = j >= 1;
-  const uint32_t dxp = xp ? 1 : 0, dyp = yp ? sy : 0, dxm = xm ? 1 : 0, dym = ym ? sy : 0;
+  const uint32_t dyp = yp ? sy : 0;
+  // the row's first lane recomputes H at column x-1 (the left tile's), its
+  // last lane loads E at column x+1; the block's first row recomputes H at
+  // row y-1 (the tile below's); every other halo value comes from a
+  // neighbouring lane or from the shared rows
+  const bool first = act && lane == 0 && xm;
+  const bool last = act && lane == kBX - 1 && xp;
+  const bool low = ty == 0;  // uniform over the wavefront
   // E update ranges of the column
-  const bool ax = i <= nx - 2 && j >= 1 && j <= ny - 2;
-  const bool ay = i >= 1 && i <= nx - 2 && j <= ny - 2;
-  const bool az = i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
-  const bool tf_xband = p.tfsf && i >= p.tf_lo[0] && i <= p.tf_hi[0] - 1 && j >= p.tf_lo[1] &&
-                        j <= p.tf_hi[1];
-  const bool tf_zside = p.tfsf && j >= p.tf_lo[1] && j <= p.tf_hi[1] &&
-                        (i == p.tf_lo[0] || i == p.tf_hi[0]);
+  const bool ax = act && i <= nx - 2 && j >= 1 && j <= ny - 2;
+  const bool ay = act && i >= 1 && i <= nx - 2 && j <= ny - 2;
+  const bool az = act && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
   // x slab (tiles that meet one): the H-slab positions of the column and of
   // column x-1, the E-slab position of the column, their coefficients, and
   // slab-array indices (axis-0 slab arrays: ((k ny + j) 2 np + s))
   const int np = p.cp[0].np;
-  const int sxh = XS ? slab_h(i, nx, np) : -1;
-  const int sxl = (XS && xm) ? slab_h(i - 1, nx, np) : -1;
-  const int sxe = XS ? slab_e(i, nx, np) : -1;
+  const int sxh = (XS && act) ? slab_h(i, nx, np) : -1;
+  const int sxl = (XS && first) ? slab_h(i - 1, nx, np) : -1;
+  const int sxe = (XS && act) ? slab_e(i, nx, np) : -1;
   XCoef<T> ch{T(1), T(0), T(1)}, cl{T(1), T(0), T(1)}, ce{T(1), T(0), T(1)};
   if (XS) {
     const CpmlAxis<T>& X = p.cp[0];
@@ -173,52 +187,63 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const AuxParams&
   const uint32_t w2 = 2 * np;
   const uint32_t sq = w2;                 // one row in a slab array
   const uint32_t sp = (uint32_t)ny * w2;  // one plane
-  uint32_t qs = ((uint32_t)k0 * ny + j) * w2 + (uint32_t)max(sxh, 0);
-  uint32_t qsl = ((uint32_t)k0 * ny + j) * w2 + (uint32_t)max(sxl, 0);
-  uint32_t qse = ((uint32_t)k0 * ny + j) * w2 + (uint32_t)max(sxe, 0);
+  const uint32_t jr = act ? (uint32_t)j : 0;
+  uint32_t qs = ((uint32_t)k0 * ny + jr) * w2 + (uint32_t)max(sxh, 0);
+  uint32_t qsl = ((uint32_t)k0 * ny + jr) * w2 + (uint32_t)max(sxl, 0);
+  uint32_t qse = ((uint32_t)k0 * ny + jr) * w2 + (uint32_t)max(sxe, 0);
 
-  uint32_t id = (uint32_t)k0 * sz + (uint32_t)j * nx + i;
-  // carried: E_x, E_y of plane k at the column, of the column x-1 (E_x) and
-  // of the row y-1 (E_y); H_x, H_y^{n+1/2} of plane k-1 at the column
-  T ex0 = Ex[id], ey0 = Ey[id];
-  T exl0 = Ex[id - dxm], eyd0 = Ey[id - dym];
+  uint32_t id = act ? (uint32_t)k0 * sz + (uint32_t)j * nx + i : 0;
+  // carried: E_x, E_y of plane k at the column, E_x of column x-1 (first
+  // lane) and E_y of row y-1 (first row); H_x, H_y^{n+1/2} of plane k-1
+  T ex0 = act ? Ex[id] : T(0), ey0 = act ? Ey[id] : T(0);
+  T exl0 = first ? Ex[id - 1] : T(0);
+  T eyd0 = (low && act && ym) ? Ey[id - sy] : T(0);
   T hxm = T(0), hym = T(0);
-  if (k0 >= 1) {
+  if (act && k0 >= 1) {
     // H_x, H_y^{n+1/2} of plane k0-1 (recomputed; stored by the tile below)
     const uint32_t q = id - sz;
     const T exq = Ex[q], eyq = Ey[q], ezq = Ez[q];
-    const T ezy = Ez[q + dyp], ezx = Ez[q + dxp];
+    const T ezy = Ez[q + dyp], ezx = Ez[q + (xp ? 1 : 0)];
     const T hx_ = p.Hi[0][q], hy_ = p.Hi[1][q];
     const T psy = XS ? p.psiHi[0][1][qs - sp] : T(0);
-    T tyv, tzv;
-    tf_h(p, i, j, k0 - 1, tyv, tzv);
     T dxy = ezx - ezq, psn;
     if (XS && sxh >= 0) dxy = xstretch(ch, dxy, psy, psn);
     hxm = upd_hx(i, j, k0 - 1, nx, ny, nz) ? hx_ - S * ((ezy - ezq) - (ey0 - eyq)) : hx_;
-    hym = upd_hy(i, j, k0 - 1, nx, ny, nz) ? hy_ - S * (((ex0 - exq) - dxy) + tyv) : hy_;
+    hym = upd_hy(i, j, k0 - 1, nx, ny, nz) ? hy_ - S * ((ex0 - exq) - dxy) : hy_;
   }
+  const bool rd = low && act && ym;  // the first row loads row y-1
   for (int k = k0; k < k1; ++k, id += sz, qs += sp, qsl += sp, qse += sp) {
     const bool zp = k <= nz - 2;
     // ---- the plane's loads, issued together (one memory round trip per
-    // plane; issuing the next plane's loads a plane ahead measured no faster)
-    PlaneLoads<T> cur;
-    load_plane<T, XS>(p, id, zp ? sz : 0, dxp, dyp, dxm, dym, qs, qsl, sq, cur);
+    // plane; issuing them a plane ahead measured no faster)
+    PlaneIn<T> cur;
+    load_plane<T, XS>(p, cur, id, zp ? sz : 0, dyp, sy, qs, qsl, sq, act, first, last, rd);
     load_fence();
-    const PlaneLoads<T>& v = cur;
+    const T ez = cur.ez, ex1 = cur.ex1, ey1 = cur.ey1, ezy = cur.ezy, exy = cur.exy;
+    const T hx = cur.hx, hy = cur.hy, hz = cur.hz, sy_ = cur.sy_, sz_ = cur.sz_;
+    const T ezr = cur.ezr, eyr = cur.eyr;
+    const T ezl = cur.ezl, eyl = cur.eyl, exl1 = cur.exl1, exly = cur.exly, hyo = cur.hyo, hzo = cur.hzo;
+    const T syl = cur.syl, szl = cur.szl;
+    const T eyd1 = cur.eyd1, ezd = cur.ezd, exd = cur.exd, hxo = cur.hxo, hzd_o = cur.hzd_o;
+    const T szd = cur.szd, eydr = cur.eydr;
+    // E_z, E_y of plane k at column x+1: the right lane's (the last lane
+    // takes the next tile's; a column without x+1 uses its own, as an H
+    // point there is not updated)
+    T ezx = from_right(ez), eyx = from_right(ey0);
+    if (last) { ezx = ezr; eyx = eyr; }
+    if (!xp) { ezx = ez; eyx = ey0; }
     // ---- H^{n+1/2} of the cell
-    T tyv, tzv;
-    tf_h(p, i, j, k, tyv, tzv);
-    T dxy = v.ezx - v.ez, dxz = v.eyx - ey0;  // x differences of H_y, H_z
+    T dxy = ezx - ez, dxz = eyx - ey0;  // x differences of H_y, H_z
     T psy = T(0), psz = T(0);
     if (XS && sxh >= 0) {
-      dxy = xstretch(ch, dxy, v.sy_, psy);
-      dxz = xstretch(ch, dxz, v.sz_, psz);
+      dxy = xstretch(ch, dxy, sy_, psy);
+      dxz = xstretch(ch, dxz, sz_, psz);
     }
-    const bool uhx = upd_hx(i, j, k, nx, ny, nz), uhy = upd_hy(i, j, k, nx, ny, nz);
-    const bool uhz = upd_hz(i, j, k, nx, ny, nz);
-    const T hxn = uhx ? v.hx - S * ((v.ezy - v.ez) - (v.ey1 - ey0)) : v.hx;
-    const T hyn = uhy ? v.hy - S * (((v.ex1 - ex0) - dxy) + tyv) : v.hy;
-    const T hzn = uhz ? v.hz - S * ((dxz - (v.exy - ex0)) + tzv) : v.hz;
+    const bool uhx = act && upd_hx(i, j, k, nx, ny, nz), uhy = act && upd_hy(i, j, k, nx, ny, nz);
+    const bool uhz = act && upd_hz(i, j, k, nx, ny, nz);
+    const T hxn = uhx ? hx - S * ((ezy - ez) - (ey1 - ey0)) : hx;
+    const T hyn = uhy ? hy - S * ((ex1 - ex0) - dxy) : hy;
+    const T hzn = uhz ? hz - S * (dxz - (exy - ex0)) : hz;
     if (uhx) put<NT>(&Hx[id], hxn);
     if (uhy) put<NT>(&Hy[id], hyn);
     if (uhz) put<NT>(&Hz[id], hzn);
@@ -226,26 +251,41 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const AuxParams&
       if (uhy) p.psiH[0][1][qs] = psy;
       if (uhz) p.psiH[0][0][qs] = psz;
     }
-    // ---- halo H^{n+1/2}: row y-1 (H_x, H_z), column x-1 (H_y, H_z)
-    T hxd = T(0), hzd = T(0), hyl = T(0), hzl = T(0);
-    if (ym) {
-      T tyd, tzd;
-      tf_h(p, i, j - 1, k, tyd, tzd);
-      T d = v.eydx - eyd0, ps;
-      if (XS && sxh >= 0) d = xstretch(ch, d, v.szd, ps);
-      hxd = upd_hx(i, j - 1, k, nx, ny, nz) ? v.hxd - S * ((v.ez - v.ezd) - (v.eyd1 - eyd0)) : v.hxd;
-      hzd = upd_hz(i, j - 1, k, nx, ny, nz) ? v.hzd - S * ((d - (ex0 - v.exd)) + tzd) : v.hzd;
-    }
-    if (xm) {
-      T tyl, tzl;
-      tf_h(p, i - 1, j, k, tyl, tzl);
-      T dy_ = v.ez - v.ezl, dz_ = ey0 - v.eyl, ps;
+    const int b = k & 1;
+    sh.h[b][0][ty][lane] = hxn;
+    sh.h[b][1][ty][lane] = hzn;
+    // ---- halo H^{n+1/2} of column x-1 (H_y, H_z): the left lane's; the
+    // first lane recomputes the left tile's from E^n and H^{n-1/2}
+    T hyl = from_left(hyn), hzl = from_left(hzn);
+    if (first) {
+      T dy_ = ez - ezl, dz_ = ey0 - eyl, ps;
       if (XS && sxl >= 0) {
-        dy_ = xstretch(cl, dy_, v.syl, ps);
-        dz_ = xstretch(cl, dz_, v.szl, ps);
+        dy_ = xstretch(cl, dy_, syl, ps);
+        dz_ = xstretch(cl, dz_, szl, ps);
       }
-      hyl = upd_hy(i - 1, j, k, nx, ny, nz) ? v.hyl - S * (((v.exl1 - exl0) - dy_) + tyl) : v.hyl;
-      hzl = upd_hz(i - 1, j, k, nx, ny, nz) ? v.hzl - S * ((dz_ - (v.exly - exl0)) + tzl) : v.hzl;
+      hyl = upd_hy(i - 1, j, k, nx, ny, nz) ? hyo - S * ((exl1 - exl0) - dy_) : hyo;
+      hzl = upd_hz(i - 1, j, k, nx, ny, nz) ? hzo - S * (dz_ - (exly - exl0)) : hzo;
+      exl0 = exl1;
+    }
+    // ---- halo H^{n+1/2} of row y-1 (H_x, H_z): the shared row below; the
+    // first row recomputes the tile below's
+    T hxd = T(0), hzd = T(0);
+    if (low) {
+      T eydx = from_right(eyd0);  // E_y(i+1, j-1, k)
+      if (last) eydx = eydr;
+      if (!xp) eydx = eyd0;
+      if (rd) {
+        T d = eydx - eyd0, ps;
+        if (XS && sxh >= 0) d = xstretch(ch, d, szd, ps);
+        hxd = upd_hx(i, j - 1, k, nx, ny, nz) ? hxo - S * ((ez - ezd) - (eyd1 - eyd0)) : hxo;
+        hzd = upd_hz(i, j - 1, k, nx, ny, nz) ? hzd_o - S * (d - (ex0 - exd)) : hzd_o;
+      }
+      eyd0 = eyd1;
+    }
+    __syncthreads();
+    if (!low && ym) {
+      hxd = sh.h[b][0][ty - 1][lane];
+      hzd = sh.h[b][1][ty - 1][lane];
     }
     // ---- E^{n+1}
     const bool kin = k >= 1 && k <= nz - 2;
@@ -268,56 +308,168 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const AuxParams&
     T cxv = (hzn - hzd) - (hyn - hym);  // dy H_z - dz H_y
     T cyv = (hxn - hxm) - d_xy;         // dz H_x - dx H_z
     T czv = d_xz - (hxn - hxd);         // dx H_y - dy H_x
-    if (tf_xband) {
-      if (k == p.tf_lo[2]) cxv += (T)fp_h_inc(a, p.tf_lo[2] - 1 + kAuxOff);
-      if (k == p.tf_hi[2]) cxv -= (T)fp_h_inc(a, p.tf_hi[2] + kAuxOff);
-    }
-    if (tf_zside && k >= p.tf_lo[2] && k <= p.tf_hi[2] - 1) {
-      const T inc = (T)fp_h_inc(a, k + kAuxOff);
-      czv += (i == p.tf_lo[0]) ? -inc : inc;
-    }
     const T sexy = k < p.sub_k ? p.SE : (k == p.sub_k ? p.se_avg : p.se_sub);
     const T sez = k < p.sub_k ? p.SE : p.se_sub;
     if (uex) put<NT>(&Ox[id], ex0 + sexy * cxv);
     if (uey) put<NT>(&Oy[id], ey0 + sexy * cyv);
-    if (uez) put<NT>(&Oz[id], v.ez + sez * czv);
+    if (uez) put<NT>(&Oz[id], ez + sez * czv);
     // ---- carry up the column
-    ex0 = v.ex1;
-    ey0 = v.ey1;
-    exl0 = v.exl1;
-    eyd0 = v.eyd1;
+    ex0 = ex1;
+    ey0 = ey1;
     hxm = hxn;
     hym = hyn;
   }
 }
 
 // Class 0 of the two-sweep tiling (plain tiles, and tiles that meet only an
-// x slab: their x-slab CPML behind a tile-uniform branch)
-template <class T, int TY, bool NT>
-__global__ void __launch_bounds__(kBX* TY) k_fplain(Params<T> p, AuxParams a) {
+// x slab).  PURE: the leading part of the class list, tiles that meet no x
+// slab; otherwise the rest, the x-slab tiles.  Two kernels, so that the bulk
+// of the grid runs code without the CPML terms (40 VGPRs and 93 SGPRs, 8
+// waves per SIMD, against 64 and 106, 7 waves, with them).
+template <class T, int TY, bool NT, bool PURE>
+__global__ void __launch_bounds__(kBX* TY) k_fplain(Params<T> p) {
+  __shared__ HRows<T, TY> sh;
   const Tile tile = decode_tile(p.tl, p.tiles, 0, blockIdx.x);
-  if (!tile.ok) return;
-  const int np = p.cp[0].np;
-  const bool xs = np > 0 && (tile.bx * kBX - 1 < np || tile.bx * kBX + kBX + 1 > p.nx - 1 - np);
-  if (xs) fplain_tile<T, TY, NT, true>(p, a, tile);
-  else fplain_tile<T, TY, NT, false>(p, a, tile);
+  if (!tile.ok) return;  // uniform over the block
+  if (PURE) fplain_tile<T, TY, NT, false>(p, tile, sh);
+  else fplain_tile<T, TY, NT, true>(p, tile, sh);
+}
+
+template <class T, bool NT, bool PURE>
+void launch_fplain_nt(const Params<T>& p, int blocks, hipStream_t s) {
+  if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain<T, 4, NT, PURE>), dim3(blocks), dim3(kBX, 4), 0, s, p);
+  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain<T, 8, NT, PURE>), dim3(blocks), dim3(kBX, 8), 0, s, p);
+  else hipLaunchKernelGGL((k_fplain<T, 2, NT, PURE>), dim3(blocks), dim3(kBX, 2), 0, s, p);
+}
+
+// Class 0 restricted to positions [first, first + n) of its list (the tile
+// order then deals that sub-list to the XCDs)
+template <class T>
+Params<T> class0_part(const Params<T>& p, int first, int n) {
+  Params<T> q = p;
+  Tiling& t = q.tl;
+  t.coff[0] += first;
+  t.cn[0] = n;
+  if (t.xcd == 1) t.cper[0] = (n + 7) / 8;
+  else if (t.xcd == 2) t.cper[0] = ((n + t.q - 1) / t.q + 7) / 8;
+  else t.cper[0] = n;
+  return q;
+}
+
+// ------------------------------------------------------- TF/SF corrections
+// H_inc^{n+1/2} at line cell q from E_inc^n and the line's H^{n-1/2} (the
+// line's own H update; the line advances after the correction)
+__device__ __forceinline__ double line_h_next(const AuxParams& a, int q) {
+  const double d = a.e1[q + 1] - a.e1[q];
+  const double ps = a.bh[q] * a.ph[q] + a.ah[q] * d;
+  return a.h1[q] - a.S * (a.kh[q] * d + ps);
+}
+// The TF/SF terms of H^{n+1/2} at an H_y and an H_z point (zero off the
+// faces): -S times the E_inc^n terms the two-sweep H update adds to its curl
+template <class T>
+__device__ __forceinline__ T tf_dhy(const Params<T>& p, int i, int j, int k) {
+  if (i < p.tf_lo[0] || i > p.tf_hi[0] - 1 || j < p.tf_lo[1] || j > p.tf_hi[1]) return T(0);
+  if (k == p.tf_lo[2] - 1) return p.S * (T)p.e1[p.tf_lo[2] + kAuxOff];
+  if (k == p.tf_hi[2]) return -(p.S * (T)p.e1[p.tf_hi[2] + kAuxOff]);
+  return T(0);
+}
+template <class T>
+__device__ __forceinline__ T tf_dhz(const Params<T>& p, int i, int j, int k) {
+  if (i < p.tf_lo[0] || i > p.tf_hi[0] - 1 || k < p.tf_lo[2] || k > p.tf_hi[2]) return T(0);
+  if (j == p.tf_lo[1] - 1) return -(p.S * (T)p.e1[k + kAuxOff]);
+  if (j == p.tf_hi[1]) return p.S * (T)p.e1[k + kAuxOff];
+  return T(0);
+}
+
+// One thread per point of the shell of the TF box: the box widened by one
+// cell, [lo - 1, hi + 1], without its inside [lo + 1, hi - 1], each point
+// once: the planes k in {lo-1, lo, hi, hi+1} (whole widened rows), then the
+// rows j in {lo-1, lo, hi, hi+1} of the planes lo+1 .. hi-1, then the
+// columns i in {lo-1, lo, hi, hi+1} of rows lo+1 .. hi-1 of those planes.
+// Every TF/SF term, and every E point whose curl holds one, lies in it.  A
+// point of a two-sweep tile is left alone (those sweeps apply the terms
+// themselves); at a point of a one-pass tile the terms go to H^{n+1/2} and
+// the E update's share of the H terms of its curl (the one-pass kernels took
+// every H of that curl without them) plus its own H_inc terms to E^{n+1}.
+template <class T>
+__global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a) {
+  const int* lo = p.tf_lo;
+  const int* hi = p.tf_hi;
+  const int Lx = hi[0] - lo[0] + 3, Ly = hi[1] - lo[1] + 3, Lz = hi[2] - lo[2] + 3;
+  const int nZ = 4 * Lx * Ly, nY = 4 * (Lz - 4) * Lx, nX = 4 * (Ly - 4) * (Lz - 4);
+  int t = blockIdx.x * 256 + threadIdx.x;
+  int i, j, k;
+  if (t < nZ) {
+    const int q = t / (Lx * Ly);
+    i = lo[0] - 1 + t % Lx;
+    j = lo[1] - 1 + (t / Lx) % Ly;
+    k = q < 2 ? lo[2] - 1 + q : hi[2] + (q - 2);
+  } else if ((t -= nZ) < nY) {
+    const int q = t / (Lx * (Lz - 4));
+    i = lo[0] - 1 + t % Lx;
+    k = lo[2] + 1 + (t / Lx) % (Lz - 4);
+    j = q < 2 ? lo[1] - 1 + q : hi[1] + (q - 2);
+  } else if ((t -= nY) < nX) {
+    const int q = t / ((Ly - 4) * (Lz - 4));
+    j = lo[1] + 1 + t % (Ly - 4);
+    k = lo[2] + 1 + (t / (Ly - 4)) % (Lz - 4);
+    i = q < 2 ? lo[0] - 1 + q : hi[0] + (q - 2);
+  } else {
+    return;
+  }
+  const Tiling& tl = p.tl;
+  if (p.tile_class[((k / tl.kz) * tl.nby + j / tl.ty) * tl.nbx + i / kBX] != 0) return;
+  const size_t id = ((size_t)k * p.ny + j) * p.nx + i;
+  const T dhy = tf_dhy(p, i, j, k), dhz = tf_dhz(p, i, j, k);
+  if (dhy != T(0)) p.H[1][id] += dhy;
+  if (dhz != T(0)) p.H[2][id] += dhz;
+  const T sexy = k < p.sub_k ? p.SE : (k == p.sub_k ? p.se_avg : p.se_sub);
+  const T sez = k < p.sub_k ? p.SE : p.se_sub;
+  // E_x: dy H_z - dz H_y, and H_inc on the z faces
+  T cx = (dhz - tf_dhz(p, i, j - 1, k)) - (dhy - tf_dhy(p, i, j, k - 1));
+  if (i >= lo[0] && i <= hi[0] - 1 && j >= lo[1] && j <= hi[1]) {
+    if (k == lo[2]) cx += (T)line_h_next(a, lo[2] - 1 + kAuxOff);
+    if (k == hi[2]) cx -= (T)line_h_next(a, hi[2] + kAuxOff);
+  }
+  if (cx != T(0)) p.O[0][id] += sexy * cx;
+  // E_y: dz H_x - dx H_z
+  const T cy = tf_dhz(p, i - 1, j, k) - dhz;
+  if (cy != T(0)) p.O[1][id] += sexy * cy;
+  // E_z: dx H_y - dy H_x, and H_inc on the x faces
+  T cz = dhy - tf_dhy(p, i - 1, j, k);
+  if ((i == lo[0] || i == hi[0]) && j >= lo[1] && j <= hi[1] && k >= lo[2] && k <= hi[2] - 1) {
+    const T inc = (T)line_h_next(a, k + kAuxOff);
+    cz += (i == lo[0]) ? -inc : inc;
+  }
+  if (cz != T(0)) p.O[2][id] += sez * cz;
 }
 
 template <class T, bool NT>
-void launch_fplain_nt(const Params<T>& p, const AuxParams& a, int blocks, hipStream_t s) {
-  if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain<T, 4, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p, a);
-  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain<T, 8, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p, a);
-  else hipLaunchKernelGGL((k_fplain<T, 2, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p, a);
+void launch_fplain_parts(const Params<T>& p, hipStream_t s) {
+  const int pure = p.tl.n0pure, rest = p.tl.cn[0] - pure;
+  if (pure > 0) {
+    const Params<T> q = class0_part(p, 0, pure);
+    launch_fplain_nt<T, NT, true>(q, class_blocks(q.tl, 0), s);
+  }
+  if (rest > 0) {
+    const Params<T> q = class0_part(p, pure, rest);
+    launch_fplain_nt<T, NT, false>(q, class_blocks(q.tl, 0), s);
+  }
 }
 
 }  // namespace
 
 template <class T>
 void launch_fplain(const Params<T>& p, const AuxParams& a, hipStream_t s) {
-  const int blocks = class_blocks(p.tl, 0);
-  if (blocks == 0) return;
-  if (p.stream_stores) launch_fplain_nt<T, true>(p, a, blocks, s);
-  else launch_fplain_nt<T, false>(p, a, blocks, s);
+  if (p.tl.cn[0] == 0) return;
+  if (p.stream_stores) launch_fplain_parts<T, true>(p, s);
+  else launch_fplain_parts<T, false>(p, s);
+  if (p.tfsf) {
+    const int Lx = p.tf_hi[0] - p.tf_lo[0] + 3, Ly = p.tf_hi[1] - p.tf_lo[1] + 3;
+    const int Lz = p.tf_hi[2] - p.tf_lo[2] + 3;
+    const long n = 4L * Lx * Ly + 4L * (Lz - 4) * Lx + 4L * (Ly - 4) * (Lz - 4);
+    hipLaunchKernelGGL(k_tfsf_fix<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, a);
+  }
 }
 template void launch_fplain<float>(const Params<float>&, const AuxParams&, hipStream_t);
 template void launch_fplain<double>(const Params<double>&, const AuxParams&, hipStream_t);

@@ -78,6 +78,7 @@ struct Tiling {
   int cn[kClasses];    // tiles per class
   int coff[kClasses];  // offset of each class's list in the tile list
   int cper[kClasses];  // positions (order 1) or chunks (order 2) per XCD, per class
+  int n0pure;          // leading class-0 tiles that meet no x slab (step form 3)
 };
 
 // Auxiliary line state (FP64 always).
@@ -166,6 +167,7 @@ struct Params {
   double* jpart;      // [nz][nbx * nby * ty]
   Tiling tl;
   const int* tiles;   // tile lists of the classes, back to back
+  const uint8_t* tile_class;  // class of every tile (tile order x, y, z)
   const int64_t* step_base;
 };
 
@@ -312,8 +314,8 @@ void launch_ej_class(const Params<T>& p, const AuxParams& a, int sub, int c, hip
 template <class T>
 void launch_step_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s);
 void launch_aux(const AuxParams& a, int sub, hipStream_t s);
-// one-pass step of the plain tiles (class 0 without CPML; gnor_fplain.hip),
-// before the auxiliary line's step
+// one-pass step of the plain tiles (class 0: no metal, at most an x slab;
+// gnor_fplain.hip) and its TF/SF corrections, before the line's step
 template <class T>
 void launch_fplain(const Params<T>& p, const AuxParams& a, hipStream_t s);
 template <class T>
@@ -370,7 +372,12 @@ Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
 // the class lists back to back.  merge_x: tiles without metal that meet only
 // an x slab go to class 0, whose two-sweep kernels update the x-slab psi of
 // such tiles (the fused kernels of class 0 have no CPML: false for them).
+// split_pure (the step form with one-pass plain tiles): class 0 lists first
+// the tiles that, widened by one cell, meet no x slab (t.n0pure of them),
+// then the others; otherwise class 0 keeps the natural order (n0pure = 0).
+// tile_class receives the class of every tile (tile order x, y, z).
 void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
-                    std::vector<int>& list, bool merge_x);
+                    std::vector<int>& list, bool merge_x, bool split_pure,
+                    std::vector<uint8_t>& tile_class);
 
 }  // namespace gnor

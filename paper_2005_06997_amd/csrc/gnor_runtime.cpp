@@ -54,7 +54,7 @@ struct Planner {
 
 struct Layout {
   // static region
-  size_t mask = 0, rho = 0, cpml[3] = {0, 0, 0}, aux_prof = 0, omega = 0, fpw = 0, tiles = 0,
+  size_t mask = 0, rho = 0, cpml[3] = {0, 0, 0}, aux_prof = 0, omega = 0, fpw = 0, tiles = 0, tile_class = 0,
          colz = 0, map_om = 0;
   // scratch outside the state: density read-out (M doubles), the flags of
   // gnor_check_finite and of the design-density check
@@ -99,6 +99,7 @@ struct gnor_sim {
   int tile_ty = 2, tile_kz = 8, tile_xcd = 2;    // sweep tiling (autotuned)
   gnor::Tiling tl{};                              // that tiling with its tile classes
   std::vector<int> tile_list;                     // the classes' tile lists (host copy)
+  std::vector<uint8_t> tile_class;                // class of every tile (host copy)
   std::vector<int> rowx;                          // x extent of the metal points per (y, z) row
   // step form: 0 H and E/J sweeps, 1 one-pass fused step, 2 hybrid, 3 fused
   // plain tiles (see hybrid_fused)
@@ -245,6 +246,7 @@ void plan_layout(gnor_sim* s) {
   L.fpw = P.take((size_t)s->npairs * 8 + 8);
   // tile lists: room for the finest tiling (ty = 2, kz = 1)
   L.tiles = P.take((size_t)s->nbx * ((s->g.ny + 1) / 2) * s->g.nz * 4 + 4);
+  L.tile_class = P.take((size_t)s->nbx * ((s->g.ny + 1) / 2) * s->g.nz + 4);
   L.map_om = P.take((size_t)std::max(1, s->maps.nmap) * 8);
   L.dens = P.take(M * 8);
   L.chk = P.take(4);
@@ -390,6 +392,7 @@ gnor::Params<T> make_params(gnor_sim* s, int parity) {
   p.jpart = ptr<double>(s, s->L.jpart);
   p.tl = s->tl;
   p.tiles = ptr<int>(s, s->L.tiles);
+  p.tile_class = ptr<uint8_t>(s, s->L.tile_class);
   p.step_base = ptr<int64_t>(s, s->L.step);
   return p;
 }
@@ -663,10 +666,12 @@ gnor_status plan_tiles(gnor_sim* s) {
   // x-slab tiles join the plain class only in the two-sweep form: the fused
   // and hybrid forms run class 0 on the fused kernel, which has no CPML
   gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->any_metal ? s->rowx.data() : nullptr,
-                       s->tile_list, merge_x_slabs(s->mode));
+                       s->tile_list, merge_x_slabs(s->mode), s->mode == 3, s->tile_class);
   if (s->bound && !s->tile_list.empty()) {
     HIPCHECK(s, hipStreamSynchronize(s->stream));
     HIPCHECK(s, hipMemcpy(s->dev + s->L.tiles, s->tile_list.data(), s->tile_list.size() * 4,
+                          hipMemcpyHostToDevice));
+    HIPCHECK(s, hipMemcpy(s->dev + s->L.tile_class, s->tile_class.data(), s->tile_class.size(),
                           hipMemcpyHostToDevice));
   }
   return GNOR_OK;
@@ -675,7 +680,7 @@ gnor_status plan_tiles(gnor_sim* s) {
 // Change the step form; the class lists depend on it (see plan_tiles).
 gnor_status set_mode(gnor_sim* s, int mode) {
   if (mode == s->mode) return GNOR_OK;
-  const bool replan = merge_x_slabs(mode) != merge_x_slabs(s->mode);
+  const bool replan = merge_x_slabs(mode) != merge_x_slabs(s->mode) || (mode == 3) != (s->mode == 3);
   s->mode = mode;
   drop_graph(s);
   return replan ? plan_tiles(s) : GNOR_OK;
@@ -1469,7 +1474,12 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
   const bool fp32 = s->g.precision == GNOR_FP32;
   const int mode = s->mode;
   const bool fused = mode == 1;
-  const bool whole = s->concurrent || mode >= 2;  // each half timed as a whole
+  // each half timed as a whole: concurrent classes, and the hybrid form (its
+  // fused classes span both halves); the form with one-pass plain tiles, run
+  // serially, times class 0's one-pass launches (with their TF/SF fix) in the
+  // first half's class-0 slot and the line in the second's
+  const bool whole = s->concurrent || mode == 2;
+  const bool plain1 = mode == 3;
   for (int64_t q = 0; q < nsteps; ++q) {
     const int64_t n = s->step;
     const int parity = (int)(n & 1);
@@ -1491,6 +1501,9 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       if (fused) {
         if (fp32) gnor::launch_step_class<float>(make_params<float>(s, parity), a, c, str);
         else gnor::launch_step_class<double>(make_params<double>(s, parity), a, c, str);
+      } else if (plain1 && c == 0) {
+        if (fp32) gnor::launch_fplain<float>(make_params<float>(s, parity), a, str);
+        else gnor::launch_fplain<double>(make_params<double>(s, parity), a, str);
       } else {
         if (fp32) gnor::launch_h_class<float>(make_params<float>(s, parity), a, c, str);
         else gnor::launch_h_class<double>(make_params<double>(s, parity), a, c, str);
@@ -1498,7 +1511,7 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       (void)hipEventRecord(ev[1 + c], str);
     }
     for (int c = 0; c < NC && !whole; ++c) {
-      if (fused) {
+      if (fused || (plain1 && c == 0)) {
         if (c == 0) gnor::launch_aux(a, 0, str);
       } else {
         if (fp32) gnor::launch_ej_class<float>(make_params<float>(s, parity), a, 0, c, str);
@@ -1566,6 +1579,40 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
 gnor_status gnor_tile_classes(const gnor_sim* s, int32_t* counts) {
   if (!s || !counts) return GNOR_E_INVALID_ARG;
   for (int c = 0; c < gnor::kClasses; ++c) counts[c] = s->tl.cn[c];
+  return GNOR_OK;
+}
+
+gnor_status gnor_tile_class_cells(const gnor_sim* s, int64_t* cells, int64_t* slab_dirs) {
+  if (!s || !cells || !slab_dirs) return GNOR_E_INVALID_ARG;
+  if (!s->bound) return GNOR_E_STATE;
+  const gnor_grid_desc& g = s->g;
+  const gnor::Tiling& t = s->tl;
+  const int n[3] = {g.nx, g.ny, g.nz}, np = g.npml;
+  // cells of [lo, hi) on an axis of n nodes that lie in its slabs
+  auto in_slab = [np](int lo, int hi, int nn) -> int64_t {
+    if (np <= 0) return 0;
+    const int a = std::max(0, std::min(hi, np) - lo);
+    const int b = std::max(0, hi - std::max(lo, nn - np));
+    return a + b;
+  };
+  for (int c = 0; c < gnor::kClasses; ++c) {
+    cells[c] = 0;
+    slab_dirs[c] = 0;
+    for (int q = 0; q < t.cn[c]; ++q) {
+      const int tile = s->tile_list[t.coff[c] + q];
+      const int b[3] = {tile % t.nbx, (tile / t.nbx) % t.nby, tile / (t.nbx * t.nby)};
+      const int w[3] = {gnor::kBX, t.ty, t.kz};
+      int lo[3], hi[3];
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = b[d] * w[d];
+        hi[d] = std::min(n[d], lo[d] + w[d]);
+      }
+      const int64_t e[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+      cells[c] += e[0] * e[1] * e[2];
+      slab_dirs[c] += in_slab(lo[0], hi[0], n[0]) * e[1] * e[2] + in_slab(lo[1], hi[1], n[1]) * e[0] * e[2] +
+                      in_slab(lo[2], hi[2], n[2]) * e[0] * e[1];
+    }
+  }
   return GNOR_OK;
 }
 

@@ -157,3 +157,22 @@ def test_watchdog_reports_a_planted_nan(B):
             s.synchronize()
             assert not s.check_finite()
         s.close()
+
+
+@pytest.mark.parametrize("form", [0, 3])
+def test_tile_class_cells_cover_the_grid(B, form):
+    """Per-class cell counts (the bench's algorithmic bytes come from them):
+    the tiles of the four classes cover every cell once, and the slab
+    (cell, axis) pairs add up to the CPML's, 2 npml N / n per axis."""
+    w = W.small_sphere(n=52, npml=6, seed=3)
+    w.nx = 150  # three x tiles, the last ragged
+    print(f"case tile class cells, form {form}", flush=True)
+    g = B.Sim(w, precision="fp32")
+    g.set_mode(form)
+    g.set_tiling(4, 5, 2)
+    cells, dirs = g.tile_class_cells()
+    N = w.nx * w.ny * w.nz
+    assert sum(cells) == N
+    assert sum(dirs) == sum(2 * w.npml * N // n for n in (w.nx, w.ny, w.nz))
+    assert cells[0] > 0 and cells[2] + cells[3] > 0
+    g.close()

@@ -208,22 +208,26 @@ def test_hybrid_and_two_sweep_forms_agree(B, prec, mode):
         assert rel_l2(sb[k], sa[k]) <= agree, k
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", (1e-10, 1e-10)), ("fp32", (1e-3, 1e-4))])
-def test_fused_plain_tiles_at_the_grid_walls_vs_oracle(B, prec, tol):
+@pytest.mark.parametrize("prec,tol,tiling", [("fp64", (1e-10, 1e-10), (2, 4, 0)),
+                                             ("fp64", (1e-10, 1e-10), (8, 3, 1)),
+                                             ("fp32", (1e-3, 1e-4), (2, 4, 0)),
+                                             ("fp32", (1e-3, 1e-4), (4, 5, 2))])
+def test_fused_plain_tiles_at_the_grid_walls_vs_oracle(B, prec, tol, tiling):
     """No CPML (a PEC box): the plain tiles of the one-pass kernel touch the
-    walls on every face, and the grid is ragged in x (72 = 64 + 8) and y, so
-    the kernel's range guards and clamped halo loads all act; against the
-    oracle, with a sphere inside the TF box."""
+    walls on every face, and the grid is ragged in x (72 = 64 + 8) and y (41
+    rows: partial blocks of 4 and 8 rows), so the kernel's range guards, its
+    idle lanes and rows, the shared rows and the recomputed halos all act;
+    against the oracle, with a sphere inside the TF box."""
     c = np.array([35.3, 20.2, 21.6])
     w = W.sphere_problem("walls", 72, 0.25e-9, 0, c, 1.6e-9, steps=240)
     w.ny, w.nz = 41, 44
     w = W._boxes(w, c * 0.25e-9 - 1.6e-9, c * 0.25e-9 + 1.6e-9)
     w = W.early_pulse(w)
     w.omega = W.spectrum_omegas(16)
-    say(f"case fused plain tiles at the walls 72x41x44, {prec}")
+    say(f"case fused plain tiles at the walls 72x41x44, {prec}, tiling {tiling}")
     g = B.Sim(w, precision=prec)
     g.set_mode(3)
-    g.set_tiling(2, 4, 0)
+    g.set_tiling(*tiling)
     assert g.tile_classes()[0] > 0
     g.run(w.steps)
     o = oracle_run(w, w.steps)
