@@ -402,16 +402,17 @@ def main():
         torch.cuda.empty_cache()
     if args.star_steps > 0:
         # the star particle: R = 15 nm sphere with six capped cones, 640^3 at
-        # 0.2 nm, 12-cell CPML (run at the sphere's tiling)
+        # 0.2 nm, 12-cell CPML (its own step form and tiling, autotuned,
+        # unless a tiling is fixed)
         wst = W.config3(seed=0)
-        tl = out["tiling"]
-        simst, dtst = run_gpu(wst, "fp32", args.star_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]), forms=(out["step_form"],))
+        simst, dtst = run_gpu(wst, "fp32", args.star_steps, args.warmup, tiling, forms=forms)
         out["star"] = {
             "workload": "640^3 star particle (sphere R 15 nm + 6 cones), dx 0.2 nm, 12-cell CPML, "
                         "100 frequencies with flux boxes, FP32",
             "steps": args.star_steps,
             "value": round(wst.cells * args.star_steps / dtst / 1e9, 3), "unit": "Gcell-updates/s",
-            "ms_per_step": round(dtst / args.star_steps * 1e3, 5)}
+            "ms_per_step": round(dtst / args.star_steps * 1e3, 5), "step_form": simst.form,
+            "tiling": {k: simst.tiling[k] for k in ("ty", "kz", "xcd")}}
         simst.close()
         del simst
         torch.cuda.empty_cache()

@@ -370,8 +370,9 @@ Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
 // cells within one cell; classes 0 plain, 1 CPML, 2 metal, 3 metal + CPML)
 // and fill the class counts, offsets and per-XCD counts of t; list receives
 // the class lists back to back.  merge_x: tiles without metal that meet only
-// an x slab go to class 0, whose two-sweep kernels update the x-slab psi of
-// such tiles (the fused kernels of class 0 have no CPML: false for them).
+// an x slab go to class 0, whose two-sweep and one-pass (form 3) kernels
+// update the x-slab psi of such tiles (the fused kernels of forms 1 and 2
+// have no CPML in class 0: false for them).
 // split_pure (the step form with one-pass plain tiles): class 0 lists first
 // the tiles that, widened by one cell, meet no x slab (t.n0pure of them),
 // then the others; otherwise class 0 keeps the natural order (n0pure = 0).

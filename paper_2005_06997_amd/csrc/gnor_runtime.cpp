@@ -519,8 +519,9 @@ void enqueue_classes(gnor_sim* s, hipStream_t st, F launch) {
 //   2. the auxiliary line (after every reader of E_inc^n);
 //   3. E/J sweeps of the two-sweep classes (they read H^{n+1/2} of fused
 //      neighbours and H_inc^{n+1/2}).
-// Form 3: only the plain tiles (no metal, no CPML slab within one cell) take
-// the one-pass kernel of gnor_fplain.hip, metal and CPML tiles the two sweeps.
+// Form 3: only class 0 (no metal; at most an x slab within one cell) takes
+// the one-pass kernels of gnor_fplain.hip, followed on the same stream by
+// their TF/SF launch; metal and CPML tiles take the two sweeps.
 bool hybrid_fused(const gnor_sim* s, int c) {
   if (s->mode == 3) return c == 0;
   return c == 0 || (c == 2 && s->mat.ncp == 0);
@@ -663,8 +664,8 @@ gnor_status plan_tiles(gnor_sim* s) {
       s->rowx[2 * r + 1] = hi;
     }
   }
-  // x-slab tiles join the plain class only in the two-sweep form: the fused
-  // and hybrid forms run class 0 on the fused kernel, which has no CPML
+  // x-slab tiles join the plain class in forms 0 and 3 (merge_x_slabs); in
+  // form 3 class 0 lists its tiles without an x slab first
   gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->any_metal ? s->rowx.data() : nullptr,
                        s->tile_list, merge_x_slabs(s->mode), s->mode == 3, s->tile_class);
   if (s->bound && !s->tile_list.empty()) {
