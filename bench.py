@@ -144,10 +144,11 @@ def spectral_errors(a, b):
 
 def error_legs(tiling, form):
     """Spectral errors of the FP32 path from runs of fixed length (independent
-    of --steps): FP32 vs FP64 on the 320^3 workload with the pulse moved early
-    (2400 steps: the pulse has crossed the particle), and FP32 vs the FP64
-    oracle's spectra of the 2x-coarsened copy over its full 10 000 steps
-    (stored in tests/golden by an oracle-only script)."""
+    of --steps), in the timed step form: FP32 vs FP64 on the 320^3 workload
+    with the pulse moved early (2400 steps: the pulse has crossed the
+    particle), and FP32 vs the FP64 oracle's spectra of the 2x-coarsened copy
+    over its full 10 000 steps (stored in tests/golden by an oracle-only
+    script)."""
     import torch
     from paper_2005_06997_amd import binding
     from paper_2005_06997_amd import workloads as W
@@ -351,22 +352,15 @@ def main():
         wc = W.with_critical_points(w)
         tl = out["tiling"]
         simc, dtc = run_gpu(wc, "fp32", args.cp_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]), forms=(out["step_form"],))
-        # the poles live in the E/J launches of the metal classes (2, 3),
-        # timed alone: 9 field words per cell of their tiles, 13 per metal
-        # cell, 12 per metal cell and pole, 4 per (cell, axis) in a slab
-        simc.set_class_streams(False)
-        profc = simc.profile(max(2, args.profile_steps // 4))
-        cc, dc = simc.tile_class_cells()
-        nmc = int(np.count_nonzero(simc.mask))
-        mbytes = 4 * (9 * (cc[2] + cc[3]) + 13 * nmc + 12 * nmc * len(wc.cp) + 4 * dc[3])
-        mms = profc["ej_cls"][2] + profc["ej_cls"][3]
+        # (the poles live in the E/J launches of the metal classes; "ej_ms"
+        # is the E/J sweep as it runs, in form 3 that of classes 1-3)
+        profc = simc.profile(max(2, args.profile_steps))
         out["critical_points"] = {
             "workload": "the same sphere with 2 synthetic critical points, eps_inf 1.1, FP32",
             "poles": len(wc.cp), "steps": args.cp_steps,
             "value": round(wc.cells * args.cp_steps / dtc / 1e9, 3), "unit": "Gcell-updates/s",
-            "ms_per_step": round(dtc / args.cp_steps * 1e3, 5),
-            "metal_ej_ms": round(mms, 5),
-            "metal_ej_roofline_frac": round(mbytes / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "ms_per_step": round(dtc / args.cp_steps * 1e3, 5), "step_form": simc.form,
+            "ej_ms": round(profc["ej"], 5)}
         del simc
         torch.cuda.empty_cache()
     if args.maps_steps > 0:
@@ -402,10 +396,11 @@ def main():
         torch.cuda.empty_cache()
     if args.star_steps > 0:
         # the star particle: R = 15 nm sphere with six capped cones, 640^3 at
-        # 0.2 nm, 12-cell CPML (its own step form and tiling, autotuned,
-        # unless a tiling is fixed)
+        # 0.2 nm, 12-cell CPML (at the sphere's step form and tiling)
         wst = W.config3(seed=0)
-        simst, dtst = run_gpu(wst, "fp32", args.star_steps, args.warmup, tiling, forms=forms)
+        tl = out["tiling"]
+        simst, dtst = run_gpu(wst, "fp32", args.star_steps, args.warmup, (tl["ty"], tl["kz"], tl["xcd"]),
+                              forms=(out["step_form"],))
         out["star"] = {
             "workload": "640^3 star particle (sphere R 15 nm + 6 cones), dx 0.2 nm, 12-cell CPML, "
                         "100 frequencies with flux boxes, FP32",
