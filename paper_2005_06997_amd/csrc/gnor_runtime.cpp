@@ -491,8 +491,10 @@ gnor::MapParams<T> make_maps(gnor_sim* s, int parity) {
 // on the device; only the host reads results, after a stream synchronize).
 constexpr unsigned kJoinEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
 
+// c3_side: class 3 after class 1 on the first side stream (the first half of
+// form 3, whose one-pass class-0 launches keep the bound stream busy longest)
 template <class F>
-void enqueue_classes(gnor_sim* s, hipStream_t st, F launch) {
+void enqueue_classes(gnor_sim* s, hipStream_t st, F launch, bool c3_side = false) {
   if (!s->concurrent) {
     for (int c = 0; c < gnor::kClasses; ++c) launch(c, st);
     return;
@@ -500,8 +502,9 @@ void enqueue_classes(gnor_sim* s, hipStream_t st, F launch) {
   (void)hipEventRecord(s->ev_fork, st);
   for (int q = 0; q < 2; ++q) (void)hipStreamWaitEvent(s->side[q], s->ev_fork, 0);
   launch(0, st);
-  launch(3, st);  // metal + CPML: small grids (usually empty otherwise)
+  if (!c3_side) launch(3, st);  // metal + CPML: small grids (usually empty otherwise)
   launch(1, s->side[0]);
+  if (c3_side) launch(3, s->side[0]);
   launch(2, s->side[1]);
   for (int q = 0; q < 2; ++q) {
     (void)hipEventRecord(s->ev_join[q], s->side[q]);
@@ -539,7 +542,7 @@ void enqueue_first(gnor_sim* s, const gnor::Params<T>& p, const gnor::AuxParams&
       if (!hybrid_fused(s, c)) gnor::launch_h_class<T>(p, a, c, q);
       else if (mode == 3) gnor::launch_fplain<T>(p, a, q);
       else gnor::launch_step_class<T>(p, a, c, q);
-    });
+    }, mode == 3);
   } else {
     enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_h_class<T>(p, a, c, q); });
   }
