@@ -80,7 +80,7 @@ def dominant(form, word, cells, slab_dirs, ejb, prof, prof_serial):
     psi words per (cell, axis) in a slab, the per-unit figures of the step.
     Form 0: the E/J sweep, its classes timed together."""
     if form == 3:
-        return ("k_fplain (class 0 in one pass: plain and x-slab launches + k_tfsf_fix, timed alone)",
+        return ("k_fplain (class 0 in one pass, x-slab tiles included, + k_tfsf_fix, timed alone)",
                 word * (18 * cells[0] + 8 * slab_dirs[0]), prof_serial["h_cls"][0], "k_fplain")
     return ("k_ej (E/J sweep = one launch per tile class, timed together)", ejb, prof["ej"], "k_ej")
 

@@ -79,12 +79,13 @@ __device__ __forceinline__ T xstretch(const XCoef<T>& c, T d, T psi_old, T& psi_
 }
 
 // The loads of one plane of a column: E^n around the cell, H^{n-1/2} and
-// x-slab memory; E at column x+1 (last lane, from the next tile); what the
-// recomputed halos need (first lane: column x-1; first row: row y-1).
+// x-slab memory (of the H and of the E update); E at column x+1 (last lane,
+// from the next tile); what the recomputed halos need (first lane: column
+// x-1; first row: row y-1).
 template <class T>
 struct PlaneIn {
   T ez = T(0), ex1 = T(0), ey1 = T(0), ezy = T(0), exy = T(0), hx = T(0), hy = T(0), hz = T(0);
-  T sy_ = T(0), sz_ = T(0);
+  T sy_ = T(0), sz_ = T(0), ey_ = T(0), ez_ = T(0);
   T ezr = T(0), eyr = T(0);
   T ezl = T(0), eyl = T(0), exl1 = T(0), exly = T(0), hyo = T(0), hzo = T(0), syl = T(0), szl = T(0);
   T eyd1 = T(0), ezd = T(0), exd = T(0), hxo = T(0), hzd_o = T(0), szd = T(0), eydr = T(0);
@@ -93,7 +94,8 @@ struct PlaneIn {
 template <class T, bool XS>
 __device__ __forceinline__ void load_plane(const Params<T>& p, PlaneIn<T>& v, uint32_t id, uint32_t dzp,
                                            uint32_t dyp, uint32_t sy, uint32_t qs, uint32_t qsl,
-                                           uint32_t sq, bool act, bool first, bool last, bool rd) {
+                                           uint32_t qse, uint32_t sq, bool act, bool first, bool last,
+                                           bool rd) {
   const T* __restrict__ Ex = p.E[0];
   const T* __restrict__ Ey = p.E[1];
   const T* __restrict__ Ez = p.E[2];
@@ -102,7 +104,10 @@ __device__ __forceinline__ void load_plane(const Params<T>& p, PlaneIn<T>& v, ui
     v.ex1 = Ex[id + dzp]; v.ey1 = Ey[id + dzp];
     v.ezy = Ez[id + dyp]; v.exy = Ex[id + dyp];
     v.hx = p.Hi[0][id]; v.hy = p.Hi[1][id]; v.hz = p.Hi[2][id];
-    if (XS) { v.sy_ = p.psiHi[0][1][qs]; v.sz_ = p.psiHi[0][0][qs]; }
+    if (XS) {
+      v.sy_ = p.psiHi[0][1][qs]; v.sz_ = p.psiHi[0][0][qs];
+      v.ey_ = p.psiE[0][1][qse]; v.ez_ = p.psiE[0][0][qse];
+    }
   }
   if (last) { v.ezr = Ez[id + 1]; v.eyr = Ey[id + 1]; }
   if (first) {
@@ -129,8 +134,8 @@ struct HRows {
   T h[2][2][TY][kBX];  // [plane & 1][0: H_x, 1: H_z][row][lane]
 };
 
-// XS: the tile meets an x slab (those tiles get a kernel of their own, so
-// that the others run code free of the CPML terms)
+// XS: the tile meets an x slab (the other tiles run code free of the CPML
+// terms)
 template <class T, int TY, bool NT, bool XS>
 __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
                                             HRows<T, TY>& sh) {
@@ -217,7 +222,7 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
     // ---- the plane's loads, issued together (one memory round trip per
     // plane; issuing them a plane ahead measured no faster)
     PlaneIn<T> cur;
-    load_plane<T, XS>(p, cur, id, zp ? sz : 0, dyp, sy, qs, qsl, sq, act, first, last, rd);
+    load_plane<T, XS>(p, cur, id, zp ? sz : 0, dyp, sy, qs, qsl, qse, sq, act, first, last, rd);
     load_fence();
     const T ez = cur.ez, ex1 = cur.ex1, ey1 = cur.ey1, ezy = cur.ezy, exy = cur.exy;
     const T hx = cur.hx, hy = cur.hy, hz = cur.hz, sy_ = cur.sy_, sz_ = cur.sz_;
@@ -292,17 +297,14 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
     const bool uex = ax && kin, uey = ay && kin, uez = az && zp;
     T d_xy = hzn - hzl, d_xz = hyn - hyl;  // x differences of E_y, E_z
     if (XS && sxe >= 0) {
+      T ps;
       if (uey) {
-        T* q = p.psiE[0][1] + qse;
-        T ps;
-        d_xy = xstretch(ce, d_xy, *q, ps);
-        *q = ps;
+        d_xy = xstretch(ce, d_xy, cur.ey_, ps);
+        p.psiE[0][1][qse] = ps;
       }
       if (uez) {
-        T* q = p.psiE[0][0] + qse;
-        T ps;
-        d_xz = xstretch(ce, d_xz, *q, ps);
-        *q = ps;
+        d_xz = xstretch(ce, d_xz, cur.ez_, ps);
+        p.psiE[0][0][qse] = ps;
       }
     }
     T cxv = (hzn - hzd) - (hyn - hym);  // dy H_z - dz H_y
@@ -322,38 +324,29 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
 }
 
 // Class 0 of the two-sweep tiling (plain tiles, and tiles that meet only an
-// x slab).  PURE: the leading part of the class list, tiles that meet no x
-// slab; otherwise the rest, the x-slab tiles.  Two kernels, so that the bulk
-// of the grid runs code without the CPML terms (40 VGPRs and 93 SGPRs, 8
-// waves per SIMD, against 64 and 106, 7 waves, with them).
-template <class T, int TY, bool NT, bool PURE>
+// x slab), one launch over the class list in its tile order.  A block whose
+// tile meets an x slab (the test the tile classes use) takes the x-slab code.
+// One launch keeps the tiles of a row of the grid in flight together: the
+// row's bytes are fetched by neighbouring blocks at about the same time, and
+// a tile's x halo is its neighbour's, still in the L2.  Split into a launch
+// for the tiles without an x slab (8 waves per SIMD) and one for the x-slab
+// tiles, the same work took 9 % longer.
+template <class T, int TY, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_fplain(Params<T> p) {
   __shared__ HRows<T, TY> sh;
   const Tile tile = decode_tile(p.tl, p.tiles, 0, blockIdx.x);
   if (!tile.ok) return;  // uniform over the block
-  if (PURE) fplain_tile<T, TY, NT, false>(p, tile, sh);
-  else fplain_tile<T, TY, NT, true>(p, tile, sh);
+  const int np = p.cp[0].np, x0 = tile.bx * kBX;
+  if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true>(p, tile, sh);
+  else fplain_tile<T, TY, NT, false>(p, tile, sh);
 }
 
-template <class T, bool NT, bool PURE>
-void launch_fplain_nt(const Params<T>& p, int blocks, hipStream_t s) {
-  if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain<T, 4, NT, PURE>), dim3(blocks), dim3(kBX, 4), 0, s, p);
-  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain<T, 8, NT, PURE>), dim3(blocks), dim3(kBX, 8), 0, s, p);
-  else hipLaunchKernelGGL((k_fplain<T, 2, NT, PURE>), dim3(blocks), dim3(kBX, 2), 0, s, p);
-}
-
-// Class 0 restricted to positions [first, first + n) of its list (the tile
-// order then deals that sub-list to the XCDs)
-template <class T>
-Params<T> class0_part(const Params<T>& p, int first, int n) {
-  Params<T> q = p;
-  Tiling& t = q.tl;
-  t.coff[0] += first;
-  t.cn[0] = n;
-  if (t.xcd == 1) t.cper[0] = (n + 7) / 8;
-  else if (t.xcd == 2) t.cper[0] = ((n + t.q - 1) / t.q + 7) / 8;
-  else t.cper[0] = n;
-  return q;
+template <class T, bool NT>
+void launch_fplain_nt(const Params<T>& p, hipStream_t s) {
+  const int blocks = class_blocks(p.tl, 0);
+  if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain<T, 4, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p);
+  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain<T, 8, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p);
+  else hipLaunchKernelGGL((k_fplain<T, 2, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p);
 }
 
 // ------------------------------------------------------- TF/SF corrections
@@ -444,26 +437,13 @@ __global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a) {
   if (cz != T(0)) p.O[2][id] += sez * cz;
 }
 
-template <class T, bool NT>
-void launch_fplain_parts(const Params<T>& p, hipStream_t s) {
-  const int pure = p.tl.n0pure, rest = p.tl.cn[0] - pure;
-  if (pure > 0) {
-    const Params<T> q = class0_part(p, 0, pure);
-    launch_fplain_nt<T, NT, true>(q, class_blocks(q.tl, 0), s);
-  }
-  if (rest > 0) {
-    const Params<T> q = class0_part(p, pure, rest);
-    launch_fplain_nt<T, NT, false>(q, class_blocks(q.tl, 0), s);
-  }
-}
-
 }  // namespace
 
 template <class T>
 void launch_fplain(const Params<T>& p, const AuxParams& a, hipStream_t s) {
   if (p.tl.cn[0] == 0) return;
-  if (p.stream_stores) launch_fplain_parts<T, true>(p, s);
-  else launch_fplain_parts<T, false>(p, s);
+  if (p.stream_stores) launch_fplain_nt<T, true>(p, s);
+  else launch_fplain_nt<T, false>(p, s);
   if (p.tfsf) {
     const int Lx = p.tf_hi[0] - p.tf_lo[0] + 3, Ly = p.tf_hi[1] - p.tf_lo[1] + 3;
     const int Lz = p.tf_hi[2] - p.tf_lo[2] + 3;

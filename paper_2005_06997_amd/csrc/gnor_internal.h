@@ -78,7 +78,6 @@ struct Tiling {
   int cn[kClasses];    // tiles per class
   int coff[kClasses];  // offset of each class's list in the tile list
   int cper[kClasses];  // positions (order 1) or chunks (order 2) per XCD, per class
-  int n0pure;          // leading class-0 tiles that meet no x slab (step form 3)
 };
 
 // Auxiliary line state (FP64 always).
@@ -373,12 +372,10 @@ Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
 // an x slab go to class 0, whose two-sweep and one-pass (form 3) kernels
 // update the x-slab psi of such tiles (the fused kernels of forms 1 and 2
 // have no CPML in class 0: false for them).
-// split_pure (the step form with one-pass plain tiles): class 0 lists first
-// the tiles that, widened by one cell, meet no x slab (t.n0pure of them),
-// then the others; otherwise class 0 keeps the natural order (n0pure = 0).
+// Each class lists its tiles in natural order (x fastest, then y, then z).
 // tile_class receives the class of every tile (tile order x, y, z).
 void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
-                    std::vector<int>& list, bool merge_x, bool split_pure,
+                    std::vector<int>& list, bool merge_x,
                     std::vector<uint8_t>& tile_class);
 
 }  // namespace gnor

@@ -667,10 +667,9 @@ gnor_status plan_tiles(gnor_sim* s) {
       s->rowx[2 * r + 1] = hi;
     }
   }
-  // x-slab tiles join the plain class in forms 0 and 3 (merge_x_slabs); in
-  // form 3 class 0 lists its tiles without an x slab first
+  // x-slab tiles join the plain class in forms 0 and 3 (merge_x_slabs)
   gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->any_metal ? s->rowx.data() : nullptr,
-                       s->tile_list, merge_x_slabs(s->mode), s->mode == 3, s->tile_class);
+                       s->tile_list, merge_x_slabs(s->mode), s->tile_class);
   if (s->bound && !s->tile_list.empty()) {
     HIPCHECK(s, hipStreamSynchronize(s->stream));
     HIPCHECK(s, hipMemcpy(s->dev + s->L.tiles, s->tile_list.data(), s->tile_list.size() * 4,
@@ -684,7 +683,7 @@ gnor_status plan_tiles(gnor_sim* s) {
 // Change the step form; the class lists depend on it (see plan_tiles).
 gnor_status set_mode(gnor_sim* s, int mode) {
   if (mode == s->mode) return GNOR_OK;
-  const bool replan = merge_x_slabs(mode) != merge_x_slabs(s->mode) || (mode == 3) != (s->mode == 3);
+  const bool replan = merge_x_slabs(mode) != merge_x_slabs(s->mode);
   s->mode = mode;
   drop_graph(s);
   return replan ? plan_tiles(s) : GNOR_OK;

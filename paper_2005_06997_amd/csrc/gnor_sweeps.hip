@@ -603,10 +603,10 @@ static bool tile_meets_metal_host(const Tiling& t, int tile, int nx, int ny, int
 }
 
 void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
-                    std::vector<int>& list, bool merge_x, bool split_pure,
+                    std::vector<int>& list, bool merge_x,
                     std::vector<uint8_t>& tile_class) {
   const int T = t.nbx * t.nby * t.nbz;
-  std::vector<int> cls[kClasses], xslab;
+  std::vector<int> cls[kClasses];
   tile_class.assign(T, 0);
   auto slab = [&](int lo, int hi, int n) { return np > 0 && (lo < np || hi > n - 1 - np); };
   for (int tile = 0; tile < T; ++tile) {
@@ -618,11 +618,8 @@ void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
     const bool pyz = slab(by * t.ty - 1, by * t.ty + t.ty + 1, ny) || slab(z0 - 1, z1 + 1, nz);
     const int c = metal ? (px || pyz ? 3 : 2) : (pyz || (px && !merge_x) ? 1 : 0);
     tile_class[tile] = (uint8_t)c;
-    if (c == 0 && split_pure && px) xslab.push_back(tile);
-    else cls[c].push_back(tile);
+    cls[c].push_back(tile);
   }
-  t.n0pure = split_pure ? (int)cls[0].size() : 0;
-  cls[0].insert(cls[0].end(), xslab.begin(), xslab.end());
   list.clear();
   for (int c = 0; c < kClasses; ++c) {
     t.coff[c] = (int)list.size();
