@@ -285,12 +285,12 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * fused pass for the tiles that meet no CPML slab (classes 0 and 2; class 2
  * stays two-sweep with critical points), then the auxiliary line, then the
  * E/J sweep of the CPML classes, whose H sweep ran alongside the fused
- * tiles; gnor_set_fused(sim, 3) the same order with only class 0 (x-slab
- * tiles included) in one pass, by a lighter kernel whose wavefronts share
- * halo H through lane shuffles and LDS, followed by a small launch that adds
- * the TF/SF terms on the faces of the TF box at class-0 points, and the
- * metal and CPML classes in two sweeps (critical points, a substrate and
- * total-field operation allowed).  All forms give the same fields up to
+ * tiles; gnor_set_fused(sim, 3) the same order with the tiles without metal
+ * (classes 0, x-slab tiles included, and 1) in one pass, by lighter kernels
+ * whose wavefronts share halo H through lane shuffles and LDS, each class's
+ * launch followed by a small one that adds the TF/SF terms on the faces of
+ * the TF box at that class's points, and the metal classes in two sweeps
+ * (critical points, a substrate and total-field operation allowed).  All forms give the same fields up to
  * rounding; batches and gnor_gradient always use the two-sweep form.
  * gnor_profile_kernels times each sweep as it runs: with concurrent class
  * launches (the default, see gnor_set_class_streams) a sweep is timed from its
@@ -300,8 +300,8 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * fused form.  In fused form ms[0] = ms[1] = 0 and ms[3] holds the fused step
  * (classes + auxiliary line); in hybrid form ms[0] is the first phase (fused
  * tiles and H sweeps) and ms[1] the second (auxiliary line and E/J sweeps);
- * in form 3 with serial class launches ms[5] is the one-pass class 0 (with
- * its TF/SF launch) and ms[9] the auxiliary line.
+ * in form 3 with serial class launches ms[5] and ms[6] are the one-pass
+ * classes 0 and 1 (each with its TF/SF launch) and ms[9] the auxiliary line.
  * gnor_tile_classes writes the number of tiles of each class of the current
  * tiling to counts[0..3] (valid once the memory is bound).
  * gnor_tile_class_cells writes, per class c, the grid cells its tiles cover

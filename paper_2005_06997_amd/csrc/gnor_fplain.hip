@@ -1,5 +1,7 @@
-// One-pass step of the plain tiles (gfx950): f1 and f2 of Sec. III fused for
-// tiles that meet no metal and at most an x slab of the CPML.  The two-sweep
+// One-pass step of the tiles without metal (gfx950): f1 and f2 of Sec. III
+// fused, with the CPML (Roden-Gedney) memory of the slabs a tile meets.  The
+// plain class (at most an x slab) and the CPML class (a y or z slab) are
+// separate launches with their own register budgets.  The two-sweep
 // form reads E^n twice and writes, then re-reads, H^{n+1/2}: 18 field words
 // per cell.  Here a tile computes H^{n+1/2} and, at once, E^{n+1} from it:
 // 12 words (read E^n and H^{n-1/2}, write H^{n+1/2} and E^{n+1}).
@@ -20,7 +22,8 @@
 //
 // TF/SF: the one-pass kernels leave the corrections out.  They are linear
 // and sit on the faces of the TF box, so k_tfsf_fix adds them afterwards, at
-// the points of one-pass tiles only: to H^{n+1/2} on the faces the E_inc^n
+// the points of one class's tiles only (one launch per one-pass class that
+// meets the shell of the TF box): to H^{n+1/2} on the faces the E_inc^n
 // terms, and to E^{n+1} the E update's share of those terms plus its own
 // H_inc^{n+1/2} terms (evaluated from the line's state with the line's own H
 // update; the line advances after the fix).  The background coefficients
@@ -89,13 +92,28 @@ struct PlaneIn {
   T ezr = T(0), eyr = T(0);
   T ezl = T(0), eyl = T(0), exl1 = T(0), exly = T(0), hyo = T(0), hzo = T(0), syl = T(0), szl = T(0);
   T eyd1 = T(0), ezd = T(0), exd = T(0), hxo = T(0), hzd_o = T(0), szd = T(0), eydr = T(0);
+  // y and z slabs: psi_H of the cell (H_x: dy E_z, dz E_y; H_y: dz E_x; H_z:
+  // dy E_x), psi_E of the cell (E_x: dy H_z, dz H_y; E_y: dz H_x; E_z: dy
+  // H_x), and the psi_H the recomputed halos need
+  T pyx = T(0), pyz = T(0), pzx = T(0), pzy = T(0);
+  T qyx = T(0), qyz = T(0), qzx = T(0), qzy = T(0);
+  T pyzl = T(0), pzyl = T(0), pyxd = T(0), pyzd = T(0), pzxd = T(0);
 };
 
-template <class T, bool XS>
+// y- and z-slab positions of a column's plane (tiles that meet a y or z
+// slab): slab-array indices of the cell's H and E points and of its row y-1
+// (axis-1 arrays: ((k 2 np + s) nx + i); axis-2: ((s ny + j) nx + i)), and
+// whether each lies in its slab (uniform over a row, resp. a plane)
+struct YZAt {
+  uint32_t qy = 0, qye = 0, qyd = 0, qz = 0, qze = 0;
+  bool yh = false, ye = false, yd = false, zh = false, ze = false;
+};
+
+template <class T, bool XS, bool YZ>
 __device__ __forceinline__ void load_plane(const Params<T>& p, PlaneIn<T>& v, uint32_t id, uint32_t dzp,
                                            uint32_t dyp, uint32_t sy, uint32_t qs, uint32_t qsl,
-                                           uint32_t qse, uint32_t sq, bool act, bool first, bool last,
-                                           bool rd) {
+                                           uint32_t qse, uint32_t sq, const YZAt& yz, bool act,
+                                           bool first, bool last, bool rd) {
   const T* __restrict__ Ex = p.E[0];
   const T* __restrict__ Ey = p.E[1];
   const T* __restrict__ Ez = p.E[2];
@@ -123,6 +141,16 @@ __device__ __forceinline__ void load_plane(const Params<T>& p, PlaneIn<T>& v, ui
     if (XS) v.szd = p.psiHi[0][0][qs - sq];
     if (last) v.eydr = Ey[qd + 1];
   }
+  if (YZ) {
+    if (act && yz.yh) { v.pyx = p.psiHi[1][0][yz.qy]; v.pyz = p.psiHi[1][1][yz.qy]; }
+    if (act && yz.zh) { v.pzx = p.psiHi[2][1][yz.qz]; v.pzy = p.psiHi[2][0][yz.qz]; }
+    if (act && yz.ye) { v.qyx = p.psiE[1][0][yz.qye]; v.qyz = p.psiE[1][1][yz.qye]; }
+    if (act && yz.ze) { v.qzx = p.psiE[2][1][yz.qze]; v.qzy = p.psiE[2][0][yz.qze]; }
+    if (first && yz.yh) v.pyzl = p.psiHi[1][1][yz.qy - 1];
+    if (first && yz.zh) v.pzyl = p.psiHi[2][0][yz.qz - 1];
+    if (rd && yz.yd) { v.pyxd = p.psiHi[1][0][yz.qyd]; v.pyzd = p.psiHi[1][1][yz.qyd]; }
+    if (rd && yz.zh) v.pzxd = p.psiHi[2][1][yz.qz - sy];
+  }
 }
 
 // Rows of H_x^{n+1/2} and H_z^{n+1/2} of one plane, shared by the wavefronts
@@ -135,12 +163,17 @@ struct HRows {
 };
 
 // XS: the tile meets an x slab (the other tiles run code free of the CPML
-// terms)
-template <class T, int TY, bool NT, bool XS>
+// terms); YZ: it may meet a y or z slab as well (the CPML class)
+template <class T, int TY, bool NT, bool XS, bool YZ>
 __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
                                             HRows<T, TY>& sh) {
   const int nx = p.nx, ny = p.ny, nz = p.nz;
-  const int lane = threadIdx.x, ty = threadIdx.y;
+  // a wavefront is one row (blockDim.x = 64): its row index is uniform, and
+  // so are the row's y-slab positions and coefficients (said explicitly in
+  // the CPML class: 13 fewer VGPRs there, FP64 1.177 -> 1.162 ms per step on
+  // the 320^3 sphere; the plain class measured no gain)
+  const int lane = threadIdx.x;
+  const int ty = YZ ? __builtin_amdgcn_readfirstlane(threadIdx.y) : (int)threadIdx.y;
   const int i = tile.bx * kBX + lane;
   const int j = tile.by * TY + ty;
   // lanes and rows outside the grid load and store nothing but take part in
@@ -177,9 +210,11 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
   const bool az = act && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;
   // x slab (tiles that meet one): the H-slab positions of the column and of
   // column x-1, the E-slab position of the column, their coefficients, and
-  // slab-array indices (axis-0 slab arrays: ((k ny + j) 2 np + s))
+  // slab-array indices (axis-0 slab arrays: ((k ny + j) 2 np + s)).  H points
+  // exist up to n - 2 along an axis, and so do their slab positions (-1 on
+  // the last node plane, where no H point is updated)
   const int np = p.cp[0].np;
-  const int sxh = (XS && act) ? slab_h(i, nx, np) : -1;
+  const int sxh = (XS && act && i <= nx - 2) ? slab_h(i, nx, np) : -1;
   const int sxl = (XS && first) ? slab_h(i - 1, nx, np) : -1;
   const int sxe = (XS && act) ? slab_e(i, nx, np) : -1;
   XCoef<T> ch{T(1), T(0), T(1)}, cl{T(1), T(0), T(1)}, ce{T(1), T(0), T(1)};
@@ -196,6 +231,20 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
   uint32_t qs = ((uint32_t)k0 * ny + jr) * w2 + (uint32_t)max(sxh, 0);
   uint32_t qsl = ((uint32_t)k0 * ny + jr) * w2 + (uint32_t)max(sxl, 0);
   uint32_t qse = ((uint32_t)k0 * ny + jr) * w2 + (uint32_t)max(sxe, 0);
+  // y slab (uniform over the row): H- and E-slab positions of the row and the
+  // H-slab position of row y-1, with their coefficients
+  const int syh = (YZ && j <= ny - 2) ? slab_h(j, ny, np) : -1;
+  const int sye = (YZ && j < ny) ? slab_e(j, ny, np) : -1;
+  const int syd = (YZ && low && ym && j < ny) ? slab_h(j - 1, ny, np) : -1;
+  XCoef<T> cyh{T(1), T(0), T(1)}, cye{T(1), T(0), T(1)}, cyd{T(1), T(0), T(1)};
+  if (YZ) {
+    const CpmlAxis<T>& Y = p.cp[1];
+    cyh = xcoef(Y.bh, Y.ah, Y.kh, syh);
+    cye = xcoef(Y.be, Y.ae, Y.ke, sye);
+    cyd = xcoef(Y.bh, Y.ah, Y.kh, syd);
+  }
+  const CpmlAxis<T>& Z = p.cp[2];
+  const uint32_t ic = act ? (uint32_t)i : 0;
 
   uint32_t id = act ? (uint32_t)k0 * sz + (uint32_t)j * nx + i : 0;
   // carried: E_x, E_y of plane k at the column, E_x of column x-1 (first
@@ -213,16 +262,45 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
     const T psy = XS ? p.psiHi[0][1][qs - sp] : T(0);
     T dxy = ezx - ezq, psn;
     if (XS && sxh >= 0) dxy = xstretch(ch, dxy, psy, psn);
-    hxm = upd_hx(i, j, k0 - 1, nx, ny, nz) ? hx_ - S * ((ezy - ezq) - (ey0 - eyq)) : hx_;
-    hym = upd_hy(i, j, k0 - 1, nx, ny, nz) ? hy_ - S * ((ex0 - exq) - dxy) : hy_;
+    T dyx = ezy - ezq, dzx = ey0 - eyq, dzy = ex0 - exq;
+    if (YZ) {
+      if (syh >= 0) {
+        const uint32_t qy = ((uint32_t)(k0 - 1) * w2 + (uint32_t)syh) * sy + ic;
+        dyx = xstretch(cyh, dyx, p.psiHi[1][0][qy], psn);
+      }
+      const int szm = slab_h(k0 - 1, nz, np);
+      if (szm >= 0) {
+        const XCoef<T> czm = xcoef(Z.bh, Z.ah, Z.kh, szm);
+        const uint32_t qz = ((uint32_t)szm * ny + jr) * sy + ic;
+        dzx = xstretch(czm, dzx, p.psiHi[2][1][qz], psn);
+        dzy = xstretch(czm, dzy, p.psiHi[2][0][qz], psn);
+      }
+    }
+    hxm = upd_hx(i, j, k0 - 1, nx, ny, nz) ? hx_ - S * (dyx - dzx) : hx_;
+    hym = upd_hy(i, j, k0 - 1, nx, ny, nz) ? hy_ - S * (dzy - dxy) : hy_;
   }
   const bool rd = low && act && ym;  // the first row loads row y-1
   for (int k = k0; k < k1; ++k, id += sz, qs += sp, qsl += sp, qse += sp) {
     const bool zp = k <= nz - 2;
     // ---- the plane's loads, issued together (one memory round trip per
     // plane; issuing them a plane ahead measured no faster)
+    YZAt yz;
+    XCoef<T> czh{T(1), T(0), T(1)}, cze{T(1), T(0), T(1)};
+    if (YZ) {
+      const int szh = k <= nz - 2 ? slab_h(k, nz, np) : -1, sze = slab_e(k, nz, np);
+      yz.yh = syh >= 0; yz.ye = sye >= 0; yz.yd = syd >= 0;
+      yz.zh = szh >= 0; yz.ze = sze >= 0;
+      const uint32_t kr = (uint32_t)k * w2;
+      yz.qy = (kr + (uint32_t)max(syh, 0)) * sy + ic;
+      yz.qye = (kr + (uint32_t)max(sye, 0)) * sy + ic;
+      yz.qyd = (kr + (uint32_t)max(syd, 0)) * sy + ic;
+      yz.qz = ((uint32_t)max(szh, 0) * ny + jr) * sy + ic;
+      yz.qze = ((uint32_t)max(sze, 0) * ny + jr) * sy + ic;
+      czh = xcoef(Z.bh, Z.ah, Z.kh, szh);
+      cze = xcoef(Z.be, Z.ae, Z.ke, sze);
+    }
     PlaneIn<T> cur;
-    load_plane<T, XS>(p, cur, id, zp ? sz : 0, dyp, sy, qs, qsl, qse, sq, act, first, last, rd);
+    load_plane<T, XS, YZ>(p, cur, id, zp ? sz : 0, dyp, sy, qs, qsl, qse, sq, yz, act, first, last, rd);
     load_fence();
     const T ez = cur.ez, ex1 = cur.ex1, ey1 = cur.ey1, ezy = cur.ezy, exy = cur.exy;
     const T hx = cur.hx, hy = cur.hy, hz = cur.hz, sy_ = cur.sy_, sz_ = cur.sz_;
@@ -246,9 +324,25 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
     }
     const bool uhx = act && upd_hx(i, j, k, nx, ny, nz), uhy = act && upd_hy(i, j, k, nx, ny, nz);
     const bool uhz = act && upd_hz(i, j, k, nx, ny, nz);
-    const T hxn = uhx ? hx - S * ((ezy - ez) - (ey1 - ey0)) : hx;
-    const T hyn = uhy ? hy - S * ((ex1 - ex0) - dxy) : hy;
-    const T hzn = uhz ? hz - S * (dxz - (exy - ex0)) : hz;
+    T dyx = ezy - ez, dzx = ey1 - ey0, dzy = ex1 - ex0, dyz = exy - ex0;
+    if (YZ) {
+      T ps;
+      if (yz.yh) {
+        dyx = xstretch(cyh, dyx, cur.pyx, ps);
+        if (uhx) p.psiH[1][0][yz.qy] = ps;
+        dyz = xstretch(cyh, dyz, cur.pyz, ps);
+        if (uhz) p.psiH[1][1][yz.qy] = ps;
+      }
+      if (yz.zh) {
+        dzx = xstretch(czh, dzx, cur.pzx, ps);
+        if (uhx) p.psiH[2][1][yz.qz] = ps;
+        dzy = xstretch(czh, dzy, cur.pzy, ps);
+        if (uhy) p.psiH[2][0][yz.qz] = ps;
+      }
+    }
+    const T hxn = uhx ? hx - S * (dyx - dzx) : hx;
+    const T hyn = uhy ? hy - S * (dzy - dxy) : hy;
+    const T hzn = uhz ? hz - S * (dxz - dyz) : hz;
     if (uhx) put<NT>(&Hx[id], hxn);
     if (uhy) put<NT>(&Hy[id], hyn);
     if (uhz) put<NT>(&Hz[id], hzn);
@@ -268,8 +362,11 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
         dy_ = xstretch(cl, dy_, syl, ps);
         dz_ = xstretch(cl, dz_, szl, ps);
       }
-      hyl = upd_hy(i - 1, j, k, nx, ny, nz) ? hyo - S * ((exl1 - exl0) - dy_) : hyo;
-      hzl = upd_hz(i - 1, j, k, nx, ny, nz) ? hzo - S * (dz_ - (exly - exl0)) : hzo;
+      T dzyl = exl1 - exl0, dyzl = exly - exl0;
+      if (YZ && yz.zh) dzyl = xstretch(czh, dzyl, cur.pzyl, ps);
+      if (YZ && yz.yh) dyzl = xstretch(cyh, dyzl, cur.pyzl, ps);
+      hyl = upd_hy(i - 1, j, k, nx, ny, nz) ? hyo - S * (dzyl - dy_) : hyo;
+      hzl = upd_hz(i - 1, j, k, nx, ny, nz) ? hzo - S * (dz_ - dyzl) : hzo;
       exl0 = exl1;
     }
     // ---- halo H^{n+1/2} of row y-1 (H_x, H_z): the shared row below; the
@@ -282,8 +379,14 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
       if (rd) {
         T d = eydx - eyd0, ps;
         if (XS && sxh >= 0) d = xstretch(ch, d, szd, ps);
-        hxd = upd_hx(i, j - 1, k, nx, ny, nz) ? hxo - S * ((ez - ezd) - (eyd1 - eyd0)) : hxo;
-        hzd = upd_hz(i, j - 1, k, nx, ny, nz) ? hzd_o - S * (d - (ex0 - exd)) : hzd_o;
+        T dyxd = ez - ezd, dzxd = eyd1 - eyd0, dyzd = ex0 - exd;
+        if (YZ && yz.yd) {
+          dyxd = xstretch(cyd, dyxd, cur.pyxd, ps);
+          dyzd = xstretch(cyd, dyzd, cur.pyzd, ps);
+        }
+        if (YZ && yz.zh) dzxd = xstretch(czh, dzxd, cur.pzxd, ps);
+        hxd = upd_hx(i, j - 1, k, nx, ny, nz) ? hxo - S * (dyxd - dzxd) : hxo;
+        hzd = upd_hz(i, j - 1, k, nx, ny, nz) ? hzd_o - S * (d - dyzd) : hzd_o;
       }
       eyd0 = eyd1;
     }
@@ -307,9 +410,33 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
         p.psiE[0][0][qse] = ps;
       }
     }
-    T cxv = (hzn - hzd) - (hyn - hym);  // dy H_z - dz H_y
-    T cyv = (hxn - hxm) - d_xy;         // dz H_x - dx H_z
-    T czv = d_xz - (hxn - hxd);         // dx H_y - dy H_x
+    T d_yx = hzn - hzd, d_zx = hyn - hym, d_zy = hxn - hxm, d_yz = hxn - hxd;
+    if (YZ) {
+      T ps;
+      if (yz.ye) {
+        if (uex) {
+          d_yx = xstretch(cye, d_yx, cur.qyx, ps);
+          p.psiE[1][0][yz.qye] = ps;
+        }
+        if (uez) {
+          d_yz = xstretch(cye, d_yz, cur.qyz, ps);
+          p.psiE[1][1][yz.qye] = ps;
+        }
+      }
+      if (yz.ze) {
+        if (uex) {
+          d_zx = xstretch(cze, d_zx, cur.qzx, ps);
+          p.psiE[2][1][yz.qze] = ps;
+        }
+        if (uey) {
+          d_zy = xstretch(cze, d_zy, cur.qzy, ps);
+          p.psiE[2][0][yz.qze] = ps;
+        }
+      }
+    }
+    T cxv = d_yx - d_zx;  // dy H_z - dz H_y
+    T cyv = d_zy - d_xy;  // dz H_x - dx H_z
+    T czv = d_xz - d_yz;  // dx H_y - dy H_x
     const T sexy = k < p.sub_k ? p.SE : (k == p.sub_k ? p.se_avg : p.se_sub);
     const T sez = k < p.sub_k ? p.SE : p.se_sub;
     if (uex) put<NT>(&Ox[id], ex0 + sexy * cxv);
@@ -337,16 +464,33 @@ __global__ void __launch_bounds__(kBX* TY) k_fplain(Params<T> p) {
   const Tile tile = decode_tile(p.tl, p.tiles, 0, blockIdx.x);
   if (!tile.ok) return;  // uniform over the block
   const int np = p.cp[0].np, x0 = tile.bx * kBX;
-  if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true>(p, tile, sh);
-  else fplain_tile<T, TY, NT, false>(p, tile, sh);
+  if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true, false>(p, tile, sh);
+  else fplain_tile<T, TY, NT, false, false>(p, tile, sh);
+}
+
+// Class 1 (tiles without metal that meet a y or z slab, and maybe an x slab)
+// in one pass: a kernel of its own, whose larger register budget the plain
+// tiles do not share.
+template <class T, int TY, bool NT>
+__global__ void __launch_bounds__(kBX* TY) k_fplain_pml(Params<T> p) {
+  __shared__ HRows<T, TY> sh;
+  const Tile tile = decode_tile(p.tl, p.tiles, 1, blockIdx.x);
+  if (!tile.ok) return;
+  fplain_tile<T, TY, NT, true, true>(p, tile, sh);
 }
 
 template <class T, bool NT>
-void launch_fplain_nt(const Params<T>& p, hipStream_t s) {
-  const int blocks = class_blocks(p.tl, 0);
-  if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain<T, 4, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p);
-  else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain<T, 8, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p);
-  else hipLaunchKernelGGL((k_fplain<T, 2, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p);
+void launch_fplain_nt(const Params<T>& p, int cls, hipStream_t s) {
+  const int blocks = class_blocks(p.tl, cls);
+  if (cls == 0) {
+    if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain<T, 4, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p);
+    else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain<T, 8, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p);
+    else hipLaunchKernelGGL((k_fplain<T, 2, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p);
+  } else {
+    if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain_pml<T, 4, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p);
+    else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain_pml<T, 8, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p);
+    else hipLaunchKernelGGL((k_fplain_pml<T, 2, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p);
+  }
 }
 
 // ------------------------------------------------------- TF/SF corrections
@@ -379,13 +523,14 @@ __device__ __forceinline__ T tf_dhz(const Params<T>& p, int i, int j, int k) {
 // once: the planes k in {lo-1, lo, hi, hi+1} (whole widened rows), then the
 // rows j in {lo-1, lo, hi, hi+1} of the planes lo+1 .. hi-1, then the
 // columns i in {lo-1, lo, hi, hi+1} of rows lo+1 .. hi-1 of those planes.
-// Every TF/SF term, and every E point whose curl holds one, lies in it.  A
-// point of a two-sweep tile is left alone (those sweeps apply the terms
-// themselves); at a point of a one-pass tile the terms go to H^{n+1/2} and
+// Every TF/SF term, and every E point whose curl holds one, lies in it.
+// Only points of tiles of class cls are touched (a point of a two-sweep tile
+// is left alone: those sweeps apply the terms themselves; one of the other
+// one-pass class, to that class's own launch); there the terms go to H^{n+1/2} and
 // the E update's share of the H terms of its curl (the one-pass kernels took
 // every H of that curl without them) plus its own H_inc terms to E^{n+1}.
 template <class T>
-__global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a) {
+__global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a, int cls) {
   const int* lo = p.tf_lo;
   const int* hi = p.tf_hi;
   const int Lx = hi[0] - lo[0] + 3, Ly = hi[1] - lo[1] + 3, Lz = hi[2] - lo[2] + 3;
@@ -411,7 +556,7 @@ __global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a) {
     return;
   }
   const Tiling& tl = p.tl;
-  if (p.tile_class[((k / tl.kz) * tl.nby + j / tl.ty) * tl.nbx + i / kBX] != 0) return;
+  if (p.tile_class[((k / tl.kz) * tl.nby + j / tl.ty) * tl.nbx + i / kBX] != cls) return;
   const size_t id = ((size_t)k * p.ny + j) * p.nx + i;
   const T dhy = tf_dhy(p, i, j, k), dhz = tf_dhz(p, i, j, k);
   if (dhy != T(0)) p.H[1][id] += dhy;
@@ -440,18 +585,18 @@ __global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a) {
 }  // namespace
 
 template <class T>
-void launch_fplain(const Params<T>& p, const AuxParams& a, hipStream_t s) {
-  if (p.tl.cn[0] == 0) return;
-  if (p.stream_stores) launch_fplain_nt<T, true>(p, s);
-  else launch_fplain_nt<T, false>(p, s);
-  if (p.tfsf) {
+void launch_fplain(const Params<T>& p, const AuxParams& a, int cls, bool fix, hipStream_t s) {
+  if (p.tl.cn[cls] == 0) return;
+  if (p.stream_stores) launch_fplain_nt<T, true>(p, cls, s);
+  else launch_fplain_nt<T, false>(p, cls, s);
+  if (p.tfsf && fix) {
     const int Lx = p.tf_hi[0] - p.tf_lo[0] + 3, Ly = p.tf_hi[1] - p.tf_lo[1] + 3;
     const int Lz = p.tf_hi[2] - p.tf_lo[2] + 3;
     const long n = 4L * Lx * Ly + 4L * (Lz - 4) * Lx + 4L * (Ly - 4) * (Lz - 4);
-    hipLaunchKernelGGL(k_tfsf_fix<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, a);
+    hipLaunchKernelGGL(k_tfsf_fix<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, a, cls);
   }
 }
-template void launch_fplain<float>(const Params<float>&, const AuxParams&, hipStream_t);
-template void launch_fplain<double>(const Params<double>&, const AuxParams&, hipStream_t);
+template void launch_fplain<float>(const Params<float>&, const AuxParams&, int, bool, hipStream_t);
+template void launch_fplain<double>(const Params<double>&, const AuxParams&, int, bool, hipStream_t);
 
 }  // namespace gnor

@@ -313,10 +313,11 @@ void launch_ej_class(const Params<T>& p, const AuxParams& a, int sub, int c, hip
 template <class T>
 void launch_step_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s);
 void launch_aux(const AuxParams& a, int sub, hipStream_t s);
-// one-pass step of the plain tiles (class 0: no metal, at most an x slab;
-// gnor_fplain.hip) and its TF/SF corrections, before the line's step
+// one-pass step of tile class cls (gnor_fplain.hip; 0: no metal, at most an
+// x slab; 1: no metal, a y or z slab) and, if fix, the TF/SF corrections at
+// that class's points; before the line's step
 template <class T>
-void launch_fplain(const Params<T>& p, const AuxParams& a, hipStream_t s);
+void launch_fplain(const Params<T>& p, const AuxParams& a, int cls, bool fix, hipStream_t s);
 template <class T>
 void launch_step(const Params<T>& p, const AuxParams& a, int sub, hipStream_t s);
 // soft plane source of total-field operation: E_x^{n+1} += f(t_{n+1}) on node

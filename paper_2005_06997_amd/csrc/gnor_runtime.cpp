@@ -100,6 +100,7 @@ struct gnor_sim {
   gnor::Tiling tl{};                              // that tiling with its tile classes
   std::vector<int> tile_list;                     // the classes' tile lists (host copy)
   std::vector<uint8_t> tile_class;                // class of every tile (host copy)
+  bool tf_shell[gnor::kClasses] = {};             // a tile of class c holds a point of the TF box's shell
   std::vector<int> rowx;                          // x extent of the metal points per (y, z) row
   // step form: 0 H and E/J sweeps, 1 one-pass fused step, 2 hybrid, 3 fused
   // plain tiles (see hybrid_fused)
@@ -522,11 +523,12 @@ void enqueue_classes(gnor_sim* s, hipStream_t st, F launch, bool c3_side = false
 //   2. the auxiliary line (after every reader of E_inc^n);
 //   3. E/J sweeps of the two-sweep classes (they read H^{n+1/2} of fused
 //      neighbours and H_inc^{n+1/2}).
-// Form 3: only class 0 (no metal; at most an x slab within one cell) takes
-// the one-pass kernels of gnor_fplain.hip, followed on the same stream by
-// their TF/SF launch; metal and CPML tiles take the two sweeps.
+// Form 3: the tiles without metal, class 0 (at most an x slab within one
+// cell) and class 1 (a y or z slab), take the one-pass kernels of
+// gnor_fplain.hip, each followed on its stream by its TF/SF launch where its
+// tiles meet the shell of the TF box; the metal tiles take the two sweeps.
 bool hybrid_fused(const gnor_sim* s, int c) {
-  if (s->mode == 3) return c == 0;
+  if (s->mode == 3) return c <= 1;
   return c == 0 || (c == 2 && s->mat.ncp == 0);
 }
 
@@ -540,7 +542,7 @@ void enqueue_first(gnor_sim* s, const gnor::Params<T>& p, const gnor::AuxParams&
   } else if (mode == 2 || mode == 3) {
     enqueue_classes(s, st, [&](int c, hipStream_t q) {
       if (!hybrid_fused(s, c)) gnor::launch_h_class<T>(p, a, c, q);
-      else if (mode == 3) gnor::launch_fplain<T>(p, a, q);
+      else if (mode == 3) gnor::launch_fplain<T>(p, a, c, s->tf_shell[c], q);
       else gnor::launch_step_class<T>(p, a, c, q);
     }, mode == 3);
   } else {
@@ -670,6 +672,27 @@ gnor_status plan_tiles(gnor_sim* s) {
   // x-slab tiles join the plain class in forms 0 and 3 (merge_x_slabs)
   gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->any_metal ? s->rowx.data() : nullptr,
                        s->tile_list, merge_x_slabs(s->mode), s->tile_class);
+  // Which classes hold points of the shell of the TF box ([lo-1, hi+1]
+  // without [lo+1, hi-1]), where the one-pass kernels need their TF/SF
+  // launch: a tile does iff it meets the widened box and does not lie inside
+  // the inner one (the shell is two cells thick, so a tile, a box of
+  // consecutive cells, that reaches from the inner box to beyond it meets it)
+  for (int c = 0; c < gnor::kClasses; ++c) s->tf_shell[c] = false;
+  if (!g.total_field) {
+    const gnor::Tiling& t = s->tl;
+    for (size_t tile = 0; tile < s->tile_class.size(); ++tile) {
+      const int bx = (int)(tile % t.nbx), by = (int)((tile / t.nbx) % t.nby), bz = (int)(tile / ((size_t)t.nbx * t.nby));
+      const int a0[3] = {bx * gnor::kBX, by * t.ty, bz * t.kz};
+      const int a1[3] = {std::min(g.nx, a0[0] + gnor::kBX) - 1, std::min(g.ny, a0[1] + t.ty) - 1,
+                         std::min(g.nz, a0[2] + t.kz) - 1};
+      bool meets = true, inside = true;
+      for (int d = 0; d < 3; ++d) {
+        meets = meets && a1[d] >= g.tf_lo[d] - 1 && a0[d] <= g.tf_hi[d] + 1;
+        inside = inside && a0[d] >= g.tf_lo[d] + 1 && a1[d] <= g.tf_hi[d] - 1;
+      }
+      if (meets && !inside) s->tf_shell[s->tile_class[tile]] = true;
+    }
+  }
   if (s->bound && !s->tile_list.empty()) {
     HIPCHECK(s, hipStreamSynchronize(s->stream));
     HIPCHECK(s, hipMemcpy(s->dev + s->L.tiles, s->tile_list.data(), s->tile_list.size() * 4,
@@ -1504,9 +1527,9 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       if (fused) {
         if (fp32) gnor::launch_step_class<float>(make_params<float>(s, parity), a, c, str);
         else gnor::launch_step_class<double>(make_params<double>(s, parity), a, c, str);
-      } else if (plain1 && c == 0) {
-        if (fp32) gnor::launch_fplain<float>(make_params<float>(s, parity), a, str);
-        else gnor::launch_fplain<double>(make_params<double>(s, parity), a, str);
+      } else if (plain1 && c <= 1) {
+        if (fp32) gnor::launch_fplain<float>(make_params<float>(s, parity), a, c, s->tf_shell[c], str);
+        else gnor::launch_fplain<double>(make_params<double>(s, parity), a, c, s->tf_shell[c], str);
       } else {
         if (fp32) gnor::launch_h_class<float>(make_params<float>(s, parity), a, c, str);
         else gnor::launch_h_class<double>(make_params<double>(s, parity), a, c, str);
@@ -1514,7 +1537,7 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       (void)hipEventRecord(ev[1 + c], str);
     }
     for (int c = 0; c < NC && !whole; ++c) {
-      if (fused || (plain1 && c == 0)) {
+      if (fused || (plain1 && c <= 1)) {
         if (c == 0) gnor::launch_aux(a, 0, str);
       } else {
         if (fp32) gnor::launch_ej_class<float>(make_params<float>(s, parity), a, 0, c, str);

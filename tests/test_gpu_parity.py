@@ -234,6 +234,36 @@ def test_fused_plain_tiles_at_the_grid_walls_vs_oracle(B, prec, tol, tiling):
     compare(g, o, *tol)
 
 
+@pytest.mark.parametrize("prec,tol,tiling", [("fp64", (1e-10, 1e-10), (2, 4, 0)),
+                                             ("fp64", (1e-10, 1e-10), (4, 5, 2)),
+                                             ("fp64", (1e-10, 1e-10), (8, 3, 1)),
+                                             ("fp32", (1e-3, 1e-4), (2, 3, 2))])
+def test_one_pass_cpml_tiles_vs_oracle(B, prec, tol, tiling):
+    """Step form 3 runs the CPML tiles (a y or z slab, maybe an x slab too)
+    in one pass as well.  A 72 x 41 x 44 grid, ragged in x and y, with a
+    6-cell CPML and the TF box one cell from the layers (the least distance
+    allowed), so that the shell of the box, and with it the TF/SF launch of
+    the CPML class, reaches into CPML tiles; a sphere inside.  Against the
+    oracle, at tilings whose tiles straddle the slab boundaries in y and z."""
+    c = np.array([35.3, 20.2, 21.6])
+    w = W.sphere_problem("cpml_one_pass", 72, 0.25e-9, 6, c, 1.6e-9, steps=260)
+    w.ny, w.nz = 41, 44
+    w = W._boxes(w, c * 0.25e-9 - 1.6e-9, c * 0.25e-9 + 1.6e-9)
+    w.flux = False
+    w.tf_lo = (7, 7, 7)
+    w.tf_hi = (w.nx - 8, w.ny - 8, w.nz - 8)
+    w = W.early_pulse(w)
+    w.omega = W.spectrum_omegas(16)
+    say(f"case one-pass CPML tiles 72x41x44, {prec}, tiling {tiling}")
+    g = B.Sim(w, precision=prec)
+    g.set_mode(3)
+    g.set_tiling(*tiling)
+    assert g.tile_classes()[1] > 0
+    g.run(w.steps)
+    o = oracle_run(w, w.steps)
+    compare(g, o, *tol, spectra=("inc", "ext"))
+
+
 def test_fp64_vacuum_no_metal(B):
     w = W.early_pulse(W.small_sphere(n=30, radius=1.0e-9, npml=4, seed=4))
     w.omega = W.spectrum_omegas(10)
