@@ -291,7 +291,7 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * launch followed by a small one that adds the TF/SF terms on the faces of
  * the TF box at that class's points, and the metal classes in two sweeps
  * (critical points, a substrate and total-field operation allowed).  All forms give the same fields up to
- * rounding; batches and gnor_gradient always use the two-sweep form.
+ * rounding; gnor_gradient always uses the two-sweep form; a batch its own (gnor_batch_set_form).
  * gnor_profile_kernels times each sweep as it runs: with concurrent class
  * launches (the default, see gnor_set_class_streams) a sweep is timed from its
  * fork to its join; with serial class launches, count >= 14 also returns
@@ -422,6 +422,13 @@ gnor_status gnor_batch_create_static(int32_t n, gnor_sim *const *sims, void *hip
 gnor_status gnor_batch_run(gnor_batch *batch, int64_t nsteps);
 gnor_status gnor_batch_synchronize(gnor_batch *batch);
 gnor_status gnor_batch_set_graph_chunk(gnor_batch *batch, int32_t steps);
+/* Step form of a batch (Sec. III: f1 and f2 of every instance, one launch
+ * per phase over all instances): 0 two sweeps (the default), 3 the tiles
+ * without metal in one pass, the metal tiles in two sweeps, as
+ * gnor_set_fused(sim, 3) for one simulation.  Results equal single runs of
+ * the same form bit for bit.  Waits for the batch's queued steps when the
+ * form changes.  INVALID_ARG unless form is 0 or 3. */
+gnor_status gnor_batch_set_form(gnor_batch *batch, int32_t form);
 const char *gnor_batch_last_error(const gnor_batch *batch);
 void gnor_batch_destroy(gnor_batch *batch);
 

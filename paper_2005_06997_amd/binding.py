@@ -136,6 +136,7 @@ def load() -> C.CDLL:
         "gnor_batch_run": (i32, [vp, i64]),
         "gnor_batch_synchronize": (i32, [vp]),
         "gnor_batch_set_graph_chunk": (i32, [vp, i32]),
+        "gnor_batch_set_form": (i32, [vp, i32]),
         "gnor_batch_last_error": (C.c_char_p, [vp]),
         "gnor_batch_destroy": (None, [vp]),
         "gnor_status_string": (C.c_char_p, [i32]),
@@ -447,7 +448,7 @@ class Batch:
     """Independent simulations stepped in lockstep; each phase of a step is one
     launch over the tiles of every instance (see gnor_batch_create)."""
 
-    def __init__(self, sims, tiling=(2, 5, 2), graph_chunk: int = 64):
+    def __init__(self, sims, tiling=(2, 5, 2), graph_chunk: int = 64, form: int = 0):
         import torch
         L = load()
         self.L = L
@@ -464,6 +465,13 @@ class Batch:
             raise GnorError(st, "gnor_batch_create rejected the instances")
         self.h = h
         self._check(L.gnor_batch_set_graph_chunk(h, int(graph_chunk)))
+        self.set_form(form)
+
+    def set_form(self, form: int):
+        """Step form of the batch: 0 two sweeps, 3 the tiles without metal in
+        one pass (as Sim.set_mode)."""
+        self._check(self.L.gnor_batch_set_form(self.h, int(form)))
+        self.form = int(form)
 
     def _check(self, st: int):
         if st:

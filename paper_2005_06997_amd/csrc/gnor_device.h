@@ -102,6 +102,26 @@ __device__ void aux_e_block(const AuxParams& a, int sub, int tid, int nthr) {
   if (tid == 0) a.e1[a.src_cell] += source_value(a, (double)(n + 1) * a.dt);
 }
 
+// Batch: the blocks of all instances in one launch per class.  Instance q
+// owns blocks [blk0[c], blk0[c] + nblk[c]) of class c (for class 0 its tiles,
+// then its auxiliary-line block); c = -1 selects the spectra launch's ranges
+// (dblk0), c = -2 the TF/SF launch's (fblk0).  A block finds its instance by
+// binary search.  With an XCD-aware tile order the ranges are spaced so that
+// instance q's first chunk runs on XCD q % 8; the blocks between the ranges
+// exit at once.
+template <class T>
+__device__ __forceinline__ int find_instance(const BatchEntry<T>* __restrict__ e, int n, int b,
+                                             int c) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int b0 = c == -1 ? e[mid].dblk0 : (c == -2 ? e[mid].fblk0 : e[mid].blk0[c]);
+    if (b0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // [lo, hi) meets [0, np) or [n - 1 - np, n)  (the E and H slabs of an axis)
 __device__ __forceinline__ bool range_in_slabs(int lo, int hi, int n, int np) {
   // [lo, hi) meets [0, np) or [n - 1 - np, n)  (the E and H slabs of an axis)

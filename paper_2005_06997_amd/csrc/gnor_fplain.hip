@@ -529,13 +529,14 @@ __device__ __forceinline__ T tf_dhz(const Params<T>& p, int i, int j, int k) {
 // one-pass class, to that class's own launch); there the terms go to H^{n+1/2} and
 // the E update's share of the H terms of its curl (the one-pass kernels took
 // every H of that curl without them) plus its own H_inc terms to E^{n+1}.
+// Point t of the shell, at tiles of classes c0 .. c1.
 template <class T>
-__global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a, int cls) {
+__device__ __forceinline__ void tfsf_fix_point(const Params<T>& p, const AuxParams& a, int t, int c0,
+                                               int c1) {
   const int* lo = p.tf_lo;
   const int* hi = p.tf_hi;
   const int Lx = hi[0] - lo[0] + 3, Ly = hi[1] - lo[1] + 3, Lz = hi[2] - lo[2] + 3;
   const int nZ = 4 * Lx * Ly, nY = 4 * (Lz - 4) * Lx, nX = 4 * (Ly - 4) * (Lz - 4);
-  int t = blockIdx.x * 256 + threadIdx.x;
   int i, j, k;
   if (t < nZ) {
     const int q = t / (Lx * Ly);
@@ -556,7 +557,8 @@ __global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a, int 
     return;
   }
   const Tiling& tl = p.tl;
-  if (p.tile_class[((k / tl.kz) * tl.nby + j / tl.ty) * tl.nbx + i / kBX] != cls) return;
+  const int c = p.tile_class[((k / tl.kz) * tl.nby + j / tl.ty) * tl.nbx + i / kBX];
+  if (c < c0 || c > c1) return;
   const size_t id = ((size_t)k * p.ny + j) * p.nx + i;
   const T dhy = tf_dhy(p, i, j, k), dhz = tf_dhz(p, i, j, k);
   if (dhy != T(0)) p.H[1][id] += dhy;
@@ -582,6 +584,59 @@ __global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a, int 
   if (cz != T(0)) p.O[2][id] += sez * cz;
 }
 
+template <class T>
+__global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a, int cls) {
+  tfsf_fix_point(p, a, blockIdx.x * 256 + threadIdx.x, cls, cls);
+}
+
+// ------------------------------------------------------------------ batches
+// Step form 3 of a batch: the one-pass class CLS of every instance in one
+// launch (class 0's last block of an instance, its line's block in the two
+// sweeps, stays idle: the lines take a launch of their own, k_aux_batch).
+template <class T, int TY, bool NT, int CLS>
+__global__ void __launch_bounds__(kBX* TY) k_fplain_batch(const BatchEntry<T>* __restrict__ e, int n) {
+  __shared__ HRows<T, TY> sh;
+  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
+  const int b = blockIdx.x - en.blk0[CLS];
+  if (b >= en.nblk[CLS] || (CLS == 0 && b == en.nblk[0] - 1)) return;
+  const Params<T>& p = en.p;
+  const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
+  if (!tile.ok) return;
+  if (CLS == 1) {
+    fplain_tile<T, TY, NT, true, true>(p, tile, sh);
+  } else {
+    const int np = p.cp[0].np, x0 = tile.bx * kBX;
+    if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true, false>(p, tile, sh);
+    else fplain_tile<T, TY, NT, false, false>(p, tile, sh);
+  }
+}
+
+// The TF/SF corrections of every instance at the points of its one-pass
+// tiles (classes 0 and 1), after both classes' launches.
+template <class T>
+__global__ void __launch_bounds__(256) k_tfsf_fix_batch(const BatchEntry<T>* __restrict__ e, int n) {
+  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, -2)];
+  const int b = blockIdx.x - en.fblk0;
+  if (b >= en.fnblk) return;
+  tfsf_fix_point(en.p, en.a, b * 256 + threadIdx.x, 0, 1);
+}
+
+// The lines' whole step, one block per instance (as k_aux for one simulation).
+template <class T>
+__global__ void __launch_bounds__(kAuxThreads) k_aux_batch(const BatchEntry<T>* __restrict__ e, int sub) {
+  const AuxParams& a = e[blockIdx.x].a;
+  aux_h_block(a, threadIdx.x, kAuxThreads);
+  __syncthreads();
+  aux_e_block(a, sub, threadIdx.x, kAuxThreads);
+}
+
+template <class T, int CLS, bool NT>
+void launch_fplain_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, hipStream_t s) {
+  if (ty == 4) hipLaunchKernelGGL((k_fplain_batch<T, 4, NT, CLS>), dim3(blocks), dim3(kBX, 4), 0, s, e, n);
+  else if (ty == 8) hipLaunchKernelGGL((k_fplain_batch<T, 8, NT, CLS>), dim3(blocks), dim3(kBX, 8), 0, s, e, n);
+  else hipLaunchKernelGGL((k_fplain_batch<T, 2, NT, CLS>), dim3(blocks), dim3(kBX, 2), 0, s, e, n);
+}
+
 }  // namespace
 
 template <class T>
@@ -589,14 +644,40 @@ void launch_fplain(const Params<T>& p, const AuxParams& a, int cls, bool fix, hi
   if (p.tl.cn[cls] == 0) return;
   if (p.stream_stores) launch_fplain_nt<T, true>(p, cls, s);
   else launch_fplain_nt<T, false>(p, cls, s);
-  if (p.tfsf && fix) {
-    const int Lx = p.tf_hi[0] - p.tf_lo[0] + 3, Ly = p.tf_hi[1] - p.tf_lo[1] + 3;
-    const int Lz = p.tf_hi[2] - p.tf_lo[2] + 3;
-    const long n = 4L * Lx * Ly + 4L * (Lz - 4) * Lx + 4L * (Ly - 4) * (Lz - 4);
-    hipLaunchKernelGGL(k_tfsf_fix<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, a, cls);
-  }
+  if (p.tfsf && fix)
+    hipLaunchKernelGGL(k_tfsf_fix<T>, dim3(tfsf_fix_blocks(p.tf_lo, p.tf_hi)), dim3(256), 0, s, p, a, cls);
 }
 template void launch_fplain<float>(const Params<float>&, const AuxParams&, int, bool, hipStream_t);
 template void launch_fplain<double>(const Params<double>&, const AuxParams&, int, bool, hipStream_t);
+
+int tfsf_fix_blocks(const int lo[3], const int hi[3]) {
+  const long Lx = hi[0] - lo[0] + 3, Ly = hi[1] - lo[1] + 3, Lz = hi[2] - lo[2] + 3;
+  const long n = 4 * Lx * Ly + 4 * (Lz - 4) * Lx + 4 * (Ly - 4) * (Lz - 4);
+  return (int)((n + 255) / 256);
+}
+
+template <class T>
+void launch_fplain_batch(const BatchEntry<T>* e, int n, int blocks, int ty, int cls, bool nt,
+                         hipStream_t s) {
+  if (blocks == 0) return;
+  if (cls == 0) nt ? launch_fplain_batch_cls<T, 0, true>(e, n, blocks, ty, s)
+                   : launch_fplain_batch_cls<T, 0, false>(e, n, blocks, ty, s);
+  else nt ? launch_fplain_batch_cls<T, 1, true>(e, n, blocks, ty, s)
+          : launch_fplain_batch_cls<T, 1, false>(e, n, blocks, ty, s);
+}
+template <class T>
+void launch_tfsf_fix_batch(const BatchEntry<T>* e, int n, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_tfsf_fix_batch<T>, dim3(blocks), dim3(256), 0, s, e, n);
+}
+template <class T>
+void launch_aux_batch(const BatchEntry<T>* e, int n, int sub, hipStream_t s) {
+  hipLaunchKernelGGL(k_aux_batch<T>, dim3(n), dim3(kAuxThreads), 0, s, e, sub);
+}
+template void launch_fplain_batch<float>(const BatchEntry<float>*, int, int, int, int, bool, hipStream_t);
+template void launch_fplain_batch<double>(const BatchEntry<double>*, int, int, int, int, bool, hipStream_t);
+template void launch_tfsf_fix_batch<float>(const BatchEntry<float>*, int, int, hipStream_t);
+template void launch_tfsf_fix_batch<double>(const BatchEntry<double>*, int, int, hipStream_t);
+template void launch_aux_batch<float>(const BatchEntry<float>*, int, int, hipStream_t);
+template void launch_aux_batch<double>(const BatchEntry<double>*, int, int, hipStream_t);
 
 }  // namespace gnor

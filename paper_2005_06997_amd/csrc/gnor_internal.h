@@ -272,8 +272,10 @@ void launch_store_design(const AdjParams<T>& A, int store_e_only, const T* Ex, c
 
 // One instance of a batch: its parameters and its block ranges in the batched
 // sweep launches of each tile class (blk0[c] .. blk0[c] + nblk[c]; class 0
-// ends with the instance's auxiliary-line block) and in the batched spectra
-// launch (dblk0 .. dblk0 + dnblk).
+// ends with the instance's auxiliary-line block), in the batched spectra
+// launch (dblk0 .. dblk0 + dnblk) and in the batched TF/SF launch of step
+// form 3 (fblk0 .. fblk0 + fnblk; none where no one-pass tile meets the
+// shell of the TF box).
 template <class T>
 struct BatchEntry {
   Params<T> p;
@@ -282,6 +284,7 @@ struct BatchEntry {
   FluxParams f;
   int blk0[kClasses], nblk[kClasses];
   int dblk0, dnblk;
+  int fblk0, fnblk;
 };
 
 // one class of the batched sweeps (blocks: that class's blocks of all instances)
@@ -295,6 +298,20 @@ void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, in
 // of the chunk: after the H sweep, before the spectra
 template <class T>
 void launch_aux_e_batch(const BatchEntry<T>* e, int n, int sub, hipStream_t s);
+// Step form 3 of a batch (gnor_fplain.hip): one-pass class cls (0 or 1) of
+// every instance (blocks: that class's blocks of all instances); the TF/SF
+// corrections at the one-pass points of every instance (blocks: the sum of
+// fnblk); and the lines' whole step (H and E, one block per instance), after
+// the TF/SF launch and before the E/J sweeps of the metal classes
+template <class T>
+void launch_fplain_batch(const BatchEntry<T>* e, int n, int blocks, int ty, int cls, bool nt,
+                         hipStream_t s);
+template <class T>
+void launch_tfsf_fix_batch(const BatchEntry<T>* e, int n, int blocks, hipStream_t s);
+template <class T>
+void launch_aux_batch(const BatchEntry<T>* e, int n, int sub, hipStream_t s);
+// blocks of the TF/SF launch for a TF box [lo, hi] (the points of its shell)
+int tfsf_fix_blocks(const int lo[3], const int hi[3]);
 template <class T>
 void launch_dft_batch(const BatchEntry<T>* e, int n, int blocks, int sub, hipStream_t s);
 template <class T>

@@ -1829,7 +1829,10 @@ struct gnor_batch {
   int ty = 2;
   char* tab = nullptr;       // two tables of n entries (parity 0, parity 1), caller memory
   size_t entry_bytes = 0;
-  int hblocks[gnor::kClasses] = {0, 0, 0, 0}, dblocks = 0;
+  int hblocks[gnor::kClasses] = {0, 0, 0, 0}, dblocks = 0, fblocks = 0;
+  // step form: 0 two sweeps; 3 the tiles without metal in one pass (as
+  // gnor_set_fused(sim, 3) for one simulation)
+  int form = 0;
   // concurrent class launches, as for a single simulation (serial on the
   // batch's stream for a batch made by gnor_batch_create_static)
   bool concurrent = true;
@@ -1870,7 +1873,7 @@ gnor_status batch_tables(gnor_batch* b) {
   const int stream = 9.0 * cells * sizeof(T) > gnor::kStreamStoreBytes ? 1 : 0;
   b->stream_stores = stream != 0;
   for (int parity = 0; parity < 2; ++parity) {
-    int h0[gnor::kClasses] = {0, 0, 0, 0}, d0 = 0;
+    int h0[gnor::kClasses] = {0, 0, 0, 0}, d0 = 0, f0 = 0;
     for (int q = 0; q < b->n; ++q) {
       gnor_sim* s = b->sims[q];
       gnor::BatchEntry<T>& e = tab[(size_t)parity * b->n + q];
@@ -1890,9 +1893,15 @@ gnor_status batch_tables(gnor_batch* b) {
       e.dblk0 = d0;
       e.dnblk = s->mon.nfreq > 0 ? gnor::dft_blocks(e.d, e.f) : 0;
       d0 += e.dnblk;
+      // step form 3: the TF/SF launch covers the instance's shell where one
+      // of its one-pass classes meets it
+      e.fblk0 = f0;
+      e.fnblk = (e.p.tfsf && (s->tf_shell[0] || s->tf_shell[1])) ? gnor::tfsf_fix_blocks(e.p.tf_lo, e.p.tf_hi) : 0;
+      f0 += e.fnblk;
     }
     for (int c = 0; c < gnor::kClasses; ++c) b->hblocks[c] = h0[c];
     b->dblocks = d0;
+    b->fblocks = f0;
   }
   b->entry_bytes = sizeof(gnor::BatchEntry<T>);
   BHIPCHECK(b, hipMemcpy(b->tab, tab.data(), tab.size() * b->entry_bytes, hipMemcpyHostToDevice));
@@ -1928,14 +1937,29 @@ void batch_enqueue(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st) {
         (void)hipStreamWaitEvent(st, b->ev_join[q2], 0);
       }
     };
-    classes([&](int c, hipStream_t q2) {
-      gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
-    });
-    classes([&](int c, hipStream_t q2) {
-      gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->any_cp, b->stream_stores, q2);
-      // the lines' E beside the sweep, after the short metal class
-      if (c == 2) gnor::launch_aux_e_batch<T>(t, b->n, sub, q2);
-    });
+    if (b->form == 3) {
+      // the tiles without metal in one pass beside the metal classes' H
+      // sweeps; then the TF/SF terms at the one-pass points, the lines'
+      // step, and the metal classes' E/J sweeps
+      classes([&](int c, hipStream_t q2) {
+        if (c <= 1) gnor::launch_fplain_batch<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
+        else gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
+      });
+      gnor::launch_tfsf_fix_batch<T>(t, b->n, b->fblocks, st);
+      gnor::launch_aux_batch<T>(t, b->n, sub, st);
+      classes([&](int c, hipStream_t q2) {
+        if (c >= 2) gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->any_cp, b->stream_stores, q2);
+      });
+    } else {
+      classes([&](int c, hipStream_t q2) {
+        gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
+      });
+      classes([&](int c, hipStream_t q2) {
+        gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->any_cp, b->stream_stores, q2);
+        // the lines' E beside the sweep, after the short metal class
+        if (c == 2) gnor::launch_aux_e_batch<T>(t, b->n, sub, q2);
+      });
+    }
     if (b->any_dft && b->dblocks > 0) gnor::launch_dft_batch<T>(t, b->n, b->dblocks, sub, st);
     if (b->any_flux && (n % gnor::kFluxSlots) == gnor::kFluxSlots - 1)
       for (gnor_sim* s : b->sims)
@@ -2075,6 +2099,19 @@ void gnor_batch_destroy(gnor_batch* b) {
   }
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   delete b;
+}
+
+gnor_status gnor_batch_set_form(gnor_batch* b, int32_t form) {
+  if (!b || (form != 0 && form != 3)) return GNOR_E_INVALID_ARG;
+  if (form != b->form) {
+    // the queued steps of the old form finish first (they read the same state)
+    BHIPCHECK(b, hipStreamSynchronize(b->stream));
+    b->form = form;
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_steps = 0;
+  }
+  return GNOR_OK;
 }
 
 gnor_status gnor_batch_set_graph_chunk(gnor_batch* b, int32_t steps) {

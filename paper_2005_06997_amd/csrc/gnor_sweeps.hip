@@ -503,22 +503,8 @@ __global__ void __launch_bounds__(kBX* TY) k_ej(Params<T> p, AuxParams a, int su
   ej_class<T, TY, CLS, CP, NT>(p, blockIdx.x);
 }
 
-// Batch: the blocks of all instances in one launch per class.  Instance q
-// owns blocks [blk0[c], blk0[c] + nblk[c]) of class c (for class 0 its tiles,
-// then its auxiliary-line block); a block finds its instance by binary search.
-// With an XCD-aware tile order the ranges are spaced so that instance q's
-// first chunk runs on XCD q % 8; the blocks between the ranges exit at once.
-template <class T>
-__device__ __forceinline__ int find_instance(const BatchEntry<T>* __restrict__ e, int n, int b,
-                                             int c) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if ((c < 0 ? e[mid].dblk0 : e[mid].blk0[c]) <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
+// Batch: the blocks of all instances in one launch per class (find_instance
+// maps a block to its instance).
 
 template <class T, int TY, int CLS, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __restrict__ e, int n) {

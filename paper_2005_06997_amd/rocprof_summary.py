@@ -23,9 +23,9 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 # kernel families launched once per tile class, the classes of one sweep
 # back to back (or concurrently)
-SWEEPS = ("k_h", "k_ej", "k_step", "k_fplain", "k_fplain_pml", "k_h_batch", "k_ej_batch")
+SWEEPS = ("k_h", "k_ej", "k_step", "k_fplain", "k_fplain_pml", "k_h_batch", "k_ej_batch", "k_fplain_batch")
 # kernels launched inside a sweep's fork/join, counted with that sweep
-MEMBER_OF = {"k_aux_e_batch": "k_ej_batch", "k_tfsf_fix": "k_fplain"}
+MEMBER_OF = {"k_aux_e_batch": "k_ej_batch", "k_tfsf_fix": "k_fplain", "k_tfsf_fix_batch": "k_fplain_batch"}
 
 
 def family(kernel: str) -> str:

@@ -173,6 +173,7 @@ def test_new_entry_points_validate_on_the_host(lib):
     arr = (C.c_void_p * 1)(h.value)
     out = C.c_void_p()
     assert lib.gnor_batch_create(1, arr, None, None, 0, C.byref(out)) == 1  # no table
+    assert lib.gnor_batch_set_form(None, 3) == 1  # no batch
     assert lib.gnor_update_design(h, None) == 5  # not bound
     assert lib.gnor_flush_spectra(h) == 5
     lib.gnor_destroy(h)

@@ -29,19 +29,23 @@ def instances(count=5, seed=0):
     return ws
 
 
-@pytest.mark.parametrize("prec,tiling", [("fp32", (2, 8, 0)), ("fp64", (2, 8, 0)),
-                                         ("fp32", (2, 3, 2)), ("fp32", (4, 4, 1))])
-def test_batch_equals_individual_runs_bitwise(B, prec, tiling):
+@pytest.mark.parametrize("prec,tiling,form", [("fp32", (2, 8, 0), 0), ("fp64", (2, 8, 0), 0),
+                                              ("fp32", (2, 3, 2), 0), ("fp32", (4, 4, 1), 0),
+                                              ("fp32", (2, 5, 2), 3), ("fp64", (2, 3, 2), 3),
+                                              ("fp32", (4, 4, 1), 3), ("fp64", (8, 4, 0), 3)])
+def test_batch_equals_individual_runs_bitwise(B, prec, tiling, form):
     """Also with the XCD-aware tile orders 1 and 2, under which the
-    instances' block ranges are spaced apart by idle blocks."""
+    instances' block ranges are spaced apart by idle blocks; in the two-sweep
+    form and in the form with the tiles without metal in one pass (whose
+    TF/SF launch covers every instance's shell)."""
     ws = instances()
-    print(f"case batch {prec} tiling {tiling}: sizes {[w.nx for w in ws]}", flush=True)
+    print(f"case batch {prec} tiling {tiling} form {form}: sizes {[w.nx for w in ws]}", flush=True)
     steps = 131  # odd: eager steps around graph chunks
     solo, fused = [], []
     for w in ws:
         s = B.Sim(w, precision=prec)
         s.set_tiling(*tiling)
-        s.set_fused(False)  # batches run the two-sweep kernels
+        s.set_mode(form)  # the batch's step form
         s.run(steps)
         solo.append(({f: s.field(f) for f in FIELDS}, s.spectra()))
         s.close()
@@ -51,7 +55,7 @@ def test_batch_equals_individual_runs_bitwise(B, prec, tiling):
         fused.append(s.spectra())
         s.close()
     sims = [B.Sim(w, precision=prec) for w in ws]
-    bt = B.Batch(sims, tiling=tiling)
+    bt = B.Batch(sims, tiling=tiling, form=form)
     bt.run(steps)
     bt.synchronize()
     for (fields, spec), s in zip(solo, sims):
@@ -100,7 +104,8 @@ def test_batch_with_streamed_stores_bitwise(B):
     assert np.abs(solo[0][0]["Jx"]).max() > 0
 
 
-def test_batch_instance_vs_oracle(B):
+@pytest.mark.parametrize("form", [0, 3])
+def test_batch_instance_vs_oracle(B, form):
     """Every instance of an FP64 batch (a 128^3 sphere, a 192^3 gap dimer with
     flux boxes, a 104^3 sphere) against the oracle after 320 steps: the
     incident front, which starts with the pulse at t = 0, crosses the last
@@ -111,9 +116,9 @@ def test_batch_instance_vs_oracle(B):
     frequency)."""
     ws = instances(count=3, seed=1)
     steps = 320
-    print(f"case batch fp64 vs oracle, {steps} steps: {[w.name for w in ws]}", flush=True)
+    print(f"case batch fp64 form {form} vs oracle, {steps} steps: {[w.name for w in ws]}", flush=True)
     sims = [B.Sim(w, precision="fp64") for w in ws]
-    bt = B.Batch(sims)  # the default batch tiling (XCD-aware order, rotated starts)
+    bt = B.Batch(sims, form=form)  # the default batch tiling (XCD-aware order, rotated starts)
     bt.run(steps)
     bt.synchronize()
     eps0 = 8.8541878128e-12
@@ -146,6 +151,8 @@ def test_batch_instance_vs_oracle(B):
 
 def test_batch_rejects_mixed_precision_and_foreign_steps(B):
     ws = instances(count=2)
+    with pytest.raises(B.GnorError):  # no such batch step form
+        B.Batch([B.Sim(ws[0], precision="fp32")], form=1)
     a = B.Sim(ws[0], precision="fp32")
     b = B.Sim(ws[1], precision="fp64")
     with pytest.raises(B.GnorError):

@@ -277,9 +277,11 @@ def test_design160_gradient_vs_fd_on_32_voxels(B):
         assert np.sign(g32[q]) == np.sign(g64[q]) or abs(g64[q]) <= 5e-3 * gmax
 
 
-def test_config4_batch_in_the_benchmark_launch(B):
+@pytest.mark.parametrize("form", [0, 3])
+def test_config4_batch_in_the_benchmark_launch(B, form):
     """All 64 instances batched as the benchmark runs them (tiling (2, 5, 2),
-    graph chunks of 64, streaming stores chosen by the batch's total size),
+    graph chunks of 64, streaming stores chosen by the batch's total size, in
+    either step form the benchmark may pick),
     with the pulse moved early so that it reaches every particle within the
     run: the smallest and the largest instance, the first gap dimer and the
     first single sphere equal their single runs bit for bit, and every
@@ -287,9 +289,9 @@ def test_config4_batch_in_the_benchmark_launch(B):
     fields = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "Jx", "Jy", "Jz")
     ws = [W.early_pulse(w) for w in W.config4(seed=0, count=64)]
     steps = 400
-    print(f"case config4 batch: {sum(w.cells for w in ws):.3e} cells, {steps} steps", flush=True)
+    print(f"case config4 batch form {form}: {sum(w.cells for w in ws):.3e} cells, {steps} steps", flush=True)
     sims = [B.Sim(w, precision="fp32") for w in ws]
-    bt = B.Batch(sims, tiling=(2, 5, 2))
+    bt = B.Batch(sims, tiling=(2, 5, 2), form=form)
     bt.run(steps)
     bt.synchronize()
     assert all(s.check_finite() for s in sims)
@@ -303,6 +305,7 @@ def test_config4_batch_in_the_benchmark_launch(B):
         spec = sims[q].spectra()
         s = B.Sim(ws[q], precision="fp32")
         s.set_tiling(2, 5, 2)
+        s.set_mode(form)
         s.run(steps)
         for f in fields:
             assert np.array_equal(s.field(f), got[f]), (ws[q].name, f)
