@@ -106,3 +106,21 @@ def test_bench_reads_traffic_only_for_the_current_sources(tmp_path):
     f.write_text("library source hash (csrc/*): `0123456789abcdef`\n<!-- traffic k_ej sweep 123456 -->\n")
     assert bench.measured_traffic("k_ej", str(f)) is None
     assert bench.measured_traffic("k_ej", str(tmp_path / "missing.md")) is None
+
+
+def test_bench_reads_traffic_only_at_the_profiled_tiling(tmp_path):
+    """With a timed tiling given, the traffic is taken only when it is the
+    tiling of the profiled run (its --tiling option for FP32, --tiling-fp64
+    for FP64); the counters of another tiling give null."""
+    import bench
+    f = tmp_path / "s.md"
+    f.write_text(f"library source hash (csrc/*): `{R.source_hash()}`\n"
+                 "    rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --tiling 4,3,2 --tiling-fp64 2,4,2 --form 3\n"
+                 "<!-- traffic k_fplain sweep 777 -->\n")
+    assert bench.profiled_tiling(str(f)) == (4, 3, 2)
+    assert bench.profiled_tiling(str(f), fp64=True) == (2, 4, 2)
+    assert bench.measured_traffic("k_fplain", str(f), (4, 3, 2)) == 777.0
+    assert bench.measured_traffic("k_fplain", str(f), (2, 3, 2)) is None
+    assert bench.measured_traffic("k_fplain", str(f), (2, 4, 2), fp64=True) == 777.0
+    assert bench.measured_traffic("k_fplain", str(f), (4, 3, 2), fp64=True) is None
+    assert bench.profiled_tiling(str(tmp_path / "missing.md")) is None
