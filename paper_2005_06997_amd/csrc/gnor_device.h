@@ -47,6 +47,21 @@ __device__ __forceinline__ Tile decode_tile(const Tiling& tl, const int* __restr
   return r;
 }
 
+// Node scalars of sub-grid node l (Eqs. NonlocalUpdate / GNORUpdate in the
+// current form; see Params): the node divergence of J^{n-1/2} (its edges at
+// the node and one below along each axis), Phi~_P^n, and Q, the scalar whose
+// differences along the edges give the nonlocal force.  One definition for
+// every kernel that writes them, so that they agree bit for bit.
+template <class T>
+__device__ __forceinline__ void store_node_scalars(const Params<T>& p, size_t l, T jx, T jxm, T jy, T jym,
+                                                   T jz, T jzm, T pp, T pj) {
+  const T div = (jx - jxm) + (jy - jym) + (jz - jzm);
+  const T phiP = pp + div;
+  p.PPo[l] = phiP;
+  p.PJo[l] = div;
+  p.Q[l] = p.g1 * phiP + p.g2 * (T(3) * div - pj);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -105,7 +120,8 @@ __device__ void aux_e_block(const AuxParams& a, int sub, int tid, int nthr) {
 // Batch: the blocks of all instances in one launch per class.  Instance q
 // owns blocks [blk0[c], blk0[c] + nblk[c]) of class c (for class 0 its tiles,
 // then its auxiliary-line block); c = -1 selects the spectra launch's ranges
-// (dblk0), c = -2 the TF/SF launch's (fblk0).  A block finds its instance by
+// (dblk0), c = -2 the TF/SF launch's (fblk0), c = -3 the node scalars'
+// (sblk0).  A block finds its instance by
 // binary search.  With an XCD-aware tile order the ranges are spaced so that
 // instance q's first chunk runs on XCD q % 8; the blocks between the ranges
 // exit at once.
@@ -115,7 +131,7 @@ __device__ __forceinline__ int find_instance(const BatchEntry<T>* __restrict__ e
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int b0 = c == -1 ? e[mid].dblk0 : (c == -2 ? e[mid].fblk0 : e[mid].blk0[c]);
+    const int b0 = c == -1 ? e[mid].dblk0 : (c == -2 ? e[mid].fblk0 : (c == -3 ? e[mid].sblk0 : e[mid].blk0[c]));
     if (b0 <= b) lo = mid;
     else hi = mid - 1;
   }

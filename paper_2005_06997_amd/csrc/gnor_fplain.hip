@@ -162,9 +162,21 @@ struct HRows {
   T h[2][2][TY][kBX];  // [plane & 1][0: H_x, 1: H_z][row][lane]
 };
 
+// What the E update of a metal point reads besides the fields: E^{n-1} (in
+// the output buffer, which it overwrites), J^{n-1/2}, the density weight, and
+// Q at the cell's node and at the nodes one cell up each axis.
+template <class T>
+struct MetalIn {
+  T em[3] = {T(0), T(0), T(0)}, j[3] = {T(0), T(0), T(0)}, qa[3] = {T(0), T(0), T(0)};
+  T q = T(0), r = T(1);
+};
+
 // XS: the tile meets an x slab (the other tiles run code free of the CPML
-// terms); YZ: it may meet a y or z slab as well (the CPML class)
-template <class T, int TY, bool NT, bool XS, bool YZ>
+// terms); YZ: it may meet a y or z slab as well (the CPML class); METAL: the
+// metal class (no slab), whose E update includes the nonlocal metal points
+// (Eqs. NonlocalUpdate / GNORUpdate in the current form, without critical
+// points) from node scalars written before the launch (k_nodes)
+template <class T, int TY, bool NT, bool XS, bool YZ, bool METAL>
 __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
                                             HRows<T, TY>& sh) {
   const int nx = p.nx, ny = p.ny, nz = p.nz;
@@ -245,6 +257,16 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
   }
   const CpmlAxis<T>& Z = p.cp[2];
   const uint32_t ic = act ? (uint32_t)i : 0;
+  // metal: the column's place in the metal sub-grid; the metal bits of a
+  // plane are loaded a plane ahead, so that the plane's metal loads go out
+  // with its other loads
+  const int lxm = i - p.mlo[0], lym = j - p.mlo[1];
+  const bool col_sub = METAL && act && lxm >= 0 && lym >= 0 && lxm < p.mn[0] && lym < p.mn[1];
+  const uint32_t m1 = METAL ? (uint32_t)p.mn[0] : 0u, m2 = METAL ? m1 * (uint32_t)p.mn[1] : 0u;
+  const uint32_t lcol = col_sub ? (uint32_t)lym * m1 + (uint32_t)lxm : 0u;
+  uint32_t mbn = 0u;
+  if (METAL && col_sub && k0 - p.mlo[2] >= 0 && k0 - p.mlo[2] < p.mn[2])
+    mbn = p.mask[(uint32_t)(k0 - p.mlo[2]) * m2 + lcol];
 
   uint32_t id = act ? (uint32_t)k0 * sz + (uint32_t)j * nx + i : 0;
   // carried: E_x, E_y of plane k at the column, E_x of column x-1 (first
@@ -301,6 +323,24 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
     }
     PlaneIn<T> cur;
     load_plane<T, XS, YZ>(p, cur, id, zp ? sz : 0, dyp, sy, qs, qsl, qse, sq, yz, act, first, last, rd);
+    MetalIn<T> mt;
+    uint32_t mb = 0u, l = 0u;
+    bool zsub = false;
+    if (METAL) {
+      const int lz = k - p.mlo[2];
+      zsub = lz >= 0 && lz < p.mn[2];  // uniform over the block
+      l = (col_sub && zsub) ? (uint32_t)lz * m2 + lcol : 0u;
+      mb = mbn;
+      mbn = (col_sub && lz + 1 >= 0 && lz + 1 < p.mn[2]) ? p.mask[(uint32_t)(lz + 1) * m2 + lcol] : 0u;
+      // metal points lie two cells inside the sub-grid: the upper nodes exist
+      if (mb & 1u) { mt.em[0] = Ox[id]; mt.j[0] = p.Ji[0][l]; mt.qa[0] = p.Q[l + 1]; }
+      if (mb & 2u) { mt.em[1] = Oy[id]; mt.j[1] = p.Ji[1][l]; mt.qa[1] = p.Q[l + m1]; }
+      if (mb & 4u) { mt.em[2] = Oz[id]; mt.j[2] = p.Ji[2][l]; mt.qa[2] = p.Q[l + m2]; }
+      if (mb) {
+        mt.q = p.Q[l];
+        if (p.rho) mt.r = (T)p.rho[l];
+      }
+    }
     load_fence();
     const T ez = cur.ez, ex1 = cur.ex1, ey1 = cur.ey1, ezy = cur.ezy, exy = cur.exy;
     const T hx = cur.hx, hy = cur.hy, hz = cur.hz, sy_ = cur.sy_, sz_ = cur.sz_;
@@ -439,9 +479,53 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
     T czv = d_xz - d_yz;  // dx H_y - dy H_x
     const T sexy = k < p.sub_k ? p.SE : (k == p.sub_k ? p.se_avg : p.se_sub);
     const T sez = k < p.sub_k ? p.SE : p.se_sub;
-    if (uex) put<NT>(&Ox[id], ex0 + sexy * cxv);
-    if (uey) put<NT>(&Oy[id], ey0 + sexy * cyv);
-    if (uez) put<NT>(&Oz[id], ez + sez * czv);
+    T enx = ex0 + sexy * cxv, eny = ey0 + sexy * cyv, enz = ez + sez * czv;
+    if (METAL) {
+      // metal points: E^{n+1} and J^{n+1/2} together (the same update as
+      // the two-sweep E/J kernel's), and the wavefront's share of the plane
+      // sum of J_x for the extinction transform
+      double jsum = 0.0;
+      if (mb) {
+        T cS = p.cS, c3 = p.c3, c1 = p.c1, cJ = p.cJ, cG = p.cG, d3 = p.d3, r = T(1);
+        if (p.rho) {
+          r = mt.r;
+          d3 = r * p.d3;
+          const T inv = T(1) / (p.eps_inf + d3 + T(0));
+          cS = p.S * inv; c3 = T(3) * d3 * inv; c1 = d3 * inv; cJ = p.D2 * inv; cG = inv;
+        }
+        const T ag = p.agam;
+        if (mb & 1u) {
+          const T G = r * (mt.qa[0] - mt.q);
+          const T en = ex0 + (cS * cxv - c3 * ex0 - c1 * mt.em[0] + cJ * mt.j[0] - cG * G);
+          const T jn = mt.j[0] + (d3 * (mt.em[0] + T(2) * ex0 + en) - ag * mt.j[0] + G);
+          p.Jo[0][l] = jn;
+          jsum = (double)jn + (double)p.ebd * ((double)en - (double)ex0);
+          enx = en;
+        }
+        if (mb & 2u) {
+          const T G = r * (mt.qa[1] - mt.q);
+          const T en = ey0 + (cS * cyv - c3 * ey0 - c1 * mt.em[1] + cJ * mt.j[1] - cG * G);
+          p.Jo[1][l] = mt.j[1] + (d3 * (mt.em[1] + T(2) * ey0 + en) - ag * mt.j[1] + G);
+          eny = en;
+        }
+        if (mb & 4u) {
+          const T G = r * (mt.qa[2] - mt.q);
+          const T en = ez + (cS * czv - c3 * ez - c1 * mt.em[2] + cJ * mt.j[2] - cG * G);
+          p.Jo[2][l] = mt.j[2] + (d3 * (mt.em[2] + T(2) * ez + en) - ag * mt.j[2] + G);
+          enz = en;
+        }
+      }
+      if (zsub && __any(mb != 0u)) {
+        const double s = wave_sum(jsum);
+        if (lane == 0) {
+          const int nbxy = p.tl.nbx * p.tl.nby * TY;
+          p.jpart[(size_t)k * nbxy + (tile.by * p.tl.nbx + tile.bx) * TY + ty] = s;
+        }
+      }
+    }
+    if (uex) put<NT>(&Ox[id], enx);
+    if (uey) put<NT>(&Oy[id], eny);
+    if (uez) put<NT>(&Oz[id], enz);
     // ---- carry up the column
     ex0 = ex1;
     ey0 = ey1;
@@ -464,8 +548,8 @@ __global__ void __launch_bounds__(kBX* TY) k_fplain(Params<T> p) {
   const Tile tile = decode_tile(p.tl, p.tiles, 0, blockIdx.x);
   if (!tile.ok) return;  // uniform over the block
   const int np = p.cp[0].np, x0 = tile.bx * kBX;
-  if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true, false>(p, tile, sh);
-  else fplain_tile<T, TY, NT, false, false>(p, tile, sh);
+  if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true, false, false>(p, tile, sh);
+  else fplain_tile<T, TY, NT, false, false, false>(p, tile, sh);
 }
 
 // Class 1 (tiles without metal that meet a y or z slab, and maybe an x slab)
@@ -476,7 +560,43 @@ __global__ void __launch_bounds__(kBX* TY) k_fplain_pml(Params<T> p) {
   __shared__ HRows<T, TY> sh;
   const Tile tile = decode_tile(p.tl, p.tiles, 1, blockIdx.x);
   if (!tile.ok) return;
-  fplain_tile<T, TY, NT, true, true>(p, tile, sh);
+  fplain_tile<T, TY, NT, true, true, false>(p, tile, sh);
+}
+
+// Class 2 (metal tiles without a slab) in one pass, without critical points;
+// its node scalars come from k_nodes, launched before it.
+template <class T, int TY, bool NT>
+__global__ void __launch_bounds__(kBX* TY) k_fplain_metal(Params<T> p) {
+  __shared__ HRows<T, TY> sh;
+  const Tile tile = decode_tile(p.tl, p.tiles, 2, blockIdx.x);
+  if (!tile.ok) return;
+  fplain_tile<T, TY, NT, false, false, true>(p, tile, sh);
+}
+
+// Node scalars of every node of the metal sub-grid that lies on a metal edge
+// (its column's planes zlo .. zhi; the other nodes keep zero), from
+// J^{n-1/2} and the previous node scalars, the step's inputs.  One thread per
+// sub-grid node, x fastest.  (One thread per column and run of 8 planes,
+// marching them, took 42 us per step on the 320^3 sphere: too few loads in
+// flight.)
+template <class T>
+__device__ __forceinline__ void nodes_at(const Params<T>& p, long t) {
+  const int m0 = p.mn[0];
+  const long C = (long)m0 * p.mn[1];
+  if (t >= C * p.mn[2]) return;
+  const int col = (int)(t % C), lz = (int)(t / C);
+  if (lz < p.colz[2 * col] || lz > p.colz[2 * col + 1]) return;
+  const int lx = col % m0, ly = col / m0;
+  const size_t l = (size_t)t, m1 = (size_t)m0, m2 = (size_t)C;
+  const T jx = p.Ji[0][l], jy = p.Ji[1][l], jz = p.Ji[2][l];
+  const T jxm = lx > 0 ? p.Ji[0][l - 1] : T(0);
+  const T jym = ly > 0 ? p.Ji[1][l - m1] : T(0);
+  const T jzm = lz > 0 ? p.Ji[2][l - m2] : T(0);
+  store_node_scalars(p, l, jx, jxm, jy, jym, jz, jzm, p.PPi[l], p.PJi[l]);
+}
+template <class T>
+__global__ void __launch_bounds__(256) k_nodes(Params<T> p) {
+  nodes_at(p, (long)blockIdx.x * 256 + threadIdx.x);
 }
 
 template <class T, bool NT>
@@ -486,10 +606,14 @@ void launch_fplain_nt(const Params<T>& p, int cls, hipStream_t s) {
     if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain<T, 4, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p);
     else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain<T, 8, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p);
     else hipLaunchKernelGGL((k_fplain<T, 2, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p);
-  } else {
+  } else if (cls == 1) {
     if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain_pml<T, 4, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p);
     else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain_pml<T, 8, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p);
     else hipLaunchKernelGGL((k_fplain_pml<T, 2, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p);
+  } else {
+    if (p.tl.ty == 4) hipLaunchKernelGGL((k_fplain_metal<T, 4, NT>), dim3(blocks), dim3(kBX, 4), 0, s, p);
+    else if (p.tl.ty == 8) hipLaunchKernelGGL((k_fplain_metal<T, 8, NT>), dim3(blocks), dim3(kBX, 8), 0, s, p);
+    else hipLaunchKernelGGL((k_fplain_metal<T, 2, NT>), dim3(blocks), dim3(kBX, 2), 0, s, p);
   }
 }
 
@@ -598,27 +722,40 @@ __global__ void __launch_bounds__(kBX* TY) k_fplain_batch(const BatchEntry<T>* _
   __shared__ HRows<T, TY> sh;
   const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
   const int b = blockIdx.x - en.blk0[CLS];
-  if (b >= en.nblk[CLS] || (CLS == 0 && b == en.nblk[0] - 1)) return;
+  if (b >= en.nblk[CLS] || (CLS == 0 && b == en.nblk[0] - 1) || (CLS == 2 && en.two_sweep2)) return;
   const Params<T>& p = en.p;
   const Tile tile = decode_tile(p.tl, p.tiles, CLS, b);
   if (!tile.ok) return;
   if (CLS == 1) {
-    fplain_tile<T, TY, NT, true, true>(p, tile, sh);
+    fplain_tile<T, TY, NT, true, true, false>(p, tile, sh);
+  } else if (CLS == 2) {
+    fplain_tile<T, TY, NT, false, false, true>(p, tile, sh);
   } else {
     const int np = p.cp[0].np, x0 = tile.bx * kBX;
-    if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true, false>(p, tile, sh);
-    else fplain_tile<T, TY, NT, false, false>(p, tile, sh);
+    if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true, false, false>(p, tile, sh);
+    else fplain_tile<T, TY, NT, false, false, false>(p, tile, sh);
   }
 }
 
 // The TF/SF corrections of every instance at the points of its one-pass
-// tiles (classes 0 and 1), after both classes' launches.
+// tiles (classes 0 and 1, and 2 unless its metal tiles take the two sweeps),
+// after those classes' launches.
 template <class T>
 __global__ void __launch_bounds__(256) k_tfsf_fix_batch(const BatchEntry<T>* __restrict__ e, int n) {
   const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, -2)];
   const int b = blockIdx.x - en.fblk0;
   if (b >= en.fnblk) return;
-  tfsf_fix_point(en.p, en.a, b * 256 + threadIdx.x, 0, 1);
+  tfsf_fix_point(en.p, en.a, b * 256 + threadIdx.x, 0, en.two_sweep2 ? 1 : 2);
+}
+
+// The node scalars of every instance (before the metal class's one-pass
+// launch), block range sblk0 .. sblk0 + snblk of each instance.
+template <class T>
+__global__ void __launch_bounds__(256) k_nodes_batch(const BatchEntry<T>* __restrict__ e, int n) {
+  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, -3)];
+  const int b = blockIdx.x - en.sblk0;
+  if (b >= en.snblk) return;
+  nodes_at(en.p, (long)b * 256 + threadIdx.x);
 }
 
 // The lines' whole step, one block per instance (as k_aux for one simulation).
@@ -642,6 +779,10 @@ void launch_fplain_batch_cls(const BatchEntry<T>* e, int n, int blocks, int ty, 
 template <class T>
 void launch_fplain(const Params<T>& p, const AuxParams& a, int cls, bool fix, hipStream_t s) {
   if (p.tl.cn[cls] == 0) return;
+  if (cls == 2 && p.any_metal) {
+    const int nb = node_blocks(p.mn);
+    if (nb > 0) hipLaunchKernelGGL(k_nodes<T>, dim3(nb), dim3(256), 0, s, p);
+  }
   if (p.stream_stores) launch_fplain_nt<T, true>(p, cls, s);
   else launch_fplain_nt<T, false>(p, cls, s);
   if (p.tfsf && fix)
@@ -649,6 +790,11 @@ void launch_fplain(const Params<T>& p, const AuxParams& a, int cls, bool fix, hi
 }
 template void launch_fplain<float>(const Params<float>&, const AuxParams&, int, bool, hipStream_t);
 template void launch_fplain<double>(const Params<double>&, const AuxParams&, int, bool, hipStream_t);
+
+int node_blocks(const int mn[3]) {
+  const long t = (long)mn[0] * mn[1] * mn[2];
+  return (int)((t + 255) / 256);
+}
 
 int tfsf_fix_blocks(const int lo[3], const int hi[3]) {
   const long Lx = hi[0] - lo[0] + 3, Ly = hi[1] - lo[1] + 3, Lz = hi[2] - lo[2] + 3;
@@ -662,9 +808,17 @@ void launch_fplain_batch(const BatchEntry<T>* e, int n, int blocks, int ty, int 
   if (blocks == 0) return;
   if (cls == 0) nt ? launch_fplain_batch_cls<T, 0, true>(e, n, blocks, ty, s)
                    : launch_fplain_batch_cls<T, 0, false>(e, n, blocks, ty, s);
-  else nt ? launch_fplain_batch_cls<T, 1, true>(e, n, blocks, ty, s)
-          : launch_fplain_batch_cls<T, 1, false>(e, n, blocks, ty, s);
+  else if (cls == 1) nt ? launch_fplain_batch_cls<T, 1, true>(e, n, blocks, ty, s)
+                        : launch_fplain_batch_cls<T, 1, false>(e, n, blocks, ty, s);
+  else nt ? launch_fplain_batch_cls<T, 2, true>(e, n, blocks, ty, s)
+          : launch_fplain_batch_cls<T, 2, false>(e, n, blocks, ty, s);
 }
+template <class T>
+void launch_nodes_batch(const BatchEntry<T>* e, int n, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_nodes_batch<T>, dim3(blocks), dim3(256), 0, s, e, n);
+}
+template void launch_nodes_batch<float>(const BatchEntry<float>*, int, int, hipStream_t);
+template void launch_nodes_batch<double>(const BatchEntry<double>*, int, int, hipStream_t);
 template <class T>
 void launch_tfsf_fix_batch(const BatchEntry<T>* e, int n, int blocks, hipStream_t s) {
   if (blocks > 0) hipLaunchKernelGGL(k_tfsf_fix_batch<T>, dim3(blocks), dim3(256), 0, s, e, n);

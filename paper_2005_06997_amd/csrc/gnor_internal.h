@@ -273,9 +273,10 @@ void launch_store_design(const AdjParams<T>& A, int store_e_only, const T* Ex, c
 // One instance of a batch: its parameters and its block ranges in the batched
 // sweep launches of each tile class (blk0[c] .. blk0[c] + nblk[c]; class 0
 // ends with the instance's auxiliary-line block), in the batched spectra
-// launch (dblk0 .. dblk0 + dnblk) and in the batched TF/SF launch of step
+// launch (dblk0 .. dblk0 + dnblk), in the batched TF/SF launch of step
 // form 3 (fblk0 .. fblk0 + fnblk; none where no one-pass tile meets the
-// shell of the TF box).
+// shell of the TF box) and in its node-scalar launch (sblk0 .. sblk0 +
+// snblk; none without metal).
 template <class T>
 struct BatchEntry {
   Params<T> p;
@@ -285,6 +286,10 @@ struct BatchEntry {
   int blk0[kClasses], nblk[kClasses];
   int dblk0, dnblk;
   int fblk0, fnblk;
+  int sblk0, snblk;
+  // 1: the instance's metal tiles (class 2) take the two sweeps in the
+  // batch's current step form (form 0, or critical points); 0: one pass
+  int two_sweep2;
 };
 
 // one class of the batched sweeps (blocks: that class's blocks of all instances)
@@ -298,7 +303,7 @@ void launch_ej_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, in
 // of the chunk: after the H sweep, before the spectra
 template <class T>
 void launch_aux_e_batch(const BatchEntry<T>* e, int n, int sub, hipStream_t s);
-// Step form 3 of a batch (gnor_fplain.hip): one-pass class cls (0 or 1) of
+// Step form 3 of a batch (gnor_fplain.hip): one-pass class cls (0, 1 or 2) of
 // every instance (blocks: that class's blocks of all instances); the TF/SF
 // corrections at the one-pass points of every instance (blocks: the sum of
 // fnblk); and the lines' whole step (H and E, one block per instance), after
@@ -308,6 +313,12 @@ void launch_fplain_batch(const BatchEntry<T>* e, int n, int blocks, int ty, int 
                          hipStream_t s);
 template <class T>
 void launch_tfsf_fix_batch(const BatchEntry<T>* e, int n, int blocks, hipStream_t s);
+// the node scalars of every instance's metal sub-grid (blocks: the sum of
+// snblk), before the metal class's one-pass launch
+template <class T>
+void launch_nodes_batch(const BatchEntry<T>* e, int n, int blocks, hipStream_t s);
+// blocks of the node-scalar launch for a metal sub-grid of mn nodes
+int node_blocks(const int mn[3]);
 template <class T>
 void launch_aux_batch(const BatchEntry<T>* e, int n, int sub, hipStream_t s);
 // blocks of the TF/SF launch for a TF box [lo, hi] (the points of its shell)
@@ -331,8 +342,9 @@ template <class T>
 void launch_step_class(const Params<T>& p, const AuxParams& a, int c, hipStream_t s);
 void launch_aux(const AuxParams& a, int sub, hipStream_t s);
 // one-pass step of tile class cls (gnor_fplain.hip; 0: no metal, at most an
-// x slab; 1: no metal, a y or z slab) and, if fix, the TF/SF corrections at
-// that class's points; before the line's step
+// x slab; 1: no metal, a y or z slab; 2: metal, no slab, no critical points,
+// its node scalars first) and, if fix, the TF/SF corrections at that class's
+// points; before the line's step
 template <class T>
 void launch_fplain(const Params<T>& p, const AuxParams& a, int cls, bool fix, hipStream_t s);
 template <class T>

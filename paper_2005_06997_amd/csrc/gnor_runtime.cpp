@@ -524,11 +524,13 @@ void enqueue_classes(gnor_sim* s, hipStream_t st, F launch, bool c3_side = false
 //   3. E/J sweeps of the two-sweep classes (they read H^{n+1/2} of fused
 //      neighbours and H_inc^{n+1/2}).
 // Form 3: the tiles without metal, class 0 (at most an x slab within one
-// cell) and class 1 (a y or z slab), take the one-pass kernels of
-// gnor_fplain.hip, each followed on its stream by its TF/SF launch where its
-// tiles meet the shell of the TF box; the metal tiles take the two sweeps.
+// cell) and class 1 (a y or z slab), and, without critical points, the metal
+// tiles without a slab (class 2, after a launch that writes the node
+// scalars) take the one-pass kernels of gnor_fplain.hip, each followed on its
+// stream by its TF/SF launch where its tiles meet the shell of the TF box;
+// the metal tiles in a slab (class 3) take the two sweeps.
 bool hybrid_fused(const gnor_sim* s, int c) {
-  if (s->mode == 3) return c <= 1;
+  if (s->mode == 3) return c <= 1 || (c == 2 && s->mat.ncp == 0);
   return c == 0 || (c == 2 && s->mat.ncp == 0);
 }
 
@@ -1527,7 +1529,7 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       if (fused) {
         if (fp32) gnor::launch_step_class<float>(make_params<float>(s, parity), a, c, str);
         else gnor::launch_step_class<double>(make_params<double>(s, parity), a, c, str);
-      } else if (plain1 && c <= 1) {
+      } else if (plain1 && hybrid_fused(s, c)) {
         if (fp32) gnor::launch_fplain<float>(make_params<float>(s, parity), a, c, s->tf_shell[c], str);
         else gnor::launch_fplain<double>(make_params<double>(s, parity), a, c, s->tf_shell[c], str);
       } else {
@@ -1537,7 +1539,7 @@ gnor_status gnor_profile_kernels(gnor_sim* s, int64_t nsteps, double* ms, int32_
       (void)hipEventRecord(ev[1 + c], str);
     }
     for (int c = 0; c < NC && !whole; ++c) {
-      if (fused || (plain1 && c <= 1)) {
+      if (fused || (plain1 && hybrid_fused(s, c))) {
         if (c == 0) gnor::launch_aux(a, 0, str);
       } else {
         if (fp32) gnor::launch_ej_class<float>(make_params<float>(s, parity), a, 0, c, str);
@@ -1829,7 +1831,7 @@ struct gnor_batch {
   int ty = 2;
   char* tab = nullptr;       // two tables of n entries (parity 0, parity 1), caller memory
   size_t entry_bytes = 0;
-  int hblocks[gnor::kClasses] = {0, 0, 0, 0}, dblocks = 0, fblocks = 0;
+  int hblocks[gnor::kClasses] = {0, 0, 0, 0}, dblocks = 0, fblocks = 0, sblocks = 0;
   // step form: 0 two sweeps; 3 the tiles without metal in one pass (as
   // gnor_set_fused(sim, 3) for one simulation)
   int form = 0;
@@ -1840,7 +1842,7 @@ struct gnor_batch {
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   std::vector<int> tiling;   // (ty, kz, order) of every instance at creation
-  bool any_dft = false, any_flux = false, any_cp = false;
+  bool any_dft = false, any_flux = false, any_cp = false, all_cp = false;
   bool stream_stores = false;  // nontemporal field stores (by the batch's total size)
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -1873,7 +1875,7 @@ gnor_status batch_tables(gnor_batch* b) {
   const int stream = 9.0 * cells * sizeof(T) > gnor::kStreamStoreBytes ? 1 : 0;
   b->stream_stores = stream != 0;
   for (int parity = 0; parity < 2; ++parity) {
-    int h0[gnor::kClasses] = {0, 0, 0, 0}, d0 = 0, f0 = 0;
+    int h0[gnor::kClasses] = {0, 0, 0, 0}, d0 = 0, f0 = 0, s0 = 0;
     for (int q = 0; q < b->n; ++q) {
       gnor_sim* s = b->sims[q];
       gnor::BatchEntry<T>& e = tab[(size_t)parity * b->n + q];
@@ -1893,15 +1895,24 @@ gnor_status batch_tables(gnor_batch* b) {
       e.dblk0 = d0;
       e.dnblk = s->mon.nfreq > 0 ? gnor::dft_blocks(e.d, e.f) : 0;
       d0 += e.dnblk;
-      // step form 3: the TF/SF launch covers the instance's shell where one
-      // of its one-pass classes meets it
+      // step form 3: the metal tiles take one pass unless the instance has
+      // critical points (as for one simulation); the TF/SF launch covers the
+      // instance's shell where one of its one-pass classes meets it; the
+      // node-scalar launch covers the metal sub-grid of instances whose metal
+      // tiles take one pass
+      e.two_sweep2 = (b->form != 3 || s->mat.ncp > 0) ? 1 : 0;
+      const bool shell = s->tf_shell[0] || s->tf_shell[1] || (s->tf_shell[2] && !e.two_sweep2);
       e.fblk0 = f0;
-      e.fnblk = (e.p.tfsf && (s->tf_shell[0] || s->tf_shell[1])) ? gnor::tfsf_fix_blocks(e.p.tf_lo, e.p.tf_hi) : 0;
+      e.fnblk = (e.p.tfsf && shell) ? gnor::tfsf_fix_blocks(e.p.tf_lo, e.p.tf_hi) : 0;
       f0 += e.fnblk;
+      e.sblk0 = s0;
+      e.snblk = (!e.two_sweep2 && s->any_metal) ? gnor::node_blocks(e.p.mn) : 0;
+      s0 += e.snblk;
     }
     for (int c = 0; c < gnor::kClasses; ++c) b->hblocks[c] = h0[c];
     b->dblocks = d0;
     b->fblocks = f0;
+    b->sblocks = s0;
   }
   b->entry_bytes = sizeof(gnor::BatchEntry<T>);
   BHIPCHECK(b, hipMemcpy(b->tab, tab.data(), tab.size() * b->entry_bytes, hipMemcpyHostToDevice));
@@ -1941,14 +1952,25 @@ void batch_enqueue(gnor_batch* b, int64_t n0, int64_t count, hipStream_t st) {
       // the tiles without metal in one pass beside the metal classes' H
       // sweeps; then the TF/SF terms at the one-pass points, the lines'
       // step, and the metal classes' E/J sweeps
+      // (the metal tiles of instances with critical points keep the two
+      // sweeps: in those launches the other instances' blocks exit at once,
+      // and the reverse in the one-pass launch)
       classes([&](int c, hipStream_t q2) {
-        if (c <= 1) gnor::launch_fplain_batch<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
-        else gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
+        if (c <= 1) {
+          gnor::launch_fplain_batch<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
+        } else if (c == 2) {
+          if (b->sblocks > 0) gnor::launch_nodes_batch<T>(t, b->n, b->sblocks, q2);
+          if (!b->all_cp) gnor::launch_fplain_batch<T>(t, b->n, b->hblocks[2], b->ty, 2, b->stream_stores, q2);
+          if (b->any_cp) gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[2], b->ty, 2, b->stream_stores, q2);
+        } else {
+          gnor::launch_h_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->stream_stores, q2);
+        }
       });
       gnor::launch_tfsf_fix_batch<T>(t, b->n, b->fblocks, st);
       gnor::launch_aux_batch<T>(t, b->n, sub, st);
       classes([&](int c, hipStream_t q2) {
-        if (c >= 2) gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->any_cp, b->stream_stores, q2);
+        if (c == 3 || (c == 2 && b->any_cp))
+          gnor::launch_ej_batch_class<T>(t, b->n, b->hblocks[c], b->ty, c, b->any_cp, b->stream_stores, q2);
       });
     } else {
       classes([&](int c, hipStream_t q2) {
@@ -2015,6 +2037,7 @@ gnor_status batch_create_impl(int32_t n, gnor_sim* const* sims, void* stream, vo
     b->any_dft = b->any_dft || s->mon.nfreq > 0;
     b->any_flux = b->any_flux || s->nsamp > 0;
     b->any_cp = b->any_cp || s->mat.ncp > 0;
+    b->all_cp = (q == 0 || b->all_cp) && s->mat.ncp > 0;
   }
   b->fp32 = sims[0]->g.precision == GNOR_FP32;
   b->tab = static_cast<char*>(table);
@@ -2104,9 +2127,12 @@ void gnor_batch_destroy(gnor_batch* b) {
 gnor_status gnor_batch_set_form(gnor_batch* b, int32_t form) {
   if (!b || (form != 0 && form != 3)) return GNOR_E_INVALID_ARG;
   if (form != b->form) {
-    // the queued steps of the old form finish first (they read the same state)
+    // the queued steps of the old form finish first (they read the same state
+    // and the parameter tables, which name the form's launches per instance)
     BHIPCHECK(b, hipStreamSynchronize(b->stream));
     b->form = form;
+    const gnor_status st = b->fp32 ? batch_tables<float>(b) : batch_tables<double>(b);
+    if (st != GNOR_OK) return st;
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
     b->graph_steps = 0;

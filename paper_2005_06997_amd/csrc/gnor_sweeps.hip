@@ -214,13 +214,7 @@ __device__ __forceinline__ void h_tile(const Params<T>& p, const Tile tile, bool
       const T jym = (sub && ly > 0) ? p.Ji[1][l - m1] : T(0);
       const T pp = sub ? p.PPi[l] : T(0);
       const T pj = sub ? p.PJi[l] : T(0);
-      if (sub) {
-        const T div = (jx - jxm) + (jy - jym) + (jz - jzm);
-        const T phiP = pp + div;
-        p.PPo[l] = phiP;
-        p.PJo[l] = div;
-        p.Q[l] = p.g1 * phiP + p.g2 * (T(3) * div - pj);
-      }
+      if (sub) store_node_scalars(p, l, jx, jxm, jy, jym, jz, jzm, pp, pj);
       jzm = jz;
     }
     ex0 = ex1;
@@ -510,7 +504,7 @@ template <class T, int TY, int CLS, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __restrict__ e, int n) {
   const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
   const int b = blockIdx.x - en.blk0[CLS];
-  if (b >= en.nblk[CLS]) return;
+  if (b >= en.nblk[CLS] || (CLS == 2 && !en.two_sweep2)) return;
   if (CLS == 0 && b == en.nblk[0] - 1) {
     aux_h_block(en.a, threadIdx.y * kBX + threadIdx.x, kBX * TY);
     return;
@@ -524,7 +518,7 @@ template <class T, int TY, int CLS, bool CP, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __restrict__ e, int n) {
   const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
   const int b = blockIdx.x - en.blk0[CLS];
-  if (b >= en.nblk[CLS] || (CLS == 0 && b == en.nblk[0] - 1)) return;
+  if (b >= en.nblk[CLS] || (CLS == 0 && b == en.nblk[0] - 1) || (CLS == 2 && !en.two_sweep2)) return;
   ej_class<T, TY, CLS, CP, NT>(en.p, b);
 }
 

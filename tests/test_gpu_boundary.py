@@ -97,6 +97,38 @@ def test_design_from_device_equals_setup_and_refuses_bad_values(B):
         assert np.array_equal(s.field(f), v), f
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_design_density_in_the_one_pass_metal_tiles(B, prec, tol):
+    """Fractional densities (a design region) in step form 3, whose metal
+    tiles without a slab take one pass with their weight of wp^2, beta^2 and D
+    per point: fields, current and spectra equal the two-sweep form's up to
+    rounding."""
+    # the 160^3 design problem (its metal tiles away from the layers are
+    # slab-free), with the pulse moved early
+    w = W.early_pulse(W.config5(0))
+    w.omega = W.spectrum_omegas(6, 2.0, 4.5)
+    w.steps = 400
+    print(f"case design densities 160^3, step form 3 vs 0, {prec}", flush=True)
+    runs = []
+    for form in (0, 3):
+        g = B.Sim(w, precision=prec)
+        g.set_mode(form)
+        g.run(w.steps)
+        runs.append(g)
+    assert runs[1].tile_classes()[2] > 0
+    for f in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "Jx", "Jy", "Jz"):
+        a, b = runs[1].field(f), runs[0].field(f)
+        scale = max(np.linalg.norm(runs[0].field(h)) for h in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz",
+                                                              "Jx", "Jy", "Jz") if h[0] == f[0])
+        d = np.linalg.norm(a - b) / scale
+        print(f"  {f}: {d:.2e}", flush=True)
+        assert d <= tol, f
+    assert np.abs(runs[0].field("Jx")).max() > 0
+    sa, sb = runs[1].spectra(), runs[0].spectra()
+    for k in ("inc", "ext"):
+        assert np.linalg.norm(sa[k] - sb[k]) <= tol * np.linalg.norm(sb[k]), k
+
+
 def test_caller_buffers_are_sized_by_the_library(B):
     import torch
     w = small_design(64)
