@@ -471,7 +471,7 @@ def main():
         sims = [binding.Sim(x, precision="fp32") for x in ws]
         # both step forms of the batch (two sweeps; the tiles without metal
         # in one pass), each warmed up and timed; the faster is reported
-        bt = binding.Batch(sims, tiling=(2, 5, 2))
+        bt = binding.Batch(sims, tiling=(4, 5, 2))
         tforms = {}
         for form in (0, 3):
             bt.set_form(form)

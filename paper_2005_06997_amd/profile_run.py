@@ -13,7 +13,7 @@ adjoint: the 160^3 dimer design problem (FP32, 60^3 design region): the
          objective and its adjoint gradient over --steps steps, checkpoints
          every 500.
 batch:   the 64 instances of the batched workload (spheres and gap dimers,
-         grids 64^3-200^3, FP32, tiling (2, 5, 2)) in step form --form
+         grids 64^3-200^3, FP32, tiling (4, 5, 2)) in step form --form
          (default 3): 64 warm-up steps, then --steps steps.
 Prints one JSON line with the wall time.
 """
@@ -67,7 +67,7 @@ def main(argv=None):
     elif args.workload == "batch":
         form = 3 if args.form is None else args.form
         sims = [binding.Sim(x, precision="fp32") for x in W.config4(seed=0, count=64)]
-        bt = binding.Batch(sims, tiling=(2, 5, 2), form=form)
+        bt = binding.Batch(sims, tiling=(4, 5, 2), form=form)
         bt.run(64)
         bt.synchronize()
         t0 = time.perf_counter()

@@ -23,14 +23,26 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 # kernel families launched once per tile class, the classes of one sweep
 # back to back (or concurrently)
-SWEEPS = ("k_h", "k_ej", "k_step", "k_fplain", "k_fplain_pml", "k_h_batch", "k_ej_batch", "k_fplain_batch")
-# kernels launched inside a sweep's fork/join, counted with that sweep
-MEMBER_OF = {"k_aux_e_batch": "k_ej_batch", "k_tfsf_fix": "k_fplain", "k_tfsf_fix_batch": "k_fplain_batch"}
+SWEEPS = ("k_h", "k_ej", "k_step", "k_fplain", "k_fplain_pml", "k_fplain_metal", "k_h_batch", "k_ej_batch",
+          "k_fplain_batch")
+# kernels launched with a sweep (inside its fork/join, or just before or
+# after its launch on the same stream), counted with that sweep: the sweeps
+# each may belong to, the first when the launch before it is none of them
+MEMBER_OF = {"k_aux_e_batch": ("k_ej_batch",),
+             "k_tfsf_fix": ("k_fplain", "k_fplain_pml", "k_fplain_metal"),
+             "k_nodes": ("k_fplain_metal",),
+             "k_tfsf_fix_batch": ("k_fplain_batch",),
+             "k_nodes_batch": ("k_fplain_batch",)}
 
 
-def family(kernel: str) -> str:
+def family(kernel: str, prev=None) -> str:
+    """The sweep family of a launch; prev: the family of the launch before it
+    (a member kernel joins it when it may)."""
     base = kernel.split("<")[0]
-    return MEMBER_OF.get(base, base)
+    parents = MEMBER_OF.get(base)
+    if not parents:
+        return base
+    return prev if prev in parents else parents[0]
 
 
 def of_type(kernel: str, typ) -> bool:
@@ -64,16 +76,20 @@ def counters(d):
     return out
 
 
-def sweep_spans(trace_dir, typ=None):
+def sweep_spans(trace_dir, typ=None, joined=None):
     """Per sweep family (SWEEPS): number of sweeps and the mean span
     (us) from the first start to the last end of each run of that family's
-    class launches, with the dispatches of the whole run in start order."""
+    class launches, with the dispatches of the whole run in start order.
+    joined (a dict, filled if given): member kernel -> the sweeps it joined."""
     rows = _csv(trace_dir, "kernel_trace.csv")
-    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), family(short(r["Kernel_Name"])))
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(r["Kernel_Name"]))
                 for r in rows if of_type(short(r["Kernel_Name"]), typ))
     out = defaultdict(list)
     cur, lo, hi = None, 0, 0
-    for st, en, base in ev + [(0, 0, None)]:
+    for st, en, name in ev + [(0, 0, None)]:
+        base = None if name is None else family(name, cur)
+        if joined is not None and name is not None and name.split("<")[0] in MEMBER_OF:
+            joined.setdefault(name.split("<")[0], set()).add(base)
         if base != cur:
             if cur in SWEEPS:
                 out[cur].append((hi - lo) / 1e3)
@@ -124,6 +140,8 @@ def main(argv):
               "| kernel | calls | avg us | FETCH MB/dispatch (scaled) | WRITE MB/dispatch (scaled) |"
               " HBM GB/s |", "|---|---|---|---|---|---|"]
     fam = defaultdict(lambda: [0.0, 0.0, 0.0])  # sweep: avg us, fetch MB, write MB (sum of classes)
+    joined = {}
+    spans = sweep_spans(trace, typ, joined)
     for r in stats[:16]:
         k = short(r["Name"])
         avg = float(r["AverageNs"])
@@ -131,18 +149,19 @@ def main(argv):
         wm = sum(w[k]) / len(w[k]) * 1024 * w_scale / 1e6 if k in w else float("nan")
         bw = (fm + wm) * 1e6 / (avg * 1e-9) / 1e9 if avg > 0 else float("nan")
         lines.append(f"| {k} | {r['Calls']} | {avg / 1e3:.1f} | {fm:.1f} | {wm:.1f} | {bw:.0f} |")
-        base = family(k)
-        if base in SWEEPS:
-            e = fam[base]
-            e[0] += avg / 1e3
-            e[1] += fm
-            e[2] += wm
-    spans = sweep_spans(trace, typ)
+        # a member kernel counts once with each of its sweeps in the summary
+        bases = sorted(joined.get(k.split("<")[0], ())) or [family(k)]
+        for base in bases:
+            if base in SWEEPS:
+                e = fam[base]
+                e[0] += avg / 1e3
+                e[1] += fm
+                e[2] += wm
     lines += ["", "Sweeps (one launch per tile class, the classes of a sweep running concurrently).",
               "Span = first start to last end of a sweep's class launches, averaged over the sweeps;",
               "bytes = per-dispatch counters summed over the classes (each runs once per sweep)",
               "and over the kernels launched inside the sweep (" +
-              ", ".join(f"{k} in {v}" for k, v in MEMBER_OF.items()) + "):", "",
+              ", ".join(f"{k} in {' or '.join(v)}" for k, v in MEMBER_OF.items()) + "):", "",
               "| sweep | sweeps | avg span us | FETCH MB | WRITE MB | HBM GB/s over the span |",
               "|---|---|---|---|---|---|"]
     for base, (us, fm, wm) in sorted(fam.items()):

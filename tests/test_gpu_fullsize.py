@@ -279,7 +279,7 @@ def test_design160_gradient_vs_fd_on_32_voxels(B):
 
 @pytest.mark.parametrize("form", [0, 3])
 def test_config4_batch_in_the_benchmark_launch(B, form):
-    """All 64 instances batched as the benchmark runs them (tiling (2, 5, 2),
+    """All 64 instances batched as the benchmark runs them (tiling (4, 5, 2),
     graph chunks of 64, streaming stores chosen by the batch's total size, in
     either step form the benchmark may pick),
     with the pulse moved early so that it reaches every particle within the
@@ -291,7 +291,7 @@ def test_config4_batch_in_the_benchmark_launch(B, form):
     steps = 400
     print(f"case config4 batch form {form}: {sum(w.cells for w in ws):.3e} cells, {steps} steps", flush=True)
     sims = [B.Sim(w, precision="fp32") for w in ws]
-    bt = B.Batch(sims, tiling=(2, 5, 2), form=form)
+    bt = B.Batch(sims, tiling=(4, 5, 2), form=form)
     bt.run(steps)
     bt.synchronize()
     assert all(s.check_finite() for s in sims)
@@ -304,7 +304,7 @@ def test_config4_batch_in_the_benchmark_launch(B, form):
         got = {f: sims[q].field(f) for f in fields}
         spec = sims[q].spectra()
         s = B.Sim(ws[q], precision="fp32")
-        s.set_tiling(2, 5, 2)
+        s.set_tiling(4, 5, 2)
         s.set_mode(form)
         s.run(steps)
         for f in fields:

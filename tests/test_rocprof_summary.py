@@ -29,6 +29,12 @@ def counters(d, rows):
 def test_family_and_type_filter():
     assert R.family("k_aux_e_batch<float>") == "k_ej_batch"
     assert R.family("k_h<float, 2, 0, true>") == "k_h"
+    # the TF/SF launch joins the one-pass sweep launched before it; the node
+    # scalars open the metal class's
+    assert R.family("k_tfsf_fix<float>", "k_fplain_metal") == "k_fplain_metal"
+    assert R.family("k_tfsf_fix<float>", "k_fplain") == "k_fplain"
+    assert R.family("k_tfsf_fix<float>", "k_h") == "k_fplain"
+    assert R.family("k_nodes<float>", "k_fplain_pml") == "k_fplain_metal"
     assert R.of_type("k_h<double, 2, 0, true>", "double")
     assert not R.of_type("k_h<float, 2, 0, true>", "double")
     assert R.of_type("k_dft<double>", "double")
