@@ -285,13 +285,15 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * fused pass for the tiles that meet no CPML slab (classes 0 and 2; class 2
  * stays two-sweep with critical points), then the auxiliary line, then the
  * E/J sweep of the CPML classes, whose H sweep ran alongside the fused
- * tiles; gnor_set_fused(sim, 3) the same order with the tiles without metal
- * (classes 0, x-slab tiles included, and 1) in one pass, by lighter kernels
- * whose wavefronts share halo H through lane shuffles and LDS, each class's
- * launch followed by a small one that adds the TF/SF terms on the faces of
- * the TF box at that class's points, and the metal classes in two sweeps
- * (critical points, a substrate and total-field operation allowed).  All forms give the same fields up to
- * rounding; gnor_gradient always uses the two-sweep form; a batch its own (gnor_batch_set_form).
+ * tiles; gnor_set_fused(sim, 3) the same order with classes 0 (x-slab tiles
+ * included), 1 and, without critical points, 2 in one pass, by lighter
+ * kernels whose wavefronts share halo H through lane shuffles and LDS (class
+ * 2 after a launch that writes the step's node scalars), each class's launch
+ * followed by a small one that adds the TF/SF terms on the faces of the TF
+ * box at that class's points, and class 3 in two sweeps (critical points, a
+ * substrate and total-field operation allowed).  All forms give the same
+ * fields up to rounding; gnor_gradient always uses the two-sweep form; a
+ * batch its own (gnor_batch_set_form).
  * gnor_profile_kernels times each sweep as it runs: with concurrent class
  * launches (the default, see gnor_set_class_streams) a sweep is timed from its
  * fork to its join; with serial class launches, count >= 14 also returns
@@ -300,8 +302,9 @@ gnor_status gnor_profile_kernels(gnor_sim *sim, int64_t nsteps, double *ms, int3
  * fused form.  In fused form ms[0] = ms[1] = 0 and ms[3] holds the fused step
  * (classes + auxiliary line); in hybrid form ms[0] is the first phase (fused
  * tiles and H sweeps) and ms[1] the second (auxiliary line and E/J sweeps);
- * in form 3 with serial class launches ms[5] and ms[6] are the one-pass
- * classes 0 and 1 (each with its TF/SF launch) and ms[9] the auxiliary line.
+ * in form 3 with serial class launches ms[5 + c] is one-pass class c (with
+ * its TF/SF launch, and for class 2 its node scalars) and ms[9] the
+ * auxiliary line.
  * gnor_tile_classes writes the number of tiles of each class of the current
  * tiling to counts[0..3] (valid once the memory is bound).
  * gnor_tile_class_cells writes, per class c, the grid cells its tiles cover
