@@ -493,20 +493,30 @@ gnor::MapParams<T> make_maps(gnor_sim* s, int parity) {
 constexpr unsigned kJoinEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
 
 // c3_side: class 3 after class 1 on the first side stream (the first half of
-// form 3, whose one-pass class-0 launches keep the bound stream busy longest)
-template <class F>
-void enqueue_classes(gnor_sim* s, hipStream_t st, F launch, bool c3_side = false) {
-  if (!s->concurrent) {
-    for (int c = 0; c < gnor::kClasses; ++c) launch(c, st);
+// form 3, whose one-pass class-0 launches keep the bound stream busy longest).
+// active(c): whether launch(c) launches anything; with at most one such
+// class the launches stay on the bound stream, without the fork and join
+// (their events cost about 10 us of idle GPU per join in a replayed graph:
+// form 3's second half has only class 3's E/J sweep).
+template <class F, class A>
+void enqueue_classes(gnor_sim* s, hipStream_t st, F launch, A active, bool c3_side = false) {
+  int n_active = 0;
+  for (int c = 0; c < gnor::kClasses; ++c) n_active += active(c) ? 1 : 0;
+  if (!s->concurrent || n_active <= 1) {
+    for (int c = 0; c < gnor::kClasses; ++c)
+      if (active(c)) launch(c, st);
     return;
   }
   (void)hipEventRecord(s->ev_fork, st);
   for (int q = 0; q < 2; ++q) (void)hipStreamWaitEvent(s->side[q], s->ev_fork, 0);
-  launch(0, st);
-  if (!c3_side) launch(3, st);  // metal + CPML: small grids (usually empty otherwise)
-  launch(1, s->side[0]);
-  if (c3_side) launch(3, s->side[0]);
-  launch(2, s->side[1]);
+  auto go = [&](int c, hipStream_t q) {
+    if (active(c)) launch(c, q);
+  };
+  go(0, st);
+  if (!c3_side) go(3, st);  // metal + CPML: small grids (usually empty otherwise)
+  go(1, s->side[0]);
+  if (c3_side) go(3, s->side[0]);
+  go(2, s->side[1]);
   for (int q = 0; q < 2; ++q) {
     (void)hipEventRecord(s->ev_join[q], s->side[q]);
     (void)hipStreamWaitEvent(st, s->ev_join[q], 0);
@@ -539,16 +549,20 @@ bool hybrid_fused(const gnor_sim* s, int c) {
 template <class T>
 void enqueue_first(gnor_sim* s, const gnor::Params<T>& p, const gnor::AuxParams& a, int mode,
                    hipStream_t st) {
+  // classes with tiles; in the two sweeps class 0's launch also carries the
+  // line's block
+  auto tiles = [&](int c) { return s->tl.cn[c] > 0; };
+  auto swept = [&](int c) { return c == 0 || s->tl.cn[c] > 0; };
   if (mode == 1) {
-    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_step_class<T>(p, a, c, q); });
+    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_step_class<T>(p, a, c, q); }, tiles);
   } else if (mode == 2 || mode == 3) {
     enqueue_classes(s, st, [&](int c, hipStream_t q) {
       if (!hybrid_fused(s, c)) gnor::launch_h_class<T>(p, a, c, q);
       else if (mode == 3) gnor::launch_fplain<T>(p, a, c, s->tf_shell[c], q);
       else gnor::launch_step_class<T>(p, a, c, q);
-    }, mode == 3);
+    }, tiles, mode == 3);
   } else {
-    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_h_class<T>(p, a, c, q); });
+    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_h_class<T>(p, a, c, q); }, swept);
   }
 }
 // Second half: the E/J sweep (mode 0), the auxiliary line (mode 1), or the
@@ -560,11 +574,11 @@ void enqueue_second(gnor_sim* s, const gnor::Params<T>& p, const gnor::AuxParams
     gnor::launch_aux(a, sub, st);
   } else if (mode == 2 || mode == 3) {
     gnor::launch_aux(a, sub, st);
-    enqueue_classes(s, st, [&](int c, hipStream_t q) {
-      if (!hybrid_fused(s, c)) gnor::launch_ej_class<T>(p, a, sub, c, q);
-    });
+    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_ej_class<T>(p, a, sub, c, q); },
+                    [&](int c) { return !hybrid_fused(s, c) && s->tl.cn[c] > 0; });
   } else {
-    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_ej_class<T>(p, a, sub, c, q); });
+    enqueue_classes(s, st, [&](int c, hipStream_t q) { gnor::launch_ej_class<T>(p, a, sub, c, q); },
+                    [&](int c) { return c == 0 || s->tl.cn[c] > 0; });
   }
 }
 
