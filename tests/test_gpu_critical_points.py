@@ -107,23 +107,30 @@ def test_critical_points_in_metal_cpml_class(B, mode):
     compare(g, o, w, 1e-10, 1e-10)
 
 
-def test_batch_with_and_without_poles_bitwise(B):
-    ws = [W.early_pulse(w) for w in W.config4(seed=2, count=3)]
+@pytest.mark.parametrize("form", [0, 3])
+def test_batch_with_and_without_poles_bitwise(B, form):
+    """Instances of 128^3 - 200^3, the 192^3 gap dimer with critical points.
+    In step form 3 that instance keeps its metal tiles in the two sweeps
+    while the 200^3 one takes them in one pass, as each would alone."""
+    ws = [W.early_pulse(w) for w in W.config4(seed=1, count=3) + W.config4(seed=0, count=4)[3:]]
     ws[1] = W.with_critical_points(ws[1])
     for q, w in enumerate(ws):
         w.omega = W.spectrum_omegas(10 + 2 * q)
         w.flux = q == 1
     steps = 97
-    say(f"case batch with critical points: sizes {[w.nx for w in ws]}, poles {[len(w.cp) for w in ws]}")
+    say(f"case batch with critical points, form {form}: sizes {[w.nx for w in ws]}, "
+        f"poles {[len(w.cp) for w in ws]}")
     solo = []
     for w in ws:
         s = B.Sim(w, precision="fp32")
         s.set_tiling(2, 8, 0)
+        s.set_mode(form)
         s.run(steps)
         solo.append(({f: s.field(f) for f in fields_of(w)}, s.spectra()))
         s.close()
     sims = [B.Sim(w, precision="fp32") for w in ws]
-    bt = B.Batch(sims, tiling=(2, 8, 0))
+    assert sims[1].tile_classes()[2] > 0 and sims[3].tile_classes()[2] > 0
+    bt = B.Batch(sims, tiling=(2, 8, 0), form=form)
     bt.run(steps)
     bt.synchronize()
     for (fields, spec), s in zip(solo, sims):
