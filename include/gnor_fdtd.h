@@ -428,9 +428,11 @@ gnor_status gnor_batch_set_graph_chunk(gnor_batch *batch, int32_t steps);
 /* Step form of a batch (Sec. III: f1 and f2 of every instance, one launch
  * per phase over all instances): 0 two sweeps (the default), 3 the tiles
  * without metal in one pass, the metal tiles in two sweeps, as
- * gnor_set_fused(sim, 3) for one simulation.  Results equal single runs of
- * the same form bit for bit.  Waits for the batch's queued steps when the
- * form changes.  INVALID_ARG unless form is 0 or 3. */
+ * gnor_set_fused(sim, 3) for one simulation.  The instances take the
+ * batch's form (gnor_batch_create sets them to form 0): their tile lists
+ * follow it.  Results equal single runs of the same form bit for bit.  Waits
+ * for the batch's queued steps when the form changes.  INVALID_ARG unless
+ * form is 0 or 3. */
 gnor_status gnor_batch_set_form(gnor_batch *batch, int32_t form);
 const char *gnor_batch_last_error(const gnor_batch *batch);
 void gnor_batch_destroy(gnor_batch *batch);

@@ -465,13 +465,18 @@ class Batch:
             raise GnorError(st, "gnor_batch_create rejected the instances")
         self.h = h
         self._check(L.gnor_batch_set_graph_chunk(h, int(graph_chunk)))
+        for s in self.sims:
+            s.mode = 0  # the library sets the instances to the batch's form
         self.set_form(form)
 
     def set_form(self, form: int):
-        """Step form of the batch: 0 two sweeps, 3 the tiles without metal in
-        one pass (as Sim.set_mode)."""
+        """Step form of the batch and of its instances: 0 two sweeps, 3 the
+        tiles in one pass but those with metal and a y or z slab (as
+        Sim.set_mode)."""
         self._check(self.L.gnor_batch_set_form(self.h, int(form)))
         self.form = int(form)
+        for s in self.sims:
+            s.mode = int(form)
 
     def _check(self, st: int):
         if st:

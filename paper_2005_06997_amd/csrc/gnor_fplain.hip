@@ -486,16 +486,21 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
       // sum of J_x for the extinction transform
       double jsum = 0.0;
       if (mb) {
+        // total-field operation: a metal point in an absorbing layer (here
+        // the x slab) follows the local Drude model (no nonlocal force)
+        const bool local = XS && p.lra_pml && sxe >= 0;
         T cS = p.cS, c3 = p.c3, c1 = p.c1, cJ = p.cJ, cG = p.cG, d3 = p.d3, r = T(1);
         if (p.rho) {
           r = mt.r;
           d3 = r * p.d3;
+          // the two-sweep kernel's divisor without critical points (its
+          // pole term a literal zero), so that the forms round alike
           const T inv = T(1) / (p.eps_inf + d3 + T(0));
           cS = p.S * inv; c3 = T(3) * d3 * inv; c1 = d3 * inv; cJ = p.D2 * inv; cG = inv;
         }
         const T ag = p.agam;
         if (mb & 1u) {
-          const T G = r * (mt.qa[0] - mt.q);
+          const T G = local ? T(0) : r * (mt.qa[0] - mt.q);
           const T en = ex0 + (cS * cxv - c3 * ex0 - c1 * mt.em[0] + cJ * mt.j[0] - cG * G);
           const T jn = mt.j[0] + (d3 * (mt.em[0] + T(2) * ex0 + en) - ag * mt.j[0] + G);
           p.Jo[0][l] = jn;
@@ -503,13 +508,13 @@ __device__ __forceinline__ void fplain_tile(const Params<T>& p, const Tile tile,
           enx = en;
         }
         if (mb & 2u) {
-          const T G = r * (mt.qa[1] - mt.q);
+          const T G = local ? T(0) : r * (mt.qa[1] - mt.q);
           const T en = ey0 + (cS * cyv - c3 * ey0 - c1 * mt.em[1] + cJ * mt.j[1] - cG * G);
           p.Jo[1][l] = mt.j[1] + (d3 * (mt.em[1] + T(2) * ey0 + en) - ag * mt.j[1] + G);
           eny = en;
         }
         if (mb & 4u) {
-          const T G = r * (mt.qa[2] - mt.q);
+          const T G = local ? T(0) : r * (mt.qa[2] - mt.q);
           const T en = ez + (cS * czv - c3 * ez - c1 * mt.em[2] + cJ * mt.j[2] - cG * G);
           p.Jo[2][l] = mt.j[2] + (d3 * (mt.em[2] + T(2) * ez + en) - ag * mt.j[2] + G);
           enz = en;
@@ -563,14 +568,17 @@ __global__ void __launch_bounds__(kBX* TY) k_fplain_pml(Params<T> p) {
   fplain_tile<T, TY, NT, true, true, false>(p, tile, sh);
 }
 
-// Class 2 (metal tiles without a slab) in one pass, without critical points;
-// its node scalars come from k_nodes, launched before it.
+// Class 2 (metal tiles that meet no slab but maybe an x slab) in one pass,
+// without critical points; its node scalars come from k_nodes, launched
+// before it.
 template <class T, int TY, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_fplain_metal(Params<T> p) {
   __shared__ HRows<T, TY> sh;
   const Tile tile = decode_tile(p.tl, p.tiles, 2, blockIdx.x);
   if (!tile.ok) return;
-  fplain_tile<T, TY, NT, false, false, true>(p, tile, sh);
+  const int np = p.cp[0].np, x0 = tile.bx * kBX;
+  if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true, false, true>(p, tile, sh);
+  else fplain_tile<T, TY, NT, false, false, true>(p, tile, sh);
 }
 
 // Node scalars of every node of the metal sub-grid that lies on a metal edge
@@ -729,7 +737,9 @@ __global__ void __launch_bounds__(kBX* TY) k_fplain_batch(const BatchEntry<T>* _
   if (CLS == 1) {
     fplain_tile<T, TY, NT, true, true, false>(p, tile, sh);
   } else if (CLS == 2) {
-    fplain_tile<T, TY, NT, false, false, true>(p, tile, sh);
+    const int np = p.cp[0].np, x0 = tile.bx * kBX;
+    if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true, false, true>(p, tile, sh);
+    else fplain_tile<T, TY, NT, false, false, true>(p, tile, sh);
   } else {
     const int np = p.cp[0].np, x0 = tile.bx * kBX;
     if (np > 0 && (x0 - 1 < np || x0 + kBX + 1 > p.nx - 1 - np)) fplain_tile<T, TY, NT, true, false, false>(p, tile, sh);

@@ -401,11 +401,13 @@ Tiling make_tiling(int nx, int ny, int nz, int ty, int kz, int xcd);
 // the class lists back to back.  merge_x: tiles without metal that meet only
 // an x slab go to class 0, whose two-sweep and one-pass (form 3) kernels
 // update the x-slab psi of such tiles (the fused kernels of forms 1 and 2
-// have no CPML in class 0: false for them).
+// have no CPML in class 0: false for them).  merge_x_metal: likewise metal
+// tiles that meet only an x slab go to class 2 (form 3 without critical
+// points, whose one-pass metal kernel carries the x-slab psi).
 // Each class lists its tiles in natural order (x fastest, then y, then z).
 // tile_class receives the class of every tile (tile order x, y, z).
 void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
-                    std::vector<int>& list, bool merge_x,
+                    std::vector<int>& list, bool merge_x, bool merge_x_metal,
                     std::vector<uint8_t>& tile_class);
 
 }  // namespace gnor

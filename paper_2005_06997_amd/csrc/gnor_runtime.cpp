@@ -664,6 +664,10 @@ gnor_status upload_rho(gnor_sim* s) {
 // whose class-0 kernels carry the x-slab CPML (the two-sweep plain kernels and
 // the one-pass plain kernel of form 3), no for the fused kernel of forms 1, 2.
 bool merge_x_slabs(int mode) { return mode == 0 || mode == 3; }
+// Do the metal tiles that meet only an x slab join class 2?  Yes where that
+// class takes the one-pass metal kernel, which carries the x-slab CPML: form
+// 3 without critical points.
+bool merge_x_metal(const gnor_sim* s, int mode) { return mode == 3 && s->mat.ncp == 0; }
 
 // Tile classes of the current tiling and step form; uploaded when the memory
 // is bound (after the stream's queued steps, which read the old lists).
@@ -685,9 +689,10 @@ gnor_status plan_tiles(gnor_sim* s) {
       s->rowx[2 * r + 1] = hi;
     }
   }
-  // x-slab tiles join the plain class in forms 0 and 3 (merge_x_slabs)
+  // x-slab tiles join the plain class in forms 0 and 3 (merge_x_slabs), and
+  // the metal class in form 3 without critical points (merge_x_metal)
   gnor::classify_tiles(s->tl, g.nx, g.ny, g.nz, g.npml, s->any_metal ? s->rowx.data() : nullptr,
-                       s->tile_list, merge_x_slabs(s->mode), s->tile_class);
+                       s->tile_list, merge_x_slabs(s->mode), merge_x_metal(s, s->mode), s->tile_class);
   // Which classes hold points of the shell of the TF box ([lo-1, hi+1]
   // without [lo+1, hi-1]), where the one-pass kernels need their TF/SF
   // launch: a tile does iff it meets the widened box and does not lie inside
@@ -722,7 +727,8 @@ gnor_status plan_tiles(gnor_sim* s) {
 // Change the step form; the class lists depend on it (see plan_tiles).
 gnor_status set_mode(gnor_sim* s, int mode) {
   if (mode == s->mode) return GNOR_OK;
-  const bool replan = merge_x_slabs(mode) != merge_x_slabs(s->mode);
+  const bool replan = merge_x_slabs(mode) != merge_x_slabs(s->mode) ||
+                      merge_x_metal(s, mode) != merge_x_metal(s, s->mode);
   s->mode = mode;
   drop_graph(s);
   return replan ? plan_tiles(s) : GNOR_OK;
@@ -2075,9 +2081,14 @@ gnor_status batch_create_impl(int32_t n, gnor_sim* const* sims, void* stream, vo
       return GNOR_E_DEVICE;
     }
   }
-  // the instances' own queued work must be complete before the batch runs
-  for (gnor_sim* s : b->sims)
+  // the instances' own queued work must be complete before the batch runs;
+  // their tile lists are those of the batch's step form (form 0 at first:
+  // in form 3 metal tiles that meet only an x slab are listed with the metal
+  // class, whose two-sweep kernels lack the x-slab terms)
+  for (gnor_sim* s : b->sims) {
     if (hipStreamSynchronize(s->stream) != hipSuccess) { gnor_batch_destroy(b); return GNOR_E_DEVICE; }
+    if (set_mode(s, 0) != GNOR_OK) { gnor_batch_destroy(b); return GNOR_E_DEVICE; }
+  }
   const gnor_status st = b->fp32 ? batch_tables<float>(b) : batch_tables<double>(b);
   if (st != GNOR_OK) { gnor_batch_destroy(b); return st; }
   *out = b;
@@ -2145,6 +2156,9 @@ gnor_status gnor_batch_set_form(gnor_batch* b, int32_t form) {
     // and the parameter tables, which name the form's launches per instance)
     BHIPCHECK(b, hipStreamSynchronize(b->stream));
     b->form = form;
+    // the instances take the form too (their tile lists follow it)
+    for (gnor_sim* s : b->sims)
+      if (set_mode(s, form) != GNOR_OK) return bfail(b, GNOR_E_DEVICE, "re-planning an instance's tiles failed");
     const gnor_status st = b->fp32 ? batch_tables<float>(b) : batch_tables<double>(b);
     if (st != GNOR_OK) return st;
     if (b->graph) (void)hipGraphExecDestroy(b->graph);

@@ -583,7 +583,7 @@ static bool tile_meets_metal_host(const Tiling& t, int tile, int nx, int ny, int
 }
 
 void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
-                    std::vector<int>& list, bool merge_x,
+                    std::vector<int>& list, bool merge_x, bool merge_x_metal,
                     std::vector<uint8_t>& tile_class) {
   const int T = t.nbx * t.nby * t.nbz;
   std::vector<int> cls[kClasses];
@@ -596,7 +596,7 @@ void classify_tiles(Tiling& t, int nx, int ny, int nz, int np, const int* rowx,
     const bool metal = tile_meets_metal_host(t, tile, nx, ny, nz, rowx);
     const bool px = slab(bx * kBX - 1, bx * kBX + kBX + 1, nx);
     const bool pyz = slab(by * t.ty - 1, by * t.ty + t.ty + 1, ny) || slab(z0 - 1, z1 + 1, nz);
-    const int c = metal ? (px || pyz ? 3 : 2) : (pyz || (px && !merge_x) ? 1 : 0);
+    const int c = metal ? (pyz || (px && !merge_x_metal) ? 3 : 2) : (pyz || (px && !merge_x) ? 1 : 0);
     tile_class[tile] = (uint8_t)c;
     cls[c].push_back(tile);
   }

@@ -168,7 +168,8 @@ def test_metal_across_x_tiles_vs_oracle(B, mode):
     g = B.Sim(w, precision="fp64")
     g.set_mode(mode)
     g.set_tiling(4, 16, 2)
-    assert g.tile_classes()[2] > 0 and g.tile_classes()[3] > 0
+    # (in form 3 the metal tiles that meet only the x slab join class 2)
+    assert g.tile_classes()[2] > 0 and (mode == 3 or g.tile_classes()[3] > 0)
     g.run(w.steps)
     o = oracle_run(w, w.steps)
     compare(g, o, 1e-10, 1e-10)
@@ -194,7 +195,9 @@ def test_hybrid_and_two_sweep_forms_agree(B, prec, mode):
         g.set_mode(m)
         g.run(w.steps)
         runs.append(g)
-    assert min(runs[1].tile_classes()) > 0
+    # every class occurs (in form 3 the metal tiles that meet only the x slab
+    # join class 2, and class 3 may be empty)
+    assert min(runs[1].tile_classes()[:3 if mode == 3 else 4]) > 0
     agree = 1e-12 if prec == "fp64" else 1e-5
     fa = {f: runs[0].field(f) for f in FIELDS}
     fb = {f: runs[1].field(f) for f in FIELDS}
