@@ -33,12 +33,19 @@ MEMBER_OF = {"k_aux_e_batch": ("k_ej_batch",),
              "k_nodes": ("k_fplain_metal",),
              "k_tfsf_fix_batch": ("k_fplain_batch",),
              "k_nodes_batch": ("k_fplain_batch",)}
+# sweeps that run beside another family's launches in one phase of a step:
+# such a launch joins that family when the launch before it is one of them
+# (the batched H sweep of the metal tiles next to the batched one-pass
+# launches), and is a sweep of its own otherwise (the two-sweep form)
+BESIDE = {"k_h_batch": ("k_fplain_batch",)}
 
 
 def family(kernel: str, prev=None) -> str:
     """The sweep family of a launch; prev: the family of the launch before it
     (a member kernel joins it when it may)."""
     base = kernel.split("<")[0]
+    if base in BESIDE:
+        return prev if prev in BESIDE[base] else base
     parents = MEMBER_OF.get(base)
     if not parents:
         return base
@@ -88,7 +95,8 @@ def sweep_spans(trace_dir, typ=None, joined=None):
     cur, lo, hi = None, 0, 0
     for st, en, name in ev + [(0, 0, None)]:
         base = None if name is None else family(name, cur)
-        if joined is not None and name is not None and name.split("<")[0] in MEMBER_OF:
+        if joined is not None and name is not None and (name.split("<")[0] in MEMBER_OF or
+                                                         name.split("<")[0] in BESIDE):
             joined.setdefault(name.split("<")[0], set()).add(base)
         if base != cur:
             if cur in SWEEPS:
@@ -161,7 +169,9 @@ def main(argv):
               "Span = first start to last end of a sweep's class launches, averaged over the sweeps;",
               "bytes = per-dispatch counters summed over the classes (each runs once per sweep)",
               "and over the kernels launched inside the sweep (" +
-              ", ".join(f"{k} in {' or '.join(v)}" for k, v in MEMBER_OF.items()) + "):", "",
+              ", ".join(f"{k} in {' or '.join(v)}" for k, v in MEMBER_OF.items()) + "; " +
+              ", ".join(f"{k} in {' or '.join(v)} when it starts inside it" for k, v in BESIDE.items()) +
+              "):", "",
               "| sweep | sweeps | avg span us | FETCH MB | WRITE MB | HBM GB/s over the span |",
               "|---|---|---|---|---|---|"]
     for base, (us, fm, wm) in sorted(fam.items()):

@@ -69,6 +69,40 @@ def test_sweep_spans_group_concurrent_classes(tmp_path):
     assert no_filter["k_h"][0] == 1  # the FP64 launch forms a sweep of its own
 
 
+def test_batched_metal_h_sweep_joins_the_one_pass_phase(tmp_path):
+    """Form 3 of a batch: the one-pass launches of classes 0-2 (with the node
+    scalars before class 2) and the H sweep of the metal tiles beside them,
+    then the TF/SF launch, then the metal E/J sweep.  Two steps: each phase
+    is one sweep (0..700 and 1000..1700, the TF/SF launch included: 0.7 us),
+    the H launch counted inside it; on its own (no one-pass launch before
+    it) the H launch is a sweep of its own."""
+    assert R.family("k_h_batch<float, 4, 3, true>", "k_fplain_batch") == "k_fplain_batch"
+    assert R.family("k_h_batch<float, 4, 3, true>", "k_ej_batch") == "k_h_batch"
+    d = str(tmp_path / "t")
+    ns = "void gnor::(anonymous namespace)::"
+    step = [
+        (ns + "k_fplain_batch<float, 4, true, 0>(...)", 0, 600),
+        (ns + "k_fplain_batch<float, 4, true, 1>(...)", 10, 650),
+        (ns + "k_nodes_batch<float>(...)", 20, 100),
+        (ns + "k_h_batch<float, 4, 3, true>(...)", 30, 60),
+        (ns + "k_fplain_batch<float, 4, true, 2>(...)", 110, 690),
+        (ns + "k_tfsf_fix_batch<float>(...)", 690, 700),
+        (ns + "k_aux_batch<float>(...)", 705, 710),
+        (ns + "k_ej_batch<float, 4, 3, false, true>(...)", 715, 720),
+    ]
+    ev = step + [(k, a + 1000, b + 1000) for k, a, b in step]
+    trace(d, ev)
+    joined = {}
+    spans = R.sweep_spans(d, "float", joined)
+    assert spans["k_fplain_batch"][0] == 2 and abs(spans["k_fplain_batch"][1] - 0.7) < 1e-12
+    assert "k_h_batch" not in spans and joined["k_h_batch"] == {"k_fplain_batch"}
+    assert spans["k_ej_batch"][0] == 2
+    alone = str(tmp_path / "a")
+    trace(alone, [(ns + "k_h_batch<float, 4, 0, true>(...)", 0, 300),
+                  (ns + "k_ej_batch<float, 4, 0, false, true>(...)", 400, 800)])
+    assert R.sweep_spans(alone, "float")["k_h_batch"][0] == 1
+
+
 def test_summary_scales_counters_and_sums_classes(tmp_path):
     """A copy of 2 GiB reads FETCH_SIZE 2 GiB / 2 and WRITE_SIZE 2 GiB in
     KiB, so the scales are 2 and 1.  The H sweep's two classes read 100 and
