@@ -208,6 +208,13 @@ struct FluxParams {
   int nseg;
   FluxSeg seg[kMaxSeg];
   int nx, ny;
+  // staging order of the sampling launch: first one thread per (y, z) row of
+  // the union of the x-normal faces (rows [xj0, xj0 + xnj) x [xk0, ...),
+  // xnrow rows in all), which stages every x-normal sample on its row (a
+  // gather of one value per row, whichever thread takes it); then the nrest
+  // pairs of the faces whose normal is y or z, in segment order
+  int xj0, xnj, xk0, xnrow;
+  int nrest;
   double* stage;         // [kFluxSlots][nsamp]
   double* acc_re;        // [nf][nsamp]
   double* acc_im;

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -449,6 +450,15 @@ gnor::FluxParams make_flux(gnor_sim* s) {
   f.nseg = (int)s->fseg.size();
   for (int q = 0; q < f.nseg; ++q) f.seg[q] = s->fseg[q];
   f.nx = s->g.nx; f.ny = s->g.ny;
+  // the rows (y, z) that the x-normal faces cover, and the other faces' pairs
+  int j0 = INT_MAX, j1 = INT_MIN, k0 = INT_MAX, k1 = INT_MIN;
+  for (int q = 0; q < f.nseg; ++q) {
+    const gnor::FluxSeg& g = f.seg[q];
+    if (g.a != 0) { f.nrest += g.count; continue; }  // x-normal faces run y inside, z outside
+    j0 = std::min(j0, g.in_lo); j1 = std::max(j1, g.in_lo + g.n_in);
+    k0 = std::min(k0, g.out_lo); k1 = std::max(k1, g.out_lo + g.count / g.n_in);
+  }
+  if (j0 < j1) { f.xj0 = j0; f.xnj = j1 - j0; f.xk0 = k0; f.xnrow = (j1 - j0) * (k1 - k0); }
   f.stage = ptr<double>(s, s->L.fstage);
   f.acc_re = ptr<double>(s, s->L.facc);
   f.acc_im = f.acc_re + (size_t)s->mon.nfreq * s->nsamp;

@@ -5,7 +5,8 @@
 //                  (n+1/2) dt) and of the incident line E_inc (stamped
 //                  (n+1) dt), with the step's phase table from the E sweep;
 //                  blocks [nz, ...): staging of the flux-box samples (E on
-//                  the face, H averaged across it)
+//                  the face, H averaged across it), the x-normal faces one
+//                  thread per grid row)
 //   k_flux_phase   phase table of one accumulation window (matrix-core
 //                  fragments)
 //   k_flux_acc     acc[m][s] += sum_b wdt e^{i w_m t_b} stage[b][s]: the
@@ -59,25 +60,46 @@ __device__ __forceinline__ void dft_block(const DftParams& d, const FluxParams& 
     }
     return;
   }
-  // flux staging: pair q -> (segment, face point)
-  const int q = (blk - d.nz) * 256 + threadIdx.x;
-  if (q >= f.npairs) return;
+  // flux staging: E^{n+1} on the face, H^{n+1/2} averaged across it
+  const int u = (blk - d.nz) * 256 + threadIdx.x;
+  const size_t sy = f.nx, sz = (size_t)f.nx * f.ny;
+  double* stage = f.stage + (size_t)(n % kFluxSlots) * f.nsamp;
+  if (u < f.xnrow) {
+    // one (y, z) row: the samples of every x-normal face on it (inner index
+    // y, outer z; the H neighbour across the face is the row's previous cell)
+    const int j = f.xj0 + u % f.xnj, k = f.xk0 + u / f.xnj;
+    for (int sgi = 0; sgi < f.nseg; ++sgi) {
+      const FluxSeg& g = f.seg[sgi];
+      if (g.a != 0) continue;
+      const int ri = j - g.in_lo, ro = k - g.out_lo;
+      if (ri < 0 || ri >= g.n_in || ro < 0 || ro >= g.count / g.n_in) continue;
+      const int q = g.first + ro * g.n_in + ri;
+      const size_t idx = (size_t)k * sz + (size_t)j * sy + g.p;
+      stage[q] = (double)p.O[g.ecomp][idx];
+      stage[f.npairs + q] = 0.5 * ((double)p.H[g.hcomp][idx - 1] + (double)p.H[g.hcomp][idx]);
+    }
+    return;
+  }
+  // the r-th pair of the faces whose normal is y or z -> (segment, face point)
+  int r = u - f.xnrow;
+  if (r >= f.nrest) return;
   int sgi = 0;
-  while (sgi + 1 < f.nseg && q >= f.seg[sgi + 1].first) ++sgi;
+  for (; sgi < f.nseg; ++sgi) {
+    if (f.seg[sgi].a == 0) continue;
+    if (r < f.seg[sgi].count) break;
+    r -= f.seg[sgi].count;
+  }
+  if (sgi == f.nseg) return;
   const FluxSeg& g = f.seg[sgi];
-  const int r = q - g.first;
   int c[3];
   c[g.a] = g.p;
   c[g.in_axis] = g.in_lo + r % g.n_in;
   c[g.out_axis] = g.out_lo + r / g.n_in;
-  const size_t sy = f.nx, sz = (size_t)f.nx * f.ny;
   const size_t idx = (size_t)c[2] * sz + (size_t)c[1] * sy + c[0];
-  const size_t st = g.a == 0 ? 1 : (g.a == 1 ? sy : sz);
-  const int slot = (int)(n % kFluxSlots);
-  const double e = (double)p.O[g.ecomp][idx];  // E^{n+1}
-  const double h = 0.5 * ((double)p.H[g.hcomp][idx - st] + (double)p.H[g.hcomp][idx]);  // H^{n+1/2}
-  f.stage[(size_t)slot * f.nsamp + q] = e;
-  f.stage[(size_t)slot * f.nsamp + f.npairs + q] = h;
+  const size_t st = g.a == 1 ? sy : sz;
+  const int q = g.first + r;
+  stage[q] = (double)p.O[g.ecomp][idx];
+  stage[f.npairs + q] = 0.5 * ((double)p.H[g.hcomp][idx - st] + (double)p.H[g.hcomp][idx]);
 }
 
 template <class T>
@@ -347,7 +369,7 @@ __global__ void __launch_bounds__(256) k_nonfinite(const T* a, size_t n, int* fl
 
 }  // namespace
 
-int dft_blocks(const DftParams& d, const FluxParams& f) { return d.nz + (f.npairs + 255) / 256; }
+int dft_blocks(const DftParams& d, const FluxParams& f) { return d.nz + (f.xnrow + f.nrest + 255) / 256; }
 
 template <class T>
 void launch_dft_stage(const DftParams& d, const FluxParams& f, const Params<T>& p, int sub,
