@@ -216,8 +216,7 @@ struct FluxParams {
   int xj0, xnj, xk0, xnrow;
   int nrest;
   double* stage;         // [kFluxSlots][nsamp]
-  double* acc_re;        // [nf][nsamp]
-  double* acc_im;
+  double* acc;           // [nsamp][2 nf]: sample s, frequency m: re at 2m, im at 2m + 1
   const double* omega;
   double* ptab;          // window phase factors as matrix fragments (flux_ptab_doubles)
   double dt, wdt;
@@ -372,8 +371,13 @@ void launch_flux_accumulate(const FluxParams& f, int* lo_ptr, int sub, hipStream
 size_t flux_ptab_doubles(int nf);
 template <class T>
 void launch_maps(const MapParams<T>& m, int sub, hipStream_t s);
-void launch_flux_reduce(const double* acc_re, const double* acc_im, const double* pw, int npairs,
-                        int npairs_box0, int nf, double* out, hipStream_t s);
+// pair chunks of the flux reduction (each within one box) and their partial sums
+constexpr int kFluxChunk = 512;
+inline int flux_reduce_chunks(int npairs, int npairs_box0) {
+  return (npairs_box0 + kFluxChunk - 1) / kFluxChunk + (npairs - npairs_box0 + kFluxChunk - 1) / kFluxChunk;
+}
+void launch_flux_reduce(const double* acc, const double* pw, int npairs, int npairs_box0, int nf,
+                        double* part, double* out, hipStream_t s);
 template <class T>
 void launch_nonfinite(const T* a, size_t n, int* flag, hipStream_t s);
 

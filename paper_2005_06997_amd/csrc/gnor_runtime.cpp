@@ -68,7 +68,7 @@ struct Layout {
   size_t cpP[gnor::kMaxCP][3] = {{0}}, cpQ[gnor::kMaxCP][3] = {{0}};  // critical points
   size_t psiE[3][2] = {{0}}, psiH[2][3][2] = {{{0}}};
   size_t aux = 0, phase = 0, jpart = 0, dft = 0, fstage = 0, facc = 0, ptab = 0, step = 0,
-         flux_lo = 0, flag = 0, fsum = 0, maps = 0, map_inc = 0;
+         flux_lo = 0, flag = 0, fsum = 0, fpart = 0, maps = 0, map_inc = 0;
   size_t state_end = 0;
 };
 
@@ -287,6 +287,7 @@ void plan_layout(gnor_sim* s) {
   L.facc = P.take((size_t)2 * std::max(1, s->mon.nfreq) * s->nsamp * 8 + 8);
   L.ptab = P.take(gnor::flux_ptab_doubles(std::max(1, s->mon.nfreq)) * 8);
   L.fsum = P.take((size_t)2 * std::max(1, s->mon.nfreq) * 8);
+  L.fpart = P.take((size_t)gnor::flux_reduce_chunks(s->npairs, s->npairs_box0) * std::max(1, s->mon.nfreq) * 8 + 8);
   L.maps = P.take((size_t)8 * s->maps.nmap * map_plane(s) * 8 + 8);
   L.map_inc = P.take((size_t)2 * std::max(1, s->maps.nmap) * 8);
   L.step = P.take(8);
@@ -460,8 +461,7 @@ gnor::FluxParams make_flux(gnor_sim* s) {
   }
   if (j0 < j1) { f.xj0 = j0; f.xnj = j1 - j0; f.xk0 = k0; f.xnrow = (j1 - j0) * (k1 - k0); }
   f.stage = ptr<double>(s, s->L.fstage);
-  f.acc_re = ptr<double>(s, s->L.facc);
-  f.acc_im = f.acc_re + (size_t)s->mon.nfreq * s->nsamp;
+  f.acc = ptr<double>(s, s->L.facc);
   f.omega = ptr<double>(s, s->L.omega);
   f.ptab = ptr<double>(s, s->L.ptab);
   f.dt = s->dt; f.wdt = s->dt;
@@ -1331,9 +1331,9 @@ gnor_status gnor_get_spectra(gnor_sim* s, double* inc, double* ext, double* absn
     // fold the partially filled staging window into the accumulators
     st = gnor_flush_spectra(s);
     if (st != GNOR_OK) return st;
-    gnor::launch_flux_reduce(ptr<double>(s, s->L.facc), ptr<double>(s, s->L.facc) + (size_t)nf * s->nsamp,
-                       ptr<double>(s, s->L.fpw), s->npairs, s->npairs_box0, nf,
-                       ptr<double>(s, s->L.fsum), s->stream);
+    gnor::launch_flux_reduce(ptr<double>(s, s->L.facc), ptr<double>(s, s->L.fpw), s->npairs,
+                             s->npairs_box0, nf, ptr<double>(s, s->L.fpart), ptr<double>(s, s->L.fsum),
+                             s->stream);
     HIPCHECK(s, hipGetLastError());
     HIPCHECK(s, hipStreamSynchronize(s->stream));
     HIPCHECK(s, hipMemcpy(fs.data(), s->dev + s->L.fsum, fs.size() * 8, hipMemcpyDeviceToHost));

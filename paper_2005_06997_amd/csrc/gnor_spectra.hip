@@ -9,11 +9,11 @@
 //                  thread per grid row)
 //   k_flux_phase   phase table of one accumulation window (matrix-core
 //                  fragments)
-//   k_flux_acc     acc[m][s] += sum_b wdt e^{i w_m t_b} stage[b][s]: the
+//   k_flux_acc     acc[s][m] += sum_b wdt e^{i w_m t_b} stage[b][s]: the
 //                  staged window folded into the flux-box transforms, on the
-//                  FP64 matrix cores
-//   k_flux_reduce  sum over sample pairs of w_p Re(E conj(H)) per box and
-//                  frequency (fixed order)
+//                  FP64 matrix cores (each sample's transforms contiguous)
+//   k_flux_reduce  sums of w_p Re(E conj(H)) over chunks of sample pairs,
+//   k_flux_sum     then over a box's chunks, per frequency (fixed order)
 //   k_maps         near-field and density maps on one grid plane: running
 //                  transforms of E (stamped (n+1) dt) and of n - n0 from the
 //                  step's node scalars Phi~_P^n (stamped n dt)
@@ -265,17 +265,33 @@ __global__ void __launch_bounds__(256) k_flux_acc(FluxParams f, const int* lo_pt
 #pragma unroll
     for (int j = 0; j < G; ++j) bq[j] = bn[j];
   }
+  // acc[s][R] (R = 2m + c): the wavefront's 16 samples are 16 consecutive
+  // runs of 2 nf doubles, and the four elements q of a tile t fill its
+  // 16-row slice of each
+  // run in turn.  Tiles go in groups of 4 whose 16 loads are all issued
+  // before the group's stores (rows past 2 nf read the run's last element
+  // and store nothing): 4 round trips per lane instead of one guarded round
+  // trip per element.
+  double* const dst = f.acc + s * (2 * (size_t)f.nf);
+  const int rlast = 2 * f.nf - 1;
+  constexpr int TG = 4;
 #pragma unroll
-  for (int t = 0; t < kFluxTW; ++t) {
+  for (int tg = 0; tg < kFluxTW; tg += TG) {
+    double old[TG][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int R = 16 * (t0 + t) + 4 * q + (l >> 4);
-      const int m = R >> 1;
-      if (colok && m < f.nf) {
-        double* dst = ((R & 1) ? f.acc_im : f.acc_re) + (size_t)m * ns + s;
-        __builtin_nontemporal_store(__builtin_nontemporal_load(dst) + acc[t][q], dst);
+    for (int u = 0; u < TG; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (tg + u < kFluxTW) old[u][q] = dst[min(16 * (t0 + tg + u) + 4 * q + (l >> 4), rlast)];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < TG; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int R = 16 * (t0 + tg + u) + 4 * q + (l >> 4);
+        if (tg + u < kFluxTW && colok && R <= rlast) dst[R] = old[u][q] + acc[tg + u][q];
       }
-    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -337,25 +353,37 @@ __global__ void k_flux_set(int* lo_ptr, FluxParams f, int sub) {
 }
 
 // out[box * nf + m] = sum over the box's (E, H) pairs of w_p Re(E conj(H~))
-__global__ void __launch_bounds__(256) k_flux_reduce(const double* are, const double* aim,
-                                                     const double* pw, int npairs, int np0, int nf,
-                                                     double* out) {
-  const int m = blockIdx.x, box = blockIdx.y;
-  const int p0 = box == 0 ? 0 : np0, p1 = box == 0 ? np0 : npairs;
-  const size_t nsamp = 2 * (size_t)npairs;
-  const double* re = are + (size_t)m * nsamp;
-  const double* im = aim + (size_t)m * nsamp;
-  double s = 0.0;
-  for (int q = p0 + threadIdx.x; q < p1; q += 256)
-    s += pw[q] * (re[q] * re[npairs + q] + im[q] * im[npairs + q]);
-  __shared__ double red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+// part[b][m] = sum over the pairs p of chunk b of w_p Re(E conj(H~)) at
+// frequency m, in pair order: block b takes chunk b (box 0's chunks first,
+// kFluxChunk pairs each, none across the boxes' boundary), thread i the
+// frequencies m = i, i + 128, ... (a wavefront reads a pair's transforms
+// as one contiguous run)
+__global__ void __launch_bounds__(128) k_flux_reduce(const double* acc, const double* pw, int npairs,
+                                                     int np0, int nf, double* part) {
+  const int b = blockIdx.x;
+  const int nb0 = (np0 + kFluxChunk - 1) / kFluxChunk;
+  const int p0 = b < nb0 ? b * kFluxChunk : np0 + (b - nb0) * kFluxChunk;
+  const int p1 = min(p0 + kFluxChunk, b < nb0 ? np0 : npairs);
+  const size_t rs = 2 * (size_t)nf;
+  for (int m = threadIdx.x; m < nf; m += 128) {
+    double s = 0.0;
+    for (int q = p0; q < p1; ++q) {
+      const double* e = acc + (size_t)q * rs + 2 * m;
+      const double* h = acc + (size_t)(npairs + q) * rs + 2 * m;
+      s += pw[q] * (e[0] * h[0] + e[1] * h[1]);
+    }
+    part[(size_t)b * nf + m] = s;
   }
-  if (threadIdx.x == 0) out[(size_t)box * nf + m] = red[0];
+}
+
+// out[box nf + m] = the box's chunk sums in chunk order
+__global__ void k_flux_sum(const double* part, int nb0, int nb, int nf, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * nf) return;
+  const int box = i / nf, m = i - box * nf;
+  double s = 0.0;
+  for (int b = box == 0 ? 0 : nb0; b < (box == 0 ? nb0 : nb); ++b) s += part[(size_t)b * nf + m];
+  out[i] = s;
 }
 
 template <class T>
@@ -413,10 +441,13 @@ void launch_flux_accumulate(const FluxParams& f, int* lo_ptr, int sub, hipStream
                      ncg8);
   hipLaunchKernelGGL(k_flux_set, dim3(1), dim3(64), 0, s, lo_ptr, f, sub);
 }
-void launch_flux_reduce(const double* are, const double* aim, const double* pw, int npairs,
-                        int npairs_box0, int nf, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_flux_reduce, dim3(nf, 2), dim3(256), 0, s, are, aim, pw, npairs, npairs_box0,
-                     nf, out);
+void launch_flux_reduce(const double* acc, const double* pw, int npairs, int npairs_box0, int nf,
+                        double* part, double* out, hipStream_t s) {
+  const int nb = flux_reduce_chunks(npairs, npairs_box0);
+  const int nb0 = (npairs_box0 + kFluxChunk - 1) / kFluxChunk;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_flux_reduce, dim3(nb), dim3(128), 0, s, acc, pw, npairs, npairs_box0, nf, part);
+  hipLaunchKernelGGL(k_flux_sum, dim3((2 * nf + 255) / 256), dim3(256), 0, s, part, nb0, nb, nf, out);
 }
 template <class T>
 void launch_nonfinite(const T* a, size_t n, int* flag, hipStream_t s) {
