@@ -268,13 +268,13 @@ __global__ void __launch_bounds__(256) k_flux_acc(FluxParams f, const int* lo_pt
   // acc[s][R] (R = 2m + c): the wavefront's 16 samples are 16 consecutive
   // runs of 2 nf doubles, and the four elements q of a tile t fill its
   // 16-row slice of each
-  // run in turn.  Tiles go in groups of 4 whose 16 loads are all issued
+  // run in turn.  Tiles go in groups of 7 whose 28 loads are all issued
   // before the group's stores (rows past 2 nf read the run's last element
-  // and store nothing): 4 round trips per lane instead of one guarded round
-  // trip per element.
+  // and store nothing): 2 round trips per lane instead of one guarded round
+  // trip per element, within the registers of the fold loop.
   double* const dst = f.acc + s * (2 * (size_t)f.nf);
   const int rlast = 2 * f.nf - 1;
-  constexpr int TG = 4;
+  constexpr int TG = 7;
 #pragma unroll
   for (int tg = 0; tg < kFluxTW; tg += TG) {
     double old[TG][4];
