@@ -81,6 +81,39 @@ def test_fp64_early_pulse_parity(B):
     compare(g, o, 1e-10, 1e-10)
 
 
+def test_flux_folds_split_at_any_step(B):
+    """The flux-box transforms do not depend on where the staging windows are
+    folded: a run read out or flushed at steps before, on and across the
+    256-step window boundaries (each a fold of a partly filled window), then
+    continued, ends with the spectra of an unbroken run to the rounding of
+    the split sums, and with the oracle's."""
+    w = W.early_pulse(W.config1(0))
+    cuts = (5, 256, 300, 511, w.steps)
+    say(f"case fp64 config1 early pulse, folds at steps {cuts}")
+    a = B.Sim(w, precision="fp64")
+    a.run(w.steps)
+    sa = a.spectra()
+    b = B.Sim(w, precision="fp64")
+    done = 0
+    for i, n in enumerate(cuts):
+        b.run(n - done)
+        done = n
+        if i % 2:
+            b.flush_spectra()
+        else:
+            b.spectra()
+    sb = b.spectra()
+    for k in ("inc", "ext", "abs", "sca"):
+        e = rel_l2(sb[k], sa[k])
+        say(f"  {k}: split vs unbroken {e:.2e}")
+        assert e <= 1e-12, (k, e)
+    assert np.abs(sa["sca"]).max() > 0
+    o = oracle_run(w, w.steps)
+    so = o.spectra()
+    for k in ("abs", "sca"):
+        assert rel_l2(sb[k], so[k]) <= 1e-10, k
+
+
 def test_fp64_ragged_grid_and_general_cpml(B):
     """Sizes that are not multiples of the block shape; kappa > 1, alpha > 0;
     strong nonlocality (beta, D) and eps_inf != 1."""
