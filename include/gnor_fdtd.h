@@ -255,7 +255,10 @@ gnor_status gnor_get_field(gnor_sim *sim, int32_t which, double *host_dst, size_
 gnor_status gnor_get_aux(gnor_sim *sim, double *e1, double *h1, size_t count);
 
 /* Full state snapshot (fields, currents, node scalars, CPML memory,
- * auxiliary line, accumulators, step index) to/from host memory. */
+ * auxiliary line, accumulators, step index) to/from host memory.  The image
+ * is the library's device layout of this simulation's state, unversioned:
+ * load it only into a simulation of the same description, with the same
+ * library build. */
 size_t gnor_state_bytes(const gnor_sim *sim);
 gnor_status gnor_save_state(gnor_sim *sim, void *host_dst, size_t bytes);
 gnor_status gnor_load_state(gnor_sim *sim, const void *host_src, size_t bytes);
