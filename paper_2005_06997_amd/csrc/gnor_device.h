@@ -131,7 +131,8 @@ __device__ __forceinline__ int find_instance(const BatchEntry<T>* __restrict__ e
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int b0 = c == -1 ? e[mid].dblk0 : (c == -2 ? e[mid].fblk0 : (c == -3 ? e[mid].sblk0 : e[mid].blk0[c]));
+    const BatchEntry<T>& m = entry_at(e, mid);
+    const int b0 = c == -1 ? m.dblk0 : (c == -2 ? m.fblk0 : (c == -3 ? m.sblk0 : m.blk0[c]));
     if (b0 <= b) lo = mid;
     else hi = mid - 1;
   }

@@ -728,7 +728,7 @@ __global__ void __launch_bounds__(256) k_tfsf_fix(Params<T> p, AuxParams a, int 
 template <class T, int TY, bool NT, int CLS>
 __global__ void __launch_bounds__(kBX* TY) k_fplain_batch(const BatchEntry<T>* __restrict__ e, int n) {
   __shared__ HRows<T, TY> sh;
-  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
+  const BatchEntry<T>& en = entry_at(e, find_instance(e, n, blockIdx.x, CLS));
   const int b = blockIdx.x - en.blk0[CLS];
   if (b >= en.nblk[CLS] || (CLS == 0 && b == en.nblk[0] - 1) || (CLS == 2 && en.two_sweep2)) return;
   const Params<T>& p = en.p;
@@ -752,7 +752,7 @@ __global__ void __launch_bounds__(kBX* TY) k_fplain_batch(const BatchEntry<T>* _
 // after those classes' launches.
 template <class T>
 __global__ void __launch_bounds__(256) k_tfsf_fix_batch(const BatchEntry<T>* __restrict__ e, int n) {
-  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, -2)];
+  const BatchEntry<T>& en = entry_at(e, find_instance(e, n, blockIdx.x, -2));
   const int b = blockIdx.x - en.fblk0;
   if (b >= en.fnblk) return;
   tfsf_fix_point(en.p, en.a, b * 256 + threadIdx.x, 0, en.two_sweep2 ? 1 : 2);
@@ -762,7 +762,7 @@ __global__ void __launch_bounds__(256) k_tfsf_fix_batch(const BatchEntry<T>* __r
 // launch), block range sblk0 .. sblk0 + snblk of each instance.
 template <class T>
 __global__ void __launch_bounds__(256) k_nodes_batch(const BatchEntry<T>* __restrict__ e, int n) {
-  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, -3)];
+  const BatchEntry<T>& en = entry_at(e, find_instance(e, n, blockIdx.x, -3));
   const int b = blockIdx.x - en.sblk0;
   if (b >= en.snblk) return;
   nodes_at(en.p, (long)b * 256 + threadIdx.x);
@@ -771,7 +771,7 @@ __global__ void __launch_bounds__(256) k_nodes_batch(const BatchEntry<T>* __rest
 // The lines' whole step, one block per instance (as k_aux for one simulation).
 template <class T>
 __global__ void __launch_bounds__(kAuxThreads) k_aux_batch(const BatchEntry<T>* __restrict__ e, int sub) {
-  const AuxParams& a = e[blockIdx.x].a;
+  const AuxParams& a = entry_at(e, blockIdx.x).a;
   aux_h_block(a, threadIdx.x, kAuxThreads);
   __syncthreads();
   aux_e_block(a, sub, threadIdx.x, kAuxThreads);

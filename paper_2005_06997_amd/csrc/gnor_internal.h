@@ -298,6 +298,17 @@ struct BatchEntry {
   int two_sweep2;
 };
 
+// Entry i of a batch table on the device.  The table is written before a
+// launch and only read during it, so it is read through the constant
+// address space: its loads are then invariant, and the compiler reloads an
+// instance's parameters where they are used instead of holding them all in
+// registers (which had lowered the batched kernels' occupancy).
+template <class T>
+__device__ __forceinline__ const BatchEntry<T>& entry_at(const BatchEntry<T>* e, int i) {
+  typedef __attribute__((address_space(4))) const BatchEntry<T> ConstEntry;
+  return *(const BatchEntry<T>*)((ConstEntry*)e + i);
+}
+
 // one class of the batched sweeps (blocks: that class's blocks of all instances)
 template <class T>
 void launch_h_batch_class(const BatchEntry<T>* e, int n, int blocks, int ty, int c, bool nt,

@@ -113,10 +113,10 @@ __global__ void __launch_bounds__(256) k_dft_batch(const BatchEntry<T>* __restri
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (e[mid].dblk0 <= (int)blockIdx.x) lo = mid;
+    if (entry_at(e, mid).dblk0 <= (int)blockIdx.x) lo = mid;
     else hi = mid - 1;
   }
-  const BatchEntry<T>& en = e[lo];
+  const BatchEntry<T>& en = entry_at(e, lo);
   dft_block<T>(en.d, en.f, en.p, sub, blockIdx.x - en.dblk0);
 }
 

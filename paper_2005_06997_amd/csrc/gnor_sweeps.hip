@@ -502,7 +502,7 @@ __global__ void __launch_bounds__(kBX* TY) k_ej(Params<T> p, AuxParams a, int su
 
 template <class T, int TY, int CLS, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __restrict__ e, int n) {
-  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
+  const BatchEntry<T>& en = entry_at(e, find_instance(e, n, blockIdx.x, CLS));
   const int b = blockIdx.x - en.blk0[CLS];
   if (b >= en.nblk[CLS] || (CLS == 2 && !en.two_sweep2)) return;
   if (CLS == 0 && b == en.nblk[0] - 1) {
@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(kBX* TY) k_h_batch(const BatchEntry<T>* __rest
 // E update is k_aux_e_batch.
 template <class T, int TY, int CLS, bool CP, bool NT>
 __global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __restrict__ e, int n) {
-  const BatchEntry<T>& en = e[find_instance(e, n, blockIdx.x, CLS)];
+  const BatchEntry<T>& en = entry_at(e, find_instance(e, n, blockIdx.x, CLS));
   const int b = blockIdx.x - en.blk0[CLS];
   if (b >= en.nblk[CLS] || (CLS == 0 && b == en.nblk[0] - 1) || (CLS == 2 && !en.two_sweep2)) return;
   ej_class<T, TY, CLS, CP, NT>(en.p, b);
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(kBX* TY) k_ej_batch(const BatchEntry<T>* __res
 // occupancy.
 template <class T>
 __global__ void __launch_bounds__(kAuxThreads) k_aux_e_batch(const BatchEntry<T>* __restrict__ e, int sub) {
-  aux_e_block(e[blockIdx.x].a, sub, threadIdx.x, kAuxThreads);
+  aux_e_block(entry_at(e, blockIdx.x).a, sub, threadIdx.x, kAuxThreads);
 }
 
 // Soft plane source of total-field operation: E_x^{n+1} += f(t_{n+1}) at
