@@ -570,11 +570,12 @@ __global__ void __launch_bounds__(kBX* TY) k_fplain_pml(Params<T> p) {
 
 // Class 2 (metal tiles that meet no slab but maybe an x slab) in one pass,
 // without critical points; its node scalars come from k_nodes, launched
-// before it.  FP32: held to 6 wavefronts per SIMD (80 VGPRs and a 12-byte
+// before it.  Held to 6 wavefronts per SIMD in FP32 (80 VGPRs and a 12-byte
 // spill, against 82 and 5 wavefronts unbounded; 0.6 % faster per step on
-// the 320^3 sphere).
+// the 320^3 sphere) and to 4 in FP64 (128 VGPRs and a 36-byte spill,
+// against 136 and 3: the class 349.6 -> 333.4 us there).
 template <class T, int TY, bool NT>
-__global__ void __launch_bounds__(kBX* TY, sizeof(T) == 4 ? 6 : 1) k_fplain_metal(Params<T> p) {
+__global__ void __launch_bounds__(kBX* TY, sizeof(T) == 4 ? 6 : 4) k_fplain_metal(Params<T> p) {
   __shared__ HRows<T, TY> sh;
   const Tile tile = decode_tile(p.tl, p.tiles, 2, blockIdx.x);
   if (!tile.ok) return;
